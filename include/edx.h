@@ -1,0 +1,214 @@
+/*
+ * edx.h -- C ABI of the MI355X exact-diagonalisation hot path.
+ *
+ * The library computes, for an Anderson impurity model with a normal bath and a
+ * density-density interaction (eq. Ham1), in one sector of fixed (N_up, N_dw)
+ * (Sec. 2.2), the storage-free product w = H v with the decomposition
+ * H = H_d + H_up (x) 1 + 1 (x) H_dw (eq. Hdecomp, eq. Hbuild), the Lanczos ground
+ * state (Sec. 5 "Diagonalization") and the impurity Green's function by the
+ * Krylov continued fraction (Sec. 5 "Dynamical correlation functions").
+ *
+ * Conventions (every index is 0-based; the paper's are 1-based):
+ *   - level k of spin s: impurity orbital a at level a, bath level (a, nu) at
+ *     level norb + a*nbath + nu.  Spin strings are Ns-bit integers, bit k =
+ *     occupation of level k.  All spin-up modes precede all spin-down modes in
+ *     the fermionic order (Sec. 2.3).
+ *   - the strings of one spin in a sector are the Ns-bit integers with the
+ *     right popcount in ascending order (the build_sector listing of Sec. 5
+ *     "Sector construction"); map_s[i] is the i-th one.
+ *   - sector index i = i_up + i_dw * D_up: a vector is the D_up x D_dw
+ *     column-major matrix of eq. Vmatrix, spin-up fastest, dense, no padding.
+ *   - the interaction is plain U n_up n_dw (no Hartree constant); xmu shifts
+ *     the impurity levels only.
+ *
+ * Memory and ownership: model arrays are host memory, copied at build time.
+ * Vectors, workspaces and psi0 are device memory owned by the caller; hip
+ * streams are the caller's (NULL = default stream).  The library owns the
+ * opaque sector handle and its device tables.  edx_hv allocates nothing.
+ *
+ * Errors: every call returns an edx_status; edx_last_error() gives a
+ * thread-local message for the last failing call on this thread.  Nothing
+ * crosses the ABI as an exception.  One sector handle may be used from
+ * several streams at once for edx_hv (it is read-only after build); the
+ * Lanczos and Green calls use only the workspace they are given.
+ */
+#ifndef EDX_H
+#define EDX_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  EDX_OK = 0,
+  EDX_E_INVALID = 1,     /* bad argument, empty or impossible sector        */
+  EDX_E_NOMEM = 2,       /* workspace too small / device allocation failed  */
+  EDX_E_DEVICE = 3,      /* a HIP runtime call failed                       */
+  EDX_E_NOCONV = 4,      /* Lanczos did not meet its stop rule in niter     */
+  EDX_E_DEGENERATE = 5,  /* ground state gap below 1e-9 (flag, e0 is valid) */
+  EDX_E_UNSUPPORTED = 6  /* outside the implemented model space            */
+} edx_status;
+
+/* storage type of v, w, Krylov vectors and psi0; scalars are always FP64 */
+typedef enum { EDX_F64 = 0, EDX_F32 = 1 } edx_vtype;
+
+/* Normal-bath impurity model, density-density part of eq. Ham1
+ * (J_X = J_P = 0).  Ns = norb*(nbath+1) must be <= 24, norb <= 3. */
+typedef struct {
+  int32_t norb;
+  int32_t nbath;
+  const double* eps_imp;   /* [norb]                       host */
+  const double* eps_bath;  /* [norb*nbath], orbital-major host */
+  const double* vhyb;      /* [norb*nbath], orbital-major host */
+  double U;                /* intra-orbital n_up n_dw                    */
+  double Ust;              /* U': inter-orbital opposite spin            */
+  double Jh;               /* J: same-spin inter-orbital gets U' - J     */
+  double xmu;              /* chemical potential on the impurity levels  */
+} edx_model;
+
+typedef struct edx_sector edx_sector;
+
+/* Build the tables of sector (nup, ndw) on the current device (Sec. 5 "Sector
+ * construction", eq. nud_dimension): per spin the ascending string map, its
+ * inverse over all 2^Ns integers, the hopping lists with fermionic signs
+ * (Sec. 2.3) and the diagonal tables (eq. Hbuild).  Runs kernels on `stream`
+ * and returns after they finish.  nup/ndw outside [0, Ns] -> EDX_E_INVALID. */
+edx_status edx_build_sector(const edx_model* model, int32_t nup, int32_t ndw,
+                            void* stream, edx_sector** out);
+
+void edx_sector_destroy(edx_sector* s);
+
+/* D_up, D_dw and D = D_up * D_dw of a sector (eq. nud_dimension). */
+edx_status edx_sector_dims(const edx_sector* s, int64_t* dup, int64_t* ddw,
+                           int64_t* dim);
+
+/* Number of hopping entries of one spin (0 = up, 1 = down) and the largest
+ * number in any row. */
+edx_status edx_sector_hop_nnz(const edx_sector* s, int32_t spin, int64_t* nnz,
+                              int32_t* max_row);
+
+/* Host copies of one spin's tables, for tests.  Any pointer may be NULL.
+ *   map[D_s]           ascending strings
+ *   hop_off[D_s + 1]   CSR row offsets; row i lists j with <i|H_s|j> != 0
+ *   hop_col[nnz]       column j, ascending within a row
+ *   hop_sign[nnz]      +1 / -1: (-1)^(occupied levels strictly between the
+ *                      two levels of the hop), Sec. 2.3
+ *   hop_amp[nnz]       sign * V of the hop
+ *   diag_e[D_s]        one-body energy + same-spin inter-orbital term
+ *   diag_p[D_s]        impurity occupation pattern (bits 0..norb-1) */
+edx_status edx_sector_get_tables(const edx_sector* s, int32_t spin,
+                                 uint32_t* map, int64_t* hop_off,
+                                 int32_t* hop_col, int8_t* hop_sign,
+                                 double* hop_amp, double* diag_e,
+                                 uint8_t* diag_p);
+
+/* w = H v for the sector (Sec. 3 MVP, eq. Hbuild; storage-free, Sec. 2.4).
+ * v and w are device arrays of D elements of `vtype`, must not overlap, and
+ * are accessed on `stream`.  Enqueues kernels and returns; allocates nothing. */
+edx_status edx_hv(const edx_sector* s, edx_vtype vtype, const void* v, void* w,
+                  void* stream);
+
+/* Launch plan of edx_hv (tile shapes; the result is the same for every plan up
+ * to rounding order).  mode 0: whole sector in LDS, one block; mode 1: two
+ * passes (spin-down rows, then spin-up columns + diagonal); mode 2: one pass
+ * over columns that also gathers the spin-down neighbours from global memory.
+ * col_cols: columns per block (1..8) of the column pass; col_threads: 256, 512
+ * or 1024; row_rows: rows per slab (16, 32, 64); row_cols: columns per block of
+ * the row pass (>= 1). */
+typedef struct {
+  int32_t mode, col_cols, col_threads, row_rows, row_cols;
+} edx_hv_plan;
+
+/* Current plan of a sector for one vtype (the built-in heuristic until set). */
+edx_status edx_hv_get_plan(const edx_sector* s, edx_vtype vtype, edx_hv_plan* plan);
+/* Replace the plan (validated; EDX_E_INVALID / EDX_E_UNSUPPORTED if it cannot
+ * run on this sector).  Not thread-safe against concurrent edx_hv calls. */
+edx_status edx_hv_set_plan(edx_sector* s, edx_vtype vtype, const edx_hv_plan* plan);
+/* Project autotuner: times every candidate plan with `reps` launches on the
+ * caller's v, w (device, D elements) and keeps the fastest in the sector. */
+edx_status edx_autotune_hv(edx_sector* s, edx_vtype vtype, const void* v, void* w,
+                           int32_t reps, void* stream, edx_hv_plan* best,
+                           double* best_us);
+
+typedef struct {
+  int32_t niter;        /* max steps, default 512 (lanc_niter)              */
+  int32_t vtype;        /* edx_vtype of the Krylov vectors and psi0         */
+  int32_t reorth;       /* 0 none (plain, as the paper), 1 local, 2 full    */
+  int32_t check_every;  /* host stop-rule check period in steps (>= 1)      */
+  double tol;           /* stop if |E_j - E_{j-1}| <= tol * max(1, |E_j|)   */
+  double rtol;          /* and (if > 0) beta_{j+1}|y_j| <= rtol * max(1,|E|) */
+  uint64_t seed;        /* SplitMix64 seed of the start vector              */
+} edx_lanczos_opts;
+
+typedef struct {
+  int32_t iters;        /* Lanczos steps taken                              */
+  int32_t converged;    /* 1 if the stop rule was met                       */
+  int32_t breakdown;    /* 1 if beta fell below 1e-12 * |T|                 */
+  int32_t degenerate;   /* 1 if E1 - E0 < 1e-9                             */
+  double e0, e1;        /* lowest two Ritz values                           */
+  double beta_last;     /* last beta                                        */
+  double resid;         /* beta_{m} |y_{m-1}|                               */
+} edx_lanczos_report;
+
+void edx_lanczos_default_opts(edx_lanczos_opts* o);
+
+#define EDX_WS_LANCZOS 0
+#define EDX_WS_GREEN 1
+
+/* Device workspace bytes for edx_lanczos_ground_state (what = EDX_WS_LANCZOS,
+ * n = niter) or edx_green_cf (what = EDX_WS_GREEN, n = ngf). */
+size_t edx_workspace_bytes(const edx_sector* s, int32_t what, int32_t vtype,
+                           int32_t n);
+
+/* Lowest eigenpair of the sector by Lanczos (Sec. 5 "Diagonalization"):
+ * alpha_j = <v_j, H v_j>, w = H v_j - alpha_j v_j - beta_j v_{j-1},
+ * beta_{j+1} = |w|, v_{j+1} = w / beta_{j+1}; scalars and dots in FP64.
+ * psi0 (nullable, D elements of opts->vtype) receives the normalised ground
+ * vector from a second replay of the same recurrence.  Returns EDX_OK,
+ * EDX_E_NOCONV (e0 is the best estimate) or EDX_E_DEGENERATE (flag). */
+edx_status edx_lanczos_ground_state(const edx_sector* s,
+                                    const edx_lanczos_opts* opts, void* ws,
+                                    size_t ws_bytes, double* e0, void* psi0,
+                                    edx_lanczos_report* rep, void* stream);
+
+typedef struct {
+  int32_t ngf;     /* Krylov depth per branch (lanc_ngfiter), default 200 */
+  int32_t lmats;   /* number of Matsubara frequencies                   */
+  int32_t vtype;   /* storage of the Krylov vectors (psi0 has this type) */
+  int32_t pad_;
+  double beta;     /* inverse temperature of w_n = (2n+1) pi / beta      */
+} edx_gf_opts;
+
+typedef struct {
+  double wp, wh;       /* |c+ psi0|^2 and |c psi0|^2                      */
+  int32_t np, nh;      /* recurrence lengths of the two branches          */
+  double* alpha_p;     /* optional host outputs [ngf] (may be NULL)       */
+  double* beta_p;      /* beta_p[k] couples steps k and k+1, [ngf]        */
+  double* alpha_h;
+  double* beta_h;
+} edx_gf_report;
+
+/* Impurity Green's function G(i w_n) of orbital `orb`, spin `spin` at T = 0
+ * (eq. KLgf, both fermionic terms +, energies from e0) by the Krylov
+ * continued fraction: phi_p = c+ psi0 in (N_s + 1), phi_h = c psi0 in
+ * (N_s - 1), ngf plain Lanczos steps per branch,
+ *   G = w_p / (z - (a0p - e0) - b1p^2 / (z - (a1p - e0) - ...))
+ *     + w_h / (z + (a0h - e0) - b1h^2 / (z + (a1h - e0) - ...)).
+ * The (N_s +- 1) sector tables are built on first use and kept with `gs`.
+ * g_host receives 2*lmats doubles (re, im interleaved). */
+edx_status edx_green_cf(const edx_sector* gs, const void* psi0, double e0,
+                        int32_t orb, int32_t spin, const edx_gf_opts* opts,
+                        void* ws, size_t ws_bytes, double* g_host,
+                        edx_gf_report* rep, void* stream);
+
+const char* edx_status_str(edx_status st);
+const char* edx_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* EDX_H */

@@ -1,0 +1,277 @@
+// extern "C" entry points of libedx (declared in include/edx.h): argument
+// checking, error strings and dispatch to the drivers.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <string>
+
+#include "edx_internal.h"
+
+namespace edx {
+
+namespace {
+thread_local std::string g_last_error;
+}
+
+void set_error(const std::string& msg) { g_last_error = msg; }
+
+size_t lanczos_workspace_bytes(const edx_sector* s, int vtype, int niter, int reorth);
+edx_status hv_autotune(edx_sector* s, int vtype, const void* v, void* w, int reps,
+                       hipStream_t st, HvPlan* best, double* best_us);
+size_t green_workspace_bytes(const edx_sector* s, int vtype, int ngf);
+edx_status lanczos_ground_state_impl(const edx_sector* s, const edx_lanczos_opts* o, void* ws,
+                                     size_t ws_bytes, double* e0, void* psi0,
+                                     edx_lanczos_report* rep, hipStream_t st);
+edx_status green_cf_impl(const edx_sector* gs, const void* psi0, double e0, int orb, int spin,
+                         const edx_gf_opts* o, void* ws, size_t ws_bytes, double* g_host,
+                         edx_gf_report* rep, hipStream_t st);
+
+static edx_status invalid(const std::string& msg) {
+  set_error(msg);
+  return EDX_E_INVALID;
+}
+
+static edx_status check_model(const edx_model* m, Model* out) {
+  if (!m) return invalid("model is NULL");
+  if (m->norb < 1 || m->norb > kMaxNorb) return invalid("norb must be in [1, 3]");
+  if (m->nbath < 0) return invalid("nbath must be >= 0");
+  const int ns = m->norb * (m->nbath + 1);
+  if (ns > kMaxNs) {
+    set_error("Ns = norb*(nbath+1) must be <= 24");
+    return EDX_E_UNSUPPORTED;
+  }
+  if (m->norb * m->nbath > 127) {
+    set_error("at most 127 hybridisation pairs");
+    return EDX_E_UNSUPPORTED;
+  }
+  if (!m->eps_imp) return invalid("eps_imp is NULL");
+  if (m->nbath > 0 && (!m->eps_bath || !m->vhyb)) return invalid("eps_bath/vhyb is NULL");
+  out->norb = m->norb;
+  out->nbath = m->nbath;
+  out->ns = ns;
+  out->eps_imp.assign(m->eps_imp, m->eps_imp + m->norb);
+  const int nb = m->norb * m->nbath;
+  out->eps_bath.assign(m->eps_bath, m->eps_bath + nb);
+  out->vhyb.assign(m->vhyb, m->vhyb + nb);
+  out->U = m->U;
+  out->Ust = m->Ust;
+  out->Jh = m->Jh;
+  out->xmu = m->xmu;
+  for (double x : out->eps_imp)
+    if (!std::isfinite(x)) return invalid("non-finite eps_imp");
+  for (double x : out->eps_bath)
+    if (!std::isfinite(x)) return invalid("non-finite eps_bath");
+  for (double x : out->vhyb)
+    if (!std::isfinite(x)) return invalid("non-finite vhyb");
+  if (!std::isfinite(m->U) || !std::isfinite(m->Ust) || !std::isfinite(m->Jh) ||
+      !std::isfinite(m->xmu))
+    return invalid("non-finite interaction parameter");
+  return EDX_OK;
+}
+
+static edx_status check_sector(const edx_sector* s) {
+  if (!s) return invalid("sector is NULL");
+  int dev = -1;
+  EDX_HIP(hipGetDevice(&dev));
+  if (dev != s->device) return invalid("sector was built on another device than the current one");
+  return EDX_OK;
+}
+
+static bool valid_vtype(int v) { return v == EDX_F64 || v == EDX_F32; }
+
+}  // namespace edx
+
+using namespace edx;
+
+extern "C" {
+
+edx_status edx_build_sector(const edx_model* model, int32_t nup, int32_t ndw, void* stream,
+                            edx_sector** out) {
+  if (!out) return invalid("out is NULL");
+  *out = nullptr;
+  Model m;
+  EDX_TRY(check_model(model, &m));
+  if (nup < 0 || ndw < 0 || nup > m.ns || ndw > m.ns)
+    return invalid("nup/ndw must be in [0, Ns]");
+  return build_sector_impl(m, nup, ndw, static_cast<hipStream_t>(stream), out);
+}
+
+void edx_sector_destroy(edx_sector* s) { destroy_sector(s); }
+
+edx_status edx_sector_dims(const edx_sector* s, int64_t* dup, int64_t* ddw, int64_t* dim) {
+  if (!s) return invalid("sector is NULL");
+  if (dup) *dup = s->dup;
+  if (ddw) *ddw = s->ddw;
+  if (dim) *dim = s->dim;
+  return EDX_OK;
+}
+
+edx_status edx_sector_hop_nnz(const edx_sector* s, int32_t spin, int64_t* nnz, int32_t* max_row) {
+  if (!s) return invalid("sector is NULL");
+  if (spin != 0 && spin != 1) return invalid("spin must be 0 or 1");
+  const SpinTables& T = spin == 0 ? s->up : s->dw;
+  if (nnz) *nnz = T.nnz;
+  if (max_row) *max_row = T.width;
+  return EDX_OK;
+}
+
+edx_status edx_sector_get_tables(const edx_sector* s, int32_t spin, uint32_t* map,
+                                 int64_t* hop_off, int32_t* hop_col, int8_t* hop_sign,
+                                 double* hop_amp, double* diag_e, uint8_t* diag_p) {
+  EDX_TRY(check_sector(s));
+  if (spin != 0 && spin != 1) return invalid("spin must be 0 or 1");
+  const SpinTables& T = spin == 0 ? s->up : s->dw;
+  const int64_t D = T.D;
+  if (map) EDX_HIP(hipMemcpy(map, T.map, D * sizeof(uint32_t), hipMemcpyDeviceToHost));
+  if (diag_e) EDX_HIP(hipMemcpy(diag_e, T.e64, D * sizeof(double), hipMemcpyDeviceToHost));
+  if (diag_p) EDX_HIP(hipMemcpy(diag_p, T.pat, D, hipMemcpyDeviceToHost));
+  if (hop_off || hop_col || hop_sign || hop_amp) {
+    std::vector<uint32_t> ell((size_t)T.width * D);
+    if (!ell.empty())
+      EDX_HIP(hipMemcpy(ell.data(), T.hop, ell.size() * sizeof(uint32_t), hipMemcpyDeviceToHost));
+    int64_t pos = 0;
+    std::vector<std::pair<uint32_t, uint32_t>> row;
+    for (int64_t i = 0; i < D; ++i) {
+      if (hop_off) hop_off[i] = pos;
+      row.clear();
+      for (int k = 0; k < T.width; ++k) {
+        const uint32_t e = ell[(size_t)k * D + i];
+        if (((e >> kAmpShift) & 0x7Fu) == kPadPair) continue;
+        row.emplace_back(e & kColMask, e);
+      }
+      std::sort(row.begin(), row.end());
+      for (auto& ce : row) {
+        if (hop_col) hop_col[pos] = (int32_t)ce.first;
+        if (hop_sign) hop_sign[pos] = (ce.second >> 31) ? -1 : 1;
+        if (hop_amp) hop_amp[pos] = s->amp_host[ce.second >> kAmpShift];
+        ++pos;
+      }
+    }
+    if (hop_off) hop_off[D] = pos;
+  }
+  return EDX_OK;
+}
+
+edx_status edx_hv(const edx_sector* s, edx_vtype vtype, const void* v, void* w, void* stream) {
+  EDX_TRY(check_sector(s));
+  if (!valid_vtype(vtype)) return invalid("vtype must be EDX_F64 or EDX_F32");
+  if (!v || !w) return invalid("v or w is NULL");
+  const size_t bytes = (size_t)s->dim * vbytes(vtype);
+  const char* pv = static_cast<const char*>(v);
+  const char* pw = static_cast<const char*>(w);
+  if (pv < pw + bytes && pw < pv + bytes) return invalid("v and w overlap");
+  return hv_launch(s, vtype, v, w, nullptr, nullptr, static_cast<hipStream_t>(stream));
+}
+
+edx_status edx_hv_get_plan(const edx_sector* s, edx_vtype vtype, edx_hv_plan* plan) {
+  if (!s || !plan) return invalid("sector or plan is NULL");
+  if (!valid_vtype(vtype)) return invalid("vtype must be EDX_F64 or EDX_F32");
+  const HvPlan p = hv_plan(s, vtype);
+  plan->mode = p.mode;
+  plan->col_cols = p.col_cols;
+  plan->col_threads = p.col_threads;
+  plan->row_rows = p.row_rows;
+  plan->row_cols = p.row_cols;
+  return EDX_OK;
+}
+
+edx_status edx_hv_set_plan(edx_sector* s, edx_vtype vtype, const edx_hv_plan* plan) {
+  if (!s || !plan) return invalid("sector or plan is NULL");
+  if (!valid_vtype(vtype)) return invalid("vtype must be EDX_F64 or EDX_F32");
+  HvPlan p;
+  p.mode = plan->mode;
+  p.col_cols = plan->col_cols;
+  p.col_threads = plan->col_threads;
+  p.row_rows = plan->row_rows;
+  p.row_cols = plan->row_cols;
+  EDX_TRY(hv_validate(s, vtype, &p));
+  const int k = vtype == EDX_F32 ? 1 : 0;
+  s->plan_v[k][0] = p.mode;
+  s->plan_v[k][1] = p.col_cols;
+  s->plan_v[k][2] = p.col_threads;
+  s->plan_v[k][3] = p.row_rows;
+  s->plan_v[k][4] = p.row_cols;
+  s->plan_v[k][5] = p.col_blocks;
+  s->plan_set[k] = true;
+  return EDX_OK;
+}
+
+edx_status edx_autotune_hv(edx_sector* s, edx_vtype vtype, const void* v, void* w, int32_t reps,
+                           void* stream, edx_hv_plan* best, double* best_us) {
+  EDX_TRY(check_sector(s));
+  if (!valid_vtype(vtype)) return invalid("vtype must be EDX_F64 or EDX_F32");
+  if (!v || !w) return invalid("v or w is NULL");
+  HvPlan bp;
+  EDX_TRY(hv_autotune(s, vtype, v, w, std::max(1, (int)reps), static_cast<hipStream_t>(stream),
+                      &bp, best_us));
+  if (best) {
+    best->mode = bp.mode;
+    best->col_cols = bp.col_cols;
+    best->col_threads = bp.col_threads;
+    best->row_rows = bp.row_rows;
+    best->row_cols = bp.row_cols;
+  }
+  return EDX_OK;
+}
+
+void edx_lanczos_default_opts(edx_lanczos_opts* o) {
+  if (!o) return;
+  o->niter = 512;
+  o->vtype = EDX_F64;
+  o->reorth = 0;
+  o->check_every = 8;
+  o->tol = 1e-12;
+  o->rtol = 0.0;
+  o->seed = 1234567;
+}
+
+size_t edx_workspace_bytes(const edx_sector* s, int32_t what, int32_t vtype, int32_t n) {
+  if (!s || !valid_vtype(vtype) || n < 1) return 0;
+  if (what == EDX_WS_LANCZOS) return lanczos_workspace_bytes(s, vtype, n, 0);
+  if (what == EDX_WS_GREEN) return green_workspace_bytes(s, vtype, n);
+  if (what == 2) return lanczos_workspace_bytes(s, vtype, n, 2);   // full re-orthogonalisation
+  return 0;
+}
+
+edx_status edx_lanczos_ground_state(const edx_sector* s, const edx_lanczos_opts* opts, void* ws,
+                                    size_t ws_bytes, double* e0, void* psi0,
+                                    edx_lanczos_report* rep, void* stream) {
+  EDX_TRY(check_sector(s));
+  if (!opts || !e0 || !ws) return invalid("opts, e0 and ws must be non-NULL");
+  if (!valid_vtype(opts->vtype)) return invalid("vtype must be EDX_F64 or EDX_F32");
+  if (opts->niter < 1 || opts->niter > 4096) return invalid("niter must be in [1, 4096]");
+  if (opts->reorth < 0 || opts->reorth > 2) return invalid("reorth must be 0, 1 or 2");
+  if (!(opts->tol >= 0.0) || !(opts->rtol >= 0.0)) return invalid("tol/rtol must be >= 0");
+  return lanczos_ground_state_impl(s, opts, ws, ws_bytes, e0, psi0, rep,
+                                   static_cast<hipStream_t>(stream));
+}
+
+edx_status edx_green_cf(const edx_sector* gs, const void* psi0, double e0, int32_t orb,
+                        int32_t spin, const edx_gf_opts* opts, void* ws, size_t ws_bytes,
+                        double* g_host, edx_gf_report* rep, void* stream) {
+  EDX_TRY(check_sector(gs));
+  if (!opts || !psi0 || !ws || !g_host) return invalid("opts, psi0, ws and g_host must be non-NULL");
+  if (!valid_vtype(opts->vtype)) return invalid("vtype must be EDX_F64 or EDX_F32");
+  if (orb < 0 || orb >= gs->model.norb) return invalid("orb out of range");
+  if (spin != 0 && spin != 1) return invalid("spin must be 0 or 1");
+  if (opts->ngf > 4096) return invalid("ngf must be <= 4096");
+  return green_cf_impl(gs, psi0, e0, orb, spin, opts, ws, ws_bytes, g_host, rep,
+                       static_cast<hipStream_t>(stream));
+}
+
+const char* edx_status_str(edx_status st) {
+  switch (st) {
+    case EDX_OK: return "EDX_OK";
+    case EDX_E_INVALID: return "EDX_E_INVALID";
+    case EDX_E_NOMEM: return "EDX_E_NOMEM";
+    case EDX_E_DEVICE: return "EDX_E_DEVICE";
+    case EDX_E_NOCONV: return "EDX_E_NOCONV";
+    case EDX_E_DEGENERATE: return "EDX_E_DEGENERATE";
+    case EDX_E_UNSUPPORTED: return "EDX_E_UNSUPPORTED";
+  }
+  return "EDX_E_UNKNOWN";
+}
+
+const char* edx_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"

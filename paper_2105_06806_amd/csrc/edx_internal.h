@@ -1,0 +1,168 @@
+// Internal declarations shared by the translation units of libedx.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/edx.h"
+
+namespace edx {
+
+constexpr int kMaxNs = 24;
+constexpr int kMaxNorb = 3;
+constexpr uint32_t kColMask = 0x00FFFFFFu;   // hop entry: bits 0..23 column
+constexpr int kAmpShift = 24;                // bits 24..30 pair, bit 31 sign
+constexpr uint32_t kPadPair = 0x7Fu;         // pair index of padding entries
+constexpr int kAmpTable = 256;               // signed amplitude per (pair, sign)
+constexpr int kMaxPartials = 2048;           // partial sums per reduction
+constexpr int kReduceSlots = 8;              // dots reduced by one kernel
+
+void set_error(const std::string& msg);
+
+#define EDX_HIP(call)                                                        \
+  do {                                                                       \
+    hipError_t e_ = (call);                                                  \
+    if (e_ != hipSuccess) {                                                  \
+      ::edx::set_error(std::string(#call) + ": " + hipGetErrorString(e_));   \
+      return EDX_E_DEVICE;                                                   \
+    }                                                                        \
+  } while (0)
+
+#define EDX_TRY(expr)               \
+  do {                              \
+    edx_status s_ = (expr);         \
+    if (s_ != EDX_OK) return s_;    \
+  } while (0)
+
+// Host copy of the model (arrays owned).
+struct Model {
+  int norb = 0, nbath = 0, ns = 0;
+  std::vector<double> eps_imp, eps_bath, vhyb;
+  double U = 0, Ust = 0, Jh = 0, xmu = 0;
+};
+
+// Tables of one spin species of a sector, device resident.
+struct SpinTables {
+  int n = 0;              // electrons of this spin
+  int64_t D = 0;          // number of strings
+  int width = 0;          // ELL width: max hops per row
+  int64_t nnz = 0;        // non-padding hop entries
+  uint32_t* map = nullptr;    // [D] ascending strings
+  int32_t* rank = nullptr;    // [2^Ns] index of a string, -1 if other popcount
+  uint32_t* hop = nullptr;    // [width * D] packed ELL, hop[k*D + i]
+  double* e64 = nullptr;      // [D] diagonal energy
+  float* e32 = nullptr;       // [D] same, rounded
+  uint8_t* pat = nullptr;     // [D] impurity pattern
+};
+
+}  // namespace edx
+
+struct edx_sector {
+  edx::Model model;
+  int nup = 0, ndw = 0;
+  int64_t dup = 0, ddw = 0, dim = 0;
+  int device = 0;
+  edx::SpinTables up, dw;
+  // Signed amplitudes indexed by (hop entry >> 24); identical for both spins.
+  double* amp64 = nullptr;   // [256] device
+  float* amp32 = nullptr;    // [256] device
+  // W[p_up * 8 + p_dw]: density-density energy of two impurity patterns.
+  double* w64 = nullptr;     // [64] device
+  float* w32 = nullptr;      // [64] device
+  int32_t* binom = nullptr;  // [25*25] device binomial table
+  double amp_host[edx::kAmpTable];
+  // launch plans of edx_hv per vtype (set by the autotuner or the caller)
+  bool plan_set[2] = {false, false};
+  int plan_v[2][6] = {{0}};
+  // lazily built neighbour sectors for the Green's function:
+  // [spin][0] = N_s + 1 (particle), [spin][1] = N_s - 1 (hole)
+  std::mutex nb_mu;
+  edx_sector* nb[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
+};
+
+namespace edx {
+
+// ---- tables.hip
+edx_status build_sector_impl(const Model& m, int nup, int ndw, hipStream_t st,
+                             edx_sector** out);
+void destroy_sector(edx_sector* s);
+
+// ---- hv.hip
+struct HvPlan {
+  int mode = 0;      // 0 small (whole sector in LDS), 1 two-pass, 2 fused column
+  int col_cols = 1;  // columns per block in the column pass
+  int col_threads = 512;
+  int row_rows = 64; // rows per slab in the row pass
+  int row_cols = 16; // columns per block in the row pass
+  int col_blocks = 0;  // blocks of the last pass (partial count)
+};
+HvPlan hv_plan(const edx_sector* s, int vtype);
+HvPlan hv_default_plan(const edx_sector* s, int vtype);
+edx_status hv_validate(const edx_sector* s, int vtype, HvPlan* p);
+// w = H (scale * v); if partial != nullptr the last pass writes per-block
+// partial sums of <scale v, w> (FP64) and plan.col_blocks of them.
+edx_status hv_launch(const edx_sector* s, int vtype, const void* v, void* w,
+                     const double* vscale, double* partial, hipStream_t st,
+                     const HvPlan* plan = nullptr);
+int hv_partial_blocks(const edx_sector* s, int vtype);
+
+// ---- krylov.hip
+int elem_blocks(int64_t n);
+edx_status k_start_vector(int vtype, void* u, int64_t n, uint64_t seed,
+                          double* partial, hipStream_t st);
+// reduce `nslots` sets of `nparts` partials (slot-major, stride kMaxPartials)
+// into out[0..nslots); op: 0 plain sum, 1 Lanczos alpha, 2 Lanczos beta.
+edx_status k_reduce(const double* partial, int nparts, int nslots, double* out,
+                    hipStream_t st);
+struct LanczosScalars;  // device layout, see krylov.hip
+edx_status k_alpha_finish(const double* partial, int nparts, double* alpha_j,
+                          hipStream_t st);
+edx_status k_beta_finish(const double* partial, int nparts, double* beta_next,
+                         double* scale_next, hipStream_t st);
+edx_status k_update(int vtype, void* w, const void* vcur, const double* scur,
+                    const void* vprev, const double* sprev,
+                    const double* alpha, const double* beta, int64_t n,
+                    void* psi, const double* ycoef, double* partial,
+                    hipStream_t st);
+edx_status k_norm2(int vtype, const void* x, int64_t n, double* partial,
+                   hipStream_t st);
+edx_status k_scale_copy(int vtype, const void* x, const double* scale,
+                        void* y, int64_t n, hipStream_t st);
+edx_status k_dot2(int vtype, const void* w, const void* a, const double* sa,
+                  const void* b, const double* sb, int64_t n, double* partial,
+                  hipStream_t st);
+edx_status k_axpy2(int vtype, void* w, const void* a, const double* ca,
+                   const double* sa, const void* b, const double* cb,
+                   const double* sb, int64_t n, double* partial,
+                   hipStream_t st);
+edx_status k_multi_dot(int vtype, const void* basis, int64_t ld, int m,
+                       const void* w, int64_t n, double* partial,
+                       hipStream_t st);
+edx_status k_multi_axpy(int vtype, void* w, const void* basis, int64_t ld,
+                        int m, const double* coef, int64_t n, double* partial,
+                        hipStream_t st);
+int multi_blocks(int64_t n);
+
+// ---- green.hip
+edx_status k_apply_op(const edx_sector* src, const edx_sector* dst, int vtype,
+                      const void* psi, void* phi, int orb, int spin, int create,
+                      hipStream_t st);
+edx_status k_green_cf(const double* ap, const double* bp, int np, double wp,
+                      const double* ah, const double* bh, int nh, double wh,
+                      double e0, double beta, int lmats, double* g,
+                      hipStream_t st);
+
+// ---- lanczos.cpp (host)
+double tridiag_lowest(const double* a, const double* b, int m, int k);
+void tridiag_vector(const double* a, const double* b, int m, double lam,
+                    double* y);
+
+inline size_t vbytes(int vtype) { return vtype == EDX_F32 ? 4 : 8; }
+inline size_t align_up(size_t x, size_t a = 256) { return (x + a - 1) / a * a; }
+
+}  // namespace edx

@@ -1,0 +1,113 @@
+// Green's-function kernels (Sec. 5 "Dynamical correlation functions").
+//
+//  * k_apply: phi = c+_{orb,s} psi (N_s -> N_s + 1) or c_{orb,s} psi
+//    (N_s -> N_s - 1).  One thread per element of the target sector: it looks
+//    up the source string through the rank table and copies the amplitude with
+//    the fermionic sign (Sec. 2.3): (-1)^(occupied levels below orb of the same
+//    spin), times (-1)^N_up for spin down because every spin-up mode precedes
+//    the spin-down modes.  The paper applies the operator on the master rank and
+//    then scatters the vector; here it is a streaming gather on the device.
+//  * k_cf: the two continued fractions at the Matsubara frequencies
+//    w_n = (2n+1) pi / beta, one thread per frequency, evaluated from the
+//    deepest level up:
+//      d = z -+ (a_{n-1} - E0);  d = z -+ (a_k - E0) - b_{k+1}^2 / d, k = n-2..0;
+//      G += w / d    (- for the particle branch, + for the hole branch).
+#include "common.cuh"
+#include "edx_internal.h"
+
+namespace edx {
+namespace {
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_apply(const T* __restrict__ psi, T* __restrict__ phi,
+                                               int64_t tdup, int64_t tdim, int64_t sdup,
+                                               const uint32_t* __restrict__ tmap,
+                                               const int32_t* __restrict__ srank, int orb,
+                                               int spin, int create, int nup) {
+  const uint32_t bit = 1u << orb;
+  const uint32_t below = bit - 1u;
+  for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < tdim;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t iu = idx % tdup;
+    const int64_t id = idx / tdup;
+    const uint32_t t = tmap[spin == 0 ? iu : id];
+    const bool has = (t & bit) != 0u;
+    T val = T(0);
+    if (has == (create != 0)) {
+      const uint32_t s = create ? (t ^ bit) : (t | bit);
+      const int64_t r = srank[s];
+      int par = __popc(s & below) & 1;
+      if (spin == 1) par ^= (nup & 1);
+      const int64_t src = spin == 0 ? r + id * sdup : iu + r * sdup;
+      const T x = psi[src];
+      val = par ? -x : x;
+    }
+    phi[idx] = val;
+  }
+}
+
+__global__ void k_cf(const double* __restrict__ ap, const double* __restrict__ bp, int np,
+                     double wp, const double* __restrict__ ah, const double* __restrict__ bh,
+                     int nh, double wh, double e0, double beta, int lmats,
+                     double* __restrict__ g) {
+  const int n = blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= lmats) return;
+  const double wn = (2.0 * n + 1.0) * M_PI / beta;
+  double gr = 0.0, gi = 0.0;
+  for (int br = 0; br < 2; ++br) {
+    const double* a = br == 0 ? ap : ah;
+    const double* b = br == 0 ? bp : bh;
+    const int m = br == 0 ? np : nh;
+    const double wgt = br == 0 ? wp : wh;
+    const double sg = br == 0 ? -1.0 : 1.0;
+    if (m <= 0 || wgt == 0.0) continue;
+    // d = z + sg (a_k - e0) - b_{k+1}^2 / d, with z = i wn
+    double dr = sg * (a[m - 1] - e0), di = wn;
+    for (int k = m - 2; k >= 0; --k) {
+      const double b2 = b[k] * b[k];
+      const double den = dr * dr + di * di;
+      // b2 / d = b2 * conj(d) / |d|^2
+      const double qr = b2 * dr / den, qi = -b2 * di / den;
+      dr = sg * (a[k] - e0) - qr;
+      di = wn - qi;
+    }
+    const double den = dr * dr + di * di;
+    gr += wgt * dr / den;
+    gi += -wgt * di / den;
+  }
+  g[2 * n] = gr;
+  g[2 * n + 1] = gi;
+}
+
+}  // namespace
+
+edx_status k_apply_op(const edx_sector* src, const edx_sector* dst, int vtype, const void* psi,
+                      void* phi, int orb, int spin, int create, hipStream_t st) {
+  const int64_t n = dst->dim;
+  const int64_t b = (n + 255) / 256;
+  const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(b, 8192));
+  const uint32_t* tmap = spin == 0 ? dst->up.map : dst->dw.map;
+  const int32_t* srank = spin == 0 ? src->up.rank : src->dw.rank;
+  if (vtype == EDX_F64)
+    hipLaunchKernelGGL(k_apply<double>, dim3(grid), dim3(256), 0, st, (const double*)psi,
+                       (double*)phi, dst->dup, n, src->dup, tmap, srank, orb, spin, create,
+                       src->nup);
+  else
+    hipLaunchKernelGGL(k_apply<float>, dim3(grid), dim3(256), 0, st, (const float*)psi,
+                       (float*)phi, dst->dup, n, src->dup, tmap, srank, orb, spin, create,
+                       src->nup);
+  EDX_HIP(hipGetLastError());
+  return EDX_OK;
+}
+
+edx_status k_green_cf(const double* ap, const double* bp, int np, double wp, const double* ah,
+                      const double* bh, int nh, double wh, double e0, double beta, int lmats,
+                      double* g, hipStream_t st) {
+  const int grid = (lmats + 255) / 256;
+  hipLaunchKernelGGL(k_cf, dim3(grid), dim3(256), 0, st, ap, bp, np, wp, ah, bh, nh, wh, e0,
+                     beta, lmats, g);
+  EDX_HIP(hipGetLastError());
+  return EDX_OK;
+}
+
+}  // namespace edx

@@ -1,0 +1,385 @@
+// Krylov-vector kernels of the Lanczos recurrence (Sec. 5 "Diagonalization"):
+// start vector, FP64-accumulated dot products with a deterministic two-stage
+// reduction (per-block partials, then one block in fixed order), the fused
+// three-term update w <- w - alpha v_j - beta v_{j-1} with |w|^2, and the
+// Gram-Schmidt kernels of the precision mode.
+//
+// Lanczos vectors are kept unnormalised: vector j is u_j with a device scale
+// s_j = 1 / |u_j|, so v_j = s_j u_j and no separate normalisation pass is needed.
+// Every kernel reads its scalars (alpha, beta, scales, coefficients) from device
+// memory, so a whole Lanczos step is enqueued without a host round trip.
+#include <algorithm>
+#include <cmath>
+
+#include "common.cuh"
+#include "edx_internal.h"
+
+namespace edx {
+
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kMaxElemBlocks = 1024;
+
+__device__ __forceinline__ uint64_t splitmix64(uint64_t seed, uint64_t k) {
+  uint64_t z = seed + (k + 1) * 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_start(T* __restrict__ u, int64_t n, uint64_t seed,
+                                                    double* __restrict__ partial) {
+  __shared__ double red[kThreads / 64];
+  double acc = 0.0;
+  for (int64_t i = blockIdx.x * (int64_t)kThreads + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * kThreads) {
+    const uint64_t z = splitmix64(seed, (uint64_t)i);
+    const double x = (double)(z >> 11) * 0x1.0p-53 * 2.0 - 1.0;
+    const T t = (T)x;
+    u[i] = t;
+    acc += (double)t * (double)t;
+  }
+  const double s = block_sum(acc, red);
+  if (threadIdx.x == 0) partial[blockIdx.x] = s;
+}
+
+__global__ __launch_bounds__(kThreads) void k_reduce_kernel(const double* __restrict__ partial,
+                                                            int nparts, int stride,
+                                                            double* __restrict__ out, int mode,
+                                                            double* __restrict__ out2) {
+  __shared__ double red[kThreads / 64];
+  const int slot = blockIdx.x;
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < nparts; i += kThreads) acc += partial[(int64_t)slot * stride + i];
+  const double s = block_sum(acc, red);
+  if (threadIdx.x == 0) {
+    if (mode == 2) {            // beta: sqrt of |w|^2 and the next scale
+      const double b = sqrt(s > 0.0 ? s : 0.0);
+      out[slot] = b;
+      out2[slot] = b > 0.0 ? 1.0 / b : 0.0;
+    } else {
+      out[slot] = s;
+    }
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_update_kernel(
+    T* __restrict__ w, const T* __restrict__ vc, const double* __restrict__ scur,
+    const T* __restrict__ vp, const double* __restrict__ sprev,
+    const double* __restrict__ alpha, const double* __restrict__ beta, int64_t n,
+    T* __restrict__ psi, const double* __restrict__ ycoef, double* __restrict__ partial) {
+  __shared__ double red[kThreads / 64];
+  const double ac = (*alpha) * (*scur);
+  const double bp = vp ? (*beta) * (*sprev) : 0.0;
+  const double yc = psi ? (*ycoef) * (*scur) : 0.0;
+  double acc = 0.0;
+  for (int64_t i = blockIdx.x * (int64_t)kThreads + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * kThreads) {
+    const double x = (double)vc[i];
+    double r = (double)w[i] - ac * x;
+    if (vp) r -= bp * (double)vp[i];
+    const T t = (T)r;
+    w[i] = t;
+    acc += (double)t * (double)t;
+    if (psi) psi[i] = (T)((double)psi[i] + yc * x);
+  }
+  const double s = block_sum(acc, red);
+  if (threadIdx.x == 0) partial[blockIdx.x] = s;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_norm2_kernel(const T* __restrict__ x, int64_t n,
+                                                           double* __restrict__ partial) {
+  __shared__ double red[kThreads / 64];
+  double acc = 0.0;
+  for (int64_t i = blockIdx.x * (int64_t)kThreads + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * kThreads) {
+    const double t = (double)x[i];
+    acc += t * t;
+  }
+  const double s = block_sum(acc, red);
+  if (threadIdx.x == 0) partial[blockIdx.x] = s;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_scale_copy_kernel(const T* __restrict__ x,
+                                                                const double* __restrict__ sc,
+                                                                T* __restrict__ y, int64_t n) {
+  const double s = *sc;
+  for (int64_t i = blockIdx.x * (int64_t)kThreads + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * kThreads)
+    y[i] = (T)((double)x[i] * s);
+}
+
+// partial[0][b] = <w, sa a>, partial[1][b] = <w, sb b>
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_dot2_kernel(const T* __restrict__ w,
+                                                          const T* __restrict__ a,
+                                                          const double* __restrict__ sa,
+                                                          const T* __restrict__ b,
+                                                          const double* __restrict__ sb,
+                                                          int64_t n, double* __restrict__ partial,
+                                                          int stride) {
+  __shared__ double red[kThreads / 64];
+  double da = 0.0, db = 0.0;
+  for (int64_t i = blockIdx.x * (int64_t)kThreads + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * kThreads) {
+    const double x = (double)w[i];
+    da += x * (double)a[i];
+    if (b) db += x * (double)b[i];
+  }
+  const double s1 = block_sum(da, red);
+  const double s2 = block_sum(db, red);
+  if (threadIdx.x == 0) {
+    partial[blockIdx.x] = s1 * (*sa);
+    partial[stride + blockIdx.x] = b ? s2 * (*sb) : 0.0;
+  }
+}
+
+// w -= ca sa a + cb sb b; partial |w|^2
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_axpy2_kernel(
+    T* __restrict__ w, const T* __restrict__ a, const double* __restrict__ ca,
+    const double* __restrict__ sa, const T* __restrict__ b, const double* __restrict__ cb,
+    const double* __restrict__ sb, int64_t n, double* __restrict__ partial) {
+  __shared__ double red[kThreads / 64];
+  const double fa = (*ca) * (*sa);
+  const double fb = b ? (*cb) * (*sb) : 0.0;
+  double acc = 0.0;
+  for (int64_t i = blockIdx.x * (int64_t)kThreads + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * kThreads) {
+    double r = (double)w[i] - fa * (double)a[i];
+    if (b) r -= fb * (double)b[i];
+    const T t = (T)r;
+    w[i] = t;
+    acc += (double)t * (double)t;
+  }
+  const double s = block_sum(acc, red);
+  if (threadIdx.x == 0) partial[blockIdx.x] = s;
+}
+
+// Full re-orthogonalisation: partial[k][b] = <basis_k, w> for k < m
+constexpr int kMultiChunk = 8;   // basis vectors per pass over w
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_multi_dot_kernel(const T* __restrict__ basis,
+                                                               int64_t ld, int m,
+                                                               const T* __restrict__ w,
+                                                               int64_t n,
+                                                               double* __restrict__ partial,
+                                                               int stride) {
+  __shared__ double red[kThreads / 64];
+  for (int k0 = 0; k0 < m; k0 += kMultiChunk) {
+    double acc[kMultiChunk];
+#pragma unroll
+    for (int c = 0; c < kMultiChunk; ++c) acc[c] = 0.0;
+    for (int64_t i = blockIdx.x * (int64_t)kThreads + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * kThreads) {
+      const double x = (double)w[i];
+#pragma unroll
+      for (int c = 0; c < kMultiChunk; ++c)
+        if (k0 + c < m) acc[c] += x * (double)basis[(int64_t)(k0 + c) * ld + i];
+    }
+    for (int c = 0; c < kMultiChunk && k0 + c < m; ++c) {
+      const double s = block_sum(acc[c], red);
+      if (threadIdx.x == 0) partial[(int64_t)(k0 + c) * stride + blockIdx.x] = s;
+    }
+  }
+}
+
+// w -= sum_k coef[k] basis_k; partial |w|^2
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_multi_axpy_kernel(T* __restrict__ w,
+                                                                const T* __restrict__ basis,
+                                                                int64_t ld, int m,
+                                                                const double* __restrict__ coef,
+                                                                int64_t n,
+                                                                double* __restrict__ partial) {
+  __shared__ double red[kThreads / 64];
+  double acc = 0.0;
+  for (int64_t i = blockIdx.x * (int64_t)kThreads + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * kThreads) {
+    double r = (double)w[i];
+    for (int k = 0; k < m; ++k) r -= coef[k] * (double)basis[(int64_t)k * ld + i];
+    const T t = (T)r;
+    w[i] = t;
+    acc += (double)t * (double)t;
+  }
+  const double s = block_sum(acc, red);
+  if (partial && threadIdx.x == 0) partial[blockIdx.x] = s;
+}
+
+// coef[k] *= scale[k]^2: <v_k, w> v_k = s_k^2 <u_k, w> u_k for unnormalised u_k
+__global__ void k_coef_scale2_kernel(double* __restrict__ coef, const double* __restrict__ scale,
+                                     int m) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < m) coef[k] *= scale[k] * scale[k];
+}
+
+}  // namespace
+
+edx_status k_coef_scale2(double* coef, const double* scale, int m, hipStream_t st) {
+  hipLaunchKernelGGL(k_coef_scale2_kernel, dim3((m + 255) / 256), dim3(256), 0, st, coef, scale,
+                     m);
+  EDX_HIP(hipGetLastError());
+  return EDX_OK;
+}
+
+int elem_blocks(int64_t n) {
+  int64_t b = (n + kThreads * 4 - 1) / (kThreads * 4);
+  return (int)std::max<int64_t>(1, std::min<int64_t>(b, kMaxElemBlocks));
+}
+
+int multi_blocks(int64_t n) { return elem_blocks(n); }
+
+#define EDX_DISPATCH(vtype, KERN, GRID, ...)                                           \
+  do {                                                                                 \
+    if ((vtype) == EDX_F64)                                                            \
+      hipLaunchKernelGGL(KERN<double>, dim3(GRID), dim3(kThreads), 0, st, __VA_ARGS__); \
+    else                                                                               \
+      hipLaunchKernelGGL(KERN<float>, dim3(GRID), dim3(kThreads), 0, st, __VA_ARGS__);  \
+    EDX_HIP(hipGetLastError());                                                        \
+  } while (0)
+
+#define PT(x) reinterpret_cast<T*>(x)
+
+edx_status k_start_vector(int vtype, void* u, int64_t n, uint64_t seed, double* partial,
+                          hipStream_t st) {
+  const int g = elem_blocks(n);
+  if (vtype == EDX_F64)
+    hipLaunchKernelGGL(k_start<double>, dim3(g), dim3(kThreads), 0, st, (double*)u, n, seed,
+                       partial);
+  else
+    hipLaunchKernelGGL(k_start<float>, dim3(g), dim3(kThreads), 0, st, (float*)u, n, seed,
+                       partial);
+  EDX_HIP(hipGetLastError());
+  return EDX_OK;
+}
+
+edx_status k_reduce(const double* partial, int nparts, int nslots, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_reduce_kernel, dim3(nslots), dim3(kThreads), 0, st, partial, nparts,
+                     kMaxPartials, out, 0, (double*)nullptr);
+  EDX_HIP(hipGetLastError());
+  return EDX_OK;
+}
+
+edx_status k_reduce_strided(const double* partial, int nparts, int stride, int nslots,
+                            double* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_reduce_kernel, dim3(nslots), dim3(kThreads), 0, st, partial, nparts,
+                     stride, out, 0, (double*)nullptr);
+  EDX_HIP(hipGetLastError());
+  return EDX_OK;
+}
+
+edx_status k_alpha_finish(const double* partial, int nparts, double* alpha_j, hipStream_t st) {
+  hipLaunchKernelGGL(k_reduce_kernel, dim3(1), dim3(kThreads), 0, st, partial, nparts, 0,
+                     alpha_j, 0, (double*)nullptr);
+  EDX_HIP(hipGetLastError());
+  return EDX_OK;
+}
+
+edx_status k_beta_finish(const double* partial, int nparts, double* beta_next,
+                         double* scale_next, hipStream_t st) {
+  hipLaunchKernelGGL(k_reduce_kernel, dim3(1), dim3(kThreads), 0, st, partial, nparts, 0,
+                     beta_next, 2, scale_next);
+  EDX_HIP(hipGetLastError());
+  return EDX_OK;
+}
+
+edx_status k_update(int vtype, void* w, const void* vcur, const double* scur, const void* vprev,
+                    const double* sprev, const double* alpha, const double* beta, int64_t n,
+                    void* psi, const double* ycoef, double* partial, hipStream_t st) {
+  const int g = elem_blocks(n);
+  if (vtype == EDX_F64)
+    hipLaunchKernelGGL(k_update_kernel<double>, dim3(g), dim3(kThreads), 0, st, (double*)w,
+                       (const double*)vcur, scur, (const double*)vprev, sprev, alpha, beta, n,
+                       (double*)psi, ycoef, partial);
+  else
+    hipLaunchKernelGGL(k_update_kernel<float>, dim3(g), dim3(kThreads), 0, st, (float*)w,
+                       (const float*)vcur, scur, (const float*)vprev, sprev, alpha, beta, n,
+                       (float*)psi, ycoef, partial);
+  EDX_HIP(hipGetLastError());
+  return EDX_OK;
+}
+
+edx_status k_norm2(int vtype, const void* x, int64_t n, double* partial, hipStream_t st) {
+  const int g = elem_blocks(n);
+  if (vtype == EDX_F64)
+    hipLaunchKernelGGL(k_norm2_kernel<double>, dim3(g), dim3(kThreads), 0, st,
+                       (const double*)x, n, partial);
+  else
+    hipLaunchKernelGGL(k_norm2_kernel<float>, dim3(g), dim3(kThreads), 0, st, (const float*)x,
+                       n, partial);
+  EDX_HIP(hipGetLastError());
+  return EDX_OK;
+}
+
+edx_status k_scale_copy(int vtype, const void* x, const double* scale, void* y, int64_t n,
+                        hipStream_t st) {
+  const int g = elem_blocks(n);
+  if (vtype == EDX_F64)
+    hipLaunchKernelGGL(k_scale_copy_kernel<double>, dim3(g), dim3(kThreads), 0, st,
+                       (const double*)x, scale, (double*)y, n);
+  else
+    hipLaunchKernelGGL(k_scale_copy_kernel<float>, dim3(g), dim3(kThreads), 0, st,
+                       (const float*)x, scale, (float*)y, n);
+  EDX_HIP(hipGetLastError());
+  return EDX_OK;
+}
+
+edx_status k_dot2(int vtype, const void* w, const void* a, const double* sa, const void* b,
+                  const double* sb, int64_t n, double* partial, hipStream_t st) {
+  const int g = elem_blocks(n);
+  if (vtype == EDX_F64)
+    hipLaunchKernelGGL(k_dot2_kernel<double>, dim3(g), dim3(kThreads), 0, st, (const double*)w,
+                       (const double*)a, sa, (const double*)b, sb, n, partial, kMaxPartials);
+  else
+    hipLaunchKernelGGL(k_dot2_kernel<float>, dim3(g), dim3(kThreads), 0, st, (const float*)w,
+                       (const float*)a, sa, (const float*)b, sb, n, partial, kMaxPartials);
+  EDX_HIP(hipGetLastError());
+  return EDX_OK;
+}
+
+edx_status k_axpy2(int vtype, void* w, const void* a, const double* ca, const double* sa,
+                   const void* b, const double* cb, const double* sb, int64_t n,
+                   double* partial, hipStream_t st) {
+  const int g = elem_blocks(n);
+  if (vtype == EDX_F64)
+    hipLaunchKernelGGL(k_axpy2_kernel<double>, dim3(g), dim3(kThreads), 0, st, (double*)w,
+                       (const double*)a, ca, sa, (const double*)b, cb, sb, n, partial);
+  else
+    hipLaunchKernelGGL(k_axpy2_kernel<float>, dim3(g), dim3(kThreads), 0, st, (float*)w,
+                       (const float*)a, ca, sa, (const float*)b, cb, sb, n, partial);
+  EDX_HIP(hipGetLastError());
+  return EDX_OK;
+}
+
+edx_status k_multi_dot(int vtype, const void* basis, int64_t ld, int m, const void* w, int64_t n,
+                       double* partial, hipStream_t st) {
+  const int g = multi_blocks(n);
+  if (vtype == EDX_F64)
+    hipLaunchKernelGGL(k_multi_dot_kernel<double>, dim3(g), dim3(kThreads), 0, st,
+                       (const double*)basis, ld, m, (const double*)w, n, partial, kMaxPartials);
+  else
+    hipLaunchKernelGGL(k_multi_dot_kernel<float>, dim3(g), dim3(kThreads), 0, st,
+                       (const float*)basis, ld, m, (const float*)w, n, partial, kMaxPartials);
+  EDX_HIP(hipGetLastError());
+  return EDX_OK;
+}
+
+edx_status k_multi_axpy(int vtype, void* w, const void* basis, int64_t ld, int m,
+                        const double* coef, int64_t n, double* partial, hipStream_t st) {
+  const int g = multi_blocks(n);
+  if (vtype == EDX_F64)
+    hipLaunchKernelGGL(k_multi_axpy_kernel<double>, dim3(g), dim3(kThreads), 0, st, (double*)w,
+                       (const double*)basis, ld, m, coef, n, partial);
+  else
+    hipLaunchKernelGGL(k_multi_axpy_kernel<float>, dim3(g), dim3(kThreads), 0, st, (float*)w,
+                       (const float*)basis, ld, m, coef, n, partial);
+  EDX_HIP(hipGetLastError());
+  return EDX_OK;
+}
+
+}  // namespace edx

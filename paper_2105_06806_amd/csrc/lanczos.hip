@@ -1,0 +1,520 @@
+// Lanczos ground state and Krylov Green's function drivers (host side).
+//
+// Ground state (Sec. 5 "Diagonalization", plain Lanczos as the paper runs it):
+//   alpha_j = <v_j, H v_j>;  w = H v_j - alpha_j v_j - beta_j v_{j-1};
+//   beta_{j+1} = |w|;  v_{j+1} = w / beta_{j+1}.
+// A step is enqueued without host synchronisation (scalars stay on the
+// device); every `check_every` steps the host copies alpha/beta back and
+// applies the stop rule:
+//   |E_j - E_{j-1}| <= tol max(1, |E_j|)  [and beta_{j+1}|y_j| <= rtol max(1,|E|)],
+//   or breakdown beta_{j+1} <= 1e-12 max_i(|alpha_i| + beta_i + beta_{i+1}),
+//   or j + 1 = niter.
+// E_j is the lowest eigenvalue of the tridiagonal T_j (Sturm bisection).  The
+// ground vector psi0 = sum_j y_j v_j is formed by replaying the identical
+// recurrence (deterministic kernels), so no basis is stored.
+//
+// Precision mode (vtype = F32): vectors in FP32, all scalars, dot products
+// and the tridiagonal problem in FP64; reorth = 1 adds one Gram-Schmidt pass
+// against v_j and v_{j-1} per step, reorth = 2 keeps every v_j and applies
+// classical Gram-Schmidt twice against all of them.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <limits>
+
+#include "edx_internal.h"
+
+namespace edx {
+
+edx_status k_reduce_strided(const double* partial, int nparts, int stride, int nslots,
+                            double* out, hipStream_t st);
+edx_status k_coef_scale2(double* coef, const double* scale, int m, hipStream_t st);
+
+// ---------------------------------------------------------------- tridiagonal
+namespace {
+
+// number of eigenvalues of T (diag a[0..m), off b[0..m-1)) smaller than x
+int sturm_count(const double* a, const double* b, int m, double x, double tiny) {
+  int cnt = 0;
+  double q = a[0] - x;
+  if (q < 0) ++cnt;
+  for (int i = 1; i < m; ++i) {
+    if (std::fabs(q) < tiny) q = -tiny;
+    q = a[i] - x - b[i - 1] * b[i - 1] / q;
+    if (q < 0) ++cnt;
+  }
+  return cnt;
+}
+
+}  // namespace
+
+// k-th smallest eigenvalue (k = 0, 1, ...) of the symmetric tridiagonal matrix.
+double tridiag_lowest(const double* a, const double* b, int m, int k) {
+  if (m == 1) return a[0];
+  double lo = a[0], hi = a[0], nrm = 0.0;
+  for (int i = 0; i < m; ++i) {
+    const double r = (i > 0 ? std::fabs(b[i - 1]) : 0.0) + (i < m - 1 ? std::fabs(b[i]) : 0.0);
+    lo = std::min(lo, a[i] - r);
+    hi = std::max(hi, a[i] + r);
+    nrm = std::max(nrm, std::fabs(a[i]) + r);
+  }
+  const double tiny = std::max(nrm, 1.0) * 1e-300;
+  const double eps = std::numeric_limits<double>::epsilon();
+  lo -= eps * nrm + tiny;
+  hi += eps * nrm + tiny;
+  for (int it = 0; it < 200; ++it) {
+    const double mid = 0.5 * (lo + hi);
+    if (mid <= lo || mid >= hi) break;
+    if (sturm_count(a, b, m, mid, tiny) > k)
+      hi = mid;
+    else
+      lo = mid;
+    if (hi - lo <= 2.0 * eps * std::max(std::fabs(lo), std::fabs(hi))) break;
+  }
+  return 0.5 * (lo + hi);
+}
+
+// Eigenvector of T for eigenvalue lam by inverse iteration, Gaussian
+// elimination with partial pivoting on (T - lam I).  y is normalised, with a
+// positive component of largest magnitude.
+void tridiag_vector(const double* a, const double* b, int m, double lam, double* y) {
+  if (m == 1) {
+    y[0] = 1.0;
+    return;
+  }
+  double nrm = 0.0;
+  for (int i = 0; i < m; ++i) nrm = std::max(nrm, std::fabs(a[i]) + (i < m - 1 ? std::fabs(b[i]) : 0.0));
+  const double tiny = std::max(nrm, 1e-300) * std::numeric_limits<double>::epsilon();
+  std::vector<double> u0(m), u1(m), u2(m), f(m), r(m);
+  std::vector<int> sw(m);
+  // factorisation (independent of the right-hand side)
+  double c0 = a[0] - lam, c1 = m > 1 ? b[0] : 0.0, c2 = 0.0;   // candidate row k
+  for (int k = 0; k < m - 1; ++k) {
+    const double n0 = b[k], n1 = a[k + 1] - lam, n2 = (k + 1 < m - 1) ? b[k + 1] : 0.0;
+    if (std::fabs(n0) > std::fabs(c0)) {
+      sw[k] = 1;
+      u0[k] = n0; u1[k] = n1; u2[k] = n2;
+      const double fk = c0 / n0;
+      f[k] = fk;
+      c0 = c1 - fk * n1;
+      c1 = c2 - fk * n2;
+      c2 = 0.0;
+    } else {
+      sw[k] = 0;
+      if (std::fabs(c0) < tiny) c0 = tiny;
+      u0[k] = c0; u1[k] = c1; u2[k] = c2;
+      const double fk = n0 / c0;
+      f[k] = fk;
+      c0 = n1 - fk * c1;
+      c1 = n2 - fk * c2;
+      c2 = 0.0;
+    }
+  }
+  if (std::fabs(c0) < tiny) c0 = tiny;
+  u0[m - 1] = c0; u1[m - 1] = 0.0; u2[m - 1] = 0.0;
+  for (int i = 0; i < m; ++i) y[i] = 1.0;
+  for (int iter = 0; iter < 3; ++iter) {
+    // forward elimination of the right-hand side
+    double cr = y[0];
+    for (int k = 0; k < m - 1; ++k) {
+      const double nr = y[k + 1];
+      if (sw[k]) {
+        r[k] = nr;
+        cr = cr - f[k] * nr;
+      } else {
+        r[k] = cr;
+        cr = nr - f[k] * cr;
+      }
+    }
+    r[m - 1] = cr;
+    // back substitution
+    for (int k = m - 1; k >= 0; --k) {
+      double s = r[k];
+      if (k + 1 < m) s -= u1[k] * y[k + 1];
+      if (k + 2 < m) s -= u2[k] * y[k + 2];
+      y[k] = s / u0[k];
+    }
+    double n2 = 0.0, big = 0.0;
+    int ib = 0;
+    for (int i = 0; i < m; ++i) {
+      n2 += y[i] * y[i];
+      if (std::fabs(y[i]) > big) { big = std::fabs(y[i]); ib = i; }
+    }
+    const double inv = (y[ib] < 0 ? -1.0 : 1.0) / std::sqrt(n2);
+    for (int i = 0; i < m; ++i) y[i] *= inv;
+  }
+}
+
+// ---------------------------------------------------------------- workspace
+namespace {
+
+struct LanczosWs {
+  char* vec = nullptr;       // 3 rotating vectors, or niter+1 basis vectors
+  size_t vstride = 0;        // bytes between vectors
+  int nvec = 0;
+  double* partial = nullptr; // nslots * kMaxPartials (or hv blocks)
+  int partial_cap = 0;       // doubles per slot
+  double* alpha = nullptr;   // [niter + 2]
+  double* beta = nullptr;    // [niter + 2]   beta[j] couples j-1 and j; beta[0] = |u0|
+  double* scale = nullptr;   // [niter + 2]   1/|u_j|
+  double* coef = nullptr;    // [niter + 2]
+  double* y = nullptr;       // [niter + 2]
+  double* alpha2 = nullptr;  // replay copies
+  double* beta2 = nullptr;
+  double* scale2 = nullptr;
+  double* gbuf = nullptr;    // Green: 2 * kMaxLmats
+};
+
+constexpr int kMaxLmats = 65536;
+
+size_t lanczos_ws_layout(int64_t dim, int vtype, int niter, int reorth, int hv_blocks,
+                         char* base, LanczosWs* L) {
+  const size_t vs = align_up((size_t)dim * vbytes(vtype));
+  const int nvec = reorth == 2 ? niter + 1 : 3;
+  const int slots = reorth == 2 ? std::max(niter + 1, 2) : 2;
+  const int pcap = std::max(kMaxPartials, hv_blocks);
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    size_t o = off;
+    off += align_up(bytes);
+    return base ? base + o : nullptr;
+  };
+  char* vec = take(vs * nvec);
+  double* partial = (double*)take(sizeof(double) * (size_t)std::max(slots * kMaxPartials, pcap));
+  const size_t ns = sizeof(double) * (size_t)(niter + 2);
+  double* alpha = (double*)take(ns);
+  double* beta = (double*)take(ns);
+  double* scale = (double*)take(ns);
+  double* coef = (double*)take(ns);
+  double* y = (double*)take(ns);
+  double* alpha2 = (double*)take(ns);
+  double* beta2 = (double*)take(ns);
+  double* scale2 = (double*)take(ns);
+  if (L) {
+    L->vec = vec; L->vstride = vs; L->nvec = nvec; L->partial = partial;
+    L->partial_cap = pcap; L->alpha = alpha; L->beta = beta; L->scale = scale;
+    L->coef = coef; L->y = y; L->alpha2 = alpha2; L->beta2 = beta2; L->scale2 = scale2;
+  }
+  return off;
+}
+
+struct StepBufs {
+  void* cur;
+  void* prev;
+  void* w;
+};
+
+StepBufs bufs_for(const LanczosWs& L, int j, int reorth) {
+  StepBufs b;
+  if (reorth == 2) {
+    b.cur = L.vec + (size_t)j * L.vstride;
+    b.prev = j > 0 ? L.vec + (size_t)(j - 1) * L.vstride : nullptr;
+    b.w = L.vec + (size_t)(j + 1) * L.vstride;
+  } else {
+    b.cur = L.vec + (size_t)(j % 3) * L.vstride;
+    b.prev = j > 0 ? L.vec + (size_t)((j + 2) % 3) * L.vstride : nullptr;
+    b.w = L.vec + (size_t)((j + 1) % 3) * L.vstride;
+  }
+  return b;
+}
+
+// One Lanczos step j: w = H v_j, alpha_j, three-term update, optional
+// re-orthogonalisation, beta_{j+1} and scale_{j+1}.  psi/ycoef accumulate
+// psi += y_j v_j (replay).
+edx_status lanczos_step(const edx_sector* s, int vtype, const LanczosWs& L, int j, int reorth,
+                        double* alpha, double* beta, double* scale, void* psi,
+                        const double* ycoef, hipStream_t st) {
+  const StepBufs b = bufs_for(L, j, reorth);
+  const int64_t n = s->dim;
+  const int hb = hv_partial_blocks(s, vtype);
+  EDX_TRY(hv_launch(s, vtype, b.cur, b.w, scale + j, L.partial, st));
+  EDX_TRY(k_alpha_finish(L.partial, hb, alpha + j, st));
+  EDX_TRY(k_update(vtype, b.w, b.cur, scale + j, b.prev, j > 0 ? scale + j - 1 : nullptr,
+                   alpha + j, beta + j, n, psi, ycoef, L.partial, st));
+  if (reorth == 1) {
+    EDX_TRY(k_dot2(vtype, b.w, b.cur, scale + j, b.prev, j > 0 ? scale + j - 1 : nullptr, n,
+                   L.partial, st));
+    EDX_TRY(k_reduce_strided(L.partial, elem_blocks(n), kMaxPartials, 2, L.coef, st));
+    EDX_TRY(k_axpy2(vtype, b.w, b.cur, L.coef, scale + j, b.prev, L.coef + 1,
+                    j > 0 ? scale + j - 1 : nullptr, n, L.partial, st));
+  } else if (reorth == 2) {
+    for (int pass = 0; pass < 2; ++pass) {
+      EDX_TRY(k_multi_dot(vtype, L.vec, (int64_t)(L.vstride / vbytes(vtype)), j + 1, b.w, n,
+                          L.partial, st));
+      EDX_TRY(k_reduce_strided(L.partial, multi_blocks(n), kMaxPartials, j + 1, L.coef, st));
+      EDX_TRY(k_coef_scale2(L.coef, scale, j + 1, st));
+      EDX_TRY(k_multi_axpy(vtype, b.w, L.vec, (int64_t)(L.vstride / vbytes(vtype)), j + 1,
+                           L.coef, n, L.partial, st));
+    }
+  }
+  const int eb = reorth == 2 ? multi_blocks(n) : elem_blocks(n);
+  EDX_TRY(k_beta_finish(L.partial, eb, beta + j + 1, scale + j + 1, st));
+  return EDX_OK;
+}
+
+struct StopState {
+  double tnorm = 0.0;
+  double Eprev = NAN;
+};
+
+}  // namespace
+
+size_t lanczos_workspace_bytes(const edx_sector* s, int vtype, int niter, int reorth) {
+  return lanczos_ws_layout(s->dim, vtype, niter, reorth, hv_partial_blocks(s, vtype), nullptr,
+                           nullptr) + 256;
+}
+
+edx_status lanczos_ground_state_impl(const edx_sector* s, const edx_lanczos_opts* o, void* ws,
+                                     size_t ws_bytes, double* e0, void* psi0,
+                                     edx_lanczos_report* rep, hipStream_t st) {
+  const int vtype = o->vtype;
+  const int niter = o->niter;
+  const int reorth = o->reorth;
+  LanczosWs L;
+  char* base = reinterpret_cast<char*>(align_up(reinterpret_cast<uintptr_t>(ws)));
+  const size_t need = lanczos_ws_layout(s->dim, vtype, niter, reorth,
+                                        hv_partial_blocks(s, vtype), base, &L);
+  if (need + (size_t)(base - (char*)ws) > ws_bytes) {
+    set_error("lanczos: workspace too small (need " + std::to_string(need + 256) + " bytes)");
+    return EDX_E_NOMEM;
+  }
+  const int64_t n = s->dim;
+  // start vector u_0 and scale_0 = 1/|u_0|
+  EDX_TRY(k_start_vector(vtype, L.vec, n, o->seed, L.partial, st));
+  EDX_TRY(k_beta_finish(L.partial, elem_blocks(n), L.beta, L.scale, st));
+  EDX_HIP(hipMemsetAsync(L.beta, 0, sizeof(double), st));   // beta_0 couples nothing
+
+  std::vector<double> ha(niter + 2), hb(niter + 2);
+  int m = 0;              // number of Lanczos steps kept (size of T)
+  int done = 0;           // steps enqueued
+  bool converged = false, breakdown = false;
+  double E = 0.0, Eold = NAN, tnorm = 0.0, resid = 0.0;
+  const int every = std::max(1, o->check_every);
+  while (done < niter && m == 0) {
+    const int upto = std::min(niter, done + every);
+    for (int j = done; j < upto; ++j)
+      EDX_TRY(lanczos_step(s, vtype, L, j, reorth, L.alpha, L.beta, L.scale, nullptr, nullptr, st));
+    EDX_HIP(hipMemcpyAsync(ha.data(), L.alpha, sizeof(double) * upto, hipMemcpyDeviceToHost, st));
+    EDX_HIP(hipMemcpyAsync(hb.data(), L.beta, sizeof(double) * (upto + 1), hipMemcpyDeviceToHost, st));
+    EDX_HIP(hipStreamSynchronize(st));
+    for (int j = done; j < upto; ++j) {
+      // T_j: alpha[0..j], off-diagonal beta[1..j]
+      tnorm = std::max(tnorm, std::fabs(ha[j]) + hb[j] + hb[j + 1]);
+      E = tridiag_lowest(ha.data(), hb.data() + 1, j + 1, 0);
+      const bool bd = !(hb[j + 1] > 1e-12 * tnorm);
+      bool ok = j > 0 && std::fabs(E - Eold) <= o->tol * std::max(1.0, std::fabs(E));
+      if (ok && o->rtol > 0.0) {
+        std::vector<double> yv(j + 1);
+        tridiag_vector(ha.data(), hb.data() + 1, j + 1, E, yv.data());
+        resid = hb[j + 1] * std::fabs(yv[j]);
+        ok = resid <= o->rtol * std::max(1.0, std::fabs(E));
+      }
+      Eold = E;
+      if (ok || bd || j + 1 == niter) {
+        m = j + 1;
+        converged = ok || bd;
+        breakdown = bd;
+        break;
+      }
+    }
+    done = upto;
+  }
+  if (m == 0) m = niter;
+  E = tridiag_lowest(ha.data(), hb.data() + 1, m, 0);
+  std::vector<double> y(m);
+  tridiag_vector(ha.data(), hb.data() + 1, m, E, y.data());
+  if (resid == 0.0) resid = hb[m] * std::fabs(y[m - 1]);
+  // second Ritz value that is not a numerical copy of E (ghost copies of a
+  // converged eigenvalue appear in plain Lanczos)
+  double E1 = E;
+  for (int k = 1; k < m; ++k) {
+    const double x = tridiag_lowest(ha.data(), hb.data() + 1, m, k);
+    if (x - E > 1e-10 * std::max(1.0, std::fabs(E))) { E1 = x; break; }
+  }
+  const bool degenerate = m > 1 && E1 > E && (E1 - E) < 1e-9;
+
+  if (psi0) {
+    if (reorth == 2) {
+      std::vector<double> hs(m);
+      EDX_HIP(hipMemcpyAsync(hs.data(), L.scale, sizeof(double) * m, hipMemcpyDeviceToHost, st));
+      EDX_HIP(hipStreamSynchronize(st));
+      std::vector<double> c(m);
+      for (int k = 0; k < m; ++k) c[k] = -y[k] * hs[k];
+      EDX_HIP(hipMemcpyAsync(L.coef, c.data(), sizeof(double) * m, hipMemcpyHostToDevice, st));
+      EDX_HIP(hipMemsetAsync(psi0, 0, (size_t)n * vbytes(vtype), st));
+      EDX_TRY(k_multi_axpy(vtype, psi0, L.vec, (int64_t)(L.vstride / vbytes(vtype)), m, L.coef, n,
+                           nullptr, st));
+    } else {
+      // replay: identical start vector and recurrence, psi += y_j v_j
+      EDX_HIP(hipMemcpyAsync(L.y, y.data(), sizeof(double) * m, hipMemcpyHostToDevice, st));
+      EDX_HIP(hipMemsetAsync(psi0, 0, (size_t)n * vbytes(vtype), st));
+      EDX_TRY(k_start_vector(vtype, L.vec, n, o->seed, L.partial, st));
+      EDX_TRY(k_beta_finish(L.partial, elem_blocks(n), L.beta2, L.scale2, st));
+      EDX_HIP(hipMemsetAsync(L.beta2, 0, sizeof(double), st));
+      for (int j = 0; j < m; ++j)
+        EDX_TRY(lanczos_step(s, vtype, L, j, reorth, L.alpha2, L.beta2, L.scale2, psi0, L.y + j,
+                             st));
+    }
+    // normalise psi0
+    EDX_TRY(k_norm2(vtype, psi0, n, L.partial, st));
+    EDX_TRY(k_beta_finish(L.partial, elem_blocks(n), L.coef, L.coef + 1, st));
+    EDX_TRY(k_scale_copy(vtype, psi0, L.coef + 1, psi0, n, st));
+    EDX_HIP(hipStreamSynchronize(st));
+  }
+  *e0 = E;
+  if (rep) {
+    rep->iters = m;
+    rep->converged = converged ? 1 : 0;
+    rep->breakdown = breakdown ? 1 : 0;
+    rep->degenerate = degenerate ? 1 : 0;
+    rep->e0 = E;
+    rep->e1 = E1;
+    rep->beta_last = hb[m];
+    rep->resid = resid;
+  }
+  if (!converged) {
+    set_error("lanczos: stop rule not met within niter");
+    return EDX_E_NOCONV;
+  }
+  if (degenerate) return EDX_E_DEGENERATE;
+  return EDX_OK;
+}
+
+// ---------------------------------------------------------------- Green
+size_t green_workspace_bytes(const edx_sector* s, int vtype, int ngf) {
+  // the largest neighbour sector of either spin bounds the vectors
+  int64_t dmax = 1;
+  const int ns = s->model.ns;
+  auto comb = [](int nn, int k) -> int64_t {
+    if (k < 0 || k > nn) return 0;
+    int64_t r = 1;
+    for (int i = 1; i <= k; ++i) r = r * (nn - k + i) / i;
+    return r;
+  };
+  const int64_t cu = comb(ns, s->nup), cd = comb(ns, s->ndw);
+  for (int d : {-1, 1}) {
+    dmax = std::max(dmax, comb(ns, s->nup + d) * cd);
+    dmax = std::max(dmax, cu * comb(ns, s->ndw + d));
+  }
+  // hv partial blocks of a neighbour sector: bounded by its column count
+  const int64_t ddw_max = std::max({comb(ns, s->ndw - 1), comb(ns, s->ndw), comb(ns, s->ndw + 1)});
+  const int hvb = (int)std::max<int64_t>(kMaxPartials, ddw_max + 8);
+  return lanczos_ws_layout(dmax, vtype, ngf, 0, hvb, nullptr, nullptr) +
+         sizeof(double) * (2 * kMaxLmats + 4 * (ngf + 1)) + 512;
+}
+
+namespace {
+
+edx_status ensure_neighbours(const edx_sector* gs, int spin, hipStream_t st) {
+  edx_sector* g = const_cast<edx_sector*>(gs);
+  std::lock_guard<std::mutex> lk(g->nb_mu);
+  const int n0 = spin == 0 ? gs->nup : gs->ndw;
+  for (int k = 0; k < 2; ++k) {
+    const int nn = n0 + (k == 0 ? 1 : -1);
+    if (g->nb[spin][k] || nn < 0 || nn > gs->model.ns) continue;
+    edx_sector* t = nullptr;
+    EDX_TRY(build_sector_impl(gs->model, spin == 0 ? nn : gs->nup, spin == 0 ? gs->ndw : nn, st,
+                              &t));
+    g->nb[spin][k] = t;
+  }
+  return EDX_OK;
+}
+
+}  // namespace
+
+edx_status green_cf_impl(const edx_sector* gs, const void* psi0, double e0, int orb, int spin,
+                         const edx_gf_opts* o, void* ws, size_t ws_bytes, double* g_host,
+                         edx_gf_report* rep, hipStream_t st) {
+  const int vtype = o->vtype;
+  const int ngf = o->ngf;
+  if (o->lmats < 1 || o->lmats > kMaxLmats || ngf < 1 || !(o->beta > 0.0)) {
+    set_error("green: need 1 <= lmats <= 65536, ngf >= 1, beta > 0");
+    return EDX_E_INVALID;
+  }
+  const size_t need = green_workspace_bytes(gs, vtype, ngf);
+  if (need > ws_bytes) {
+    set_error("green: workspace too small (need " + std::to_string(need) + " bytes)");
+    return EDX_E_NOMEM;
+  }
+  EDX_TRY(ensure_neighbours(gs, spin, st));
+  char* base = reinterpret_cast<char*>(align_up(reinterpret_cast<uintptr_t>(ws)));
+  double* gdev = nullptr;
+  double w[2] = {0.0, 0.0};
+  int nlen[2] = {0, 0};
+  std::vector<double> ha[2], hb[2];
+  // the two branches run one after the other in the same workspace
+  for (int br = 0; br < 2; ++br) {
+    const edx_sector* t = gs->nb[spin][br];
+    LanczosWs L;
+    lanczos_ws_layout(t ? t->dim : 1, vtype, ngf, 0, t ? hv_partial_blocks(t, vtype) : 1, base,
+                      &L);
+    if (!t) continue;
+    EDX_TRY(k_apply_op(gs, t, vtype, psi0, L.vec, orb, spin, br == 0 ? 1 : 0, st));
+    EDX_TRY(k_norm2(vtype, L.vec, t->dim, L.partial, st));
+    EDX_TRY(k_beta_finish(L.partial, elem_blocks(t->dim), L.beta, L.scale, st));
+    double nrm = 0.0;
+    EDX_HIP(hipMemcpyAsync(&nrm, L.beta, sizeof(double), hipMemcpyDeviceToHost, st));
+    EDX_HIP(hipStreamSynchronize(st));
+    w[br] = nrm * nrm;
+    if (!(nrm > 0.0)) continue;
+    EDX_HIP(hipMemsetAsync(L.beta, 0, sizeof(double), st));
+    for (int j = 0; j < ngf; ++j)
+      EDX_TRY(lanczos_step(t, vtype, L, j, 0, L.alpha, L.beta, L.scale, nullptr, nullptr, st));
+    ha[br].resize(ngf + 1);
+    hb[br].resize(ngf + 1);
+    EDX_HIP(hipMemcpyAsync(ha[br].data(), L.alpha, sizeof(double) * ngf, hipMemcpyDeviceToHost, st));
+    EDX_HIP(hipMemcpyAsync(hb[br].data(), L.beta, sizeof(double) * (ngf + 1), hipMemcpyDeviceToHost,
+                           st));
+    EDX_HIP(hipStreamSynchronize(st));
+    // truncate at the first breakdown
+    double tn = 0.0;
+    int len = ngf;
+    for (int j = 0; j < ngf; ++j) {
+      tn = std::max(tn, std::fabs(ha[br][j]) + hb[br][j] + hb[br][j + 1]);
+      if (j + 1 < ngf && !(hb[br][j + 1] > 1e-12 * tn)) {
+        len = j + 1;
+        break;
+      }
+    }
+    nlen[br] = len;
+  }
+  // G and the staged coefficients sit after the larger of the two layouts
+  size_t off = 0;
+  for (int br = 0; br < 2; ++br) {
+    const edx_sector* t = gs->nb[spin][br];
+    off = std::max(off, lanczos_ws_layout(t ? t->dim : 1, vtype, ngf, 0,
+                                          t ? hv_partial_blocks(t, vtype) : 1, nullptr, nullptr));
+  }
+  gdev = reinterpret_cast<double*>(base + off);
+  double* cdev = gdev + 2 * kMaxLmats;
+  std::vector<double> coeff(4 * (ngf + 1), 0.0);
+  for (int br = 0; br < 2; ++br) {
+    if (nlen[br] == 0) continue;
+    std::copy(ha[br].begin(), ha[br].begin() + nlen[br], coeff.begin() + (2 * br) * (ngf + 1));
+    std::copy(hb[br].begin() + 1, hb[br].begin() + 1 + nlen[br],
+              coeff.begin() + (2 * br + 1) * (ngf + 1));
+  }
+  EDX_HIP(hipMemcpyAsync(cdev, coeff.data(), sizeof(double) * coeff.size(), hipMemcpyHostToDevice,
+                         st));
+  EDX_TRY(k_green_cf(cdev, cdev + (ngf + 1), nlen[0], w[0], cdev + 2 * (ngf + 1),
+                     cdev + 3 * (ngf + 1), nlen[1], w[1], e0, o->beta, o->lmats, gdev, st));
+  EDX_HIP(hipMemcpyAsync(g_host, gdev, sizeof(double) * 2 * o->lmats, hipMemcpyDeviceToHost, st));
+  EDX_HIP(hipStreamSynchronize(st));
+  if (rep) {
+    rep->wp = w[0];
+    rep->wh = w[1];
+    rep->np = nlen[0];
+    rep->nh = nlen[1];
+    for (int br = 0; br < 2; ++br) {
+      double* ao = br == 0 ? rep->alpha_p : rep->alpha_h;
+      double* bo = br == 0 ? rep->beta_p : rep->beta_h;
+      for (int k = 0; k < ngf; ++k) {
+        if (ao) ao[k] = k < nlen[br] ? ha[br][k] : 0.0;
+        if (bo) bo[k] = k + 1 < nlen[br] ? hb[br][k + 1] : 0.0;
+      }
+    }
+  }
+  return EDX_OK;
+}
+
+}  // namespace edx

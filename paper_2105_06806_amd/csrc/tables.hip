@@ -1,0 +1,287 @@
+// Sector tables on the device: string map and rank, per-spin hopping lists with
+// fermionic signs, and the diagonal ("popcount") tables.
+//
+//  * map / rank (Sec. 5 "Sector construction"): the strings of one spin are the
+//    Ns-bit integers with popcount N in ascending order.  Instead of scanning and
+//    binary-searching, every integer s < 2^Ns computes its position directly as
+//    its colex rank sum_k C(c_k, k) over its set bits c_1 < c_2 < ... (ascending
+//    integer order of fixed-popcount strings is colex order), so rank[] and
+//    map[] come out of one parallel pass and agree with the listing order.
+//  * hops (eq. Hbuild, Sec. 2.3): for impurity level a and bath level b > a
+//    with exactly one of the two occupied, the neighbour string is
+//    s ^ 2^a ^ 2^b and the sign is (-1)^(occupied levels strictly between a and
+//    b); the other spin's string never enters because all spin-up modes
+//    precede all spin-down modes.  Stored as a column-major ELL table of packed
+//    32-bit entries: column (24 bits) | pair index (7 bits) | sign (1 bit).
+//  * diagonal (eq. Hbuild, H_d): E_s = sum_k e_k n_k + (U'-J) sum_{a<b} n_a n_b
+//    per string and the impurity pattern p = s & (2^norb - 1); the cross-spin
+//    terms come from W[p_up][p_dw].
+#include <algorithm>
+#include <cstring>
+
+#include "edx_internal.h"
+
+namespace edx {
+namespace {
+
+__global__ void k_rank_map(int ns, int n, const int32_t* __restrict__ binom,
+                           int32_t* __restrict__ rank, uint32_t* __restrict__ map) {
+  const uint32_t total = 1u << ns;
+  for (uint32_t s = blockIdx.x * blockDim.x + threadIdx.x; s < total;
+       s += gridDim.x * blockDim.x) {
+    if (__popc(s) != n) {
+      rank[s] = -1;
+      continue;
+    }
+    int32_t r = 0;
+    int k = 1;
+    uint32_t x = s;
+    while (x) {
+      const int c = __ffs(x) - 1;   // lowest set bit
+      r += binom[c * (kMaxNs + 1) + k];
+      ++k;
+      x &= x - 1;
+    }
+    rank[s] = r;
+    map[r] = s;
+  }
+}
+
+__device__ __forceinline__ int hops_of_row(uint32_t s, int norb, int nbath) {
+  int cnt = 0;
+  for (int a = 0; a < norb; ++a) {
+    const uint32_t na = (s >> a) & 1u;
+    for (int nu = 0; nu < nbath; ++nu) {
+      const int b = norb + a * nbath + nu;
+      cnt += (int)(na ^ ((s >> b) & 1u));
+    }
+  }
+  return cnt;
+}
+
+__global__ void k_hop_count(const uint32_t* __restrict__ map, int64_t D, int norb,
+                            int nbath, int* __restrict__ width,
+                            unsigned long long* __restrict__ nnz) {
+  int local_max = 0;
+  unsigned long long local_sum = 0;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < D;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int c = hops_of_row(map[i], norb, nbath);
+    local_max = max(local_max, c);
+    local_sum += (unsigned long long)c;
+  }
+  // integer atomics: order-independent, so the result is deterministic
+  atomicMax(width, local_max);
+  atomicAdd(nnz, local_sum);
+}
+
+__global__ void k_hop_fill(const uint32_t* __restrict__ map,
+                           const int32_t* __restrict__ rank, int64_t D, int norb,
+                           int nbath, int width, uint32_t* __restrict__ hop) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < D;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const uint32_t s = map[i];
+    int k = 0;
+    for (int a = 0; a < norb; ++a) {
+      for (int nu = 0; nu < nbath; ++nu) {
+        const int p = a * nbath + nu;
+        const int b = norb + p;
+        if ((((s >> a) ^ (s >> b)) & 1u) == 0u) continue;
+        const uint32_t t = s ^ (1u << a) ^ (1u << b);
+        const uint32_t between = ((1u << b) - 1u) & ~((2u << a) - 1u);
+        const uint32_t sgn = (uint32_t)(__popc(s & between) & 1);
+        const uint32_t col = (uint32_t)rank[t];
+        hop[(int64_t)k * D + i] = col | ((uint32_t)p << kAmpShift) | (sgn << 31);
+        ++k;
+      }
+    }
+    for (; k < width; ++k)
+      hop[(int64_t)k * D + i] = (uint32_t)i | (kPadPair << kAmpShift);
+  }
+}
+
+__global__ void k_diag(const uint32_t* __restrict__ map, int64_t D, int norb,
+                       int ns, const double* __restrict__ elev, double upj,
+                       double* __restrict__ e64, float* __restrict__ e32,
+                       uint8_t* __restrict__ pat) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < D;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const uint32_t s = map[i];
+    double e = 0.0;
+    for (int k = 0; k < ns; ++k)
+      if ((s >> k) & 1u) e += elev[k];
+    for (int a = 0; a < norb; ++a)
+      for (int b = a + 1; b < norb; ++b)
+        if (((s >> a) & (s >> b) & 1u)) e += upj;
+    e64[i] = e;
+    e32[i] = (float)e;
+    pat[i] = (uint8_t)(s & ((1u << norb) - 1u));
+  }
+}
+
+int grid_for(int64_t n, int threads) {
+  int64_t b = (n + threads - 1) / threads;
+  return (int)std::max<int64_t>(1, std::min<int64_t>(b, 4096));
+}
+
+edx_status build_spin(edx_sector* S, SpinTables& T, int n, const double* d_elev,
+                      hipStream_t st) {
+  const Model& m = S->model;
+  T.n = n;
+  int64_t D = 1;
+  {
+    // C(ns, n) from Pascal's triangle
+    std::vector<int64_t> row(m.ns + 1, 0);
+    row[0] = 1;
+    for (int r = 1; r <= m.ns; ++r)
+      for (int k = r; k >= 1; --k) row[k] += row[k - 1];
+    D = row[n];
+  }
+  T.D = D;
+  const size_t total = size_t(1) << m.ns;
+  EDX_HIP(hipMalloc(&T.rank, total * sizeof(int32_t)));
+  EDX_HIP(hipMalloc(&T.map, D * sizeof(uint32_t)));
+  k_rank_map<<<grid_for(total, 256), 256, 0, st>>>(m.ns, n, S->binom, T.rank, T.map);
+  EDX_HIP(hipGetLastError());
+
+  int* d_width = nullptr;
+  unsigned long long* d_nnz = nullptr;
+  EDX_HIP(hipMalloc(&d_width, sizeof(int) + sizeof(unsigned long long) + 8));
+  d_nnz = reinterpret_cast<unsigned long long*>(reinterpret_cast<char*>(d_width) + 8);
+  EDX_HIP(hipMemsetAsync(d_width, 0, 16, st));
+  k_hop_count<<<grid_for(D, 256), 256, 0, st>>>(T.map, D, m.norb, m.nbath, d_width, d_nnz);
+  EDX_HIP(hipGetLastError());
+  int width = 0;
+  unsigned long long nnz = 0;
+  EDX_HIP(hipMemcpyAsync(&width, d_width, sizeof(int), hipMemcpyDeviceToHost, st));
+  EDX_HIP(hipMemcpyAsync(&nnz, d_nnz, sizeof(nnz), hipMemcpyDeviceToHost, st));
+  EDX_HIP(hipStreamSynchronize(st));
+  EDX_HIP(hipFree(d_width));
+  T.width = width;
+  T.nnz = (int64_t)nnz;
+  EDX_HIP(hipMalloc(&T.hop, std::max<int64_t>(1, (int64_t)width * D) * sizeof(uint32_t)));
+  if (width > 0) {
+    k_hop_fill<<<grid_for(D, 256), 256, 0, st>>>(T.map, T.rank, D, m.norb, m.nbath,
+                                                 width, T.hop);
+    EDX_HIP(hipGetLastError());
+  }
+  EDX_HIP(hipMalloc(&T.e64, D * sizeof(double)));
+  EDX_HIP(hipMalloc(&T.e32, D * sizeof(float)));
+  EDX_HIP(hipMalloc(&T.pat, D));
+  k_diag<<<grid_for(D, 256), 256, 0, st>>>(T.map, D, m.norb, m.ns, d_elev,
+                                           m.Ust - m.Jh, T.e64, T.e32, T.pat);
+  EDX_HIP(hipGetLastError());
+  return EDX_OK;
+}
+
+void free_spin(SpinTables& T) {
+  (void)hipFree(T.map);
+  (void)hipFree(T.rank);
+  (void)hipFree(T.hop);
+  (void)hipFree(T.e64);
+  (void)hipFree(T.e32);
+  (void)hipFree(T.pat);
+  T = SpinTables{};
+}
+
+}  // namespace
+
+void destroy_sector(edx_sector* s) {
+  if (!s) return;
+  for (int sp = 0; sp < 2; ++sp)
+    for (int k = 0; k < 2; ++k) destroy_sector(s->nb[sp][k]);
+  const bool shared = (s->dw.map == s->up.map);
+  free_spin(s->up);
+  if (!shared) free_spin(s->dw);
+  (void)hipFree(s->amp64);
+  (void)hipFree(s->amp32);
+  (void)hipFree(s->w64);
+  (void)hipFree(s->w32);
+  (void)hipFree(s->binom);
+  delete s;
+}
+
+edx_status build_sector_impl(const Model& m, int nup, int ndw, hipStream_t st,
+                             edx_sector** out) {
+  std::unique_ptr<edx_sector, void (*)(edx_sector*)> S(new edx_sector(), destroy_sector);
+  S->model = m;
+  S->nup = nup;
+  S->ndw = ndw;
+  EDX_HIP(hipGetDevice(&S->device));
+
+  // binomial table C(c, k), c, k <= 24
+  std::vector<int32_t> binom((kMaxNs + 1) * (kMaxNs + 1), 0);
+  for (int c = 0; c <= kMaxNs; ++c) {
+    binom[c * (kMaxNs + 1) + 0] = 1;
+    for (int k = 1; k <= c; ++k)
+      binom[c * (kMaxNs + 1) + k] =
+          binom[(c - 1) * (kMaxNs + 1) + k - 1] + (k <= c - 1 ? binom[(c - 1) * (kMaxNs + 1) + k] : 0);
+  }
+  EDX_HIP(hipMalloc(&S->binom, binom.size() * sizeof(int32_t)));
+  EDX_HIP(hipMemcpyAsync(S->binom, binom.data(), binom.size() * sizeof(int32_t),
+                         hipMemcpyHostToDevice, st));
+
+  // level energies e_k (impurity shifted by -xmu)
+  std::vector<double> elev(m.ns, 0.0);
+  for (int a = 0; a < m.norb; ++a) elev[a] = m.eps_imp[a] - m.xmu;
+  for (int p = 0; p < m.norb * m.nbath; ++p) elev[m.norb + p] = m.eps_bath[p];
+  double* d_elev = nullptr;
+  EDX_HIP(hipMalloc(&d_elev, m.ns * sizeof(double)));
+  EDX_HIP(hipMemcpyAsync(d_elev, elev.data(), m.ns * sizeof(double),
+                         hipMemcpyHostToDevice, st));
+
+  edx_status rc = build_spin(S.get(), S->up, nup, d_elev, st);
+  if (rc == EDX_OK) {
+    if (ndw == nup) {
+      S->dw = S->up;   // identical tables, shared
+    } else {
+      rc = build_spin(S.get(), S->dw, ndw, d_elev, st);
+    }
+  }
+  if (rc != EDX_OK) {
+    (void)hipFree(d_elev);
+    return rc;
+  }
+  S->dup = S->up.D;
+  S->ddw = S->dw.D;
+  S->dim = S->dup * S->ddw;
+
+  // signed amplitude table and pattern interaction table
+  double amp[kAmpTable];
+  float ampf[kAmpTable];
+  for (int idx = 0; idx < kAmpTable; ++idx) {
+    const int p = idx & 0x7F;
+    const double sg = (idx & 0x80) ? -1.0 : 1.0;
+    amp[idx] = (p == (int)kPadPair || p >= m.norb * m.nbath) ? 0.0 : sg * m.vhyb[p];
+    ampf[idx] = (float)amp[idx];
+  }
+  std::memcpy(S->amp_host, amp, sizeof(amp));
+  double W[64];
+  float Wf[64];
+  for (int pu = 0; pu < 8; ++pu)
+    for (int pd = 0; pd < 8; ++pd) {
+      double w = 0.0;
+      for (int a = 0; a < m.norb; ++a) {
+        const int na = (pu >> a) & 1;
+        w += m.U * na * ((pd >> a) & 1);
+        for (int b = 0; b < m.norb; ++b)
+          if (a != b) w += m.Ust * na * ((pd >> b) & 1);
+      }
+      W[pu * 8 + pd] = w;
+      Wf[pu * 8 + pd] = (float)w;
+    }
+  EDX_HIP(hipMalloc(&S->amp64, sizeof(amp)));
+  EDX_HIP(hipMalloc(&S->amp32, sizeof(ampf)));
+  EDX_HIP(hipMalloc(&S->w64, sizeof(W)));
+  EDX_HIP(hipMalloc(&S->w32, sizeof(Wf)));
+  EDX_HIP(hipMemcpyAsync(S->amp64, amp, sizeof(amp), hipMemcpyHostToDevice, st));
+  EDX_HIP(hipMemcpyAsync(S->amp32, ampf, sizeof(ampf), hipMemcpyHostToDevice, st));
+  EDX_HIP(hipMemcpyAsync(S->w64, W, sizeof(W), hipMemcpyHostToDevice, st));
+  EDX_HIP(hipMemcpyAsync(S->w32, Wf, sizeof(Wf), hipMemcpyHostToDevice, st));
+  EDX_HIP(hipStreamSynchronize(st));
+  EDX_HIP(hipFree(d_elev));
+  *out = S.release();
+  return EDX_OK;
+}
+
+}  // namespace edx

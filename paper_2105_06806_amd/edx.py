@@ -1,0 +1,304 @@
+"""Thin Python binding of libedx (include/edx.h): argument marshalling only.
+
+Every step of the path runs in the HIP library; this module converts Python
+dictionaries and torch tensors to the C ABI and raises on every non-OK status.
+There is no fallback: importing it without the built library raises.
+PyTorch provides device memory and streams only.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+import torch  # imported before libedx so both share one HIP runtime
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libedx.so")
+
+EDX_OK, EDX_E_INVALID, EDX_E_NOMEM, EDX_E_DEVICE, EDX_E_NOCONV, EDX_E_DEGENERATE, EDX_E_UNSUPPORTED = range(7)
+F64, F32 = 0, 1
+WS_LANCZOS, WS_GREEN, WS_LANCZOS_FULL = 0, 1, 2
+
+
+class EdxError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{status_str(status)}: {msg}")
+        self.status = status
+
+
+class _Model(ctypes.Structure):
+    _fields_ = [("norb", ctypes.c_int32), ("nbath", ctypes.c_int32),
+                ("eps_imp", ctypes.POINTER(ctypes.c_double)),
+                ("eps_bath", ctypes.POINTER(ctypes.c_double)),
+                ("vhyb", ctypes.POINTER(ctypes.c_double)),
+                ("U", ctypes.c_double), ("Ust", ctypes.c_double),
+                ("Jh", ctypes.c_double), ("xmu", ctypes.c_double)]
+
+
+class HvPlan(ctypes.Structure):
+    _fields_ = [("mode", ctypes.c_int32), ("col_cols", ctypes.c_int32),
+                ("col_threads", ctypes.c_int32), ("row_rows", ctypes.c_int32),
+                ("row_cols", ctypes.c_int32)]
+
+
+class LanczosOpts(ctypes.Structure):
+    _fields_ = [("niter", ctypes.c_int32), ("vtype", ctypes.c_int32),
+                ("reorth", ctypes.c_int32), ("check_every", ctypes.c_int32),
+                ("tol", ctypes.c_double), ("rtol", ctypes.c_double),
+                ("seed", ctypes.c_uint64)]
+
+
+class LanczosReport(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int32), ("converged", ctypes.c_int32),
+                ("breakdown", ctypes.c_int32), ("degenerate", ctypes.c_int32),
+                ("e0", ctypes.c_double), ("e1", ctypes.c_double),
+                ("beta_last", ctypes.c_double), ("resid", ctypes.c_double)]
+
+
+class GfOpts(ctypes.Structure):
+    _fields_ = [("ngf", ctypes.c_int32), ("lmats", ctypes.c_int32),
+                ("vtype", ctypes.c_int32), ("pad_", ctypes.c_int32),
+                ("beta", ctypes.c_double)]
+
+
+class GfReport(ctypes.Structure):
+    _fields_ = [("wp", ctypes.c_double), ("wh", ctypes.c_double),
+                ("np", ctypes.c_int32), ("nh", ctypes.c_int32),
+                ("alpha_p", ctypes.POINTER(ctypes.c_double)),
+                ("beta_p", ctypes.POINTER(ctypes.c_double)),
+                ("alpha_h", ctypes.POINTER(ctypes.c_double)),
+                ("beta_h", ctypes.POINTER(ctypes.c_double))]
+
+
+# name -> (restype, argtypes); the C-ABI symbols declared in include/edx.h
+_P = ctypes.c_void_p
+_SIGS = {
+    "edx_build_sector": (ctypes.c_int, [ctypes.POINTER(_Model), ctypes.c_int32, ctypes.c_int32, _P, ctypes.POINTER(_P)]),
+    "edx_sector_destroy": (None, [_P]),
+    "edx_sector_dims": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]),
+    "edx_sector_hop_nnz": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int32)]),
+    "edx_sector_get_tables": (ctypes.c_int, [_P, ctypes.c_int32, _P, _P, _P, _P, _P, _P, _P]),
+    "edx_hv": (ctypes.c_int, [_P, ctypes.c_int, _P, _P, _P]),
+    "edx_hv_get_plan": (ctypes.c_int, [_P, ctypes.c_int, ctypes.POINTER(HvPlan)]),
+    "edx_hv_set_plan": (ctypes.c_int, [_P, ctypes.c_int, ctypes.POINTER(HvPlan)]),
+    "edx_autotune_hv": (ctypes.c_int, [_P, ctypes.c_int, _P, _P, ctypes.c_int32, _P, ctypes.POINTER(HvPlan), ctypes.POINTER(ctypes.c_double)]),
+    "edx_lanczos_default_opts": (None, [ctypes.POINTER(LanczosOpts)]),
+    "edx_workspace_bytes": (ctypes.c_size_t, [_P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]),
+    "edx_lanczos_ground_state": (ctypes.c_int, [_P, ctypes.POINTER(LanczosOpts), _P, ctypes.c_size_t, ctypes.POINTER(ctypes.c_double), _P, ctypes.POINTER(LanczosReport), _P]),
+    "edx_green_cf": (ctypes.c_int, [_P, _P, ctypes.c_double, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(GfOpts), _P, ctypes.c_size_t, _P, ctypes.POINTER(GfReport), _P]),
+    "edx_status_str": (ctypes.c_char_p, [ctypes.c_int]),
+    "edx_last_error": (ctypes.c_char_p, []),
+}
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built: run `python -m paper_2105_06806_amd.build`")
+    lib = ctypes.CDLL(LIB_PATH)
+    for name, (res, args) in _SIGS.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    return lib
+
+
+lib = _load()
+
+
+def status_str(st):
+    return lib.edx_status_str(st).decode()
+
+
+def last_error():
+    return lib.edx_last_error().decode()
+
+
+def _check(st, ok=(EDX_OK,)):
+    if st not in ok:
+        raise EdxError(st, last_error())
+    return st
+
+
+def _stream_ptr(stream):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _vtype_of(t):
+    if t.dtype == torch.float64:
+        return F64
+    if t.dtype == torch.float32:
+        return F32
+    raise TypeError("vectors must be float32 or float64")
+
+
+def _dtype_of(vtype):
+    return torch.float64 if vtype == F64 else torch.float32
+
+
+def _vt(v):
+    if isinstance(v, str):
+        return {"f64": F64, "f32": F32}[v]
+    return int(v)
+
+
+class Sector:
+    """Owning wrapper of an edx_sector handle."""
+
+    def __init__(self, handle, model, nup, ndw):
+        self.handle = handle
+        self.model = model
+        self.nup, self.ndw = nup, ndw
+        dup, ddw, dim = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+        _check(lib.edx_sector_dims(handle, ctypes.byref(dup), ctypes.byref(ddw), ctypes.byref(dim)))
+        self.dup, self.ddw, self.dim = dup.value, ddw.value, dim.value
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h:
+            lib.edx_sector_destroy(h)
+            self.handle = None
+
+    def hop_nnz(self, spin):
+        nnz, mx = ctypes.c_int64(), ctypes.c_int32()
+        _check(lib.edx_sector_hop_nnz(self.handle, spin, ctypes.byref(nnz), ctypes.byref(mx)))
+        return nnz.value, mx.value
+
+    def tables(self, spin):
+        """Host copies of one spin's tables (see edx_sector_get_tables)."""
+        D = self.dup if spin == 0 else self.ddw
+        nnz, _ = self.hop_nnz(spin)
+        out = {
+            "map": np.zeros(D, np.uint32), "hop_off": np.zeros(D + 1, np.int64),
+            "hop_col": np.zeros(max(nnz, 1), np.int32), "hop_sign": np.zeros(max(nnz, 1), np.int8),
+            "hop_amp": np.zeros(max(nnz, 1), np.float64), "diag_e": np.zeros(D, np.float64),
+            "diag_p": np.zeros(D, np.uint8),
+        }
+        p = [out[k].ctypes.data_as(_P) for k in ("map", "hop_off", "hop_col", "hop_sign", "hop_amp", "diag_e", "diag_p")]
+        _check(lib.edx_sector_get_tables(self.handle, spin, *p))
+        for k in ("hop_col", "hop_sign", "hop_amp"):
+            out[k] = out[k][:nnz]
+        return out
+
+
+def _model_struct(m):
+    keep = []
+
+    def arr(x):
+        a = np.ascontiguousarray(np.asarray(x, dtype=np.float64).ravel())
+        keep.append(a)
+        return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+    s = _Model(int(m["norb"]), int(m["nbath"]), arr(m["eps_imp"]), arr(m["eps_bath"]),
+               arr(m["vhyb"]), float(m["U"]), float(m["Ust"]), float(m["Jh"]), float(m["xmu"]))
+    return s, keep
+
+
+def build_sector(model, nup, ndw, stream=None):
+    ms, keep = _model_struct(model)
+    h = _P()
+    _check(lib.edx_build_sector(ctypes.byref(ms), int(nup), int(ndw), _stream_ptr(stream), ctypes.byref(h)))
+    return Sector(h.value, model, nup, ndw)
+
+
+def hv(sector, v, w, stream=None):
+    """w = H v on the device (tensors of sector.dim elements, same dtype)."""
+    if v.dtype != w.dtype:
+        raise TypeError("v and w must have the same dtype")
+    if v.numel() != sector.dim or w.numel() != sector.dim or not v.is_contiguous() or not w.is_contiguous():
+        raise ValueError("v and w must be contiguous with sector.dim elements")
+    _check(lib.edx_hv(sector.handle, _vtype_of(v), _P(v.data_ptr()), _P(w.data_ptr()), _stream_ptr(stream)))
+    return w
+
+
+def _plan_dict(p):
+    return {f: getattr(p, f) for f, _ in HvPlan._fields_}
+
+
+def get_plan(sector, vtype):
+    p = HvPlan()
+    _check(lib.edx_hv_get_plan(sector.handle, _vt(vtype), ctypes.byref(p)))
+    return _plan_dict(p)
+
+
+def set_plan(sector, vtype, raise_on_error=True, **plan):
+    """Replace the sector's H.v launch plan; returns the status."""
+    cur = get_plan(sector, vtype)
+    cur.update(plan)
+    p = HvPlan(*[int(cur[f]) for f, _ in HvPlan._fields_])
+    st = lib.edx_hv_set_plan(sector.handle, _vt(vtype), ctypes.byref(p))
+    if raise_on_error:
+        _check(st)
+    return st
+
+
+def autotune_hv(sector, v, w, reps=5, stream=None):
+    """Time every candidate plan on (v, w) and keep the fastest; returns (plan, us)."""
+    p = HvPlan()
+    us = ctypes.c_double()
+    _check(lib.edx_autotune_hv(sector.handle, _vtype_of(v), _P(v.data_ptr()), _P(w.data_ptr()), int(reps),
+                               _stream_ptr(stream), ctypes.byref(p), ctypes.byref(us)))
+    return _plan_dict(p), us.value
+
+
+def lanczos_opts(**kw):
+    o = LanczosOpts()
+    lib.edx_lanczos_default_opts(ctypes.byref(o))
+    for k, v in kw.items():
+        if k == "vtype":
+            v = _vt(v)
+        setattr(o, k, v)
+    return o
+
+
+def workspace_bytes(sector, what, vtype, n):
+    return int(lib.edx_workspace_bytes(sector.handle, what, _vt(vtype), n))
+
+
+def alloc_workspace(nbytes, device="cuda"):
+    return torch.empty(int(nbytes), dtype=torch.uint8, device=device)
+
+
+def lanczos_ground_state(sector, want_psi=True, ws=None, stream=None, allow=(EDX_OK,), **kw):
+    """Returns (e0, psi0 tensor or None, report dict, status)."""
+    o = lanczos_opts(**kw)
+    what = WS_LANCZOS_FULL if o.reorth == 2 else WS_LANCZOS
+    need = workspace_bytes(sector, what, o.vtype, o.niter)
+    if ws is None:
+        ws = alloc_workspace(need)
+    psi = torch.empty(sector.dim, dtype=_dtype_of(o.vtype), device="cuda") if want_psi else None
+    e0 = ctypes.c_double()
+    rep = LanczosReport()
+    st = lib.edx_lanczos_ground_state(sector.handle, ctypes.byref(o), _P(ws.data_ptr()), ws.numel(),
+                                      ctypes.byref(e0), _P(psi.data_ptr()) if psi is not None else None,
+                                      ctypes.byref(rep), _stream_ptr(stream))
+    _check(st, ok=tuple(allow) + (EDX_OK,))
+    r = {f: getattr(rep, f) for f, _ in LanczosReport._fields_}
+    return e0.value, psi, r, st
+
+
+def green_cf(sector, psi0, e0, orb=0, spin=0, ngf=200, beta=200.0, lmats=4096, ws=None, stream=None,
+             coeffs=False):
+    """Impurity G(i w_n) as a complex numpy array, plus the report dict."""
+    vtype = _vtype_of(psi0)
+    o = GfOpts(int(ngf), int(lmats), vtype, 0, float(beta))
+    need = workspace_bytes(sector, WS_GREEN, vtype, ngf)
+    if ws is None:
+        ws = alloc_workspace(need)
+    g = np.zeros(2 * lmats, np.float64)
+    rep = GfReport()
+    bufs = {}
+    if coeffs:
+        for k in ("alpha_p", "beta_p", "alpha_h", "beta_h"):
+            bufs[k] = np.zeros(ngf, np.float64)
+            setattr(rep, k, bufs[k].ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+    _check(lib.edx_green_cf(sector.handle, _P(psi0.data_ptr()), float(e0), int(orb), int(spin), ctypes.byref(o),
+                            _P(ws.data_ptr()), ws.numel(), g.ctypes.data_as(_P), ctypes.byref(rep),
+                            _stream_ptr(stream)))
+    r = {"wp": rep.wp, "wh": rep.wh, "np": rep.np, "nh": rep.nh}
+    for k, b in bufs.items():
+        n = rep.np if k.endswith("_p") else rep.nh
+        r[k] = b[: n if k.startswith("alpha") else max(n - 1, 0)].copy()
+    return g[0::2] + 1j * g[1::2], r

@@ -1,0 +1,263 @@
+"""GPU parity: the HIP path through the C ABI against the CPU oracle.
+
+Bars (see the design notes):
+  * tables (map, hop columns, signs, amplitudes, impurity patterns): bit-exact;
+    diagonal energies to 1e-14 relative;
+  * H.v FP64: max |w - w_oracle| <= 1e-13 * (|H|_1-bound) * max|v|, every plan;
+  * H.v FP32: <= 2e-6 of the same scale;
+  * ground energy FP64: 1e-10 relative (spec bar); psi0 overlap 1 - 1e-8;
+  * G(i w_n) FP64: max |G - G_oracle| <= 1e-8 max |G_oracle|.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import closed, fock, green, rng, spectra
+from paper_2105_06806_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def edx():
+    import torch
+    from paper_2105_06806_amd import edx as E
+    assert torch.cuda.is_available()
+    return E
+
+
+def _cuda(x, dtype):
+    import torch
+    return torch.as_tensor(np.ascontiguousarray(x), dtype=dtype, device="cuda")
+
+
+def _hscale(m):
+    """Bound on |H|_inf (row sums of |H|) for error scaling."""
+    e = np.abs(fock.level_energies(m)).sum() * 2
+    return e + abs(m["U"]) * m["norb"] + abs(m["Ust"]) * m["norb"] ** 2 + \
+        2 * np.abs(m["vhyb"]).sum() * 2 + 1.0
+
+
+TABLE_CASES = [
+    ("ns8", inputs.workload("ns8")[0], (4, 4)),
+    ("ns8_53", inputs.workload("ns8")[0], (5, 3)),
+    ("o2", inputs.make_model(2, 4, 3.0, Jh=0.5, seed=11, symmetric=False), (4, 6)),
+    ("o3", inputs.make_model(3, 3, 3.0, Jh=0.5, seed=12, symmetric=False), (6, 5)),
+    ("ns12", inputs.workload("ns12")[0], (6, 6)),
+    ("edge0", inputs.make_model(1, 5, 2.0, seed=13), (0, 6)),
+]
+
+
+@pytest.mark.parametrize("name,m,sec", TABLE_CASES, ids=[c[0] for c in TABLE_CASES])
+def test_tables_bit_exact(edx, name, m, sec):
+    S = edx.build_sector(m, *sec)
+    ns = fock.ns_of(m)
+    assert S.dup == math.comb(ns, sec[0]) and S.ddw == math.comb(ns, sec[1])
+    for spin in (0, 1):
+        t = S.tables(spin)
+        n = sec[spin]
+        assert np.array_equal(t["map"], fock.spin_strings_listing(ns, n).astype(np.uint32))
+        off, col, sgn, amp = fock.spin_hop_csr(m, n, spin)
+        assert np.array_equal(t["hop_off"], off)
+        assert np.array_equal(t["hop_col"], col.astype(np.int32))
+        assert np.array_equal(t["hop_sign"], sgn)
+        assert np.array_equal(t["hop_amp"], amp * sgn)
+        from oracle import kron
+        E, p = kron.spin_diagonal(m, n)
+        assert np.array_equal(t["diag_p"], p.astype(np.uint8))
+        assert np.allclose(t["diag_e"], E, rtol=1e-14, atol=1e-14)
+
+
+HV_CASES = [
+    ("ns8", inputs.workload("ns8")[0], (4, 4)),
+    ("ns8_ragged", inputs.workload("ns8")[0], (5, 2)),
+    ("o2", inputs.make_model(2, 4, 3.0, Jh=0.5, seed=21, symmetric=False), (4, 6)),
+    ("o3", inputs.make_model(3, 3, 3.0, Jh=0.5, seed=22, symmetric=False), (6, 5)),
+    ("ns11", inputs.make_model(1, 10, 2.5, seed=23, symmetric=False), (5, 6)),
+    ("ns12", inputs.workload("ns12")[0], (6, 6)),
+]
+
+PLANS = [
+    dict(mode=0, col_cols=1, col_threads=512, row_rows=64, row_cols=32),
+    dict(mode=2, col_cols=1, col_threads=256, row_rows=64, row_cols=32),
+    dict(mode=2, col_cols=3, col_threads=1024, row_rows=64, row_cols=32),
+    dict(mode=1, col_cols=1, col_threads=512, row_rows=64, row_cols=16),
+    dict(mode=1, col_cols=8, col_threads=256, row_rows=16, row_cols=7),
+    dict(mode=1, col_cols=2, col_threads=1024, row_rows=32, row_cols=64),
+]
+
+
+def _set_plan(edx, S, vtype, p):
+    return edx.set_plan(S, vtype, raise_on_error=False, **p)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("name,m,sec", HV_CASES, ids=[c[0] for c in HV_CASES])
+def test_hv_every_plan(edx, name, m, sec, dtype):
+    import torch
+    H = fock.explicit_hamiltonian(m, *sec)
+    S = edx.build_sector(m, *sec)
+    x = inputs.random_vector(S.dim, seed=99)
+    ref = H @ x
+    tdt = torch.float64 if dtype == "f64" else torch.float32
+    vt = edx.F64 if dtype == "f64" else edx.F32
+    v = _cuda(x, tdt)
+    tol = (1e-13 if dtype == "f64" else 2e-6) * _hscale(m)
+    ran = 0
+    for p in PLANS:
+        st = _set_plan(edx, S, vt, p)
+        if st != 0:
+            assert st in (edx.EDX_E_UNSUPPORTED,), (p, edx.last_error())
+            continue
+        w = torch.full_like(v, float("nan"))
+        edx.hv(S, v, w)
+        torch.cuda.synchronize()
+        got = w.double().cpu().numpy()
+        err = np.abs(got - ref).max()
+        assert err <= tol, (p, err)
+        ran += 1
+    assert ran >= 2
+
+
+def test_hv_hermitian(edx):
+    import torch
+    m, [sec] = inputs.workload("ns12")
+    S = edx.build_sector(m, *sec)
+    x = _cuda(inputs.random_vector(S.dim, 1), torch.float64)
+    y = _cuda(inputs.random_vector(S.dim, 2), torch.float64)
+    hx, hy = torch.empty_like(x), torch.empty_like(y)
+    edx.hv(S, x, hx)
+    edx.hv(S, y, hy)
+    a = float(torch.dot(x, hy))
+    b = float(torch.dot(hx, y))
+    assert abs(a - b) <= 1e-13 * _hscale(m) * float(x.norm() * y.norm())
+
+
+def test_hv_rejects_bad_args(edx):
+    import torch
+    m, [sec] = inputs.workload("ns8")
+    S = edx.build_sector(m, *sec)
+    v = torch.zeros(S.dim, dtype=torch.float64, device="cuda")
+    with pytest.raises(edx.EdxError) as ei:
+        edx.hv(S, v, v)
+    assert ei.value.status == edx.EDX_E_INVALID
+    with pytest.raises(edx.EdxError) as ei:
+        edx.build_sector(m, 9, 4)
+    assert ei.value.status == edx.EDX_E_INVALID
+    with pytest.raises(edx.EdxError):
+        edx.build_sector(m, -1, 4)
+
+
+def _e0_oracle(m, sec):
+    H = fock.explicit_hamiltonian(m, *sec)
+    if H.shape[0] <= 2500:
+        w, V = spectra.dense_lowest(H)
+        return w[0], V[:, 0], H
+    E, psi, _ = spectra.lanczos_full_reorth(lambda x: H @ x, rng.start_vector(5, H.shape[0]))
+    return E, psi, H
+
+
+@pytest.mark.parametrize("wl", ["ns8"])
+def test_lanczos_ground_state_fp64(edx, wl):
+    m, [sec] = inputs.workload(wl)
+    E0, psi_ref, H = _e0_oracle(m, sec)
+    S = edx.build_sector(m, *sec)
+    e0, psi, rep, st = edx.lanczos_ground_state(S, niter=200, tol=1e-12, rtol=1e-9, seed=7)
+    assert rep["converged"] == 1
+    assert abs(e0 - E0) <= 1e-10 * abs(E0)
+    p = psi.cpu().numpy()
+    assert abs(np.linalg.norm(p) - 1) < 1e-12
+    assert abs(abs(p @ psi_ref) - 1) < 1e-8
+
+
+def test_lanczos_deterministic_and_replay(edx):
+    m, [sec] = inputs.workload("ns12")
+    S = edx.build_sector(m, *sec)
+    r1 = edx.lanczos_ground_state(S, niter=512, tol=1e-12, seed=11)
+    r2 = edx.lanczos_ground_state(S, niter=512, tol=1e-12, seed=11)
+    assert r1[0] == r2[0]
+    assert r1[2]["iters"] == r2[2]["iters"]
+    assert bool((r1[1] == r2[1]).all())
+
+
+@pytest.mark.parametrize("spin", [0, 1])
+def test_green_fp64_small(edx, spin):
+    m, [sec] = inputs.workload("ns8")
+    E0, psi_ref, H = _e0_oracle(m, sec)
+    S = edx.build_sector(m, *sec)
+    e0, psi, rep, _ = edx.lanczos_ground_state(S, niter=200, tol=1e-14, rtol=1e-11, seed=3)
+    beta, lmats = 50.0, 256
+    G, gr = edx.green_cf(S, psi, e0, 0, spin, ngf=200, beta=beta, lmats=lmats)
+    z = 1j * green.matsubara(beta, lmats)
+    Gl, _ = green.lehmann_exact(m, *sec, 0, spin, z)
+    assert abs(gr["wp"] + gr["wh"] - 1.0) < 1e-12
+    assert np.abs(G - Gl).max() <= 1e-8 * np.abs(Gl).max()
+    assert np.abs(G.real).max() < 1e-9    # particle-hole symmetric model
+
+
+def test_green_noninteracting_closed_form(edx):
+    m = inputs.make_model(1, 7, 0.0, seed=41, symmetric=False, eps_imp=0.25)
+    sec = (4, 3)
+    S = edx.build_sector(m, *sec)
+    e0, psi, rep, _ = edx.lanczos_ground_state(S, niter=300, tol=1e-14, rtol=1e-11, seed=3)
+    assert abs(e0 - closed.e0_noninteracting(m, *sec)) < 1e-10
+    z = 1j * green.matsubara(40.0, 128)
+    G, gr = edx.green_cf(S, psi, e0, 0, 0, ngf=50, beta=40.0, lmats=128)
+    assert np.abs(G - closed.g_noninteracting(m, 0, z)).max() < 1e-8
+
+
+def test_edge_sectors(edx):
+    import torch
+    m = inputs.make_model(1, 5, 2.0, seed=5)
+    ns = 6
+    # D = 1 sector: every level filled
+    S = edx.build_sector(m, ns, ns)
+    assert S.dim == 1
+    H = fock.explicit_hamiltonian(m, ns, ns)
+    v = torch.ones(1, dtype=torch.float64, device="cuda")
+    w = torch.empty_like(v)
+    edx.hv(S, v, w)
+    assert abs(float(w[0]) - H[0, 0]) < 1e-13
+    e0, psi, rep, st = edx.lanczos_ground_state(S, niter=10, tol=1e-12, seed=1)
+    assert abs(e0 - H[0, 0]) < 1e-13 and rep["iters"] == 1
+    # empty spin species
+    S0 = edx.build_sector(m, 0, 3)
+    E0, _, _ = _e0_oracle(m, (0, 3))
+    e0, _, rep, _ = edx.lanczos_ground_state(S0, niter=100, tol=1e-13, seed=1)
+    assert abs(e0 - E0) < 1e-10 * max(1, abs(E0))
+
+
+def test_noconv_and_nomem(edx):
+    import torch
+    m, [sec] = inputs.workload("ns8")
+    S = edx.build_sector(m, *sec)
+    e0, _, rep, st = edx.lanczos_ground_state(S, niter=3, tol=1e-14, seed=1, allow=(edx.EDX_E_NOCONV,))
+    assert st == edx.EDX_E_NOCONV and rep["iters"] == 3 and np.isfinite(e0)
+    small = torch.empty(64, dtype=torch.uint8, device="cuda")
+    with pytest.raises(edx.EdxError) as ei:
+        edx.lanczos_ground_state(S, ws=small, niter=10)
+    assert ei.value.status == edx.EDX_E_NOMEM
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_hv_headline_sector_sampled(edx, dtype):
+    """Ns=16 half filling (D=165,636,900) in the benchmark's launch plan:
+    sampled outputs against the oracle's row-by-row product."""
+    import torch
+    m, [sec] = inputs.workload("ns16")
+    S = edx.build_sector(m, *sec)
+    tdt = torch.float64 if dtype == "f64" else torch.float32
+    gen = torch.Generator(device="cuda").manual_seed(5)
+    v = torch.rand(S.dim, dtype=tdt, device="cuda", generator=gen) * 2 - 1
+    w = torch.empty_like(v)
+    edx.hv(S, v, w)
+    torch.cuda.synchronize()
+    rows = np.random.default_rng(3).choice(S.dim, size=2000, replace=False)
+    rows = np.concatenate([rows, [0, S.dim - 1, S.dup - 1, S.dup]])
+    # the oracle needs the neighbours of the sampled rows: pass v to the host
+    vh = v.double().cpu().numpy()
+    ref = fock.hv_rows(m, *sec, vh, rows)
+    got = w.double().cpu().numpy()[rows]
+    tol = (1e-13 if dtype == "f64" else 2e-6) * _hscale(m)
+    assert np.abs(got - ref).max() <= tol
