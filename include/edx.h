@@ -115,9 +115,9 @@ edx_status edx_hv(const edx_sector* s, edx_vtype vtype, const void* v, void* w,
  * to rounding order).  mode 0: whole sector in LDS, one block; mode 1: two
  * passes (spin-down rows, then spin-up columns + diagonal); mode 2: one pass
  * over columns that also gathers the spin-down neighbours from global memory.
- * col_cols: columns per block (1..8) of the column pass; col_threads: 256, 512
- * or 1024; row_rows: rows per slab (16, 32, 64); row_cols: columns per block of
- * the row pass (>= 1). */
+ * col_cols: columns per block (1..4) of the column pass; col_threads: 256, 512
+ * or 1024; row_rows: rows per slab (16, 32, 64, or 128 = two rows per lane,
+ * even D_up only); row_cols: columns per block of the row pass (>= 1). */
 typedef struct {
   int32_t mode, col_cols, col_threads, row_rows, row_cols;
 } edx_hv_plan;

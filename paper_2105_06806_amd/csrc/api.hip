@@ -126,16 +126,15 @@ edx_status edx_sector_get_tables(const edx_sector* s, int32_t spin, uint32_t* ma
   if (diag_e) EDX_HIP(hipMemcpy(diag_e, T.e64, D * sizeof(double), hipMemcpyDeviceToHost));
   if (diag_p) EDX_HIP(hipMemcpy(diag_p, T.pat, D, hipMemcpyDeviceToHost));
   if (hop_off || hop_col || hop_sign || hop_amp) {
-    std::vector<uint32_t> ell((size_t)T.width * D);
-    if (!ell.empty())
-      EDX_HIP(hipMemcpy(ell.data(), T.hop, ell.size() * sizeof(uint32_t), hipMemcpyDeviceToHost));
+    std::vector<uint32_t> ell((size_t)T.wpad * D);
+    EDX_HIP(hipMemcpy(ell.data(), T.hop, ell.size() * sizeof(uint32_t), hipMemcpyDeviceToHost));
     int64_t pos = 0;
     std::vector<std::pair<uint32_t, uint32_t>> row;
     for (int64_t i = 0; i < D; ++i) {
       if (hop_off) hop_off[i] = pos;
       row.clear();
-      for (int k = 0; k < T.width; ++k) {
-        const uint32_t e = ell[(size_t)k * D + i];
+      for (int k = 0; k < T.wpad; ++k) {
+        const uint32_t e = ell[(size_t)i * T.wpad + k];
         if (((e >> kAmpShift) & 0x7Fu) == kPadPair) continue;
         row.emplace_back(e & kColMask, e);
       }

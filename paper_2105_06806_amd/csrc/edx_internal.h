@@ -50,11 +50,12 @@ struct Model {
 struct SpinTables {
   int n = 0;              // electrons of this spin
   int64_t D = 0;          // number of strings
-  int width = 0;          // ELL width: max hops per row
+  int width = 0;          // max hops in any row
+  int wpad = 8;           // row stride of the hop table: 8, 16 or 24 entries
   int64_t nnz = 0;        // non-padding hop entries
   uint32_t* map = nullptr;    // [D] ascending strings
   int32_t* rank = nullptr;    // [2^Ns] index of a string, -1 if other popcount
-  uint32_t* hop = nullptr;    // [width * D] packed ELL, hop[k*D + i]
+  uint32_t* hop = nullptr;    // [D * wpad] packed, row-major: hop[i*wpad + k]
   double* e64 = nullptr;      // [D] diagonal energy
   float* e32 = nullptr;       // [D] same, rounded
   uint8_t* pat = nullptr;     // [D] impurity pattern
@@ -162,6 +163,7 @@ double tridiag_lowest(const double* a, const double* b, int m, int k);
 void tridiag_vector(const double* a, const double* b, int m, double lam,
                     double* y);
 
+inline int wpad_of(int width) { return width <= 8 ? 8 : (width <= 16 ? 16 : 24); }
 inline size_t vbytes(int vtype) { return vtype == EDX_F32 ? 4 : 8; }
 inline size_t align_up(size_t x, size_t a = 256) { return (x + a - 1) / a * a; }
 

@@ -34,9 +34,9 @@ namespace edx {
 template <typename T>
 struct HvArgs {
   int64_t dup, ddw;
-  const uint32_t* __restrict__ hup;
-  const uint32_t* __restrict__ hdw;
-  int wup, wdw;
+  const uint32_t* __restrict__ hup;   // row-major, stride sup
+  const uint32_t* __restrict__ hdw;   // row-major, stride sdw
+  int sup, sdw;                       // padded row lengths (8, 16 or 24)
   const T* __restrict__ eup;
   const T* __restrict__ edw;
   const uint8_t* __restrict__ pup;
@@ -50,12 +50,12 @@ HvArgs<T> make_args(const edx_sector* s);
 
 template <>
 HvArgs<double> make_args<double>(const edx_sector* s) {
-  return HvArgs<double>{s->dup, s->ddw, s->up.hop, s->dw.hop, s->up.width, s->dw.width,
+  return HvArgs<double>{s->dup, s->ddw, s->up.hop, s->dw.hop, s->up.wpad, s->dw.wpad,
                         s->up.e64, s->dw.e64, s->up.pat, s->dw.pat, s->amp64, s->w64};
 }
 template <>
 HvArgs<float> make_args<float>(const edx_sector* s) {
-  return HvArgs<float>{s->dup, s->ddw, s->up.hop, s->dw.hop, s->up.width, s->dw.width,
+  return HvArgs<float>{s->dup, s->ddw, s->up.hop, s->dw.hop, s->up.wpad, s->dw.wpad,
                        s->up.e32, s->dw.e32, s->up.pat, s->dw.pat, s->amp32, s->w32};
 }
 
@@ -82,12 +82,12 @@ __global__ __launch_bounds__(1024) void k_hv_small(HvArgs<T> a, const T* __restr
     const int64_t id = idx / a.dup;
     const T x = vs[idx];
     T acc = (a.eup[iu] + a.edw[id] + Wt[a.pup[iu] * 8 + a.pdw[id]]) * x;
-    for (int k = 0; k < a.wup; ++k) {
-      const uint32_t e = a.hup[k * a.dup + iu];
+    for (int k = 0; k < a.sup; ++k) {
+      const uint32_t e = a.hup[iu * a.sup + k];
       acc += amp[e >> kAmpShift] * vs[id * a.dup + (e & kColMask)];
     }
-    for (int k = 0; k < a.wdw; ++k) {
-      const uint32_t e = a.hdw[k * a.ddw + id];
+    for (int k = 0; k < a.sdw; ++k) {
+      const uint32_t e = a.hdw[id * a.sdw + k];
       acc += amp[e >> kAmpShift] * vs[iu + (int64_t)(e & kColMask) * a.dup];
     }
     w[idx] = acc;
@@ -100,13 +100,44 @@ __global__ __launch_bounds__(1024) void k_hv_small(HvArgs<T> a, const T* __restr
 }
 
 // ---------------------------------------------------------------- column pass
-constexpr int kColMax = 8;   // columns per block held in registers per thread
+// Latency hiding: the column staging issues 8 independent loads per thread
+// before storing them; every row's whole (padded) hop list comes in with
+// vector loads; the accumulate variant processes two rows per thread so that
+// the table loads and the read of w for both are in flight together.
+constexpr int kColMax = 4;   // columns per block held in registers per thread
 
-template <typename T, bool FUSE_DW, bool ACCUM>
+template <typename T>
+__device__ __forceinline__ void stage(T* __restrict__ vs, const T* __restrict__ src, int64_t n,
+                                      T sc) {
+  const int bd = blockDim.x;
+  int64_t i = threadIdx.x;
+  for (; i + 7 * bd < n; i += 8 * bd) {
+    T x[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) x[u] = src[i + u * bd];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) vs[i + u * bd] = x[u] * sc;
+  }
+  for (; i < n; i += bd) vs[i] = src[i] * sc;
+}
+
+template <int W>
+__device__ __forceinline__ void load_row(const uint32_t* __restrict__ h, int64_t i,
+                                         uint32_t (&e)[W]) {
+  const uint4* ep = reinterpret_cast<const uint4*>(h + i * W);
+#pragma unroll
+  for (int q = 0; q < W / 4; ++q) {
+    const uint4 x = ep[q];
+    e[4 * q] = x.x; e[4 * q + 1] = x.y; e[4 * q + 2] = x.z; e[4 * q + 3] = x.w;
+  }
+}
+
+template <typename T, int WUP, int WDW, bool FUSE_DW, bool ACCUM>
 __global__ __launch_bounds__(1024) void k_hv_col(HvArgs<T> a, const T* __restrict__ v,
-                                                T* __restrict__ w,
-                                                const double* __restrict__ vscale,
-                                                double* __restrict__ partial, int ncol) {
+                                                 T* __restrict__ w,
+                                                 const double* __restrict__ vscale,
+                                                 double* __restrict__ partial, int ncol) {
+  constexpr int RPT = FUSE_DW ? 1 : 2;   // rows per thread per iteration
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T* amp = reinterpret_cast<T*>(smem_raw);
   T* Wt = amp + kAmpTable;
@@ -118,45 +149,76 @@ __global__ __launch_bounds__(1024) void k_hv_col(HvArgs<T> a, const T* __restric
   const T sc = vscale ? (T)(*vscale) : T(1);
   for (int i = threadIdx.x; i < kAmpTable; i += blockDim.x) amp[i] = a.amp[i];
   for (int i = threadIdx.x; i < 64; i += blockDim.x) Wt[i] = a.W[i];
-  {
-    const T* src = v + j0 * dup;
-    const int64_t n = (int64_t)nc * dup;
-    for (int64_t i = threadIdx.x; i < n; i += blockDim.x) vs[i] = src[i] * sc;
-  }
+  stage(vs, v + j0 * dup, (int64_t)nc * dup, sc);
   __syncthreads();
+  int64_t jc[kColMax];
+  T ed[kColMax];
+  int pd[kColMax];
+#pragma unroll
+  for (int c = 0; c < kColMax; ++c) {
+    jc[c] = j0 + (c < nc ? c : 0);
+    ed[c] = a.edw[jc[c]];
+    pd[c] = a.pdw[jc[c]];
+  }
   double dot = 0.0;
-  for (int64_t iu = threadIdx.x; iu < dup; iu += blockDim.x) {
-    T acc[kColMax];
+  for (int64_t base = threadIdx.x; base < dup; base += RPT * blockDim.x) {
+    int64_t rows[RPT];
+    bool ok[RPT];
+    uint32_t e[RPT][WUP];
+    T eu[RPT];
+    int pu[RPT];
+    T wold[RPT][kColMax];
 #pragma unroll
-    for (int c = 0; c < kColMax; ++c) acc[c] = T(0);
-    for (int k = 0; k < a.wup; ++k) {
-      const uint32_t e = a.hup[k * dup + iu];
-      const T am = amp[e >> kAmpShift];
-      const int64_t col = e & kColMask;
+    for (int r = 0; r < RPT; ++r) {
+      const int64_t iu = base + (int64_t)r * blockDim.x;
+      ok[r] = iu < dup;
+      rows[r] = ok[r] ? iu : base;
+      load_row<WUP>(a.hup, rows[r], e[r]);
+      eu[r] = a.eup[rows[r]];
+      pu[r] = a.pup[rows[r]] * 8;
+      if (ACCUM) {
 #pragma unroll
-      for (int c = 0; c < kColMax; ++c)
-        if (c < nc) acc[c] += am * vs[c * dup + col];
-    }
-    const T eu = a.eup[iu];
-    const int pu = a.pup[iu] * 8;
-#pragma unroll
-    for (int c = 0; c < kColMax; ++c) {
-      if (c >= nc) break;
-      const int64_t j = j0 + c;
-      const T x = vs[c * dup + iu];
-      T r = acc[c] + (eu + a.edw[j] + Wt[pu + a.pdw[j]]) * x;
-      if (FUSE_DW) {
-        T g = T(0);
-        for (int k = 0; k < a.wdw; ++k) {
-          const uint32_t e = a.hdw[k * a.ddw + j];
-          g += amp[e >> kAmpShift] * v[iu + (int64_t)(e & kColMask) * dup];
-        }
-        r += g * sc;
+        for (int c = 0; c < kColMax; ++c)
+          wold[r][c] = c < nc ? w[rows[r] + jc[c] * dup] : T(0);
       }
-      const int64_t o = iu + j * dup;
-      if (ACCUM) r += w[o];
-      w[o] = r;
-      dot += (double)x * (double)r;
+    }
+#pragma unroll
+    for (int r = 0; r < RPT; ++r) {
+      if (!ok[r]) continue;
+      const int64_t iu = rows[r];
+      T acc[kColMax];
+#pragma unroll
+      for (int c = 0; c < kColMax; ++c) acc[c] = T(0);
+#pragma unroll
+      for (int k = 0; k < WUP; ++k) {
+        const T am = amp[e[r][k] >> kAmpShift];
+        const int64_t col = e[r][k] & kColMask;
+#pragma unroll
+        for (int c = 0; c < kColMax; ++c)
+          if (c < nc) acc[c] += am * vs[c * dup + col];
+      }
+#pragma unroll
+      for (int c = 0; c < kColMax; ++c) {
+        if (c >= nc) break;
+        const int64_t j = jc[c];
+        const T x = vs[c * dup + iu];
+        T res = acc[c] + (eu[r] + ed[c] + Wt[pu[r] + pd[c]]) * x;
+        if (FUSE_DW) {
+          uint32_t f[WDW];
+#pragma unroll
+          for (int k = 0; k < WDW; ++k) f[k] = a.hdw[j * WDW + k];
+          T g[WDW];
+#pragma unroll
+          for (int k = 0; k < WDW; ++k) g[k] = v[iu + (int64_t)(f[k] & kColMask) * dup];
+          T s2 = T(0);
+#pragma unroll
+          for (int k = 0; k < WDW; ++k) s2 += amp[f[k] >> kAmpShift] * g[k];
+          res += s2 * sc;
+        }
+        if (ACCUM) res += wold[r][c];
+        w[iu + j * dup] = res;
+        dot += (double)x * (double)res;
+      }
     }
   }
   if (partial) {
@@ -166,11 +228,24 @@ __global__ __launch_bounds__(1024) void k_hv_col(HvArgs<T> a, const T* __restric
 }
 
 // ---------------------------------------------------------------- row pass
-template <typename T, int R>
+// A wave covers R*VEC consecutive rows (VEC rows per lane, one vector load) of
+// 64/R columns; each thread handles two columns per iteration with all their
+// gathers in flight.
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef double f64x2 __attribute__((ext_vector_type(2)));
+template <typename T, int VEC>
+struct VecT;
+template <> struct VecT<float, 1> { using type = float; };
+template <> struct VecT<float, 2> { using type = f32x2; };
+template <> struct VecT<double, 1> { using type = double; };
+template <> struct VecT<double, 2> { using type = f64x2; };
+
+template <typename T, int R, int VEC, int WDW>
 __global__ __launch_bounds__(256) void k_hv_row(HvArgs<T> a, const T* __restrict__ v,
                                                 T* __restrict__ w,
                                                 const double* __restrict__ vscale,
                                                 int64_t nchunk, int cpb, int64_t nwork) {
+  using V = typename VecT<T, VEC>::type;
   __shared__ T amp[kAmpTable];
   for (int i = threadIdx.x; i < kAmpTable; i += blockDim.x) amp[i] = a.amp[i];
   __syncthreads();
@@ -185,19 +260,43 @@ __global__ __launch_bounds__(256) void k_hv_row(HvArgs<T> a, const T* __restrict
   const int r = threadIdx.x % R;
   const int cw = threadIdx.x / R;
   constexpr int kColsInFlight = 256 / R;
-  const int64_t iu = slab * R + r;
-  const bool ok = iu < a.dup;
+  const int64_t iu = (slab * R + r) * VEC;        // first row of this lane
+  const bool ok = iu < a.dup;                     // VEC = 2 needs an even D_up
   const int64_t iuc = ok ? iu : 0;
   const T sc = vscale ? (T)(*vscale) : T(1);
   const int64_t jb = chunk * cpb;
   const int64_t je = std::min<int64_t>(jb + cpb, a.ddw);
-  for (int64_t j = jb + cw; j < je; j += kColsInFlight) {
-    T acc = T(0);
-    for (int k = 0; k < a.wdw; ++k) {
-      const uint32_t e = a.hdw[k * a.ddw + j];
-      acc += amp[e >> kAmpShift] * v[iuc + (int64_t)(e & kColMask) * a.dup];
+  for (int64_t j = jb + cw; j < je; j += 2 * kColsInFlight) {
+    const int64_t j2 = j + kColsInFlight;
+    const bool has2 = j2 < je;
+    const int64_t j2c = has2 ? j2 : j;
+    // with R = 64 a wave covers one column, so the table row is wave-uniform
+    // and goes through the scalar cache
+    const int64_t ja = R == 64 ? (int64_t)__builtin_amdgcn_readfirstlane((int)j) : j;
+    const int64_t jb2 = R == 64 ? (int64_t)__builtin_amdgcn_readfirstlane((int)j2c) : j2c;
+    uint32_t e1[WDW], e2[WDW];
+#pragma unroll
+    for (int k = 0; k < WDW; ++k) {
+      e1[k] = a.hdw[ja * WDW + k];
+      e2[k] = a.hdw[jb2 * WDW + k];
     }
-    if (ok) w[iu + j * a.dup] = acc * sc;
+    V g1[WDW], g2[WDW];
+#pragma unroll
+    for (int k = 0; k < WDW; ++k) {
+      g1[k] = *reinterpret_cast<const V*>(v + iuc + (int64_t)(e1[k] & kColMask) * a.dup);
+      g2[k] = *reinterpret_cast<const V*>(v + iuc + (int64_t)(e2[k] & kColMask) * a.dup);
+    }
+    V s1 = V(0), s2 = V(0);
+#pragma unroll
+    for (int k = 0; k < WDW; ++k) {
+      s1 += (amp[e1[k] >> kAmpShift] * sc) * g1[k];
+      s2 += (amp[e2[k] >> kAmpShift] * sc) * g2[k];
+    }
+    // streaming stores: keep L2 for the slab being gathered
+    if (ok) {
+      __builtin_nontemporal_store(s1, reinterpret_cast<V*>(w + iu + j * a.dup));
+      if (has2) __builtin_nontemporal_store(s2, reinterpret_cast<V*>(w + iu + j2 * a.dup));
+    }
   }
 }
 
@@ -205,7 +304,7 @@ __global__ __launch_bounds__(256) void k_hv_row(HvArgs<T> a, const T* __restrict
 namespace {
 
 constexpr size_t kSmallLdsBytes = 60 * 1024;
-constexpr size_t kColLdsBytes = 96 * 1024;
+constexpr size_t kColLdsBytes = 150 * 1024;
 
 size_t smem_header() { return kAmpTable * 8 + 64 * 8 + 16 * 8; }
 
@@ -230,8 +329,8 @@ HvPlan hv_default_plan(const edx_sector* s, int vtype) {
   // the fused single pass reads whole neighbour columns from global memory; it
   // is the right choice while the vector is cache resident
   p.mode = bytes <= (size_t)32 * 1024 * 1024 ? 2 : 1;
-  p.row_rows = vtype == EDX_F32 ? 64 : 32;
-  p.row_cols = 32;
+  p.row_rows = (s->dup % 2 == 0) ? 128 : 64;
+  p.row_cols = 8;
   return p;
 }
 
@@ -251,13 +350,18 @@ edx_status hv_validate(const edx_sector* s, int vtype, HvPlan* p) {
   }
   if (p->col_cols < 1 || p->col_cols > kColMax ||
       (p->col_threads != 256 && p->col_threads != 512 && p->col_threads != 1024)) {
-    set_error("hv plan: col_cols in [1, 8], col_threads in {256, 512, 1024}");
+    set_error("hv plan: col_cols in [1, 4], col_threads in {256, 512, 1024}");
     return EDX_E_INVALID;
   }
-  if (p->mode == 1 && ((p->row_rows != 16 && p->row_rows != 32 && p->row_rows != 64) ||
+  if (p->mode == 1 && ((p->row_rows != 16 && p->row_rows != 32 && p->row_rows != 64 &&
+                        p->row_rows != 128) ||
                        p->row_cols < 1)) {
-    set_error("hv plan: row_rows in {16, 32, 64}, row_cols >= 1");
+    set_error("hv plan: row_rows in {16, 32, 64, 128}, row_cols >= 1");
     return EDX_E_INVALID;
+  }
+  if (p->mode == 1 && p->row_rows == 128 && (s->dup & 1)) {
+    set_error("hv plan: row_rows = 128 (two rows per lane) needs an even D_up");
+    return EDX_E_UNSUPPORTED;
   }
   if (smem_header() + (size_t)p->col_cols * s->dup * sz > 160 * 1024) {
     set_error("hv plan: columns do not fit in LDS");
@@ -284,6 +388,58 @@ int hv_partial_blocks(const edx_sector* s, int vtype) { return hv_plan(s, vtype)
 
 namespace {
 
+
+template <typename T, int WUP, int WDW>
+edx_status launch_col(const HvArgs<T>& a, bool fused, int nblk, int nthr, size_t lds,
+                      hipStream_t st, const T* v, T* w, const double* vscale, double* partial,
+                      int ncol) {
+  const void* kern = fused ? (const void*)k_hv_col<T, WUP, WDW, true, false>
+                           : (const void*)k_hv_col<T, WUP, WDW, false, true>;
+  EDX_HIP(hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  if (fused)
+    hipLaunchKernelGGL((k_hv_col<T, WUP, WDW, true, false>), dim3(nblk), dim3(nthr), lds, st, a,
+                       v, w, vscale, partial, ncol);
+  else
+    hipLaunchKernelGGL((k_hv_col<T, WUP, WDW, false, true>), dim3(nblk), dim3(nthr), lds, st, a,
+                       v, w, vscale, partial, ncol);
+  EDX_HIP(hipGetLastError());
+  return EDX_OK;
+}
+
+template <typename T, int WUP>
+edx_status launch_col_w(const HvArgs<T>& a, bool fused, int nblk, int nthr, size_t lds,
+                        hipStream_t st, const T* v, T* w, const double* vscale, double* partial,
+                        int ncol) {
+  if (!fused)   // the spin-down width does not enter the accumulate variant
+    return launch_col<T, WUP, 8>(a, false, nblk, nthr, lds, st, v, w, vscale, partial, ncol);
+  switch (a.sdw) {
+    case 8: return launch_col<T, WUP, 8>(a, true, nblk, nthr, lds, st, v, w, vscale, partial, ncol);
+    case 16: return launch_col<T, WUP, 16>(a, true, nblk, nthr, lds, st, v, w, vscale, partial, ncol);
+    default: return launch_col<T, WUP, 24>(a, true, nblk, nthr, lds, st, v, w, vscale, partial, ncol);
+  }
+}
+
+template <typename T, int R, int VEC>
+edx_status launch_row_r(const HvArgs<T>& a, int64_t grid, hipStream_t st, const T* v, T* w,
+                        const double* vscale, int64_t nchunk, int cpb, int64_t nwork) {
+  switch (a.sdw) {
+    case 8:
+      hipLaunchKernelGGL((k_hv_row<T, R, VEC, 8>), dim3(grid), dim3(256), 0, st, a, v, w, vscale,
+                         nchunk, cpb, nwork);
+      break;
+    case 16:
+      hipLaunchKernelGGL((k_hv_row<T, R, VEC, 16>), dim3(grid), dim3(256), 0, st, a, v, w, vscale,
+                         nchunk, cpb, nwork);
+      break;
+    default:
+      hipLaunchKernelGGL((k_hv_row<T, R, VEC, 24>), dim3(grid), dim3(256), 0, st, a, v, w, vscale,
+                         nchunk, cpb, nwork);
+      break;
+  }
+  EDX_HIP(hipGetLastError());
+  return EDX_OK;
+}
+
 template <typename T>
 edx_status launch_t(const edx_sector* s, const T* v, T* w, const double* vscale,
                     double* partial, hipStream_t st, const HvPlan& p) {
@@ -295,7 +451,8 @@ edx_status launch_t(const edx_sector* s, const T* v, T* w, const double* vscale,
     EDX_HIP(hipFuncSetAttribute((const void*)k_hv_small<T>,
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     hipLaunchKernelGGL(k_hv_small<T>, dim3(1), dim3(1024), lds, st, a, v, w, vscale, partial);
-    return hipGetLastError() == hipSuccess ? EDX_OK : EDX_E_DEVICE;
+    EDX_HIP(hipGetLastError());
+    return EDX_OK;
   }
   if (p.col_cols > kColMax || p.col_cols < 1) return EDX_E_INVALID;
   const size_t lds = hdr + (size_t)p.col_cols * s->dup * sizeof(T);
@@ -305,48 +462,31 @@ edx_status launch_t(const edx_sector* s, const T* v, T* w, const double* vscale,
     return EDX_E_UNSUPPORTED;
   }
   const int nblk = (int)((s->ddw + p.col_cols - 1) / p.col_cols);
-  if (p.mode == 2) {
-    auto kern = k_hv_col<T, true, false>;
-    EDX_HIP(hipFuncSetAttribute((const void*)kern,
-                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-    hipLaunchKernelGGL(kern, dim3(nblk), dim3(nthr), lds, st, a, v, w, vscale, partial,
-                       p.col_cols);
-    EDX_HIP(hipGetLastError());
-    return EDX_OK;
-  }
-  // two-pass: rows (spin down) then columns (diag + spin up, accumulate)
-  {
+  if (p.mode == 1) {
+    // spin-down rows first (writes w), then the column pass accumulates
     const int R = p.row_rows;
     const int64_t nslab = (s->dup + R - 1) / R;
     const int64_t nchunk = (s->ddw + p.row_cols - 1) / p.row_cols;
     const int64_t nwork = nslab * nchunk;
     const int64_t grid = ((nwork + 7) / 8) * 8;
     if (grid > 0x7FFFFFFF) return EDX_E_UNSUPPORTED;
-    switch (R) {
-      case 16:
-        hipLaunchKernelGGL((k_hv_row<T, 16>), dim3(grid), dim3(256), 0, st, a, v, w, vscale,
-                           nchunk, p.row_cols, nwork);
-        break;
-      case 32:
-        hipLaunchKernelGGL((k_hv_row<T, 32>), dim3(grid), dim3(256), 0, st, a, v, w, vscale,
-                           nchunk, p.row_cols, nwork);
-        break;
-      case 64:
-        hipLaunchKernelGGL((k_hv_row<T, 64>), dim3(grid), dim3(256), 0, st, a, v, w, vscale,
-                           nchunk, p.row_cols, nwork);
-        break;
-      default:
-        return EDX_E_INVALID;
-    }
-    EDX_HIP(hipGetLastError());
+    if (R == 16)
+      EDX_TRY((launch_row_r<T, 16, 1>(a, grid, st, v, w, vscale, nchunk, p.row_cols, nwork)));
+    else if (R == 32)
+      EDX_TRY((launch_row_r<T, 32, 1>(a, grid, st, v, w, vscale, nchunk, p.row_cols, nwork)));
+    else if (R == 64)
+      EDX_TRY((launch_row_r<T, 64, 1>(a, grid, st, v, w, vscale, nchunk, p.row_cols, nwork)));
+    else if (R == 128)
+      EDX_TRY((launch_row_r<T, 64, 2>(a, grid, st, v, w, vscale, nchunk, p.row_cols, nwork)));
+    else
+      return EDX_E_INVALID;
   }
-  auto kern = k_hv_col<T, false, true>;
-  EDX_HIP(hipFuncSetAttribute((const void*)kern,
-                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-  hipLaunchKernelGGL(kern, dim3(nblk), dim3(nthr), lds, st, a, v, w, vscale, partial,
-                     p.col_cols);
-  EDX_HIP(hipGetLastError());
-  return EDX_OK;
+  const bool fused = p.mode == 2;
+  switch (a.sup) {
+    case 8: return launch_col_w<T, 8>(a, fused, nblk, nthr, lds, st, v, w, vscale, partial, p.col_cols);
+    case 16: return launch_col_w<T, 16>(a, fused, nblk, nthr, lds, st, v, w, vscale, partial, p.col_cols);
+    default: return launch_col_w<T, 24>(a, fused, nblk, nthr, lds, st, v, w, vscale, partial, p.col_cols);
+  }
 }
 
 }  // namespace
@@ -354,7 +494,11 @@ edx_status launch_t(const edx_sector* s, const T* v, T* w, const double* vscale,
 edx_status hv_launch(const edx_sector* s, int vtype, const void* v, void* w,
                      const double* vscale, double* partial, hipStream_t st,
                      const HvPlan* plan) {
-  const HvPlan p = plan ? *plan : hv_plan(s, vtype);
+  HvPlan p = plan ? *plan : hv_plan(s, vtype);
+  // two rows per lane uses 8/16-byte loads: only for 16-byte aligned vectors
+  if (p.mode == 1 && p.row_rows == 128 &&
+      ((reinterpret_cast<uintptr_t>(v) | reinterpret_cast<uintptr_t>(w)) & 15u))
+    p.row_rows = 64;
   if (vtype == EDX_F64)
     return launch_t<double>(s, static_cast<const double*>(v), static_cast<double*>(w), vscale,
                             partial, st, p);
@@ -373,15 +517,15 @@ edx_status hv_autotune(edx_sector* s, int vtype, const void* v, void* w, int rep
     p.mode = 0;
     add(p);
   }
-  for (int cc : {1, 2, 4, 8})
+  for (int cc : {1, 2, 3, 4})
     for (int th : {256, 512, 1024}) {
       HvPlan p;
       p.mode = 2;
       p.col_cols = cc;
       p.col_threads = th;
       add(p);
-      for (int rr : {16, 32, 64})
-        for (int rc : {16, 64}) {
+      for (int rr : {32, 64, 128})
+        for (int rc : {8, 32}) {
           HvPlan q = p;
           q.mode = 1;
           q.row_rows = rr;

@@ -11,8 +11,10 @@
 //    with exactly one of the two occupied, the neighbour string is
 //    s ^ 2^a ^ 2^b and the sign is (-1)^(occupied levels strictly between a and
 //    b); the other spin's string never enters because all spin-up modes
-//    precede all spin-down modes.  Stored as a column-major ELL table of packed
-//    32-bit entries: column (24 bits) | pair index (7 bits) | sign (1 bit).
+//    precede all spin-down modes.  Stored row-major with a padded row length of
+//    8, 16 or 24 packed 32-bit entries: column (24 bits) | pair index (7 bits) |
+//    sign (1 bit); padding entries point at the row itself with a zero
+//    amplitude, so kernels read whole rows without bounds checks.
 //  * diagonal (eq. Hbuild, H_d): E_s = sum_k e_k n_k + (U'-J) sum_{a<b} n_a n_b
 //    per string and the impurity pattern p = s & (2^norb - 1); the cross-spin
 //    terms come from W[p_up][p_dw].
@@ -77,7 +79,7 @@ __global__ void k_hop_count(const uint32_t* __restrict__ map, int64_t D, int nor
 
 __global__ void k_hop_fill(const uint32_t* __restrict__ map,
                            const int32_t* __restrict__ rank, int64_t D, int norb,
-                           int nbath, int width, uint32_t* __restrict__ hop) {
+                           int nbath, int wpad, uint32_t* __restrict__ hop) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < D;
        i += (int64_t)gridDim.x * blockDim.x) {
     const uint32_t s = map[i];
@@ -91,12 +93,11 @@ __global__ void k_hop_fill(const uint32_t* __restrict__ map,
         const uint32_t between = ((1u << b) - 1u) & ~((2u << a) - 1u);
         const uint32_t sgn = (uint32_t)(__popc(s & between) & 1);
         const uint32_t col = (uint32_t)rank[t];
-        hop[(int64_t)k * D + i] = col | ((uint32_t)p << kAmpShift) | (sgn << 31);
+        hop[i * wpad + k] = col | ((uint32_t)p << kAmpShift) | (sgn << 31);
         ++k;
       }
     }
-    for (; k < width; ++k)
-      hop[(int64_t)k * D + i] = (uint32_t)i | (kPadPair << kAmpShift);
+    for (; k < wpad; ++k) hop[i * wpad + k] = (uint32_t)i | (kPadPair << kAmpShift);
   }
 }
 
@@ -158,13 +159,11 @@ edx_status build_spin(edx_sector* S, SpinTables& T, int n, const double* d_elev,
   EDX_HIP(hipStreamSynchronize(st));
   EDX_HIP(hipFree(d_width));
   T.width = width;
+  T.wpad = wpad_of(width);
   T.nnz = (int64_t)nnz;
-  EDX_HIP(hipMalloc(&T.hop, std::max<int64_t>(1, (int64_t)width * D) * sizeof(uint32_t)));
-  if (width > 0) {
-    k_hop_fill<<<grid_for(D, 256), 256, 0, st>>>(T.map, T.rank, D, m.norb, m.nbath,
-                                                 width, T.hop);
-    EDX_HIP(hipGetLastError());
-  }
+  EDX_HIP(hipMalloc(&T.hop, (size_t)D * T.wpad * sizeof(uint32_t)));
+  k_hop_fill<<<grid_for(D, 256), 256, 0, st>>>(T.map, T.rank, D, m.norb, m.nbath, T.wpad, T.hop);
+  EDX_HIP(hipGetLastError());
   EDX_HIP(hipMalloc(&T.e64, D * sizeof(double)));
   EDX_HIP(hipMalloc(&T.e32, D * sizeof(float)));
   EDX_HIP(hipMalloc(&T.pat, D));

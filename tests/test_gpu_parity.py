@@ -76,6 +76,7 @@ HV_CASES = [
     ("o3", inputs.make_model(3, 3, 3.0, Jh=0.5, seed=22, symmetric=False), (6, 5)),
     ("ns11", inputs.make_model(1, 10, 2.5, seed=23, symmetric=False), (5, 6)),
     ("ns12", inputs.workload("ns12")[0], (6, 6)),
+    ("ns7_odd", inputs.make_model(1, 6, 1.7, seed=24, symmetric=False), (3, 3)),
 ]
 
 PLANS = [
@@ -83,8 +84,9 @@ PLANS = [
     dict(mode=2, col_cols=1, col_threads=256, row_rows=64, row_cols=32),
     dict(mode=2, col_cols=3, col_threads=1024, row_rows=64, row_cols=32),
     dict(mode=1, col_cols=1, col_threads=512, row_rows=64, row_cols=16),
-    dict(mode=1, col_cols=8, col_threads=256, row_rows=16, row_cols=7),
+    dict(mode=1, col_cols=4, col_threads=256, row_rows=16, row_cols=7),
     dict(mode=1, col_cols=2, col_threads=1024, row_rows=32, row_cols=64),
+    dict(mode=1, col_cols=3, col_threads=512, row_rows=128, row_cols=5),
 ]
 
 
