@@ -204,6 +204,52 @@ edx_status edx_green_cf(const edx_sector* gs, const void* psi0, double e0,
                         void* ws, size_t ws_bytes, double* g_host,
                         edx_gf_report* rep, void* stream);
 
+/* ---- batched ground states (many sectors, one persistent launch) ----
+ * Every job is an independent sector; the ground energy of each follows the
+ * recurrence and stop rule of edx_lanczos_ground_state (psi0 is not formed).
+ * The paper's counterpart is its parallelism over independent impurity
+ * problems (Sec. 5 "Main", inequivalent sites).  One cooperative launch:
+ * lanes of `lane_wgs` workgroups on one XCD each pull jobs (largest first)
+ * from a device queue.  A job's status is EDX_OK, EDX_E_NOCONV (e0 is the last
+ * estimate) or EDX_E_DEVICE (a lane barrier timed out). */
+typedef struct {
+  double e0;
+  double beta_last;
+  int32_t iters;
+  int32_t status;
+  int32_t breakdown;
+  int32_t pad_;
+} edx_batch_result;
+
+typedef struct {
+  int32_t lane_wgs;       /* workgroups per lane: 8, 16 or 32             */
+  const int32_t* ccols;   /* [n] columns per column-pass item, or NULL (1) */
+  const int32_t* rcols;   /* [n] columns per row-pass item, or NULL (32)   */
+} edx_batch_tiles;
+
+/* Device workspace bytes for n jobs with lanes of lane_wgs workgroups. */
+size_t edx_batch_workspace_bytes(const edx_sector* const* sectors, int32_t n,
+                                 int32_t vtype, int32_t lane_wgs);
+
+/* Ground energies of n sectors (host array of handles).  opts: niter, vtype,
+ * tol, check_every and seed are used (reorth must be 0).  tiles may be NULL
+ * (lane_wgs 32).  results: host array of n.  Blocks until done; elapsed_ms
+ * (nullable) receives the kernel time. */
+edx_status edx_batch_ground_state(const edx_sector* const* sectors, int32_t n,
+                                  const edx_lanczos_opts* opts,
+                                  const edx_batch_tiles* tiles, void* ws,
+                                  size_t ws_bytes, edx_batch_result* results,
+                                  double* elapsed_ms, void* stream);
+
+/* Project autotuner for the batched launch: per distinct (D_up, D_dw) it
+ * times short runs of each (ccols, rcols) candidate, then each lane size;
+ * writes ccols[n], rcols[n] (host) and *lane_wgs.  ws must be sized for
+ * lane_wgs = 8. */
+edx_status edx_batch_autotune(const edx_sector* const* sectors, int32_t n,
+                              const edx_lanczos_opts* opts, void* ws,
+                              size_t ws_bytes, int32_t* ccols, int32_t* rcols,
+                              int32_t* lane_wgs, void* stream);
+
 const char* edx_status_str(edx_status st);
 const char* edx_last_error(void);
 

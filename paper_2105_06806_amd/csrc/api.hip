@@ -258,6 +258,46 @@ edx_status edx_green_cf(const edx_sector* gs, const void* psi0, double e0, int32
                        static_cast<hipStream_t>(stream));
 }
 
+size_t edx_batch_workspace_bytes(const edx_sector* const* sectors, int32_t n, int32_t vtype,
+                                 int32_t lane_wgs) {
+  if (!sectors || n < 1 || !valid_vtype(vtype) || lane_wgs < 1) return 0;
+  for (int i = 0; i < n; ++i)
+    if (!sectors[i]) return 0;
+  return batch_workspace_bytes(sectors, n, vtype, lane_wgs);
+}
+
+static edx_status check_batch(const edx_sector* const* sectors, int32_t n,
+                              const edx_lanczos_opts* opts) {
+  if (!sectors || n < 1 || !opts) return invalid("sectors, n >= 1 and opts are required");
+  if (!valid_vtype(opts->vtype)) return invalid("vtype must be EDX_F64 or EDX_F32");
+  if (opts->reorth != 0) return invalid("the batched solver runs plain Lanczos (reorth = 0)");
+  if (opts->niter < 1 || opts->niter > 2048) return invalid("niter must be in [1, 2048]");
+  for (int i = 0; i < n; ++i) EDX_TRY(check_sector(sectors[i]));
+  return EDX_OK;
+}
+
+edx_status edx_batch_ground_state(const edx_sector* const* sectors, int32_t n,
+                                  const edx_lanczos_opts* opts, const edx_batch_tiles* tiles,
+                                  void* ws, size_t ws_bytes, edx_batch_result* results,
+                                  double* elapsed_ms, void* stream) {
+  EDX_TRY(check_batch(sectors, n, opts));
+  if (!ws || !results) return invalid("ws and results must be non-NULL");
+  const int L = tiles ? tiles->lane_wgs : 32;
+  if (L != 8 && L != 16 && L != 32) return invalid("lane_wgs must be 8, 16 or 32");
+  return batch_run(sectors, n, opts, tiles ? tiles->ccols : nullptr,
+                   tiles ? tiles->rcols : nullptr, L, ws, ws_bytes, results,
+                   static_cast<hipStream_t>(stream), elapsed_ms);
+}
+
+edx_status edx_batch_autotune(const edx_sector* const* sectors, int32_t n,
+                              const edx_lanczos_opts* opts, void* ws, size_t ws_bytes,
+                              int32_t* ccols, int32_t* rcols, int32_t* lane_wgs, void* stream) {
+  EDX_TRY(check_batch(sectors, n, opts));
+  if (!ws || !ccols || !rcols || !lane_wgs) return invalid("ws and outputs must be non-NULL");
+  return batch_autotune(sectors, n, opts, ws, ws_bytes, ccols, rcols, lane_wgs,
+                        static_cast<hipStream_t>(stream));
+}
+
 const char* edx_status_str(edx_status st) {
   switch (st) {
     case EDX_OK: return "EDX_OK";

@@ -1,0 +1,558 @@
+// Batched ground states of many sectors in one persistent launch.
+//
+// The grid is one workgroup per CU, launched cooperatively so that every
+// workgroup is resident.  Workgroups are grouped into lanes of L workgroups
+// that sit on one XCD (workgroup b runs on XCD b % 8), so a lane shares one L2.
+// A lane pulls the next job from a device queue (jobs sorted by decreasing
+// dimension), runs the whole Lanczos recurrence of Sec. 5 "Diagonalization" for
+// it, writes E0 and takes the next job; lanes synchronise internally with a
+// counter barrier (bounded spin: a stuck lane reports an error instead of
+// hanging).  Inside a lane a step is the same sequence as the plain path:
+//   row pass (spin-down hops, slabs of 64 rows, the slab stays in the XCD's L2)
+//   -> column pass (LDS-staged columns: diagonal + spin-up hops, <v, Hv>)
+//   -> three-term update with |w|^2 -> beta, scale.
+// The stop rule |E_j - E_{j-1}| <= tol max(1, |E_j|), breakdown or niter is
+// evaluated on the device every `check_every` steps: one wave finds the lowest
+// eigenvalue of T_j by multisection (64 Sturm counts per round), redundantly and
+// identically in every workgroup of the lane, so no broadcast is needed.
+// Dot products accumulate in FP64 with a fixed reduction order.
+#include <algorithm>
+#include <cmath>
+#include <vector>
+
+#include "common.cuh"
+#include "edx_internal.h"
+
+namespace edx {
+
+struct BatchJob {
+  const uint32_t* hup;
+  const uint32_t* hdw;
+  const void* eup;
+  const void* edw;
+  const uint8_t* pup;
+  const uint8_t* pdw;
+  const void* amp;
+  const void* W;
+  int64_t dup, ddw;
+  int sup, sdw;
+  int ccols;        // columns per column-pass item
+  int rcols;        // columns per row-pass item
+  int pad0, pad1;
+};
+
+struct BatchOut {
+  double e0;
+  double beta_last;
+  int iters;
+  int status;       // 0 ok, 4 no convergence, 3 device (barrier timeout)
+  int breakdown;
+  int pad;
+};
+
+namespace {
+
+constexpr int kThreads = 1024;
+constexpr int kWaves = kThreads / 64;
+constexpr long long kSpinLimit = 1ll << 26;
+
+__device__ __forceinline__ uint64_t splitmix64(uint64_t seed, uint64_t k) {
+  uint64_t z = seed + (k + 1) * 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+// Barrier over the L workgroups of a lane.  `gen` counts the barriers passed
+// by this workgroup; all workgroups of a lane pass the same sequence.
+__device__ bool lane_barrier(unsigned* ctr, unsigned& gen, int L, int* err) {
+  __syncthreads();
+  __shared__ int fail;
+  if (threadIdx.x == 0) {
+    fail = 0;
+    __threadfence();
+    atomicAdd(ctr, 1u);
+    const unsigned target = (gen + 1) * (unsigned)L;
+    long long spins = 0;
+    while (__hip_atomic_load(ctr, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
+      if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0 ||
+          ++spins > kSpinLimit) {
+        atomicExch(err, 1);
+        fail = 1;
+        break;
+      }
+      __builtin_amdgcn_s_sleep(2);
+    }
+    __threadfence();
+  }
+  __syncthreads();
+  ++gen;
+  return fail == 0;
+}
+
+// number of eigenvalues of T_m below x (Sturm sequence)
+__device__ int sturm(const double* a, const double* b, int m, double x) {
+  int cnt = 0;
+  double q = a[0] - x;
+  cnt += q < 0.0;
+  for (int i = 1; i < m; ++i) {
+    if (fabs(q) < 1e-300) q = -1e-300;
+    q = a[i] - x - b[i] * b[i] / q;   // b[i] couples i-1 and i
+    cnt += q < 0.0;
+  }
+  return cnt;
+}
+
+// Lowest eigenvalue of T_m (diag a[0..m), off-diagonal b[1..m)) by one wave:
+// each round evaluates 64 points of the bracket and keeps the sub-interval
+// holding the first eigenvalue.  Result valid in every lane of the wave.
+__device__ double wave_lowest(const double* a, const double* b, int m) {
+  const int lane = threadIdx.x & 63;
+  double lo = 1e300, hi = -1e300;
+  for (int i = lane; i < m; i += 64) {
+    const double r = (i > 0 ? fabs(b[i]) : 0.0) + (i + 1 < m ? fabs(b[i + 1]) : 0.0);
+    lo = fmin(lo, a[i] - r);
+    hi = fmax(hi, a[i] + r);
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    lo = fmin(lo, __shfl_xor(lo, off, 64));
+    hi = fmax(hi, __shfl_xor(hi, off, 64));
+  }
+  const double pad = 1e-14 * fmax(fabs(lo), fabs(hi)) + 1e-300;
+  lo -= pad;
+  hi += pad;
+  for (int round = 0; round < 12; ++round) {
+    const double x = lo + (hi - lo) * (double)(lane + 1) / 65.0;
+    const int c = sturm(a, b, m, x);
+    const unsigned long long mask = __ballot(c >= 1);
+    const int first = mask ? __ffsll((long long)mask) - 1 : 64;
+    const double nlo = first == 0 ? lo : lo + (hi - lo) * (double)first / 65.0;
+    const double nhi = first >= 64 ? hi : lo + (hi - lo) * (double)(first + 1) / 65.0;
+    lo = nlo;
+    hi = nhi;
+    if (hi - lo <= 4e-16 * fmax(fabs(lo), fabs(hi))) break;
+  }
+  return 0.5 * (lo + hi);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_batch(
+    const BatchJob* __restrict__ jobs, int njobs, BatchOut* __restrict__ out,
+    unsigned* __restrict__ queue, unsigned* __restrict__ bars, int* __restrict__ slots,
+    int* __restrict__ err, double* __restrict__ parts, char* __restrict__ vecs,
+    size_t vstride, int L, int lanes_per_xcd, int niter, double tol, int check_every,
+    uint64_t seed) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T* amp = reinterpret_cast<T*>(smem_raw);
+  T* Wt = amp + kAmpTable;
+  double* red = reinterpret_cast<double*>(Wt + 64);
+  double* ta = red + kWaves;           // alpha[0..niter]
+  double* tb = ta + (niter + 2);       // beta[0..niter+1]; tb[j] couples j-1 and j
+  __shared__ int s_job;
+  __shared__ int s_stop;
+  T* vs = reinterpret_cast<T*>(tb + (niter + 2));
+
+  const int b = blockIdx.x;
+  const int xcd = b & 7;
+  const int in_xcd = b >> 3;
+  const int lane = xcd * lanes_per_xcd + in_xcd / L;
+  const int member = in_xcd % L;
+  unsigned* bar = bars + lane;
+  double* pa = parts + (size_t)lane * 2 * L;     // alpha partials
+  double* pn = pa + L;                           // norm partials
+  char* lv = vecs + (size_t)lane * 3 * vstride;
+  unsigned gen = 0;
+  const int tid = threadIdx.x;
+  const int wave = tid >> 6;
+  const int wl = tid & 63;
+
+  for (;;) {
+    if (member == 0 && tid == 0) slots[lane] = (int)atomicAdd(queue, 1u);
+    if (!lane_barrier(bar, gen, L, err)) return;
+    if (tid == 0) s_job = __hip_atomic_load(slots + lane, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __syncthreads();
+    const int jid = s_job;
+    if (jid >= njobs) return;
+    const BatchJob J = jobs[jid];
+    const T* __restrict__ eup = static_cast<const T*>(J.eup);
+    const T* __restrict__ edw = static_cast<const T*>(J.edw);
+    for (int i = tid; i < kAmpTable; i += kThreads) amp[i] = static_cast<const T*>(J.amp)[i];
+    for (int i = tid; i < 64; i += kThreads) Wt[i] = static_cast<const T*>(J.W)[i];
+    const int64_t dup = J.dup, ddw = J.ddw, D = dup * ddw;
+    const int64_t gstride = (int64_t)L * kThreads;
+    const int64_t gbase = (int64_t)member * kThreads + tid;
+    T* buf[3] = {reinterpret_cast<T*>(lv), reinterpret_cast<T*>(lv + vstride),
+                 reinterpret_cast<T*>(lv + 2 * vstride)};
+
+    // start vector u_0 and |u_0|^2
+    double acc = 0.0;
+    for (int64_t i = gbase; i < D; i += gstride) {
+      const uint64_t z = splitmix64(seed, (uint64_t)i);
+      const T t = (T)((double)(z >> 11) * 0x1.0p-53 * 2.0 - 1.0);
+      buf[0][i] = t;
+      acc += (double)t * (double)t;
+    }
+    {
+      const double s = block_sum(acc, red);
+      if (tid == 0) pn[member] = s;
+    }
+    if (!lane_barrier(bar, gen, L, err)) return;
+    double nrm2 = 0.0;
+    for (int m = 0; m < L; ++m) nrm2 += pn[m];
+    double sc_cur = 1.0 / sqrt(nrm2), sc_prev = 0.0, beta_j = 0.0;
+    if (tid == 0) { s_stop = 0; tb[0] = 0.0; }
+    __syncthreads();
+    int steps = 0, status = 4, bdown = 0;
+    double E = 0.0, Eold = 0.0, tnorm = 0.0, blast = 0.0;
+    const int nslab = (int)((dup + 63) / 64);
+    const int64_t nchunk = (ddw + J.rcols - 1) / J.rcols;
+    const int64_t nrow_items = (int64_t)nslab * nchunk;
+    const int64_t ncol_items = (ddw + J.ccols - 1) / J.ccols;
+
+    for (int j = 0; j < niter; ++j) {
+      const T* cur = buf[j % 3];
+      const T* prv = buf[(j + 2) % 3];
+      T* w = buf[(j + 1) % 3];
+      const T scj = (T)sc_cur;
+      // ---- row pass: w = (1 (x) H_dw)(s_j u_j)
+      for (int64_t item = member; item < nrow_items; item += L) {
+        const int64_t slab = item / nchunk;
+        const int64_t jb = (item - slab * nchunk) * J.rcols;
+        const int64_t je = min(jb + (int64_t)J.rcols, ddw);
+        const int64_t iu = slab * 64 + wl;
+        const bool ok = iu < dup;
+        const int64_t iuc = ok ? iu : 0;
+        for (int64_t c = jb + wave; c < je; c += kWaves) {
+          const int64_t cu = __builtin_amdgcn_readfirstlane((int)c);
+          T s2 = T(0);
+          for (int k0 = 0; k0 < J.sdw; k0 += 8) {
+            uint32_t e[8];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) e[k] = J.hdw[cu * J.sdw + k0 + k];
+            T g[8];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) g[k] = cur[iuc + (int64_t)(e[k] & kColMask) * dup];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) s2 += amp[e[k] >> kAmpShift] * g[k];
+          }
+          if (ok) w[iu + cu * dup] = s2 * scj;
+        }
+      }
+      if (!lane_barrier(bar, gen, L, err)) return;
+      // ---- column pass: w += (H_d + H_up (x) 1)(s_j u_j); <v_j, w> partial
+      acc = 0.0;
+      for (int64_t g0 = member; g0 < ncol_items; g0 += L) {
+        const int64_t j0 = g0 * J.ccols;
+        const int nc = (int)min((int64_t)J.ccols, ddw - j0);
+        const int64_t n = (int64_t)nc * dup;
+        __syncthreads();
+        for (int64_t i = tid; i < n; i += kThreads) vs[i] = cur[j0 * dup + i] * scj;
+        __syncthreads();
+        for (int64_t i = tid; i < n; i += kThreads) {
+          const int cj32 = (int)i / (int)dup;           // n < 2^31 (LDS-sized)
+          const int64_t cj = cj32;
+          const int64_t iu = (int)i - cj32 * (int)dup;
+          const int64_t jj = j0 + cj;
+          const T x = vs[i];
+          T r = (eup[iu] + edw[jj] + Wt[J.pup[iu] * 8 + J.pdw[jj]]) * x;
+          for (int k0 = 0; k0 < J.sup; k0 += 8) {
+            uint32_t e[8];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) e[k] = J.hup[iu * J.sup + k0 + k];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) r += amp[e[k] >> kAmpShift] * vs[cj * dup + (e[k] & kColMask)];
+          }
+          const int64_t o = iu + jj * dup;
+          r += w[o];
+          w[o] = r;
+          acc += (double)x * (double)r;
+        }
+      }
+      {
+        const double s = block_sum(acc, red);
+        if (tid == 0) pa[member] = s;
+      }
+      if (!lane_barrier(bar, gen, L, err)) return;
+      double alpha = 0.0;
+      for (int m = 0; m < L; ++m) alpha += pa[m];
+      // ---- update: w -= alpha v_j + beta_j v_{j-1}; |w|^2 partial
+      const double ac = alpha * sc_cur, bc = beta_j * sc_prev;
+      acc = 0.0;
+      for (int64_t i = gbase; i < D; i += gstride) {
+        double r = (double)w[i] - ac * (double)cur[i];
+        if (j > 0) r -= bc * (double)prv[i];
+        const T t = (T)r;
+        w[i] = t;
+        acc += (double)t * (double)t;
+      }
+      {
+        const double s = block_sum(acc, red);
+        if (tid == 0) pn[member] = s;
+      }
+      if (!lane_barrier(bar, gen, L, err)) return;
+      nrm2 = 0.0;
+      for (int m = 0; m < L; ++m) nrm2 += pn[m];
+      const double bnext = sqrt(nrm2);
+      if (tid == 0) {
+        ta[j] = alpha;
+        tb[j + 1] = bnext;
+      }
+      __syncthreads();
+      steps = j + 1;
+      blast = bnext;
+      tnorm = fmax(tnorm, fabs(alpha) + beta_j + bnext);
+      const bool bd = !(bnext > 1e-12 * tnorm);
+      const bool check = bd || (j + 1) % check_every == 0 || j + 1 == niter;
+      if (check) {
+        if (wave == 0) {
+          const double e1 = wave_lowest(ta, tb, j + 1);
+          const double e0 = j > 0 ? wave_lowest(ta, tb, j) : e1 + 1.0;
+          if (tid == 0) {
+            red[0] = e1;
+            red[1] = e0;
+          }
+        }
+        __syncthreads();
+        E = red[0];
+        Eold = red[1];
+        __syncthreads();
+        const bool conv = j > 0 && fabs(E - Eold) <= tol * fmax(1.0, fabs(E));
+        if (conv || bd) {
+          status = 0;
+          bdown = bd ? 1 : 0;
+          break;
+        }
+      }
+      sc_prev = sc_cur;
+      sc_cur = bnext > 0.0 ? 1.0 / bnext : 0.0;
+      beta_j = bnext;
+    }
+    if (member == 0 && tid == 0) {
+      out[jid].e0 = E;
+      out[jid].beta_last = blast;
+      out[jid].iters = steps;
+      out[jid].status = status;
+      out[jid].breakdown = bdown;
+    }
+  }
+}
+
+}  // namespace
+
+size_t batch_workspace_bytes(const edx_sector* const* secs, int n, int vtype, int L);
+
+size_t batch_lds_bytes(int vtype, int64_t max_cols_elems, int niter) {
+  const size_t sz = vbytes(vtype);
+  return kAmpTable * sz + 64 * sz + kWaves * 8 + 2 * (size_t)(niter + 2) * 8 +
+         (size_t)max_cols_elems * sz + 64;
+}
+
+edx_status batch_run(const edx_sector* const* secs, int n, const edx_lanczos_opts* o,
+                     const int* ccols, const int* rcols, int L, void* ws, size_t ws_bytes,
+                     edx_batch_result* res, hipStream_t st, double* elapsed_ms) {
+  if (n <= 0) return EDX_OK;
+  const int vtype = o->vtype;
+  const size_t sz = vbytes(vtype);
+  int dev = 0;
+  EDX_HIP(hipGetDevice(&dev));
+  hipDeviceProp_t prop;
+  EDX_HIP(hipGetDeviceProperties(&prop, dev));
+  const int ncu = prop.multiProcessorCount;
+  if (ncu % 8 != 0 || (ncu / 8) % L != 0) {
+    set_error("batch: lane size must divide the CUs per XCD");
+    return EDX_E_INVALID;
+  }
+  const int per_xcd = ncu / 8;
+  const int lanes_per_xcd = per_xcd / L;
+  const int nlanes = 8 * lanes_per_xcd;
+  // job order: decreasing dimension
+  std::vector<int> order(n);
+  for (int i = 0; i < n; ++i) order[i] = i;
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int x, int y) { return secs[x]->dim > secs[y]->dim; });
+  int64_t dmax = 1, colmax = 1;
+  std::vector<BatchJob> jobs(n);
+  for (int k = 0; k < n; ++k) {
+    const edx_sector* s = secs[order[k]];
+    BatchJob& J = jobs[k];
+    J.hup = s->up.hop;
+    J.hdw = s->dw.hop;
+    J.eup = vtype == EDX_F32 ? (const void*)s->up.e32 : (const void*)s->up.e64;
+    J.edw = vtype == EDX_F32 ? (const void*)s->dw.e32 : (const void*)s->dw.e64;
+    J.pup = s->up.pat;
+    J.pdw = s->dw.pat;
+    J.amp = vtype == EDX_F32 ? (const void*)s->amp32 : (const void*)s->amp64;
+    J.W = vtype == EDX_F32 ? (const void*)s->w32 : (const void*)s->w64;
+    J.dup = s->dup;
+    J.ddw = s->ddw;
+    J.sup = s->up.wpad;
+    J.sdw = s->dw.wpad;
+    J.ccols = std::max(1, ccols ? ccols[order[k]] : 1);
+    J.rcols = std::max(1, rcols ? rcols[order[k]] : 32);
+    dmax = std::max(dmax, s->dim);
+    colmax = std::max(colmax, (int64_t)J.ccols * s->dup);
+  }
+  const size_t lds = batch_lds_bytes(vtype, colmax, o->niter);
+  if (lds > 160 * 1024) {
+    set_error("batch: columns per item do not fit in LDS");
+    return EDX_E_UNSUPPORTED;
+  }
+  // workspace: jobs | out | queue + bars + slots + err | partials | vectors
+  const size_t vstride = align_up((size_t)dmax * sz);
+  size_t off = 0;
+  auto take = [&](size_t bytes) { size_t o2 = off; off += align_up(bytes); return o2; };
+  const size_t o_jobs = take(sizeof(BatchJob) * n);
+  const size_t o_out = take(sizeof(BatchOut) * n);
+  const size_t o_ctl = take(sizeof(unsigned) * (2 + 2 * nlanes) + 64);
+  const size_t o_parts = take(sizeof(double) * 2 * L * nlanes);
+  const size_t o_vec = take(vstride * 3 * nlanes);
+  char* base = reinterpret_cast<char*>(align_up(reinterpret_cast<uintptr_t>(ws)));
+  if (off + (size_t)(base - (char*)ws) > ws_bytes) {
+    set_error("batch: workspace too small (need " + std::to_string(off + 256) + " bytes)");
+    return EDX_E_NOMEM;
+  }
+  BatchJob* d_jobs = reinterpret_cast<BatchJob*>(base + o_jobs);
+  BatchOut* d_out = reinterpret_cast<BatchOut*>(base + o_out);
+  unsigned* d_queue = reinterpret_cast<unsigned*>(base + o_ctl);
+  int* d_err = reinterpret_cast<int*>(d_queue + 1);
+  unsigned* d_bars = d_queue + 2;
+  int* d_slots = reinterpret_cast<int*>(d_bars + nlanes);
+  double* d_parts = reinterpret_cast<double*>(base + o_parts);
+  char* d_vec = base + o_vec;
+  EDX_HIP(hipMemcpyAsync(d_jobs, jobs.data(), sizeof(BatchJob) * n, hipMemcpyHostToDevice, st));
+  EDX_HIP(hipMemsetAsync(d_out, 0, sizeof(BatchOut) * n, st));
+  EDX_HIP(hipMemsetAsync(d_queue, 0, sizeof(unsigned) * (2 + 2 * nlanes), st));
+
+  int niter = o->niter;
+  double tol = o->tol;
+  int every = std::max(1, o->check_every);
+  uint64_t seed = o->seed;
+  int njobs = n;
+  void* args[] = {&d_jobs, &njobs, &d_out, &d_queue, &d_bars, &d_slots, &d_err, &d_parts, &d_vec,
+                  (void*)&vstride, &L, (void*)&lanes_per_xcd, &niter, &tol, &every, &seed};
+  const void* kern = vtype == EDX_F32 ? (const void*)k_batch<float> : (const void*)k_batch<double>;
+  EDX_HIP(hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  int per_cu = 0;
+  EDX_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, kThreads, lds));
+  if (per_cu < 1) {
+    set_error("batch: kernel does not fit on a CU");
+    return EDX_E_UNSUPPORTED;
+  }
+  hipEvent_t e0, e1;
+  EDX_HIP(hipEventCreate(&e0));
+  EDX_HIP(hipEventCreate(&e1));
+  EDX_HIP(hipEventRecord(e0, st));
+  EDX_HIP(hipLaunchCooperativeKernel(kern, dim3(ncu), dim3(kThreads), args, lds, st));
+  EDX_HIP(hipEventRecord(e1, st));
+  std::vector<BatchOut> hout(n);
+  int herr = 0;
+  EDX_HIP(hipMemcpyAsync(hout.data(), d_out, sizeof(BatchOut) * n, hipMemcpyDeviceToHost, st));
+  EDX_HIP(hipMemcpyAsync(&herr, d_err, sizeof(int), hipMemcpyDeviceToHost, st));
+  EDX_HIP(hipStreamSynchronize(st));
+  float ms = 0.f;
+  EDX_HIP(hipEventElapsedTime(&ms, e0, e1));
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (elapsed_ms) *elapsed_ms = ms;
+  for (int k = 0; k < n; ++k) {
+    edx_batch_result& r = res[order[k]];
+    r.e0 = hout[k].e0;
+    r.beta_last = hout[k].beta_last;
+    r.iters = hout[k].iters;
+    r.status = herr ? EDX_E_DEVICE : hout[k].status;
+    r.breakdown = hout[k].breakdown;
+  }
+  if (herr) {
+    set_error("batch: a lane barrier timed out");
+    return EDX_E_DEVICE;
+  }
+  return EDX_OK;
+}
+
+// Autotuner: for every distinct (D_up, D_dw) among the jobs, time a short run
+// (a few Lanczos steps, no stop rule) of up to one job per lane with each
+// candidate (columns per column item, columns per row item) and keep the
+// fastest; then time the whole batch shape with each lane size.
+edx_status batch_autotune(const edx_sector* const* secs, int n, const edx_lanczos_opts* o,
+                          void* ws, size_t ws_bytes, int* ccols, int* rcols, int* lane_wgs,
+                          hipStream_t st) {
+  edx_lanczos_opts q = *o;
+  q.niter = 6;
+  q.tol = 0.0;
+  q.check_every = 1000;
+  const size_t sz = vbytes(o->vtype);
+  std::vector<edx_batch_result> res(n);
+  // group jobs by shape
+  std::vector<std::pair<std::pair<int64_t, int64_t>, std::vector<int>>> classes;
+  for (int i = 0; i < n; ++i) {
+    const auto key = std::make_pair(secs[i]->dup, secs[i]->ddw);
+    auto it = std::find_if(classes.begin(), classes.end(),
+                           [&](const auto& c) { return c.first == key; });
+    if (it == classes.end()) {
+      classes.push_back({key, {i}});
+    } else {
+      it->second.push_back(i);
+    }
+  }
+  int L = 32;
+  for (auto& cl : classes) {
+    const int64_t dup = cl.first.first;
+    std::vector<const edx_sector*> sub;
+    for (int i : cl.second) {
+      if ((int)sub.size() >= 8) break;
+      sub.push_back(secs[i]);
+    }
+    double best = 1e300;
+    int bc = 1, br = 32;
+    for (int cc : {1, 2, 4, 8}) {
+      if (batch_lds_bytes(o->vtype, (int64_t)cc * dup, q.niter) > 150 * 1024) continue;
+      for (int rc : {16, 32, 64}) {
+        std::vector<int> c1(sub.size(), cc), r1(sub.size(), rc);
+        double ms = 0;
+        EDX_TRY(batch_run(sub.data(), (int)sub.size(), &q, c1.data(), r1.data(), L, ws, ws_bytes,
+                          res.data(), st, &ms));
+        if (ms < best) {
+          best = ms;
+          bc = cc;
+          br = rc;
+        }
+      }
+    }
+    (void)sz;
+    for (int i : cl.second) {
+      ccols[i] = bc;
+      rcols[i] = br;
+    }
+  }
+  double best = 1e300;
+  int bl = 32;
+  for (int l : {8, 16, 32}) {
+    if (batch_workspace_bytes(secs, n, o->vtype, l) > ws_bytes) continue;
+    double ms = 0;
+    EDX_TRY(batch_run(secs, n, &q, ccols, rcols, l, ws, ws_bytes, res.data(), st, &ms));
+    if (ms < best) {
+      best = ms;
+      bl = l;
+    }
+  }
+  *lane_wgs = bl;
+  return EDX_OK;
+}
+
+size_t batch_workspace_bytes(const edx_sector* const* secs, int n, int vtype, int L) {
+  int64_t dmax = 1;
+  for (int i = 0; i < n; ++i) dmax = std::max(dmax, secs[i]->dim);
+  int dev = 0, ncu = 256;
+  if (hipGetDevice(&dev) == hipSuccess) {
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, dev) == hipSuccess) ncu = prop.multiProcessorCount;
+  }
+  const int nlanes = std::max(1, ncu / std::max(1, L));
+  const size_t vstride = align_up((size_t)dmax * vbytes(vtype));
+  return align_up(sizeof(BatchJob) * n) + align_up(sizeof(BatchOut) * n) +
+         align_up(sizeof(unsigned) * (2 + 2 * nlanes) + 64) +
+         align_up(sizeof(double) * 2 * L * nlanes) + vstride * 3 * nlanes + 1024;
+}
+
+}  // namespace edx

@@ -158,6 +158,15 @@ edx_status k_green_cf(const double* ap, const double* bp, int np, double wp,
                       double e0, double beta, int lmats, double* g,
                       hipStream_t st);
 
+// ---- batch.hip
+edx_status batch_run(const edx_sector* const* secs, int n, const edx_lanczos_opts* o,
+                     const int* ccols, const int* rcols, int L, void* ws, size_t ws_bytes,
+                     edx_batch_result* res, hipStream_t st, double* elapsed_ms);
+size_t batch_workspace_bytes(const edx_sector* const* secs, int n, int vtype, int L);
+edx_status batch_autotune(const edx_sector* const* secs, int n, const edx_lanczos_opts* o,
+                          void* ws, size_t ws_bytes, int* ccols, int* rcols, int* lane_wgs,
+                          hipStream_t st);
+
 // ---- lanczos.cpp (host)
 double tridiag_lowest(const double* a, const double* b, int m, int k);
 void tridiag_vector(const double* a, const double* b, int m, double lam,

@@ -56,6 +56,17 @@ class LanczosReport(ctypes.Structure):
                 ("beta_last", ctypes.c_double), ("resid", ctypes.c_double)]
 
 
+class BatchResult(ctypes.Structure):
+    _fields_ = [("e0", ctypes.c_double), ("beta_last", ctypes.c_double),
+                ("iters", ctypes.c_int32), ("status", ctypes.c_int32),
+                ("breakdown", ctypes.c_int32), ("pad_", ctypes.c_int32)]
+
+
+class BatchTiles(ctypes.Structure):
+    _fields_ = [("lane_wgs", ctypes.c_int32), ("ccols", ctypes.POINTER(ctypes.c_int32)),
+                ("rcols", ctypes.POINTER(ctypes.c_int32))]
+
+
 class GfOpts(ctypes.Structure):
     _fields_ = [("ngf", ctypes.c_int32), ("lmats", ctypes.c_int32),
                 ("vtype", ctypes.c_int32), ("pad_", ctypes.c_int32),
@@ -87,6 +98,9 @@ _SIGS = {
     "edx_workspace_bytes": (ctypes.c_size_t, [_P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]),
     "edx_lanczos_ground_state": (ctypes.c_int, [_P, ctypes.POINTER(LanczosOpts), _P, ctypes.c_size_t, ctypes.POINTER(ctypes.c_double), _P, ctypes.POINTER(LanczosReport), _P]),
     "edx_green_cf": (ctypes.c_int, [_P, _P, ctypes.c_double, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(GfOpts), _P, ctypes.c_size_t, _P, ctypes.POINTER(GfReport), _P]),
+    "edx_batch_workspace_bytes": (ctypes.c_size_t, [_P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]),
+    "edx_batch_ground_state": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.POINTER(LanczosOpts), ctypes.POINTER(BatchTiles), _P, ctypes.c_size_t, ctypes.POINTER(BatchResult), ctypes.POINTER(ctypes.c_double), _P]),
+    "edx_batch_autotune": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.POINTER(LanczosOpts), _P, ctypes.c_size_t, _P, _P, ctypes.POINTER(ctypes.c_int32), _P]),
     "edx_status_str": (ctypes.c_char_p, [ctypes.c_int]),
     "edx_last_error": (ctypes.c_char_p, []),
 }
@@ -302,3 +316,49 @@ def green_cf(sector, psi0, e0, orb=0, spin=0, ngf=200, beta=200.0, lmats=4096, w
         n = rep.np if k.endswith("_p") else rep.nh
         r[k] = b[: n if k.startswith("alpha") else max(n - 1, 0)].copy()
     return g[0::2] + 1j * g[1::2], r
+
+
+def _handles(sectors):
+    return (ctypes.c_void_p * len(sectors))(*[s.handle for s in sectors])
+
+
+def batch_workspace_bytes(sectors, vtype="f64", lane_wgs=8):
+    return int(lib.edx_batch_workspace_bytes(_handles(sectors), len(sectors), _vt(vtype), lane_wgs))
+
+
+def batch_autotune(sectors, ws=None, stream=None, **kw):
+    """Project autotuner of the batched launch; returns a tiles dict."""
+    o = lanczos_opts(**kw)
+    n = len(sectors)
+    if ws is None:
+        ws = alloc_workspace(batch_workspace_bytes(sectors, o.vtype, 8))
+    cc = np.zeros(n, np.int32)
+    rc = np.zeros(n, np.int32)
+    lw = ctypes.c_int32()
+    _check(lib.edx_batch_autotune(_handles(sectors), n, ctypes.byref(o), _P(ws.data_ptr()), ws.numel(),
+                                  cc.ctypes.data_as(_P), rc.ctypes.data_as(_P), ctypes.byref(lw),
+                                  _stream_ptr(stream)))
+    return {"lane_wgs": lw.value, "ccols": cc, "rcols": rc}
+
+
+def batch_ground_state(sectors, tiles=None, ws=None, stream=None, **kw):
+    """Ground energies of many sectors in one persistent launch.
+    Returns (list of result dicts, kernel ms)."""
+    o = lanczos_opts(**kw)
+    n = len(sectors)
+    lw = tiles["lane_wgs"] if tiles else 32
+    if ws is None:
+        ws = alloc_workspace(batch_workspace_bytes(sectors, o.vtype, lw))
+    res = (BatchResult * n)()
+    ms = ctypes.c_double()
+    tp = None
+    if tiles:
+        cc = np.ascontiguousarray(tiles["ccols"], np.int32)
+        rc = np.ascontiguousarray(tiles["rcols"], np.int32)
+        t = BatchTiles(lw, cc.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                       rc.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)))
+        tp = ctypes.byref(t)
+    _check(lib.edx_batch_ground_state(_handles(sectors), n, ctypes.byref(o), tp, _P(ws.data_ptr()), ws.numel(),
+                                      res, ctypes.byref(ms), _stream_ptr(stream)))
+    out = [{f: getattr(r, f) for f, _ in BatchResult._fields_ if f != "pad_"} for r in res]
+    return out, ms.value

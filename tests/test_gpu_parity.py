@@ -263,3 +263,44 @@ def test_hv_headline_sector_sampled(edx, dtype):
     got = w.double().cpu().numpy()[rows]
     tol = (1e-13 if dtype == "f64" else 2e-6) * _hscale(m)
     assert np.abs(got - ref).max() <= tol
+
+
+def _batch_sectors(edx):
+    """Mixed sizes: Ns=8, 10 and 12 sectors of several bath sets."""
+    jobs = []
+    for k, ns in enumerate([8, 10, 12, 8, 10]):
+        m = inputs.make_model(1, ns - 1, 2.0, seed=4000 + k)
+        h = ns // 2
+        for (a, b) in [(h, h), (h - 1, h), (h + 1, h - 1), (h - 2, h)]:
+            jobs.append((m, (a, b), edx.build_sector(m, a, b)))
+    return jobs
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_batch_matches_plain_and_oracle(edx, dtype):
+    jobs = _batch_sectors(edx)
+    secs = [j[2] for j in jobs]
+    res, ms = edx.batch_ground_state(secs, vtype=dtype, niter=512, tol=1e-12, check_every=4, seed=9)
+    assert ms > 0
+    for (m, sec, S), r in zip(jobs, res):
+        assert r["status"] == 0, (sec, r)
+        e_plain = edx.lanczos_ground_state(S, want_psi=False, vtype=dtype, niter=512, tol=1e-12,
+                                           seed=9)[0]
+        if dtype == "f64":
+            assert abs(r["e0"] - e_plain) <= 1e-10 * abs(e_plain), (sec, r["e0"], e_plain)
+            if S.dim <= 6000:
+                E0 = spectra.dense_lowest(fock.explicit_hamiltonian(m, *sec))[0][0]
+                assert abs(r["e0"] - E0) <= 1e-10 * abs(E0)
+        else:
+            assert abs(r["e0"] - e_plain) <= 1e-5 * abs(e_plain), (sec, r["e0"], e_plain)
+
+
+def test_batch_autotune_and_lanes(edx):
+    jobs = _batch_sectors(edx)
+    secs = [j[2] for j in jobs]
+    tiles = edx.batch_autotune(secs, vtype="f64", niter=64, tol=1e-12)
+    assert tiles["lane_wgs"] in (8, 16, 32)
+    res, _ = edx.batch_ground_state(secs, tiles=tiles, vtype="f64", niter=512, tol=1e-12, seed=9)
+    ref, _ = edx.batch_ground_state(secs, vtype="f64", niter=512, tol=1e-12, seed=9)
+    for a, b in zip(res, ref):
+        assert a["status"] == 0 and abs(a["e0"] - b["e0"]) <= 1e-10 * abs(b["e0"])
