@@ -49,7 +49,8 @@ typedef enum {
   EDX_E_DEVICE = 3,      /* a HIP runtime call failed                       */
   EDX_E_NOCONV = 4,      /* Lanczos did not meet its stop rule in niter     */
   EDX_E_DEGENERATE = 5,  /* ground state gap below 1e-9 (flag, e0 is valid) */
-  EDX_E_UNSUPPORTED = 6  /* outside the implemented model space            */
+  EDX_E_UNSUPPORTED = 6, /* outside the implemented model space            */
+  EDX_PENDING = 7        /* edx_server_poll without wait: not finished yet  */
 } edx_status;
 
 /* storage type of v, w, Krylov vectors and psi0; scalars are always FP64 */
@@ -70,6 +71,7 @@ typedef struct {
 } edx_model;
 
 typedef struct edx_sector edx_sector;
+typedef struct edx_server edx_server;
 
 /* Build the tables of sector (nup, ndw) on the current device (Sec. 5 "Sector
  * construction", eq. nud_dimension): per spin the ascending string map, its
@@ -249,6 +251,53 @@ edx_status edx_batch_autotune(const edx_sector* const* sectors, int32_t n,
                               const edx_lanczos_opts* opts, void* ws,
                               size_t ws_bytes, int32_t* ccols, int32_t* rcols,
                               int32_t* lane_wgs, void* stream);
+
+/* ---- request server (continuous batching) ----
+ * Requests (a model and a sector) arrive at any time; each gets the ground
+ * state (edx_lanczos_ground_state, plain recurrence, psi0 by replay) and, if
+ * ngf > 0, G(i w_n) of orbital 0, spin up (edx_green_cf).  The server owns one
+ * device arena of hbm_budget bytes (allocated at creation; requests allocate
+ * nothing else) and max_slots worker threads with their own streams.  A
+ * request is admitted when a slot is free and its footprint (tables,
+ * workspaces, psi0) fits in the arena; smaller requests may pass one that does
+ * not fit yet, at most 8 times, then it blocks passing.  Admitted requests
+ * overlap on the device; each runs the plain path's kernels, so its result
+ * does not depend on what else runs.  Times are seconds of
+ * edx_server_clock(). */
+typedef struct {
+  size_t hbm_budget;          /* arena bytes                                  */
+  int32_t max_slots;          /* concurrent requests (1..64)                  */
+  int32_t vtype;              /* storage of the Krylov vectors                */
+  int32_t ngf;                /* Green's-function depth; 0 = ground state only */
+  int32_t lmats;              /* Matsubara frequencies                        */
+  double beta;                /* inverse temperature of the Matsubara grid    */
+  edx_lanczos_opts lanczos;   /* niter, tol, rtol, check_every, seed          */
+} edx_server_opts;
+
+typedef struct {
+  int64_t ticket;
+  int32_t status;             /* of the request's ground state / Green call   */
+  int32_t iters;
+  double e0, wp, wh;
+  double t_submit, t_start, t_done;
+  size_t footprint;           /* arena bytes the request held                 */
+} edx_server_result;
+
+void edx_server_default_opts(edx_server_opts* o);
+edx_status edx_server_create(const edx_server_opts* opts, edx_server** out);
+/* Queue a request (model arrays are copied); returns its ticket. */
+edx_status edx_server_submit(edx_server* s, const edx_model* model, int32_t nup,
+                             int32_t ndw, int64_t* ticket);
+/* Result of a finished request (then forgotten by the server).  wait = 0
+ * returns EDX_PENDING if it is not done.  g_out (nullable, host) receives
+ * 2*lmats doubles. */
+edx_status edx_server_poll(edx_server* s, int64_t ticket, int32_t wait,
+                           edx_server_result* res, double* g_out);
+edx_status edx_server_stats(edx_server* s, int32_t* pending, int32_t* running,
+                            int64_t* completed, size_t* largest_free);
+double edx_server_clock(void);
+/* Waits for admitted requests, drops queued ones, frees the arena. */
+void edx_server_destroy(edx_server* s);
 
 const char* edx_status_str(edx_status st);
 const char* edx_last_error(void);

@@ -307,6 +307,7 @@ const char* edx_status_str(edx_status st) {
     case EDX_E_NOCONV: return "EDX_E_NOCONV";
     case EDX_E_DEGENERATE: return "EDX_E_DEGENERATE";
     case EDX_E_UNSUPPORTED: return "EDX_E_UNSUPPORTED";
+    case EDX_PENDING: return "EDX_PENDING";
   }
   return "EDX_E_UNKNOWN";
 }

@@ -39,6 +39,16 @@ void set_error(const std::string& msg);
     if (s_ != EDX_OK) return s_;    \
   } while (0)
 
+// Device memory source of a sector's tables: hipMalloc/hipFree by default; the
+// request server hands out pieces of a request's reserved block instead, so
+// that no hipFree (which waits for the device) runs while other requests'
+// kernels are in flight.
+struct Allocator {
+  void* (*alloc)(void* ctx, size_t bytes) = nullptr;   // nullptr on failure
+  void (*release)(void* ctx, void* p) = nullptr;
+  void* ctx = nullptr;
+};
+
 // Host copy of the model (arrays owned).
 struct Model {
   int norb = 0, nbath = 0, ns = 0;
@@ -65,6 +75,7 @@ struct SpinTables {
 
 struct edx_sector {
   edx::Model model;
+  edx::Allocator alloc;      // where the device tables came from
   int nup = 0, ndw = 0;
   int64_t dup = 0, ddw = 0, dim = 0;
   int device = 0;
@@ -90,7 +101,9 @@ namespace edx {
 
 // ---- tables.hip
 edx_status build_sector_impl(const Model& m, int nup, int ndw, hipStream_t st,
-                             edx_sector** out);
+                             edx_sector** out, const Allocator* a = nullptr);
+// upper bound of the device bytes build_sector_impl takes from an allocator
+size_t sector_table_bytes(int ns, int nup, int ndw);
 void destroy_sector(edx_sector* s);
 
 // ---- hv.hip

@@ -414,7 +414,7 @@ edx_status ensure_neighbours(const edx_sector* gs, int spin, hipStream_t st) {
     if (g->nb[spin][k] || nn < 0 || nn > gs->model.ns) continue;
     edx_sector* t = nullptr;
     EDX_TRY(build_sector_impl(gs->model, spin == 0 ? nn : gs->nup, spin == 0 ? gs->ndw : nn, st,
-                              &t));
+                              &t, gs->alloc.alloc ? &gs->alloc : nullptr));
     g->nb[spin][k] = t;
   }
   return EDX_OK;

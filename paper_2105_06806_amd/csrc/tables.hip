@@ -120,6 +120,30 @@ __global__ void k_diag(const uint32_t* __restrict__ map, int64_t D, int norb,
   }
 }
 
+template <typename P>
+edx_status dalloc(edx_sector* S, P** p, size_t bytes) {
+  bytes = std::max<size_t>(bytes, 1);
+  if (S->alloc.alloc) {
+    *p = static_cast<P*>(S->alloc.alloc(S->alloc.ctx, bytes));
+    if (!*p) {
+      set_error("sector tables: allocator out of memory");
+      return EDX_E_NOMEM;
+    }
+    return EDX_OK;
+  }
+  EDX_HIP(hipMalloc(reinterpret_cast<void**>(p), bytes));
+  return EDX_OK;
+}
+
+void dfree(edx_sector* S, void* p) {
+  if (!p) return;
+  if (S->alloc.alloc) {
+    if (S->alloc.release) S->alloc.release(S->alloc.ctx, p);
+    return;
+  }
+  (void)hipFree(p);
+}
+
 int grid_for(int64_t n, int threads) {
   int64_t b = (n + threads - 1) / threads;
   return (int)std::max<int64_t>(1, std::min<int64_t>(b, 4096));
@@ -140,14 +164,14 @@ edx_status build_spin(edx_sector* S, SpinTables& T, int n, const double* d_elev,
   }
   T.D = D;
   const size_t total = size_t(1) << m.ns;
-  EDX_HIP(hipMalloc(&T.rank, total * sizeof(int32_t)));
-  EDX_HIP(hipMalloc(&T.map, D * sizeof(uint32_t)));
+  EDX_TRY(dalloc(S, &T.rank, total * sizeof(int32_t)));
+  EDX_TRY(dalloc(S, &T.map, D * sizeof(uint32_t)));
   k_rank_map<<<grid_for(total, 256), 256, 0, st>>>(m.ns, n, S->binom, T.rank, T.map);
   EDX_HIP(hipGetLastError());
 
   int* d_width = nullptr;
   unsigned long long* d_nnz = nullptr;
-  EDX_HIP(hipMalloc(&d_width, sizeof(int) + sizeof(unsigned long long) + 8));
+  EDX_TRY(dalloc(S, &d_width, sizeof(int) + sizeof(unsigned long long) + 8));
   d_nnz = reinterpret_cast<unsigned long long*>(reinterpret_cast<char*>(d_width) + 8);
   EDX_HIP(hipMemsetAsync(d_width, 0, 16, st));
   k_hop_count<<<grid_for(D, 256), 256, 0, st>>>(T.map, D, m.norb, m.nbath, d_width, d_nnz);
@@ -157,29 +181,29 @@ edx_status build_spin(edx_sector* S, SpinTables& T, int n, const double* d_elev,
   EDX_HIP(hipMemcpyAsync(&width, d_width, sizeof(int), hipMemcpyDeviceToHost, st));
   EDX_HIP(hipMemcpyAsync(&nnz, d_nnz, sizeof(nnz), hipMemcpyDeviceToHost, st));
   EDX_HIP(hipStreamSynchronize(st));
-  EDX_HIP(hipFree(d_width));
+  dfree(S, d_width);
   T.width = width;
   T.wpad = wpad_of(width);
   T.nnz = (int64_t)nnz;
-  EDX_HIP(hipMalloc(&T.hop, (size_t)D * T.wpad * sizeof(uint32_t)));
+  EDX_TRY(dalloc(S, &T.hop, (size_t)D * T.wpad * sizeof(uint32_t)));
   k_hop_fill<<<grid_for(D, 256), 256, 0, st>>>(T.map, T.rank, D, m.norb, m.nbath, T.wpad, T.hop);
   EDX_HIP(hipGetLastError());
-  EDX_HIP(hipMalloc(&T.e64, D * sizeof(double)));
-  EDX_HIP(hipMalloc(&T.e32, D * sizeof(float)));
-  EDX_HIP(hipMalloc(&T.pat, D));
+  EDX_TRY(dalloc(S, &T.e64, D * sizeof(double)));
+  EDX_TRY(dalloc(S, &T.e32, D * sizeof(float)));
+  EDX_TRY(dalloc(S, &T.pat, D));
   k_diag<<<grid_for(D, 256), 256, 0, st>>>(T.map, D, m.norb, m.ns, d_elev,
                                            m.Ust - m.Jh, T.e64, T.e32, T.pat);
   EDX_HIP(hipGetLastError());
   return EDX_OK;
 }
 
-void free_spin(SpinTables& T) {
-  (void)hipFree(T.map);
-  (void)hipFree(T.rank);
-  (void)hipFree(T.hop);
-  (void)hipFree(T.e64);
-  (void)hipFree(T.e32);
-  (void)hipFree(T.pat);
+void free_spin(edx_sector* S, SpinTables& T) {
+  dfree(S, T.map);
+  dfree(S, T.rank);
+  dfree(S, T.hop);
+  dfree(S, T.e64);
+  dfree(S, T.e32);
+  dfree(S, T.pat);
   T = SpinTables{};
 }
 
@@ -190,19 +214,37 @@ void destroy_sector(edx_sector* s) {
   for (int sp = 0; sp < 2; ++sp)
     for (int k = 0; k < 2; ++k) destroy_sector(s->nb[sp][k]);
   const bool shared = (s->dw.map == s->up.map);
-  free_spin(s->up);
-  if (!shared) free_spin(s->dw);
-  (void)hipFree(s->amp64);
-  (void)hipFree(s->amp32);
-  (void)hipFree(s->w64);
-  (void)hipFree(s->w32);
-  (void)hipFree(s->binom);
+  free_spin(s, s->up);
+  if (!shared) free_spin(s, s->dw);
+  dfree(s, s->amp64);
+  dfree(s, s->amp32);
+  dfree(s, s->w64);
+  dfree(s, s->w32);
+  dfree(s, s->binom);
   delete s;
 }
 
+size_t sector_table_bytes(int ns, int nup, int ndw) {
+  auto comb = [](int n, int k) -> int64_t {
+    if (k < 0 || k > n) return 0;
+    int64_t r = 1;
+    for (int i = 1; i <= k; ++i) r = r * (n - k + i) / i;
+    return r;
+  };
+  const size_t a = 256;   // per-allocation alignment slack
+  size_t b = 0;
+  for (int n : {nup, ndw}) {
+    const size_t D = (size_t)comb(ns, n);
+    b += ((size_t)4 << ns) + D * (4 + 24 * 4 + 8 + 4 + 1) + 6 * a;
+  }
+  b += (kMaxNs + 1) * (kMaxNs + 1) * 4 + 256 * 12 + 64 * 12 + 16 + 8 * kMaxNs + 8 * a;
+  return b;
+}
+
 edx_status build_sector_impl(const Model& m, int nup, int ndw, hipStream_t st,
-                             edx_sector** out) {
+                             edx_sector** out, const Allocator* alloc) {
   std::unique_ptr<edx_sector, void (*)(edx_sector*)> S(new edx_sector(), destroy_sector);
+  if (alloc) S->alloc = *alloc;
   S->model = m;
   S->nup = nup;
   S->ndw = ndw;
@@ -216,7 +258,7 @@ edx_status build_sector_impl(const Model& m, int nup, int ndw, hipStream_t st,
       binom[c * (kMaxNs + 1) + k] =
           binom[(c - 1) * (kMaxNs + 1) + k - 1] + (k <= c - 1 ? binom[(c - 1) * (kMaxNs + 1) + k] : 0);
   }
-  EDX_HIP(hipMalloc(&S->binom, binom.size() * sizeof(int32_t)));
+  EDX_TRY(dalloc(S.get(), &S->binom, binom.size() * sizeof(int32_t)));
   EDX_HIP(hipMemcpyAsync(S->binom, binom.data(), binom.size() * sizeof(int32_t),
                          hipMemcpyHostToDevice, st));
 
@@ -225,7 +267,7 @@ edx_status build_sector_impl(const Model& m, int nup, int ndw, hipStream_t st,
   for (int a = 0; a < m.norb; ++a) elev[a] = m.eps_imp[a] - m.xmu;
   for (int p = 0; p < m.norb * m.nbath; ++p) elev[m.norb + p] = m.eps_bath[p];
   double* d_elev = nullptr;
-  EDX_HIP(hipMalloc(&d_elev, m.ns * sizeof(double)));
+  EDX_TRY(dalloc(S.get(), &d_elev, m.ns * sizeof(double)));
   EDX_HIP(hipMemcpyAsync(d_elev, elev.data(), m.ns * sizeof(double),
                          hipMemcpyHostToDevice, st));
 
@@ -238,7 +280,7 @@ edx_status build_sector_impl(const Model& m, int nup, int ndw, hipStream_t st,
     }
   }
   if (rc != EDX_OK) {
-    (void)hipFree(d_elev);
+    dfree(S.get(), d_elev);
     return rc;
   }
   S->dup = S->up.D;
@@ -269,16 +311,16 @@ edx_status build_sector_impl(const Model& m, int nup, int ndw, hipStream_t st,
       W[pu * 8 + pd] = w;
       Wf[pu * 8 + pd] = (float)w;
     }
-  EDX_HIP(hipMalloc(&S->amp64, sizeof(amp)));
-  EDX_HIP(hipMalloc(&S->amp32, sizeof(ampf)));
-  EDX_HIP(hipMalloc(&S->w64, sizeof(W)));
-  EDX_HIP(hipMalloc(&S->w32, sizeof(Wf)));
+  EDX_TRY(dalloc(S.get(), &S->amp64, sizeof(amp)));
+  EDX_TRY(dalloc(S.get(), &S->amp32, sizeof(ampf)));
+  EDX_TRY(dalloc(S.get(), &S->w64, sizeof(W)));
+  EDX_TRY(dalloc(S.get(), &S->w32, sizeof(Wf)));
   EDX_HIP(hipMemcpyAsync(S->amp64, amp, sizeof(amp), hipMemcpyHostToDevice, st));
   EDX_HIP(hipMemcpyAsync(S->amp32, ampf, sizeof(ampf), hipMemcpyHostToDevice, st));
   EDX_HIP(hipMemcpyAsync(S->w64, W, sizeof(W), hipMemcpyHostToDevice, st));
   EDX_HIP(hipMemcpyAsync(S->w32, Wf, sizeof(Wf), hipMemcpyHostToDevice, st));
   EDX_HIP(hipStreamSynchronize(st));
-  EDX_HIP(hipFree(d_elev));
+  dfree(S.get(), d_elev);
   *out = S.release();
   return EDX_OK;
 }

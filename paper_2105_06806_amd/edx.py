@@ -16,7 +16,8 @@ import torch  # imported before libedx so both share one HIP runtime
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libedx.so")
 
-EDX_OK, EDX_E_INVALID, EDX_E_NOMEM, EDX_E_DEVICE, EDX_E_NOCONV, EDX_E_DEGENERATE, EDX_E_UNSUPPORTED = range(7)
+(EDX_OK, EDX_E_INVALID, EDX_E_NOMEM, EDX_E_DEVICE, EDX_E_NOCONV, EDX_E_DEGENERATE, EDX_E_UNSUPPORTED,
+ EDX_PENDING) = range(8)
 F64, F32 = 0, 1
 WS_LANCZOS, WS_GREEN, WS_LANCZOS_FULL = 0, 1, 2
 
@@ -67,6 +68,19 @@ class BatchTiles(ctypes.Structure):
                 ("rcols", ctypes.POINTER(ctypes.c_int32))]
 
 
+class ServerOpts(ctypes.Structure):
+    _fields_ = [("hbm_budget", ctypes.c_size_t), ("max_slots", ctypes.c_int32),
+                ("vtype", ctypes.c_int32), ("ngf", ctypes.c_int32), ("lmats", ctypes.c_int32),
+                ("beta", ctypes.c_double), ("lanczos", LanczosOpts)]
+
+
+class ServerResult(ctypes.Structure):
+    _fields_ = [("ticket", ctypes.c_int64), ("status", ctypes.c_int32), ("iters", ctypes.c_int32),
+                ("e0", ctypes.c_double), ("wp", ctypes.c_double), ("wh", ctypes.c_double),
+                ("t_submit", ctypes.c_double), ("t_start", ctypes.c_double),
+                ("t_done", ctypes.c_double), ("footprint", ctypes.c_size_t)]
+
+
 class GfOpts(ctypes.Structure):
     _fields_ = [("ngf", ctypes.c_int32), ("lmats", ctypes.c_int32),
                 ("vtype", ctypes.c_int32), ("pad_", ctypes.c_int32),
@@ -101,6 +115,13 @@ _SIGS = {
     "edx_batch_workspace_bytes": (ctypes.c_size_t, [_P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]),
     "edx_batch_ground_state": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.POINTER(LanczosOpts), ctypes.POINTER(BatchTiles), _P, ctypes.c_size_t, ctypes.POINTER(BatchResult), ctypes.POINTER(ctypes.c_double), _P]),
     "edx_batch_autotune": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.POINTER(LanczosOpts), _P, ctypes.c_size_t, _P, _P, ctypes.POINTER(ctypes.c_int32), _P]),
+    "edx_server_default_opts": (None, [ctypes.POINTER(ServerOpts)]),
+    "edx_server_create": (ctypes.c_int, [ctypes.POINTER(ServerOpts), ctypes.POINTER(_P)]),
+    "edx_server_submit": (ctypes.c_int, [_P, ctypes.POINTER(_Model), ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64)]),
+    "edx_server_poll": (ctypes.c_int, [_P, ctypes.c_int64, ctypes.c_int32, ctypes.POINTER(ServerResult), _P]),
+    "edx_server_stats": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_size_t)]),
+    "edx_server_clock": (ctypes.c_double, []),
+    "edx_server_destroy": (None, [_P]),
     "edx_status_str": (ctypes.c_char_p, [ctypes.c_int]),
     "edx_last_error": (ctypes.c_char_p, []),
 }
@@ -171,7 +192,7 @@ class Sector:
 
     def __del__(self):
         h = getattr(self, "handle", None)
-        if h:
+        if h and lib is not None:
             lib.edx_sector_destroy(h)
             self.handle = None
 
@@ -362,3 +383,61 @@ def batch_ground_state(sectors, tiles=None, ws=None, stream=None, **kw):
                                       res, ctypes.byref(ms), _stream_ptr(stream)))
     out = [{f: getattr(r, f) for f, _ in BatchResult._fields_ if f != "pad_"} for r in res]
     return out, ms.value
+
+
+class Server:
+    """Continuous-batching request server (edx_server_*)."""
+
+    def __init__(self, hbm_budget=8 << 30, max_slots=8, vtype="f32", ngf=200, lmats=1024, beta=200.0, **lanczos):
+        o = ServerOpts()
+        lib.edx_server_default_opts(ctypes.byref(o))
+        o.hbm_budget = int(hbm_budget)
+        o.max_slots = int(max_slots)
+        o.vtype = _vt(vtype)
+        o.ngf = int(ngf)
+        o.lmats = int(lmats)
+        o.beta = float(beta)
+        lo = lanczos_opts(vtype=o.vtype, **lanczos)
+        o.lanczos = lo
+        self.opts = o
+        h = _P()
+        _check(lib.edx_server_create(ctypes.byref(o), ctypes.byref(h)))
+        self.handle = h.value
+
+    def submit(self, model, nup, ndw):
+        ms, keep = _model_struct(model)
+        t = ctypes.c_int64()
+        _check(lib.edx_server_submit(self.handle, ctypes.byref(ms), int(nup), int(ndw), ctypes.byref(t)))
+        return t.value
+
+    def poll(self, ticket, wait=True):
+        """Result dict with "g" (complex array) or None if still pending."""
+        r = ServerResult()
+        g = np.zeros(2 * max(self.opts.lmats, 1), np.float64)
+        st = lib.edx_server_poll(self.handle, int(ticket), 1 if wait else 0, ctypes.byref(r), g.ctypes.data_as(_P))
+        if st == EDX_PENDING:
+            return None
+        _check(st)
+        out = {f: getattr(r, f) for f, _ in ServerResult._fields_}
+        out["g"] = g[0::2] + 1j * g[1::2]
+        return out
+
+    def stats(self):
+        p, r, c, f = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int64(), ctypes.c_size_t()
+        _check(lib.edx_server_stats(self.handle, ctypes.byref(p), ctypes.byref(r), ctypes.byref(c), ctypes.byref(f)))
+        return {"pending": p.value, "running": r.value, "completed": c.value, "largest_free": f.value}
+
+    @staticmethod
+    def clock():
+        return lib.edx_server_clock()
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib.edx_server_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -304,3 +304,48 @@ def test_batch_autotune_and_lanes(edx):
     ref, _ = edx.batch_ground_state(secs, vtype="f64", niter=512, tol=1e-12, seed=9)
     for a, b in zip(res, ref):
         assert a["status"] == 0 and abs(a["e0"] - b["e0"]) <= 1e-10 * abs(b["e0"])
+
+
+@pytest.mark.parametrize("vtype", ["f64", "f32"])
+def test_server_alone_equals_in_mix(edx, vtype):
+    """Requests served concurrently give bitwise the results of the same
+    request run alone through the plain API; small ones also match the oracle."""
+    import time
+    reqs = inputs.serve_requests(10, seed=77, ns_lo=8, ns_hi=12)
+    srv = edx.Server(hbm_budget=2 << 30, max_slots=4, vtype=vtype, ngf=60, lmats=128, beta=50.0,
+                     niter=300, tol=1e-12, seed=5, check_every=4)
+    tickets = []
+    for (m, a, b) in reqs:
+        tickets.append(srv.submit(m, a, b))
+        time.sleep(0.002)
+    out = [srv.poll(t) for t in tickets]
+    srv.close()
+    overlap = any(out[i]["t_start"] < out[i - 1]["t_done"] for i in range(1, len(out)))
+    assert overlap, "requests did not overlap"
+    for (m, a, b), r in zip(reqs, out):
+        assert r["status"] == 0, r
+        S = edx.build_sector(m, a, b)
+        e0, psi, rep, _ = edx.lanczos_ground_state(S, vtype=vtype, niter=300, tol=1e-12, seed=5,
+                                                   check_every=4)
+        G, gr = edx.green_cf(S, psi, e0, 0, 0, ngf=60, beta=50.0, lmats=128)
+        assert r["e0"] == e0
+        assert np.array_equal(r["g"], G)
+        if vtype == "f64" and S.dim <= 4000:
+            E0 = spectra.dense_lowest(fock.explicit_hamiltonian(m, a, b))[0][0]
+            assert abs(e0 - E0) <= 1e-10 * abs(E0)
+
+
+def test_server_admission_and_errors(edx):
+    srv = edx.Server(hbm_budget=64 << 20, max_slots=2, vtype="f32", ngf=0, niter=200, tol=1e-10)
+    m = inputs.make_model(1, 15, 2.0, seed=3)
+    with pytest.raises(edx.EdxError) as ei:          # Ns=16 half filling needs > 64 MB
+        srv.submit(m, 8, 8)
+    assert ei.value.status == edx.EDX_E_NOMEM
+    small = inputs.make_model(1, 7, 2.0, seed=3)
+    ts = [srv.submit(small, 4, 4) for _ in range(6)]
+    res = [srv.poll(t) for t in ts]
+    assert all(r["status"] == 0 for r in res)
+    assert len({r["e0"] for r in res}) == 1           # same request, same bits
+    st = srv.stats()
+    assert st["pending"] == 0 and st["running"] == 0
+    srv.close()
