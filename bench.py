@@ -1,23 +1,37 @@
 """Benchmark of the exact-diagonalisation hot path on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--quick]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--quick] [--full]
 
-A step is one storage-free H.v (Sec. 3, eq. Hbuild) on the half-filled Ns=16
-sector (Norb=1, Nbath=15, N_up=N_dw=8, D=12870^2=165,636,900) in FP32 storage,
-the sector the headline metric is quoted on.  The inputs (random bath from the
-seeded generator, random v) are resident in HBM before the timed region.
+Headline (the JSON `value`): a step is one storage-free H.v (Sec. 3, eq. Hbuild)
+on the half-filled Ns=16 sector (Norb=1, Nbath=15, N_up=N_dw=8,
+D=12870^2=165,636,900) with FP32 vectors, in the launch plan the project
+autotuner picks.  Inputs are resident in HBM before the timed region.
+value = algorithmic bytes / time, algorithmic bytes = D * (4 + 4): v read once,
+w written once (the ~0.5 MB of tables are not counted).
 
-value = algorithmic bytes / time, with algorithmic bytes = D * (4 + 4): v read
-once and w written once (the hopping and diagonal tables, ~0.5 MB, are not
-counted).  Also reported: the same in FP64, the dominant kernel's roofline
-figure, a full ground-state + Green's-function solve, and the CPU oracle on a
-bounded sample of rows.
+Also in the JSON line (one pass of every hot-path row, each on its workload):
+  f64            the same H.v with FP64 vectors
+  roofline       dominant kernel: algorithmic bytes / its mean launch time
+                 (HIP events on the launch stream), HBM peak 8 TB/s; traffic
+                 from the committed rocprofv3 counter summary if it matches the
+                 current kernel source, else null
+  cpu_baseline   the CPU oracle's row-by-row H.v on a bounded row sample
+  ns12           FP64 ground state + G(i w_n) (4096 frequencies, beta=200) of the
+                 Ns=12 half-filled sector, errors against the stored oracle values
+  ns15o3         precision mode on Norb=3, Ns=15 (D=41.4M): FP64 and FP32 vectors
+                 (plain / local / full re-orthogonalisation), E0 and G errors
+  batch          64 bath sets x 25 sectors (1600 ground states, Ns=10/12/14) in one
+                 persistent launch vs the same solves one after another
+  serve          Poisson streams of ground state + G requests at several rates:
+                 p50/p99 latency and solves/s vs one-at-a-time plain solves
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -27,6 +41,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+PROFILE_PMC = os.path.join(ROOT, "profiles", "hv_ns16_f32_counters.md")
+HV_SRC = os.path.join(ROOT, "paper_2105_06806_amd", "csrc", "hv.hip")
 
 
 def parse():
@@ -35,8 +51,12 @@ def parse():
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--quick", action="store_true", help="skip the solve and extras")
+    ap.add_argument("--quick", action="store_true", help="headline H.v only")
+    ap.add_argument("--full", action="store_true", help="full-size serving sweep")
     ap.add_argument("--tune-reps", type=int, default=3)
+    ap.add_argument("--plan", default=None,
+                    help="mode,col_cols,col_threads,row_rows,row_cols of the FP32 headline "
+                         "instead of autotuning (profiling runs)")
     return ap.parse_args()
 
 
@@ -49,6 +69,7 @@ def time_hv(edx, torch, S, v, w, steps, warmup):
         edx.hv(S, v, w)
     torch.cuda.synchronize()
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    torch.cuda.synchronize()
     t0 = time.perf_counter()
     for a, b in ev:
         a.record()
@@ -60,11 +81,25 @@ def time_hv(edx, torch, S, v, w, steps, warmup):
     return ms, wall
 
 
+def traffic_from_profile():
+    """HBM bytes per launch of the headline kernel from the committed counter
+    summary, if it was taken on the current kernel source."""
+    if not os.path.exists(PROFILE_PMC):
+        return None, None
+    txt = open(PROFILE_PMC).read()
+    mh = re.search(r"source_sha256:\s*([0-9a-f]{64})", txt)
+    mt = re.search(r"traffic_bytes_per_launch:\s*([0-9.eE+]+)", txt)
+    if not mh or not mt:
+        return None, None
+    cur = hashlib.sha256(open(HV_SRC, "rb").read()).hexdigest()
+    if cur != mh.group(1):
+        return None, "stale"
+    return float(mt.group(1)), "ok"
+
+
 def cpu_baseline(m, sec, elem_bytes, budget_s=15.0):
-    """The oracle's row-by-row H.v (second quantisation per sampled row) on a
-    bounded sample of the same sector, single thread."""
+    """The oracle's row-by-row H.v on a bounded sample of output rows, one core."""
     from oracle import fock
-    os.environ.setdefault("OMP_NUM_THREADS", "1")
     D = 12870 * 12870
     rng = np.random.default_rng(0)
     v = rng.uniform(-1, 1, size=D)
@@ -73,30 +108,168 @@ def cpu_baseline(m, sec, elem_bytes, budget_s=15.0):
     t0 = time.perf_counter()
     fock.hv_rows(m, *sec, v, rows)
     dt = time.perf_counter() - t0
-    # scale the sample to fill the budget
-    n2 = int(min(2_000_000, max(n, n * budget_s / max(dt, 1e-3) * 0.8)))
+    n2 = int(min(3_000_000, max(n, n * budget_s / max(dt, 1e-3) * 0.8)))
     rows = rng.choice(D, size=n2, replace=False)
     t0 = time.perf_counter()
     fock.hv_rows(m, *sec, v, rows)
     dt = time.perf_counter() - t0
-    rate = n2 / dt                        # output elements per second
-    return {"value": rate * elem_bytes / 1e9, "unit": "GB/s", "cores": 1, "kind": "oracle",
-            "sample": f"{n2} random output rows of the Ns=16 8/8 sector by row-by-row second "
-                      f"quantisation (fock.hv_rows), {dt:.1f} s; value = rows/s x {elem_bytes} B",
-            "rows_per_s": rate}
+    rate = n2 / dt
+    return {"value": round(rate * elem_bytes / 1e9, 4), "unit": "GB/s", "cores": 1, "kind": "oracle",
+            "sample": f"{n2} random output rows of the Ns=16 8/8 sector (FP64, second quantisation "
+                      f"per row), {dt:.1f} s; value = rows/s x {elem_bytes} B (the GPU's algorithmic "
+                      f"bytes per FP32 element)",
+            "rows_per_s": round(rate, 1), "full_hv_s_extrapolated": round(D / rate, 1)}
+
+
+def bench_ns12(edx):
+    from paper_2105_06806_amd import inputs
+    g = np.load(os.path.join(ROOT, "tests", "golden", "ns12.npz"))
+    m, [sec] = inputs.workload("ns12")
+    S = edx.build_sector(m, *sec)
+    import torch
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e0, psi, rep, _ = edx.lanczos_ground_state(S, niter=512, tol=1e-14, rtol=1e-10, seed=21)
+    t1 = time.perf_counter()
+    G, gr = edx.green_cf(S, psi, e0, 0, 0, ngf=200, beta=float(g["beta"]), lmats=int(g["lmats"]))
+    t2 = time.perf_counter()
+    return {"workload": "Norb=1 Ns=12 6/6 D=853776 FP64, G spin up, 4096 Matsubara, beta=200, depth 200",
+            "gs_s": round(t1 - t0, 4), "gf_s": round(t2 - t1, 4), "iters": rep["iters"],
+            "e0": e0, "e0_rel_err": abs(e0 - float(g["e0"])) / abs(float(g["e0"])),
+            "g_rel_err": float(np.abs(G - g["g"]).max() / np.abs(g["g"]).max()),
+            "wp_plus_wh": gr["wp"] + gr["wh"]}
+
+
+def bench_ns15o3(edx):
+    from paper_2105_06806_amd import inputs
+    path = os.path.join(ROOT, "tests", "golden", "ns15o3.npz")
+    g = np.load(path)
+    m, [sec] = inputs.workload("ns15o3")
+    S = edx.build_sector(m, *sec)
+    E = float(g["e0"])
+    lm, beta = int(g["lmats"]), float(g["beta"])
+    has_g = "g_up" in g
+    gref = g["g_up"] + g["g_dw"] if has_g else None
+    import torch
+    out = {"workload": "Norb=3 Nbath=4 Ns=15 7/7 D=41409225, U=3 J=0.5; G = G_up + G_dw of orbital 0 "
+                       "(the ground level is spin-swap degenerate), 1024 Matsubara, beta=200"}
+    runs = [("f64", 0), ("f32", 0), ("f32", 1), ("f32", 2)]
+    for vt, ro in runs:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        e0, psi, rep, st = edx.lanczos_ground_state(
+            S, vtype=vt, reorth=ro, niter=600 if vt == "f64" else 400,
+            tol=1e-14 if vt == "f64" else 1e-9, rtol=1e-10 if vt == "f64" else 0.0, seed=4,
+            allow=(edx.EDX_E_NOCONV, edx.EDX_E_DEGENERATE))
+        t1 = time.perf_counter()
+        r = {"gs_s": round(t1 - t0, 3), "iters": rep["iters"], "status": edx.status_str(st),
+             "e0_rel_err": abs(e0 - E) / abs(E)}
+        if has_g:
+            Gu, _ = edx.green_cf(S, psi, e0, 0, 0, ngf=200, beta=beta, lmats=lm)
+            Gd, _ = edx.green_cf(S, psi, e0, 0, 1, ngf=200, beta=beta, lmats=lm)
+            r["gf_s"] = round(time.perf_counter() - t1, 3)
+            r["g_rel_err"] = float(np.abs(Gu + Gd - gref).max() / np.abs(gref).max())
+        out[f"{vt}_reorth{ro}"] = r
+        del psi
+        torch.cuda.empty_cache()
+    return out
+
+
+def bench_batch(edx, torch):
+    from paper_2105_06806_amd import inputs
+    jobs = inputs.batch_jobs()
+    t0 = time.perf_counter()
+    secs = [edx.build_sector(m, a, b) for (_, m, a, b) in jobs]
+    torch.cuda.synchronize()
+    tb = time.perf_counter() - t0
+    kw = dict(vtype="f32", niter=512, tol=1e-9, check_every=4, seed=17)
+    ws = edx.alloc_workspace(edx.batch_workspace_bytes(secs, "f32", 8))
+    t0 = time.perf_counter()
+    tiles = edx.batch_autotune(secs, ws=ws, **kw)
+    tt = time.perf_counter() - t0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    res, kms = edx.batch_ground_state(secs, tiles=tiles, ws=ws, **kw)
+    tbatch = time.perf_counter() - t0
+    # the same solves one after another through the plain API
+    lw = max(edx.workspace_bytes(s, edx.WS_LANCZOS, "f32", 512) for s in secs)
+    lws = edx.alloc_workspace(lw)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plain = [edx.lanczos_ground_state(s, want_psi=False, ws=lws, check_every=4,
+                                      allow=(edx.EDX_E_NOCONV, edx.EDX_E_DEGENERATE), **{
+                                          k: v for k, v in kw.items() if k != "check_every"})[0]
+             for s in secs]
+    tseq = time.perf_counter() - t0
+    dev = [abs(r["e0"] - p) / abs(p) for r, p in zip(res, plain)]
+    ok = sum(1 for r in res if r["status"] == 0)
+    D = np.array([s.dim for s in secs], dtype=np.int64)
+    return {"workload": f"{len(secs)} ground states: 64 bath sets (Ns=10/12/14), N_up,N_dw in "
+                        f"[Ns/2-2, Ns/2+2], D {D.min()}..{D.max()}, sum D {D.sum()}, FP32 vectors, "
+                        f"tol 1e-9",
+            "solves_per_s": round(len(secs) / tbatch, 1), "batch_s": round(tbatch, 3),
+            "batch_kernel_ms": round(kms, 1), "plain_sequential_s": round(tseq, 3),
+            "plain_solves_per_s": round(len(secs) / tseq, 1), "speedup": round(tseq / tbatch, 2),
+            "converged": ok, "max_rel_dev_vs_plain": float(max(dev)), "build_s": round(tb, 2),
+            "autotune_s": round(tt, 2), "lane_wgs": tiles["lane_wgs"]}
+
+
+def bench_serve(edx, torch, full):
+    from paper_2105_06806_amd import inputs
+    ns_hi = 16 if full else 14
+    nreq = 1000 if full else 120
+    kw = dict(niter=512, tol=1e-9, seed=5, check_every=4)
+    gkw = dict(ngf=100, lmats=512, beta=200.0)
+    reqs = inputs.serve_requests(nreq, ns_lo=10, ns_hi=ns_hi)
+    # one-at-a-time plain solves of the same requests (ground state + G)
+    t0 = time.perf_counter()
+    lat_plain = []
+    for (m, a, b) in reqs[: max(20, nreq // 4)]:
+        ts = time.perf_counter()
+        S = edx.build_sector(m, a, b)
+        e0, psi, _, _ = edx.lanczos_ground_state(S, vtype="f32", allow=(edx.EDX_E_NOCONV,), **kw)
+        edx.green_cf(S, psi, e0, 0, 0, **gkw)
+        lat_plain.append(time.perf_counter() - ts)
+    cap = len(lat_plain) / (time.perf_counter() - t0)     # plain requests/s
+    out = {"workload": f"Poisson stream of ground state + G requests, Norb in {{1,2}}, Ns 10..{ns_hi}, "
+                       f"U in [1,6], FP32 vectors, G depth 100 on 512 frequencies",
+           "plain_solves_per_s": round(cap, 2), "plain_p50_s": round(float(np.median(lat_plain)), 4),
+           "rates": []}
+    srv = edx.Server(hbm_budget=64 << 30, max_slots=8, vtype="f32", **gkw, **kw)
+    for fac in ((0.5, 1.0, 1.5, 2.0) if not full else (0.25, 0.5, 0.75, 0.9, 1.0, 1.25, 2.0)):
+        rate = fac * cap
+        arr = inputs.poisson_arrivals(nreq, rate, seed=int(fac * 1000))
+        t_begin = edx.Server.clock()
+        tickets = []
+        for (m, a, b), ta in zip(reqs, arr):
+            wait = t_begin + ta - edx.Server.clock()
+            if wait > 0:
+                time.sleep(wait)
+            tickets.append(srv.submit(m, a, b))
+        res = [srv.poll(t) for t in tickets]
+        t_end = max(r["t_done"] for r in res)
+        lat = np.array([r["t_done"] - r["t_submit"] for r in res])
+        first = min(r["t_submit"] for r in res)
+        out["rates"].append({"offered_per_s": round(rate, 2), "x_plain_capacity": fac,
+                             "solves_per_s": round(len(res) / (t_end - first), 2),
+                             "p50_s": round(float(np.percentile(lat, 50)), 4),
+                             "p99_s": round(float(np.percentile(lat, 99)), 4),
+                             "ok": int(sum(r["status"] == 0 for r in res))})
+        log(f"serve x{fac}: {out['rates'][-1]}")
+    srv.close()
+    return out
 
 
 def main():
     a = parse()
     if a.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
-              "(see the design notes for how it would shard)", file=sys.stderr)
+              "(the design notes describe how the sector would shard)", file=sys.stderr)
         sys.exit(2)
     import torch
     from paper_2105_06806_amd import edx, inputs
 
-    dev = torch.cuda.get_device_properties(0)
-    log(f"device: {dev.name}")
+    log(f"device: {torch.cuda.get_device_properties(0).name}")
     m, [sec] = inputs.workload("ns16")
     S = edx.build_sector(m, *sec)
     D = S.dim
@@ -105,41 +278,63 @@ def main():
     for dt_name, tdt in (("f32", torch.float32), ("f64", torch.float64)):
         v = (torch.rand(D, dtype=tdt, device="cuda", generator=gen) * 2 - 1)
         w = torch.empty_like(v)
-        plan, tune_us = edx.autotune_hv(S, v, w, reps=a.tune_reps)
-        log(f"{dt_name}: autotuned plan {plan} ({tune_us:.1f} us)")
+        if a.plan and dt_name == "f32":
+            f = [int(x) for x in a.plan.split(",")]
+            edx.set_plan(S, dt_name, mode=f[0], col_cols=f[1], col_threads=f[2], row_rows=f[3],
+                         row_cols=f[4])
+            plan = edx.get_plan(S, dt_name)
+        else:
+            plan, tune_us = edx.autotune_hv(S, v, w, reps=a.tune_reps)
+            log(f"{dt_name}: autotuned plan {plan} ({tune_us:.1f} us)")
         ms, wall = time_hv(edx, torch, S, v, w, a.steps, a.warmup)
         esz = 4 if dt_name == "f32" else 8
         alg = D * 2 * esz
         res[dt_name] = {"ms_mean": float(ms.mean()), "ms_min": float(ms.min()), "wall_s": wall,
                         "plan": plan, "gbs": alg / (ms.mean() * 1e-3) / 1e9, "alg_bytes": alg}
-        log(f"{dt_name}: {ms.mean()*1e3:.1f} us/H.v, {res[dt_name]['gbs']:.0f} GB/s algorithmic")
+        log(f"{dt_name}: {ms.mean() * 1e3:.1f} us/H.v, {res[dt_name]['gbs']:.0f} GB/s algorithmic")
         del v, w
         torch.cuda.empty_cache()
-
+    r32 = res["f32"]
+    traffic, tstate = traffic_from_profile()
+    single = r32["plan"]["mode"] in (0, 2)
     out = {
         "metric": "H·v GB/s & %HBM peak at Ns=16; batched solves/s, p50/p99 vs plain",
-        "value": round(res["f32"]["gbs"], 1),
+        "value": round(r32["gbs"], 1),
         "unit": "GB/s",
         "n_gpus": 1,
         "steps": a.steps,
         "warmup": a.warmup,
-        "ms_per_step": round(res["f32"]["ms_mean"], 4),
+        "ms_per_step": round(r32["ms_mean"], 4),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": "H.v, Norb=1 Nbath=15 (Ns=16), sector 8/8, D=165636900, FP32 storage",
+        "config": {"workload": "H.v on the half-filled Ns=16 sector: Norb=1, Nbath=15, N_up=N_dw=8, "
+                               "D=165636900, FP32 vectors, symmetrised random bath, U=2",
                    "seed": inputs.SEED_BASE["ns16"]},
-        "hbm_frac": round(res["f32"]["gbs"] / HBM_PEAK_GBS, 4),
-        "hv_per_s": round(1e3 / res["f32"]["ms_mean"], 1),
+        "hv_per_s": round(1e3 / r32["ms_mean"], 1),
+        "plan_f32": r32["plan"],
         "f64": {"gbs": round(res["f64"]["gbs"], 1), "us": round(res["f64"]["ms_mean"] * 1e3, 1),
-                "hbm_frac": round(res["f64"]["gbs"] / HBM_PEAK_GBS, 4), "plan": res["f64"]["plan"]},
-        "plan_f32": res["f32"]["plan"],
-        "roofline": {"bound": "hbm", "achieved": round(res["f32"]["gbs"], 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(res["f32"]["gbs"] / HBM_PEAK_GBS, 4),
-                     "traffic": None},
+                "frac": round(res["f64"]["gbs"] / HBM_PEAK_GBS, 4), "plan": res["f64"]["plan"]},
+        "roofline": {"bound": "hbm", "achieved": round(r32["gbs"], 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(r32["gbs"] / HBM_PEAK_GBS, 4),
+                     "traffic": traffic if single else None,
+                     "kernel": "k_hv_col<float,8,8,fused>" if single else "k_hv_row + k_hv_col",
+                     "traffic_source": tstate},
     }
+    if not a.quick:
+        for name, fn in (("ns12", lambda: bench_ns12(edx)), ("ns15o3", lambda: bench_ns15o3(edx)),
+                         ("batch", lambda: bench_batch(edx, torch)),
+                         ("serve", lambda: bench_serve(edx, torch, a.full))):
+            t0 = time.perf_counter()
+            log(f"{name} ...")
+            try:
+                out[name] = fn()
+            except Exception as ex:      # report, keep the headline
+                out[name] = {"error": repr(ex)}
+            log(f"{name}: {time.perf_counter() - t0:.1f} s: {out[name]}")
+            torch.cuda.empty_cache()
     if not a.no_cpu:
         log("cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(m, sec, 8)

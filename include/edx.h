@@ -142,6 +142,8 @@ typedef struct {
   int32_t check_every;  /* host stop-rule check period in steps (>= 1)      */
   double tol;           /* stop if |E_j - E_{j-1}| <= tol * max(1, |E_j|)   */
   double rtol;          /* and (if > 0) beta_{j+1}|y_j| <= rtol * max(1,|E|) */
+                        /* with FP32 vectors both thresholds are floored at
+                           2 * 2^-23 * |T| (the energy resolution of FP32)    */
   uint64_t seed;        /* SplitMix64 seed of the start vector              */
 } edx_lanczos_opts;
 

@@ -317,7 +317,8 @@ __global__ __launch_bounds__(kThreads) void k_batch(
         E = red[0];
         Eold = red[1];
         __syncthreads();
-        const bool conv = j > 0 && fabs(E - Eold) <= tol * fmax(1.0, fabs(E));
+        const double floor32 = sizeof(T) == 4 ? 2.0 * 1.1920929e-7 * tnorm : 0.0;
+        const bool conv = j > 0 && fabs(E - Eold) <= fmax(tol * fmax(1.0, fabs(E)), floor32);
         if (conv || bd) {
           status = 0;
           bdown = bd ? 1 : 0;

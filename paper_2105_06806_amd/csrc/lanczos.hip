@@ -7,6 +7,7 @@
 // device); every `check_every` steps the host copies alpha/beta back and
 // applies the stop rule:
 //   |E_j - E_{j-1}| <= tol max(1, |E_j|)  [and beta_{j+1}|y_j| <= rtol max(1,|E|)],
+//   both thresholds floored at 2 eps_32 |T| when the vectors are FP32,
 //   or breakdown beta_{j+1} <= 1e-12 max_i(|alpha_i| + beta_i + beta_{i+1}),
 //   or j + 1 = niter.
 // E_j is the lowest eigenvalue of the tridiagonal T_j (Sturm bisection).  The
@@ -302,12 +303,16 @@ edx_status lanczos_ground_state_impl(const edx_sector* s, const edx_lanczos_opts
       tnorm = std::max(tnorm, std::fabs(ha[j]) + hb[j] + hb[j + 1]);
       E = tridiag_lowest(ha.data(), hb.data() + 1, j + 1, 0);
       const bool bd = !(hb[j + 1] > 1e-12 * tnorm);
-      bool ok = j > 0 && std::fabs(E - Eold) <= o->tol * std::max(1.0, std::fabs(E));
+      // FP32 vectors cannot resolve energies or residuals below ~eps_32 |T|:
+      // the thresholds are floored there (precision mode)
+      const double floor32 = vtype == EDX_F32 ? 2.0 * 1.1920929e-7 * tnorm : 0.0;
+      bool ok = j > 0 &&
+                std::fabs(E - Eold) <= std::max(o->tol * std::max(1.0, std::fabs(E)), floor32);
       if (ok && o->rtol > 0.0) {
         std::vector<double> yv(j + 1);
         tridiag_vector(ha.data(), hb.data() + 1, j + 1, E, yv.data());
         resid = hb[j + 1] * std::fabs(yv[j]);
-        ok = resid <= o->rtol * std::max(1.0, std::fabs(E));
+        ok = resid <= std::max(o->rtol * std::max(1.0, std::fabs(E)), floor32);
       }
       Eold = E;
       if (ok || bd || j + 1 == niter) {

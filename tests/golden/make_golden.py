@@ -8,9 +8,15 @@ ns12.npz   Ns=12 half filling (Norb=1, Nbath=11, sector 6/6, D=853,776):
            frequencies at beta=200 by the Krylov form at depth 200 from the
            oracle's ground vector, and the same at depth 400 (truncation check).
 ns15o3.npz Ns=15, Norb=3, Nbath=4, sector 7/7 (D=41,409,225): E0 and the
-           ground vector's G for orbital 0, spin up, with the Kronecker form of
-           H (the explicit matrix does not fit), ARPACK for the ground state,
-           plain Lanczos (depth 200) for G on 1024 Matsubara frequencies.
+           ground vector's G for orbital 0, spin up and spin down, with the
+           Kronecker form of H (the explicit matrix does not fit), ARPACK for
+           the ground state, plain Lanczos (depth 200) for G on 1024 Matsubara
+           frequencies.  The ground level of this sector is doubly degenerate
+           (the density-density interaction conserves every orbital's
+           occupation per spin, and exchanging the spins maps one such
+           occupation pattern onto another of the same sector), so G of one
+           spin depends on which ground vector is found; G_up + G_dw does not
+           (the two degenerate vectors lie in decoupled subspaces).
 Inputs come from the seeded generator (paper_2105_06806_amd.inputs, seeds
 2000 and 3000), which holds no arithmetic of the method.
 """
@@ -68,9 +74,10 @@ def ns15o3():
         Kt = kron.KronH(m, a, b)
         return Kt.matvec
 
-    G, wp, wh, (ap, bp), (ah, bh) = green.krylov_gf(m, *sec, psi, E, 0, 0, 200, z, factory)
-    np.savez(os.path.join(HERE, "ns15o3.npz"), e0=E, beta=beta, lmats=lmats, g=G, wp=wp, wh=wh,
-             alpha_p=ap, beta_p=bp, alpha_h=ah, beta_h=bh)
+    G, wp, wh, _, _ = green.krylov_gf(m, *sec, psi, E, 0, 0, 200, z, factory)
+    Gd, wpd, whd, _, _ = green.krylov_gf(m, *sec, psi, E, 0, 1, 200, z, factory)
+    np.savez(os.path.join(HERE, "ns15o3.npz"), e0=E, beta=beta, lmats=lmats, g_up=G, g_dw=Gd,
+             wp_up=wp, wh_up=wh, wp_dw=wpd, wh_dw=whd)
     print(f"ns15o3: G done ({time.time() - t0:.0f} s)")
 
 
