@@ -183,7 +183,7 @@ def bench_batch(edx, torch):
     torch.cuda.synchronize()
     tb = time.perf_counter() - t0
     kw = dict(vtype="f32", niter=512, tol=1e-9, check_every=4, seed=17)
-    ws = edx.alloc_workspace(edx.batch_workspace_bytes(secs, "f32", 8))
+    ws = edx.alloc_workspace(edx.batch_workspace_bytes(secs, "f32", 8))   # both phase layouts
     t0 = time.perf_counter()
     tiles = edx.batch_autotune(secs, ws=ws, **kw)
     tt = time.perf_counter() - t0
@@ -211,7 +211,8 @@ def bench_batch(edx, torch):
             "batch_kernel_ms": round(kms, 1), "plain_sequential_s": round(tseq, 3),
             "plain_solves_per_s": round(len(secs) / tseq, 1), "speedup": round(tseq / tbatch, 2),
             "converged": ok, "max_rel_dev_vs_plain": float(max(dev)), "build_s": round(tb, 2),
-            "autotune_s": round(tt, 2), "lane_wgs": tiles["lane_wgs"]}
+            "autotune_s": round(tt, 2), "lane_wgs": tiles["lane_wgs"],
+            "wide_min_dim": tiles["wide_min_dim"]}
 
 
 def bench_serve(edx, torch, full):

@@ -213,8 +213,9 @@ edx_status edx_green_cf(const edx_sector* gs, const void* psi0, double e0,
  * recurrence and stop rule of edx_lanczos_ground_state (psi0 is not formed).
  * The paper's counterpart is its parallelism over independent impurity
  * problems (Sec. 5 "Main", inequivalent sites).  One cooperative launch:
- * lanes of `lane_wgs` workgroups on one XCD each pull jobs (largest first)
- * from a device queue.  A job's status is EDX_OK, EDX_E_NOCONV (e0 is the last
+ * first the jobs with D >= wide_min_dim, one at a time on all workgroups;
+ * then lanes of `lane_wgs` workgroups on one XCD each pull the remaining jobs
+ * (largest first) from a device queue.  A job's status is EDX_OK, EDX_E_NOCONV (e0 is the last
  * estimate) or EDX_E_DEVICE (a lane barrier timed out). */
 typedef struct {
   double e0;
@@ -227,13 +228,18 @@ typedef struct {
 
 typedef struct {
   int32_t lane_wgs;       /* workgroups per lane: 8, 16 or 32             */
-  const int32_t* ccols;   /* [n] columns per column-pass item, or NULL (1) */
+  int32_t pad_;
+  const int32_t* ccols;   /* [n] columns per column-pass item (1..4), or NULL (1) */
   const int32_t* rcols;   /* [n] columns per row-pass item, or NULL (32)   */
+  int64_t wide_min_dim;   /* jobs with D >= this run first, one at a time on
+                             every workgroup; 0 = 2,000,000; < 0 = none    */
 } edx_batch_tiles;
 
-/* Device workspace bytes for n jobs with lanes of lane_wgs workgroups. */
+/* Device workspace bytes for n jobs with lanes of lane_wgs workgroups and the
+ * given wide threshold (0 = default, < 0 = none). */
 size_t edx_batch_workspace_bytes(const edx_sector* const* sectors, int32_t n,
-                                 int32_t vtype, int32_t lane_wgs);
+                                 int32_t vtype, int32_t lane_wgs,
+                                 int64_t wide_min_dim);
 
 /* Ground energies of n sectors (host array of handles).  opts: niter, vtype,
  * tol, check_every and seed are used (reorth must be 0).  tiles may be NULL
@@ -246,13 +252,15 @@ edx_status edx_batch_ground_state(const edx_sector* const* sectors, int32_t n,
                                   double* elapsed_ms, void* stream);
 
 /* Project autotuner for the batched launch: per distinct (D_up, D_dw) it
- * times short runs of each (ccols, rcols) candidate, then each lane size;
- * writes ccols[n], rcols[n] (host) and *lane_wgs.  ws must be sized for
- * lane_wgs = 8. */
+ * times short runs of each (ccols, rcols) candidate, then each lane size with
+ * and without the wide phase; writes ccols[n], rcols[n] (host), *lane_wgs and
+ * *wide_min_dim.  ws must hold edx_batch_workspace_bytes(..., 8, -1) and
+ * (..., 8, 0) bytes. */
 edx_status edx_batch_autotune(const edx_sector* const* sectors, int32_t n,
                               const edx_lanczos_opts* opts, void* ws,
                               size_t ws_bytes, int32_t* ccols, int32_t* rcols,
-                              int32_t* lane_wgs, void* stream);
+                              int32_t* lane_wgs, int64_t* wide_min_dim,
+                              void* stream);
 
 /* ---- request server (continuous batching) ----
  * Requests (a model and a sector) arrive at any time; each gets the ground

@@ -259,11 +259,11 @@ edx_status edx_green_cf(const edx_sector* gs, const void* psi0, double e0, int32
 }
 
 size_t edx_batch_workspace_bytes(const edx_sector* const* sectors, int32_t n, int32_t vtype,
-                                 int32_t lane_wgs) {
+                                 int32_t lane_wgs, int64_t wide_min_dim) {
   if (!sectors || n < 1 || !valid_vtype(vtype) || lane_wgs < 1) return 0;
   for (int i = 0; i < n; ++i)
     if (!sectors[i]) return 0;
-  return batch_workspace_bytes(sectors, n, vtype, lane_wgs);
+  return batch_workspace_bytes(sectors, n, vtype, lane_wgs, wide_min_dim);
 }
 
 static edx_status check_batch(const edx_sector* const* sectors, int32_t n,
@@ -285,16 +285,18 @@ edx_status edx_batch_ground_state(const edx_sector* const* sectors, int32_t n,
   const int L = tiles ? tiles->lane_wgs : 32;
   if (L != 8 && L != 16 && L != 32) return invalid("lane_wgs must be 8, 16 or 32");
   return batch_run(sectors, n, opts, tiles ? tiles->ccols : nullptr,
-                   tiles ? tiles->rcols : nullptr, L, ws, ws_bytes, results,
-                   static_cast<hipStream_t>(stream), elapsed_ms);
+                   tiles ? tiles->rcols : nullptr, L, tiles ? tiles->wide_min_dim : 0, ws,
+                   ws_bytes, results, static_cast<hipStream_t>(stream), elapsed_ms);
 }
 
 edx_status edx_batch_autotune(const edx_sector* const* sectors, int32_t n,
                               const edx_lanczos_opts* opts, void* ws, size_t ws_bytes,
-                              int32_t* ccols, int32_t* rcols, int32_t* lane_wgs, void* stream) {
+                              int32_t* ccols, int32_t* rcols, int32_t* lane_wgs,
+                              int64_t* wide_min_dim, void* stream) {
   EDX_TRY(check_batch(sectors, n, opts));
-  if (!ws || !ccols || !rcols || !lane_wgs) return invalid("ws and outputs must be non-NULL");
-  return batch_autotune(sectors, n, opts, ws, ws_bytes, ccols, rcols, lane_wgs,
+  if (!ws || !ccols || !rcols || !lane_wgs || !wide_min_dim)
+    return invalid("ws and outputs must be non-NULL");
+  return batch_autotune(sectors, n, opts, ws, ws_bytes, ccols, rcols, lane_wgs, wide_min_dim,
                         static_cast<hipStream_t>(stream));
 }
 

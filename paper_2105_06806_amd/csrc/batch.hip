@@ -55,6 +55,7 @@ namespace {
 constexpr int kThreads = 1024;
 constexpr int kWaves = kThreads / 64;
 constexpr long long kSpinLimit = 1ll << 26;
+constexpr int kColMaxB = 4;   // columns per column-pass item held in registers
 
 __device__ __forceinline__ uint64_t splitmix64(uint64_t seed, uint64_t k) {
   uint64_t z = seed + (k + 1) * 0x9E3779B97F4A7C15ull;
@@ -136,13 +137,244 @@ __device__ double wave_lowest(const double* a, const double* b, int m) {
   return 0.5 * (lo + hi);
 }
 
+// One lane's view: its barrier, partial-sum slots and vectors, and how its
+// members share the row-pass items (a lane spanning all XCDs gives every XCD
+// one contiguous range of slabs so each slab stays in one L2).
+struct LaneCtx {
+  unsigned* bar;
+  int* err;
+  double* pa;        // alpha partials [L]
+  double* pn;        // norm partials [L]
+  char* lv;          // 3 vectors
+  size_t vstride;
+  int L, member;
+  bool xsplit;
+  int xcd, in_xcd, per_xcd;
+};
+
+// The whole Lanczos recurrence of one job on one lane; returns false if a
+// barrier failed (then every member returns).
+template <typename T>
+__device__ bool solve_job(const BatchJob& J, int jid, BatchOut* __restrict__ out, LaneCtx& C,
+                          unsigned& gen, int niter, double tol, int check_every, uint64_t seed,
+                          T* amp, T* Wt, double* red, double* ta, double* tb, T* vs) {
+  const int tid = threadIdx.x;
+  const int wave = tid >> 6;
+  const int wl = tid & 63;
+  const T* __restrict__ eup = static_cast<const T*>(J.eup);
+  const T* __restrict__ edw = static_cast<const T*>(J.edw);
+  __syncthreads();
+  for (int i = tid; i < kAmpTable; i += kThreads) amp[i] = static_cast<const T*>(J.amp)[i];
+  for (int i = tid; i < 64; i += kThreads) Wt[i] = static_cast<const T*>(J.W)[i];
+  const int64_t dup = J.dup, ddw = J.ddw, D = dup * ddw;
+  const int L = C.L;
+  const int64_t gstride = (int64_t)L * kThreads;
+  const int64_t gbase = (int64_t)C.member * kThreads + tid;
+  T* buf[3] = {reinterpret_cast<T*>(C.lv), reinterpret_cast<T*>(C.lv + C.vstride),
+               reinterpret_cast<T*>(C.lv + 2 * C.vstride)};
+
+  // start vector u_0 and |u_0|^2
+  double acc = 0.0;
+  for (int64_t i = gbase; i < D; i += gstride) {
+    const uint64_t z = splitmix64(seed, (uint64_t)i);
+    const T t = (T)((double)(z >> 11) * 0x1.0p-53 * 2.0 - 1.0);
+    buf[0][i] = t;
+    acc += (double)t * (double)t;
+  }
+  {
+    const double s = block_sum(acc, red);
+    if (tid == 0) C.pn[C.member] = s;
+  }
+  if (!lane_barrier(C.bar, gen, L, C.err)) return false;
+  double nrm2 = 0.0;
+  for (int m = 0; m < L; ++m) nrm2 += C.pn[m];
+  double sc_cur = 1.0 / sqrt(nrm2), sc_prev = 0.0, beta_j = 0.0;
+  if (tid == 0) tb[0] = 0.0;
+  __syncthreads();
+  int steps = 0, status = 4, bdown = 0;
+  double E = 0.0, Eold = 0.0, tnorm = 0.0, blast = 0.0;
+  const int64_t nslab = (dup + 63) / 64;
+  const int64_t nchunk = (ddw + J.rcols - 1) / J.rcols;
+  const int64_t nrow_items = nslab * nchunk;
+  const int64_t ncol_items = (ddw + J.ccols - 1) / J.ccols;
+  int64_t rbeg, rend, rstep;
+  if (C.xsplit) {
+    const int64_t q = (nrow_items + 7) / 8;
+    rbeg = (int64_t)C.xcd * q + C.in_xcd;
+    rend = min(nrow_items, (int64_t)(C.xcd + 1) * q);
+    rstep = C.per_xcd;
+  } else {
+    rbeg = C.member;
+    rend = nrow_items;
+    rstep = L;
+  }
+
+  for (int j = 0; j < niter; ++j) {
+    const T* cur = buf[j % 3];
+    const T* prv = buf[(j + 2) % 3];
+    T* w = buf[(j + 1) % 3];
+    const T scj = (T)sc_cur;
+    // ---- row pass: w = (1 (x) H_dw)(s_j u_j); a wave covers 64 rows of a column
+    for (int64_t item = rbeg; item < rend; item += rstep) {
+      const int64_t slab = item / nchunk;
+      const int64_t jb = (item - slab * nchunk) * J.rcols;
+      const int64_t je = min(jb + (int64_t)J.rcols, ddw);
+      const int64_t iu = slab * 64 + wl;
+      const bool ok = iu < dup;
+      const int64_t iuc = ok ? iu : 0;
+      for (int64_t c = jb + wave; c < je; c += kWaves) {
+        const int64_t cu = __builtin_amdgcn_readfirstlane((int)c);
+        T s2 = T(0);
+        for (int k0 = 0; k0 < J.sdw; k0 += 8) {
+          uint32_t e[8];
+#pragma unroll
+          for (int k = 0; k < 8; ++k) e[k] = J.hdw[cu * J.sdw + k0 + k];
+          T g[8];
+#pragma unroll
+          for (int k = 0; k < 8; ++k) g[k] = cur[iuc + (int64_t)(e[k] & kColMask) * dup];
+#pragma unroll
+          for (int k = 0; k < 8; ++k) s2 += amp[e[k] >> kAmpShift] * g[k];
+        }
+        if (ok) __builtin_nontemporal_store(s2 * scj, w + iu + cu * dup);
+      }
+    }
+    if (!lane_barrier(C.bar, gen, L, C.err)) return false;
+    // ---- column pass: w += (H_d + H_up (x) 1)(s_j u_j); <v_j, w> partial.
+    // A thread owns a row and reads its hop list once for all staged columns.
+    acc = 0.0;
+    for (int64_t g0 = C.member; g0 < ncol_items; g0 += L) {
+      const int64_t j0 = g0 * J.ccols;
+      const int nc = (int)min((int64_t)J.ccols, ddw - j0);
+      const int64_t n = (int64_t)nc * dup;
+      __syncthreads();
+      {
+        const T* src = cur + j0 * dup;
+        int64_t i = tid;
+        for (; i + 3 * kThreads < n; i += 4 * kThreads) {
+          const T x0 = src[i], x1 = src[i + kThreads], x2 = src[i + 2 * kThreads],
+                  x3 = src[i + 3 * kThreads];
+          vs[i] = x0 * scj;
+          vs[i + kThreads] = x1 * scj;
+          vs[i + 2 * kThreads] = x2 * scj;
+          vs[i + 3 * kThreads] = x3 * scj;
+        }
+        for (; i < n; i += kThreads) vs[i] = src[i] * scj;
+      }
+      __syncthreads();
+      for (int64_t iu = tid; iu < dup; iu += kThreads) {
+        T wold[kColMaxB];
+#pragma unroll
+        for (int c = 0; c < kColMaxB; ++c) wold[c] = c < nc ? w[iu + (j0 + c) * dup] : T(0);
+        const T eu = eup[iu];
+        const int pu = J.pup[iu] * 8;
+        T a4[kColMaxB];
+#pragma unroll
+        for (int c = 0; c < kColMaxB; ++c) a4[c] = T(0);
+        for (int k0 = 0; k0 < J.sup; k0 += 8) {
+          uint32_t e[8];
+          const uint4* ep = reinterpret_cast<const uint4*>(J.hup + iu * J.sup + k0);
+          const uint4 x = ep[0], y = ep[1];
+          e[0] = x.x; e[1] = x.y; e[2] = x.z; e[3] = x.w;
+          e[4] = y.x; e[5] = y.y; e[6] = y.z; e[7] = y.w;
+#pragma unroll
+          for (int k = 0; k < 8; ++k) {
+            const T am = amp[e[k] >> kAmpShift];
+            const int64_t col = e[k] & kColMask;
+#pragma unroll
+            for (int c = 0; c < kColMaxB; ++c)
+              if (c < nc) a4[c] += am * vs[c * dup + col];
+          }
+        }
+#pragma unroll
+        for (int c = 0; c < kColMaxB; ++c) {
+          if (c >= nc) break;
+          const int64_t jj = j0 + c;
+          const T xv = vs[c * dup + iu];
+          const T r = a4[c] + (eu + edw[jj] + Wt[pu + J.pdw[jj]]) * xv + wold[c];
+          w[iu + jj * dup] = r;
+          acc += (double)xv * (double)r;
+        }
+      }
+    }
+    {
+      const double s = block_sum(acc, red);
+      if (tid == 0) C.pa[C.member] = s;
+    }
+    if (!lane_barrier(C.bar, gen, L, C.err)) return false;
+    double alpha = 0.0;
+    for (int m = 0; m < L; ++m) alpha += C.pa[m];
+    // ---- update: w -= alpha v_j + beta_j v_{j-1}; |w|^2 partial
+    const double ac = alpha * sc_cur, bc = beta_j * sc_prev;
+    acc = 0.0;
+    for (int64_t i = gbase; i < D; i += gstride) {
+      double r = (double)w[i] - ac * (double)cur[i];
+      if (j > 0) r -= bc * (double)prv[i];
+      const T t = (T)r;
+      w[i] = t;
+      acc += (double)t * (double)t;
+    }
+    {
+      const double s = block_sum(acc, red);
+      if (tid == 0) C.pn[C.member] = s;
+    }
+    if (!lane_barrier(C.bar, gen, L, C.err)) return false;
+    nrm2 = 0.0;
+    for (int m = 0; m < L; ++m) nrm2 += C.pn[m];
+    const double bnext = sqrt(nrm2);
+    if (tid == 0) {
+      ta[j] = alpha;
+      tb[j + 1] = bnext;
+    }
+    __syncthreads();
+    steps = j + 1;
+    blast = bnext;
+    tnorm = fmax(tnorm, fabs(alpha) + beta_j + bnext);
+    const bool bd = !(bnext > 1e-12 * tnorm);
+    const bool check = bd || (j + 1) % check_every == 0 || j + 1 == niter;
+    if (check) {
+      if (wave == 0) {
+        const double e1 = wave_lowest(ta, tb, j + 1);
+        const double e0 = j > 0 ? wave_lowest(ta, tb, j) : e1 + 1.0;
+        if (tid == 0) {
+          red[0] = e1;
+          red[1] = e0;
+        }
+      }
+      __syncthreads();
+      E = red[0];
+      Eold = red[1];
+      __syncthreads();
+      const double floor32 = sizeof(T) == 4 ? 2.0 * 1.1920929e-7 * tnorm : 0.0;
+      const bool conv = j > 0 && fabs(E - Eold) <= fmax(tol * fmax(1.0, fabs(E)), floor32);
+      if (conv || bd) {
+        status = 0;
+        bdown = bd ? 1 : 0;
+        break;
+      }
+    }
+    sc_prev = sc_cur;
+    sc_cur = bnext > 0.0 ? 1.0 / bnext : 0.0;
+    beta_j = bnext;
+  }
+  if (C.member == 0 && tid == 0) {
+    out[jid].e0 = E;
+    out[jid].beta_last = blast;
+    out[jid].iters = steps;
+    out[jid].status = status;
+    out[jid].breakdown = bdown;
+  }
+  return true;
+}
+
+// Phase 1: jobs [0, nwide) one at a time on a lane of every workgroup.
+// Phase 2: jobs [nwide, njobs) on lanes of L workgroups inside one XCD.
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_batch(
-    const BatchJob* __restrict__ jobs, int njobs, BatchOut* __restrict__ out,
-    unsigned* __restrict__ queue, unsigned* __restrict__ bars, int* __restrict__ slots,
-    int* __restrict__ err, double* __restrict__ parts, char* __restrict__ vecs,
-    size_t vstride, int L, int lanes_per_xcd, int niter, double tol, int check_every,
-    uint64_t seed) {
+    const BatchJob* __restrict__ jobs, int nwide, int njobs, BatchOut* __restrict__ out,
+    unsigned* __restrict__ ctl, int* __restrict__ slots, int* __restrict__ err,
+    double* __restrict__ parts, char* __restrict__ wide_vecs, size_t wide_vstride,
+    char* __restrict__ vecs, size_t vstride, int L, int lanes_per_xcd, int niter, double tol,
+    int check_every, uint64_t seed) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T* amp = reinterpret_cast<T*>(smem_raw);
   T* Wt = amp + kAmpTable;
@@ -150,198 +382,62 @@ __global__ __launch_bounds__(kThreads) void k_batch(
   double* ta = red + kWaves;           // alpha[0..niter]
   double* tb = ta + (niter + 2);       // beta[0..niter+1]; tb[j] couples j-1 and j
   __shared__ int s_job;
-  __shared__ int s_stop;
   T* vs = reinterpret_cast<T*>(tb + (niter + 2));
-
   const int b = blockIdx.x;
-  const int xcd = b & 7;
-  const int in_xcd = b >> 3;
-  const int lane = xcd * lanes_per_xcd + in_xcd / L;
-  const int member = in_xcd % L;
-  unsigned* bar = bars + lane;
-  double* pa = parts + (size_t)lane * 2 * L;     // alpha partials
-  double* pn = pa + L;                           // norm partials
-  char* lv = vecs + (size_t)lane * 3 * vstride;
-  unsigned gen = 0;
   const int tid = threadIdx.x;
-  const int wave = tid >> 6;
-  const int wl = tid & 63;
-
-  for (;;) {
-    if (member == 0 && tid == 0) slots[lane] = (int)atomicAdd(queue, 1u);
-    if (!lane_barrier(bar, gen, L, err)) return;
-    if (tid == 0) s_job = __hip_atomic_load(slots + lane, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    __syncthreads();
-    const int jid = s_job;
-    if (jid >= njobs) return;
-    const BatchJob J = jobs[jid];
-    const T* __restrict__ eup = static_cast<const T*>(J.eup);
-    const T* __restrict__ edw = static_cast<const T*>(J.edw);
-    for (int i = tid; i < kAmpTable; i += kThreads) amp[i] = static_cast<const T*>(J.amp)[i];
-    for (int i = tid; i < 64; i += kThreads) Wt[i] = static_cast<const T*>(J.W)[i];
-    const int64_t dup = J.dup, ddw = J.ddw, D = dup * ddw;
-    const int64_t gstride = (int64_t)L * kThreads;
-    const int64_t gbase = (int64_t)member * kThreads + tid;
-    T* buf[3] = {reinterpret_cast<T*>(lv), reinterpret_cast<T*>(lv + vstride),
-                 reinterpret_cast<T*>(lv + 2 * vstride)};
-
-    // start vector u_0 and |u_0|^2
-    double acc = 0.0;
-    for (int64_t i = gbase; i < D; i += gstride) {
-      const uint64_t z = splitmix64(seed, (uint64_t)i);
-      const T t = (T)((double)(z >> 11) * 0x1.0p-53 * 2.0 - 1.0);
-      buf[0][i] = t;
-      acc += (double)t * (double)t;
-    }
-    {
-      const double s = block_sum(acc, red);
-      if (tid == 0) pn[member] = s;
-    }
-    if (!lane_barrier(bar, gen, L, err)) return;
-    double nrm2 = 0.0;
-    for (int m = 0; m < L; ++m) nrm2 += pn[m];
-    double sc_cur = 1.0 / sqrt(nrm2), sc_prev = 0.0, beta_j = 0.0;
-    if (tid == 0) { s_stop = 0; tb[0] = 0.0; }
-    __syncthreads();
-    int steps = 0, status = 4, bdown = 0;
-    double E = 0.0, Eold = 0.0, tnorm = 0.0, blast = 0.0;
-    const int nslab = (int)((dup + 63) / 64);
-    const int64_t nchunk = (ddw + J.rcols - 1) / J.rcols;
-    const int64_t nrow_items = (int64_t)nslab * nchunk;
-    const int64_t ncol_items = (ddw + J.ccols - 1) / J.ccols;
-
-    for (int j = 0; j < niter; ++j) {
-      const T* cur = buf[j % 3];
-      const T* prv = buf[(j + 2) % 3];
-      T* w = buf[(j + 1) % 3];
-      const T scj = (T)sc_cur;
-      // ---- row pass: w = (1 (x) H_dw)(s_j u_j)
-      for (int64_t item = member; item < nrow_items; item += L) {
-        const int64_t slab = item / nchunk;
-        const int64_t jb = (item - slab * nchunk) * J.rcols;
-        const int64_t je = min(jb + (int64_t)J.rcols, ddw);
-        const int64_t iu = slab * 64 + wl;
-        const bool ok = iu < dup;
-        const int64_t iuc = ok ? iu : 0;
-        for (int64_t c = jb + wave; c < je; c += kWaves) {
-          const int64_t cu = __builtin_amdgcn_readfirstlane((int)c);
-          T s2 = T(0);
-          for (int k0 = 0; k0 < J.sdw; k0 += 8) {
-            uint32_t e[8];
-#pragma unroll
-            for (int k = 0; k < 8; ++k) e[k] = J.hdw[cu * J.sdw + k0 + k];
-            T g[8];
-#pragma unroll
-            for (int k = 0; k < 8; ++k) g[k] = cur[iuc + (int64_t)(e[k] & kColMask) * dup];
-#pragma unroll
-            for (int k = 0; k < 8; ++k) s2 += amp[e[k] >> kAmpShift] * g[k];
-          }
-          if (ok) w[iu + cu * dup] = s2 * scj;
-        }
-      }
-      if (!lane_barrier(bar, gen, L, err)) return;
-      // ---- column pass: w += (H_d + H_up (x) 1)(s_j u_j); <v_j, w> partial
-      acc = 0.0;
-      for (int64_t g0 = member; g0 < ncol_items; g0 += L) {
-        const int64_t j0 = g0 * J.ccols;
-        const int nc = (int)min((int64_t)J.ccols, ddw - j0);
-        const int64_t n = (int64_t)nc * dup;
-        __syncthreads();
-        for (int64_t i = tid; i < n; i += kThreads) vs[i] = cur[j0 * dup + i] * scj;
-        __syncthreads();
-        for (int64_t i = tid; i < n; i += kThreads) {
-          const int cj32 = (int)i / (int)dup;           // n < 2^31 (LDS-sized)
-          const int64_t cj = cj32;
-          const int64_t iu = (int)i - cj32 * (int)dup;
-          const int64_t jj = j0 + cj;
-          const T x = vs[i];
-          T r = (eup[iu] + edw[jj] + Wt[J.pup[iu] * 8 + J.pdw[jj]]) * x;
-          for (int k0 = 0; k0 < J.sup; k0 += 8) {
-            uint32_t e[8];
-#pragma unroll
-            for (int k = 0; k < 8; ++k) e[k] = J.hup[iu * J.sup + k0 + k];
-#pragma unroll
-            for (int k = 0; k < 8; ++k) r += amp[e[k] >> kAmpShift] * vs[cj * dup + (e[k] & kColMask)];
-          }
-          const int64_t o = iu + jj * dup;
-          r += w[o];
-          w[o] = r;
-          acc += (double)x * (double)r;
-        }
-      }
-      {
-        const double s = block_sum(acc, red);
-        if (tid == 0) pa[member] = s;
-      }
-      if (!lane_barrier(bar, gen, L, err)) return;
-      double alpha = 0.0;
-      for (int m = 0; m < L; ++m) alpha += pa[m];
-      // ---- update: w -= alpha v_j + beta_j v_{j-1}; |w|^2 partial
-      const double ac = alpha * sc_cur, bc = beta_j * sc_prev;
-      acc = 0.0;
-      for (int64_t i = gbase; i < D; i += gstride) {
-        double r = (double)w[i] - ac * (double)cur[i];
-        if (j > 0) r -= bc * (double)prv[i];
-        const T t = (T)r;
-        w[i] = t;
-        acc += (double)t * (double)t;
-      }
-      {
-        const double s = block_sum(acc, red);
-        if (tid == 0) pn[member] = s;
-      }
-      if (!lane_barrier(bar, gen, L, err)) return;
-      nrm2 = 0.0;
-      for (int m = 0; m < L; ++m) nrm2 += pn[m];
-      const double bnext = sqrt(nrm2);
-      if (tid == 0) {
-        ta[j] = alpha;
-        tb[j + 1] = bnext;
-      }
+  const int G = gridDim.x;
+  const int per_xcd = G / 8;
+  unsigned* qwide = ctl;
+  unsigned* qnarrow = ctl + 1;
+  unsigned* bwide = ctl + 2;
+  unsigned* bars = ctl + 3;            // one per narrow lane
+  // ---- phase 1
+  {
+    LaneCtx C{bwide, err, parts, parts + G, wide_vecs, wide_vstride, G, b, true,
+              b & 7, b >> 3, per_xcd};
+    unsigned gen = 0;
+    for (;;) {
+      if (b == 0 && tid == 0) slots[0] = (int)atomicAdd(qwide, 1u);
+      if (!lane_barrier(C.bar, gen, G, err)) return;
+      if (tid == 0) s_job = __hip_atomic_load(slots, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       __syncthreads();
-      steps = j + 1;
-      blast = bnext;
-      tnorm = fmax(tnorm, fabs(alpha) + beta_j + bnext);
-      const bool bd = !(bnext > 1e-12 * tnorm);
-      const bool check = bd || (j + 1) % check_every == 0 || j + 1 == niter;
-      if (check) {
-        if (wave == 0) {
-          const double e1 = wave_lowest(ta, tb, j + 1);
-          const double e0 = j > 0 ? wave_lowest(ta, tb, j) : e1 + 1.0;
-          if (tid == 0) {
-            red[0] = e1;
-            red[1] = e0;
-          }
-        }
-        __syncthreads();
-        E = red[0];
-        Eold = red[1];
-        __syncthreads();
-        const double floor32 = sizeof(T) == 4 ? 2.0 * 1.1920929e-7 * tnorm : 0.0;
-        const bool conv = j > 0 && fabs(E - Eold) <= fmax(tol * fmax(1.0, fabs(E)), floor32);
-        if (conv || bd) {
-          status = 0;
-          bdown = bd ? 1 : 0;
-          break;
-        }
-      }
-      sc_prev = sc_cur;
-      sc_cur = bnext > 0.0 ? 1.0 / bnext : 0.0;
-      beta_j = bnext;
+      const int jid = s_job;
+      if (jid >= nwide) break;
+      if (!solve_job<T>(jobs[jid], jid, out, C, gen, niter, tol, check_every, seed, amp, Wt, red,
+                        ta, tb, vs))
+        return;
     }
-    if (member == 0 && tid == 0) {
-      out[jid].e0 = E;
-      out[jid].beta_last = blast;
-      out[jid].iters = steps;
-      out[jid].status = status;
-      out[jid].breakdown = bdown;
+  }
+  // ---- phase 2
+  {
+    const int xcd = b & 7;
+    const int in_xcd = b >> 3;
+    const int lane = xcd * lanes_per_xcd + in_xcd / L;
+    const int member = in_xcd % L;
+    double* pa = parts + 2 * G + (size_t)lane * 2 * L;
+    LaneCtx C{bars + lane, err, pa, pa + L, vecs + (size_t)lane * 3 * vstride, vstride, L, member,
+              false, xcd, in_xcd, per_xcd};
+    unsigned gen = 0;
+    for (;;) {
+      if (member == 0 && tid == 0) slots[1 + lane] = (int)(nwide + atomicAdd(qnarrow, 1u));
+      if (!lane_barrier(C.bar, gen, L, err)) return;
+      if (tid == 0)
+        s_job = __hip_atomic_load(slots + 1 + lane, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __syncthreads();
+      const int jid = s_job;
+      if (jid >= njobs) return;
+      if (!solve_job<T>(jobs[jid], jid, out, C, gen, niter, tol, check_every, seed, amp, Wt, red,
+                        ta, tb, vs))
+        return;
     }
   }
 }
 
 }  // namespace
 
-size_t batch_workspace_bytes(const edx_sector* const* secs, int n, int vtype, int L);
+size_t batch_workspace_bytes(const edx_sector* const* secs, int n, int vtype, int L,
+                             int64_t wide_min);
+int64_t batch_wide_default();
 
 size_t batch_lds_bytes(int vtype, int64_t max_cols_elems, int niter) {
   const size_t sz = vbytes(vtype);
@@ -349,30 +445,77 @@ size_t batch_lds_bytes(int vtype, int64_t max_cols_elems, int niter) {
          (size_t)max_cols_elems * sz + 64;
 }
 
+namespace {
+
+struct BatchLayout {
+  size_t o_jobs, o_out, o_ctl, o_parts, o_wide, o_vec, total;
+  size_t wide_vstride, vstride;
+  int nlanes, lanes_per_xcd;
+};
+
+// dmax_wide / dmax_narrow: largest dimension of each phase (0 if empty)
+BatchLayout batch_layout(int n, int vtype, int L, int ncu, int64_t dmax_wide,
+                         int64_t dmax_narrow) {
+  BatchLayout B{};
+  const size_t sz = vbytes(vtype);
+  B.lanes_per_xcd = std::max(1, ncu / 8 / L);
+  B.nlanes = 8 * B.lanes_per_xcd;
+  B.wide_vstride = align_up((size_t)std::max<int64_t>(dmax_wide, 1) * sz);
+  B.vstride = align_up((size_t)std::max<int64_t>(dmax_narrow, 1) * sz);
+  size_t off = 0;
+  auto take = [&](size_t bytes) { size_t o2 = off; off += align_up(bytes); return o2; };
+  B.o_jobs = take(sizeof(BatchJob) * n);
+  B.o_out = take(sizeof(BatchOut) * n);
+  // ctl: [qwide, qnarrow, barrier_wide, barrier per lane], slots [1 + nlanes], err
+  B.o_ctl = take(sizeof(unsigned) * (3 + B.nlanes) + sizeof(int) * (2 + B.nlanes) + 64);
+  B.o_parts = take(sizeof(double) * (2 * (size_t)ncu + 2 * (size_t)L * B.nlanes));
+  B.o_wide = take(dmax_wide > 0 ? B.wide_vstride * 3 : 0);
+  B.o_vec = take(dmax_narrow > 0 ? B.vstride * 3 * B.nlanes : 0);
+  B.total = off + 256;
+  return B;
+}
+
+int device_cus() {
+  int dev = 0, ncu = 256;
+  if (hipGetDevice(&dev) == hipSuccess) {
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, dev) == hipSuccess) ncu = prop.multiProcessorCount;
+  }
+  return ncu;
+}
+
+}  // namespace
+
+int64_t batch_wide_default() { return 2000000; }
+
 edx_status batch_run(const edx_sector* const* secs, int n, const edx_lanczos_opts* o,
-                     const int* ccols, const int* rcols, int L, void* ws, size_t ws_bytes,
-                     edx_batch_result* res, hipStream_t st, double* elapsed_ms) {
+                     const int* ccols, const int* rcols, int L, int64_t wide_min, void* ws,
+                     size_t ws_bytes, edx_batch_result* res, hipStream_t st,
+                     double* elapsed_ms) {
   if (n <= 0) return EDX_OK;
   const int vtype = o->vtype;
-  const size_t sz = vbytes(vtype);
-  int dev = 0;
-  EDX_HIP(hipGetDevice(&dev));
-  hipDeviceProp_t prop;
-  EDX_HIP(hipGetDeviceProperties(&prop, dev));
-  const int ncu = prop.multiProcessorCount;
+  const int ncu = device_cus();
   if (ncu % 8 != 0 || (ncu / 8) % L != 0) {
     set_error("batch: lane size must divide the CUs per XCD");
     return EDX_E_INVALID;
   }
-  const int per_xcd = ncu / 8;
-  const int lanes_per_xcd = per_xcd / L;
-  const int nlanes = 8 * lanes_per_xcd;
-  // job order: decreasing dimension
+  if (wide_min == 0) wide_min = batch_wide_default();
+  // job order: the wide phase (D >= wide_min) first, each phase by decreasing D
   std::vector<int> order(n);
   for (int i = 0; i < n; ++i) order[i] = i;
   std::stable_sort(order.begin(), order.end(),
                    [&](int x, int y) { return secs[x]->dim > secs[y]->dim; });
-  int64_t dmax = 1, colmax = 1;
+  int nwide = 0;
+  int64_t dmax_w = 0, dmax_n = 0, colmax = 1;
+  for (int k = 0; k < n; ++k) {
+    const int64_t d = secs[order[k]]->dim;
+    if (wide_min > 0 && d >= wide_min) {
+      ++nwide;
+      dmax_w = std::max(dmax_w, d);
+    } else {
+      dmax_n = std::max(dmax_n, d);
+    }
+  }
   std::vector<BatchJob> jobs(n);
   for (int k = 0; k < n; ++k) {
     const edx_sector* s = secs[order[k]];
@@ -389,9 +532,8 @@ edx_status batch_run(const edx_sector* const* secs, int n, const edx_lanczos_opt
     J.ddw = s->ddw;
     J.sup = s->up.wpad;
     J.sdw = s->dw.wpad;
-    J.ccols = std::max(1, ccols ? ccols[order[k]] : 1);
+    J.ccols = std::min(kColMaxB, std::max(1, ccols ? ccols[order[k]] : 1));
     J.rcols = std::max(1, rcols ? rcols[order[k]] : 32);
-    dmax = std::max(dmax, s->dim);
     colmax = std::max(colmax, (int64_t)J.ccols * s->dup);
   }
   const size_t lds = batch_lds_bytes(vtype, colmax, o->niter);
@@ -399,39 +541,34 @@ edx_status batch_run(const edx_sector* const* secs, int n, const edx_lanczos_opt
     set_error("batch: columns per item do not fit in LDS");
     return EDX_E_UNSUPPORTED;
   }
-  // workspace: jobs | out | queue + bars + slots + err | partials | vectors
-  const size_t vstride = align_up((size_t)dmax * sz);
-  size_t off = 0;
-  auto take = [&](size_t bytes) { size_t o2 = off; off += align_up(bytes); return o2; };
-  const size_t o_jobs = take(sizeof(BatchJob) * n);
-  const size_t o_out = take(sizeof(BatchOut) * n);
-  const size_t o_ctl = take(sizeof(unsigned) * (2 + 2 * nlanes) + 64);
-  const size_t o_parts = take(sizeof(double) * 2 * L * nlanes);
-  const size_t o_vec = take(vstride * 3 * nlanes);
+  const BatchLayout B = batch_layout(n, vtype, L, ncu, dmax_w, dmax_n);
   char* base = reinterpret_cast<char*>(align_up(reinterpret_cast<uintptr_t>(ws)));
-  if (off + (size_t)(base - (char*)ws) > ws_bytes) {
-    set_error("batch: workspace too small (need " + std::to_string(off + 256) + " bytes)");
+  if (B.total > ws_bytes) {
+    set_error("batch: workspace too small (need " + std::to_string(B.total) + " bytes)");
     return EDX_E_NOMEM;
   }
-  BatchJob* d_jobs = reinterpret_cast<BatchJob*>(base + o_jobs);
-  BatchOut* d_out = reinterpret_cast<BatchOut*>(base + o_out);
-  unsigned* d_queue = reinterpret_cast<unsigned*>(base + o_ctl);
-  int* d_err = reinterpret_cast<int*>(d_queue + 1);
-  unsigned* d_bars = d_queue + 2;
-  int* d_slots = reinterpret_cast<int*>(d_bars + nlanes);
-  double* d_parts = reinterpret_cast<double*>(base + o_parts);
-  char* d_vec = base + o_vec;
+  BatchJob* d_jobs = reinterpret_cast<BatchJob*>(base + B.o_jobs);
+  BatchOut* d_out = reinterpret_cast<BatchOut*>(base + B.o_out);
+  unsigned* d_ctl = reinterpret_cast<unsigned*>(base + B.o_ctl);
+  int* d_slots = reinterpret_cast<int*>(d_ctl + 3 + B.nlanes);
+  int* d_err = d_slots + 1 + B.nlanes;
+  double* d_parts = reinterpret_cast<double*>(base + B.o_parts);
+  char* d_wide = base + B.o_wide;
+  char* d_vec = base + B.o_vec;
   EDX_HIP(hipMemcpyAsync(d_jobs, jobs.data(), sizeof(BatchJob) * n, hipMemcpyHostToDevice, st));
   EDX_HIP(hipMemsetAsync(d_out, 0, sizeof(BatchOut) * n, st));
-  EDX_HIP(hipMemsetAsync(d_queue, 0, sizeof(unsigned) * (2 + 2 * nlanes), st));
+  EDX_HIP(hipMemsetAsync(d_ctl, 0, sizeof(unsigned) * (3 + B.nlanes) + sizeof(int) * (2 + B.nlanes),
+                         st));
 
   int niter = o->niter;
   double tol = o->tol;
   int every = std::max(1, o->check_every);
   uint64_t seed = o->seed;
   int njobs = n;
-  void* args[] = {&d_jobs, &njobs, &d_out, &d_queue, &d_bars, &d_slots, &d_err, &d_parts, &d_vec,
-                  (void*)&vstride, &L, (void*)&lanes_per_xcd, &niter, &tol, &every, &seed};
+  size_t wvs = B.wide_vstride, vs = B.vstride;
+  int lpx = B.lanes_per_xcd;
+  void* args[] = {&d_jobs, &nwide, &njobs, &d_out, &d_ctl, &d_slots, &d_err, &d_parts, &d_wide,
+                  &wvs, &d_vec, &vs, &L, &lpx, &niter, &tol, &every, &seed};
   const void* kern = vtype == EDX_F32 ? (const void*)k_batch<float> : (const void*)k_batch<double>;
   EDX_HIP(hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
   int per_cu = 0;
@@ -477,7 +614,7 @@ edx_status batch_run(const edx_sector* const* secs, int n, const edx_lanczos_opt
 // fastest; then time the whole batch shape with each lane size.
 edx_status batch_autotune(const edx_sector* const* secs, int n, const edx_lanczos_opts* o,
                           void* ws, size_t ws_bytes, int* ccols, int* rcols, int* lane_wgs,
-                          hipStream_t st) {
+                          int64_t* wide_min, hipStream_t st) {
   edx_lanczos_opts q = *o;
   q.niter = 6;
   q.tol = 0.0;
@@ -506,13 +643,15 @@ edx_status batch_autotune(const edx_sector* const* secs, int n, const edx_lanczo
     }
     double best = 1e300;
     int bc = 1, br = 32;
-    for (int cc : {1, 2, 4, 8}) {
+    for (int cc : {1, 2, 3, 4}) {
       if (batch_lds_bytes(o->vtype, (int64_t)cc * dup, q.niter) > 150 * 1024) continue;
       for (int rc : {16, 32, 64}) {
         std::vector<int> c1(sub.size(), cc), r1(sub.size(), rc);
         double ms = 0;
-        EDX_TRY(batch_run(sub.data(), (int)sub.size(), &q, c1.data(), r1.data(), L, ws, ws_bytes,
-                          res.data(), st, &ms));
+        // shapes that run in the wide phase are timed there
+        const int64_t wm = sub[0]->dim >= batch_wide_default() ? batch_wide_default() : -1;
+        EDX_TRY(batch_run(sub.data(), (int)sub.size(), &q, c1.data(), r1.data(), L, wm, ws,
+                          ws_bytes, res.data(), st, &ms));
         if (ms < best) {
           best = ms;
           bc = cc;
@@ -528,32 +667,35 @@ edx_status batch_autotune(const edx_sector* const* secs, int n, const edx_lanczo
   }
   double best = 1e300;
   int bl = 32;
-  for (int l : {8, 16, 32}) {
-    if (batch_workspace_bytes(secs, n, o->vtype, l) > ws_bytes) continue;
-    double ms = 0;
-    EDX_TRY(batch_run(secs, n, &q, ccols, rcols, l, ws, ws_bytes, res.data(), st, &ms));
-    if (ms < best) {
-      best = ms;
-      bl = l;
+  int64_t bw = batch_wide_default();
+  for (int64_t wm : {batch_wide_default(), (int64_t)-1})
+    for (int l : {8, 16, 32}) {
+      if (batch_workspace_bytes(secs, n, o->vtype, l, wm) > ws_bytes) continue;
+      double ms = 0;
+      EDX_TRY(batch_run(secs, n, &q, ccols, rcols, l, wm, ws, ws_bytes, res.data(), st, &ms));
+      if (ms < best) {
+        best = ms;
+        bl = l;
+        bw = wm;
+      }
     }
-  }
   *lane_wgs = bl;
+  *wide_min = bw;
   return EDX_OK;
 }
 
-size_t batch_workspace_bytes(const edx_sector* const* secs, int n, int vtype, int L) {
-  int64_t dmax = 1;
-  for (int i = 0; i < n; ++i) dmax = std::max(dmax, secs[i]->dim);
-  int dev = 0, ncu = 256;
-  if (hipGetDevice(&dev) == hipSuccess) {
-    hipDeviceProp_t prop;
-    if (hipGetDeviceProperties(&prop, dev) == hipSuccess) ncu = prop.multiProcessorCount;
+size_t batch_workspace_bytes(const edx_sector* const* secs, int n, int vtype, int L,
+                             int64_t wide_min) {
+  if (wide_min == 0) wide_min = batch_wide_default();
+  int64_t dw = 0, dn = 0;
+  for (int i = 0; i < n; ++i) {
+    const int64_t d = secs[i]->dim;
+    if (wide_min > 0 && d >= wide_min)
+      dw = std::max(dw, d);
+    else
+      dn = std::max(dn, d);
   }
-  const int nlanes = std::max(1, ncu / std::max(1, L));
-  const size_t vstride = align_up((size_t)dmax * vbytes(vtype));
-  return align_up(sizeof(BatchJob) * n) + align_up(sizeof(BatchOut) * n) +
-         align_up(sizeof(unsigned) * (2 + 2 * nlanes) + 64) +
-         align_up(sizeof(double) * 2 * L * nlanes) + vstride * 3 * nlanes + 1024;
+  return batch_layout(n, vtype, L, device_cus(), dw, dn).total;
 }
 
 }  // namespace edx

@@ -173,12 +173,14 @@ edx_status k_green_cf(const double* ap, const double* bp, int np, double wp,
 
 // ---- batch.hip
 edx_status batch_run(const edx_sector* const* secs, int n, const edx_lanczos_opts* o,
-                     const int* ccols, const int* rcols, int L, void* ws, size_t ws_bytes,
-                     edx_batch_result* res, hipStream_t st, double* elapsed_ms);
-size_t batch_workspace_bytes(const edx_sector* const* secs, int n, int vtype, int L);
+                     const int* ccols, const int* rcols, int L, int64_t wide_min, void* ws,
+                     size_t ws_bytes, edx_batch_result* res, hipStream_t st,
+                     double* elapsed_ms);
+size_t batch_workspace_bytes(const edx_sector* const* secs, int n, int vtype, int L,
+                             int64_t wide_min);
 edx_status batch_autotune(const edx_sector* const* secs, int n, const edx_lanczos_opts* o,
                           void* ws, size_t ws_bytes, int* ccols, int* rcols, int* lane_wgs,
-                          hipStream_t st);
+                          int64_t* wide_min, hipStream_t st);
 
 // ---- lanczos.cpp (host)
 double tridiag_lowest(const double* a, const double* b, int m, int k);

@@ -64,8 +64,9 @@ class BatchResult(ctypes.Structure):
 
 
 class BatchTiles(ctypes.Structure):
-    _fields_ = [("lane_wgs", ctypes.c_int32), ("ccols", ctypes.POINTER(ctypes.c_int32)),
-                ("rcols", ctypes.POINTER(ctypes.c_int32))]
+    _fields_ = [("lane_wgs", ctypes.c_int32), ("pad_", ctypes.c_int32),
+                ("ccols", ctypes.POINTER(ctypes.c_int32)),
+                ("rcols", ctypes.POINTER(ctypes.c_int32)), ("wide_min_dim", ctypes.c_int64)]
 
 
 class ServerOpts(ctypes.Structure):
@@ -112,9 +113,9 @@ _SIGS = {
     "edx_workspace_bytes": (ctypes.c_size_t, [_P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]),
     "edx_lanczos_ground_state": (ctypes.c_int, [_P, ctypes.POINTER(LanczosOpts), _P, ctypes.c_size_t, ctypes.POINTER(ctypes.c_double), _P, ctypes.POINTER(LanczosReport), _P]),
     "edx_green_cf": (ctypes.c_int, [_P, _P, ctypes.c_double, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(GfOpts), _P, ctypes.c_size_t, _P, ctypes.POINTER(GfReport), _P]),
-    "edx_batch_workspace_bytes": (ctypes.c_size_t, [_P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]),
+    "edx_batch_workspace_bytes": (ctypes.c_size_t, [_P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int64]),
     "edx_batch_ground_state": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.POINTER(LanczosOpts), ctypes.POINTER(BatchTiles), _P, ctypes.c_size_t, ctypes.POINTER(BatchResult), ctypes.POINTER(ctypes.c_double), _P]),
-    "edx_batch_autotune": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.POINTER(LanczosOpts), _P, ctypes.c_size_t, _P, _P, ctypes.POINTER(ctypes.c_int32), _P]),
+    "edx_batch_autotune": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.POINTER(LanczosOpts), _P, ctypes.c_size_t, _P, _P, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int64), _P]),
     "edx_server_default_opts": (None, [ctypes.POINTER(ServerOpts)]),
     "edx_server_create": (ctypes.c_int, [ctypes.POINTER(ServerOpts), ctypes.POINTER(_P)]),
     "edx_server_submit": (ctypes.c_int, [_P, ctypes.POINTER(_Model), ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64)]),
@@ -343,8 +344,13 @@ def _handles(sectors):
     return (ctypes.c_void_p * len(sectors))(*[s.handle for s in sectors])
 
 
-def batch_workspace_bytes(sectors, vtype="f64", lane_wgs=8):
-    return int(lib.edx_batch_workspace_bytes(_handles(sectors), len(sectors), _vt(vtype), lane_wgs))
+def batch_workspace_bytes(sectors, vtype="f64", lane_wgs=8, wide_min_dim=None):
+    """Bytes for the batched launch; wide_min_dim None = enough for the
+    autotuner's candidates (with and without the wide phase)."""
+    h = _handles(sectors)
+    if wide_min_dim is None:
+        return max(int(lib.edx_batch_workspace_bytes(h, len(sectors), _vt(vtype), lane_wgs, w)) for w in (0, -1))
+    return int(lib.edx_batch_workspace_bytes(h, len(sectors), _vt(vtype), lane_wgs, int(wide_min_dim)))
 
 
 def batch_autotune(sectors, ws=None, stream=None, **kw):
@@ -356,10 +362,11 @@ def batch_autotune(sectors, ws=None, stream=None, **kw):
     cc = np.zeros(n, np.int32)
     rc = np.zeros(n, np.int32)
     lw = ctypes.c_int32()
+    wm = ctypes.c_int64()
     _check(lib.edx_batch_autotune(_handles(sectors), n, ctypes.byref(o), _P(ws.data_ptr()), ws.numel(),
                                   cc.ctypes.data_as(_P), rc.ctypes.data_as(_P), ctypes.byref(lw),
-                                  _stream_ptr(stream)))
-    return {"lane_wgs": lw.value, "ccols": cc, "rcols": rc}
+                                  ctypes.byref(wm), _stream_ptr(stream)))
+    return {"lane_wgs": lw.value, "ccols": cc, "rcols": rc, "wide_min_dim": wm.value}
 
 
 def batch_ground_state(sectors, tiles=None, ws=None, stream=None, **kw):
@@ -368,16 +375,17 @@ def batch_ground_state(sectors, tiles=None, ws=None, stream=None, **kw):
     o = lanczos_opts(**kw)
     n = len(sectors)
     lw = tiles["lane_wgs"] if tiles else 32
+    wmin = tiles.get("wide_min_dim", 0) if tiles else 0
     if ws is None:
-        ws = alloc_workspace(batch_workspace_bytes(sectors, o.vtype, lw))
+        ws = alloc_workspace(batch_workspace_bytes(sectors, o.vtype, lw, wmin))
     res = (BatchResult * n)()
     ms = ctypes.c_double()
     tp = None
     if tiles:
         cc = np.ascontiguousarray(tiles["ccols"], np.int32)
         rc = np.ascontiguousarray(tiles["rcols"], np.int32)
-        t = BatchTiles(lw, cc.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
-                       rc.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)))
+        t = BatchTiles(lw, 0, cc.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                       rc.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), int(wmin))
         tp = ctypes.byref(t)
     _check(lib.edx_batch_ground_state(_handles(sectors), n, ctypes.byref(o), tp, _P(ws.data_ptr()), ws.numel(),
                                       res, ctypes.byref(ms), _stream_ptr(stream)))

@@ -306,6 +306,20 @@ def test_batch_autotune_and_lanes(edx):
         assert a["status"] == 0 and abs(a["e0"] - b["e0"]) <= 1e-10 * abs(b["e0"])
 
 
+@pytest.mark.parametrize("wide", [1, 200000])
+def test_batch_wide_phase(edx, wide):
+    """Jobs in the phase that spans every workgroup give the plain results."""
+    jobs = _batch_sectors(edx)
+    secs = [j[2] for j in jobs]
+    n = len(secs)
+    tiles = {"lane_wgs": 16, "ccols": np.full(n, 3, np.int32), "rcols": np.full(n, 16, np.int32),
+             "wide_min_dim": wide}
+    res, _ = edx.batch_ground_state(secs, tiles=tiles, vtype="f64", niter=512, tol=1e-12, seed=9)
+    for (m, sec, S), r in zip(jobs, res):
+        e_plain = edx.lanczos_ground_state(S, want_psi=False, niter=512, tol=1e-12, seed=9)[0]
+        assert r["status"] == 0 and abs(r["e0"] - e_plain) <= 1e-10 * abs(e_plain), (sec, r)
+
+
 @pytest.mark.parametrize("vtype", ["f64", "f32"])
 def test_server_alone_equals_in_mix(edx, vtype):
     """Requests served concurrently give bitwise the results of the same
