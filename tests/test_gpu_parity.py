@@ -5,7 +5,7 @@ Bars (see the design notes):
     diagonal energies to 1e-14 relative;
   * H.v FP64: max |w - w_oracle| <= 1e-13 * (|H|_1-bound) * max|v|, every plan;
   * H.v FP32: <= 2e-6 of the same scale;
-  * ground energy FP64: 1e-10 relative (north-star bar); psi0 overlap 1 - 1e-8;
+  * ground energy FP64: 1e-10 relative; psi0 overlap 1 - 1e-8;
   * G(i w_n) FP64: max |G - G_oracle| <= 1e-8 max |G_oracle|.
 """
 import math
