@@ -64,16 +64,16 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def time_hv(edx, torch, S, v, w, steps, warmup):
+def time_hv(edx, torch, S, v, w, steps, warmup, ld=0):
     for _ in range(warmup):
-        edx.hv(S, v, w)
+        edx.hv(S, v, w, ld=ld)
     torch.cuda.synchronize()
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for a, b in ev:
         a.record()
-        edx.hv(S, v, w)
+        edx.hv(S, v, w, ld=ld)
         b.record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
@@ -274,10 +274,11 @@ def main():
     m, [sec] = inputs.workload("ns16")
     S = edx.build_sector(m, *sec)
     D = S.dim
+    ld = S.ld   # the Krylov vectors' column stride (columns start on 128-byte lines)
     gen = torch.Generator(device="cuda").manual_seed(1)
     res = {}
     for dt_name, tdt in (("f32", torch.float32), ("f64", torch.float64)):
-        v = (torch.rand(D, dtype=tdt, device="cuda", generator=gen) * 2 - 1)
+        v = edx.pad(S, torch.rand(D, dtype=tdt, device="cuda", generator=gen) * 2 - 1)
         w = torch.empty_like(v)
         if a.plan and dt_name == "f32":
             f = [int(x) for x in a.plan.split(",")]
@@ -285,15 +286,20 @@ def main():
                          row_cols=f[4])
             plan = edx.get_plan(S, dt_name)
         else:
-            plan, tune_us = edx.autotune_hv(S, v, w, reps=a.tune_reps)
+            plan, tune_us = edx.autotune_hv(S, v, w, reps=a.tune_reps, ld=ld)
             log(f"{dt_name}: autotuned plan {plan} ({tune_us:.1f} us)")
-        ms, wall = time_hv(edx, torch, S, v, w, a.steps, a.warmup)
+        ms, wall = time_hv(edx, torch, S, v, w, a.steps, a.warmup, ld=ld)
         esz = 4 if dt_name == "f32" else 8
         alg = D * 2 * esz
+        # same plan on dense vectors (column stride D_up), for comparison
+        vd, wd = edx.unpad(S, v), torch.empty(D, dtype=tdt, device="cuda")
+        msd, _ = time_hv(edx, torch, S, vd, wd, max(5, a.steps // 5), 2)
         res[dt_name] = {"ms_mean": float(ms.mean()), "ms_min": float(ms.min()), "wall_s": wall,
-                        "plan": plan, "gbs": alg / (ms.mean() * 1e-3) / 1e9, "alg_bytes": alg}
-        log(f"{dt_name}: {ms.mean() * 1e3:.1f} us/H.v, {res[dt_name]['gbs']:.0f} GB/s algorithmic")
-        del v, w
+                        "plan": plan, "gbs": alg / (ms.mean() * 1e-3) / 1e9, "alg_bytes": alg,
+                        "dense_us": float(msd.mean()) * 1e3}
+        log(f"{dt_name}: {ms.mean() * 1e3:.1f} us/H.v, {res[dt_name]['gbs']:.0f} GB/s algorithmic "
+            f"(dense layout {msd.mean() * 1e3:.1f} us)")
+        del v, w, vd, wd
         torch.cuda.empty_cache()
     r32 = res["f32"]
     traffic, tstate = traffic_from_profile()
@@ -313,15 +319,17 @@ def main():
         "data": "synthetic",
         "config": {"workload": "H.v on the half-filled Ns=16 sector: Norb=1, Nbath=15, N_up=N_dw=8, "
                                "D=165636900, FP32 vectors, symmetrised random bath, U=2",
-                   "seed": inputs.SEED_BASE["ns16"]},
+                   "seed": inputs.SEED_BASE["ns16"], "column_stride": ld},
         "hv_per_s": round(1e3 / r32["ms_mean"], 1),
         "plan_f32": r32["plan"],
+        "f32_dense_layout_us": round(r32["dense_us"], 1),
         "f64": {"gbs": round(res["f64"]["gbs"], 1), "us": round(res["f64"]["ms_mean"] * 1e3, 1),
+                "dense_layout_us": round(res["f64"]["dense_us"], 1),
                 "frac": round(res["f64"]["gbs"] / HBM_PEAK_GBS, 4), "plan": res["f64"]["plan"]},
         "roofline": {"bound": "hbm", "achieved": round(r32["gbs"], 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(r32["gbs"] / HBM_PEAK_GBS, 4),
                      "traffic": traffic if single else None,
-                     "kernel": "k_hv_col<float,8,8,fused>" if single else "k_hv_row + k_hv_col",
+                     "kernel": "k_hv_fused<float,8,8,3>" if single else "k_hv_row + k_hv_col",
                      "traffic_source": tstate},
     }
     if not a.quick:

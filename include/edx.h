@@ -87,6 +87,12 @@ void edx_sector_destroy(edx_sector* s);
 edx_status edx_sector_dims(const edx_sector* s, int64_t* dup, int64_t* ddw,
                            int64_t* dim);
 
+/* Column stride (in elements) that the library's own Krylov vectors use for
+ * this sector: D_up rounded up to a multiple of 32 (every column of V, eq.
+ * Vmatrix, then starts on a 128-byte line), or D_up itself for D_up < 256.
+ * Passing it as `ld` to edx_hv gives the fastest product. */
+edx_status edx_sector_ld(const edx_sector* s, int64_t* ld);
+
 /* Number of hopping entries of one spin (0 = up, 1 = down) and the largest
  * number in any row. */
 edx_status edx_sector_hop_nnz(const edx_sector* s, int32_t spin, int64_t* nnz,
@@ -108,10 +114,14 @@ edx_status edx_sector_get_tables(const edx_sector* s, int32_t spin,
                                  uint8_t* diag_p);
 
 /* w = H v for the sector (Sec. 3 MVP, eq. Hbuild; storage-free, Sec. 2.4).
- * v and w are device arrays of D elements of `vtype`, must not overlap, and
- * are accessed on `stream`.  Enqueues kernels and returns; allocates nothing. */
+ * v and w are device arrays of `vtype` holding the D_up x D_dw matrix V of
+ * eq. Vmatrix column by column with column stride `ld` (0 = dense, D_up;
+ * otherwise ld >= D_up, ld * D_dw elements per array).  Rows D_up..ld-1 of v
+ * are not read; those of w are written as zero.  v and w must not overlap and
+ * are accessed on `stream`.  Enqueues kernels and returns; allocates nothing.
+ * ld in (0, D_up) -> EDX_E_INVALID. */
 edx_status edx_hv(const edx_sector* s, edx_vtype vtype, const void* v, void* w,
-                  void* stream);
+                  int64_t ld, void* stream);
 
 /* Launch plan of edx_hv (tile shapes; the result is the same for every plan up
  * to rounding order).  mode 0: whole sector in LDS, one block; mode 1: two
@@ -130,9 +140,11 @@ edx_status edx_hv_get_plan(const edx_sector* s, edx_vtype vtype, edx_hv_plan* pl
  * run on this sector).  Not thread-safe against concurrent edx_hv calls. */
 edx_status edx_hv_set_plan(edx_sector* s, edx_vtype vtype, const edx_hv_plan* plan);
 /* Project autotuner: times every candidate plan with `reps` launches on the
- * caller's v, w (device, D elements) and keeps the fastest in the sector. */
+ * caller's v, w (device, column stride ld as for edx_hv) and keeps the
+ * fastest in the sector.  The Lanczos and Green calls use that plan with the
+ * stride of edx_sector_ld, so tune with that stride. */
 edx_status edx_autotune_hv(edx_sector* s, edx_vtype vtype, const void* v, void* w,
-                           int32_t reps, void* stream, edx_hv_plan* best,
+                           int64_t ld, int32_t reps, void* stream, edx_hv_plan* best,
                            double* best_us);
 
 typedef struct {

@@ -16,8 +16,6 @@ thread_local std::string g_last_error;
 void set_error(const std::string& msg) { g_last_error = msg; }
 
 size_t lanczos_workspace_bytes(const edx_sector* s, int vtype, int niter, int reorth);
-edx_status hv_autotune(edx_sector* s, int vtype, const void* v, void* w, int reps,
-                       hipStream_t st, HvPlan* best, double* best_us);
 size_t green_workspace_bytes(const edx_sector* s, int vtype, int ngf);
 edx_status lanczos_ground_state_impl(const edx_sector* s, const edx_lanczos_opts* o, void* ws,
                                      size_t ws_bytes, double* e0, void* psi0,
@@ -106,6 +104,12 @@ edx_status edx_sector_dims(const edx_sector* s, int64_t* dup, int64_t* ddw, int6
   return EDX_OK;
 }
 
+edx_status edx_sector_ld(const edx_sector* s, int64_t* ld) {
+  if (!s || !ld) return invalid("sector or ld is NULL");
+  *ld = s->ld;
+  return EDX_OK;
+}
+
 edx_status edx_sector_hop_nnz(const edx_sector* s, int32_t spin, int64_t* nnz, int32_t* max_row) {
   if (!s) return invalid("sector is NULL");
   if (spin != 0 && spin != 1) return invalid("spin must be 0 or 1");
@@ -151,15 +155,18 @@ edx_status edx_sector_get_tables(const edx_sector* s, int32_t spin, uint32_t* ma
   return EDX_OK;
 }
 
-edx_status edx_hv(const edx_sector* s, edx_vtype vtype, const void* v, void* w, void* stream) {
+edx_status edx_hv(const edx_sector* s, edx_vtype vtype, const void* v, void* w, int64_t ld,
+                  void* stream) {
   EDX_TRY(check_sector(s));
   if (!valid_vtype(vtype)) return invalid("vtype must be EDX_F64 or EDX_F32");
   if (!v || !w) return invalid("v or w is NULL");
-  const size_t bytes = (size_t)s->dim * vbytes(vtype);
+  if (ld == 0) ld = s->dup;
+  if (ld < s->dup) return invalid("ld must be 0 (dense) or >= D_up");
+  const size_t bytes = (size_t)(ld * s->ddw) * vbytes(vtype);
   const char* pv = static_cast<const char*>(v);
   const char* pw = static_cast<const char*>(w);
   if (pv < pw + bytes && pw < pv + bytes) return invalid("v and w overlap");
-  return hv_launch(s, vtype, v, w, nullptr, nullptr, static_cast<hipStream_t>(stream));
+  return hv_launch(s, vtype, v, w, ld, nullptr, nullptr, static_cast<hipStream_t>(stream));
 }
 
 edx_status edx_hv_get_plan(const edx_sector* s, edx_vtype vtype, edx_hv_plan* plan) {
@@ -195,14 +202,16 @@ edx_status edx_hv_set_plan(edx_sector* s, edx_vtype vtype, const edx_hv_plan* pl
   return EDX_OK;
 }
 
-edx_status edx_autotune_hv(edx_sector* s, edx_vtype vtype, const void* v, void* w, int32_t reps,
-                           void* stream, edx_hv_plan* best, double* best_us) {
+edx_status edx_autotune_hv(edx_sector* s, edx_vtype vtype, const void* v, void* w, int64_t ld,
+                           int32_t reps, void* stream, edx_hv_plan* best, double* best_us) {
   EDX_TRY(check_sector(s));
   if (!valid_vtype(vtype)) return invalid("vtype must be EDX_F64 or EDX_F32");
   if (!v || !w) return invalid("v or w is NULL");
+  if (ld == 0) ld = s->dup;
+  if (ld < s->dup) return invalid("ld must be 0 (dense) or >= D_up");
   HvPlan bp;
-  EDX_TRY(hv_autotune(s, vtype, v, w, std::max(1, (int)reps), static_cast<hipStream_t>(stream),
-                      &bp, best_us));
+  EDX_TRY(hv_autotune(s, vtype, v, w, ld, std::max(1, (int)reps),
+                      static_cast<hipStream_t>(stream), &bp, best_us));
   if (best) {
     best->mode = bp.mode;
     best->col_cols = bp.col_cols;

@@ -78,6 +78,8 @@ struct edx_sector {
   edx::Allocator alloc;      // where the device tables came from
   int nup = 0, ndw = 0;
   int64_t dup = 0, ddw = 0, dim = 0;
+  int64_t ld = 0;            // column stride of the library's Krylov vectors
+  int64_t vlen = 0;          // ld * ddw elements per Krylov vector
   int device = 0;
   edx::SpinTables up, dw;
   // Signed amplitudes indexed by (hop entry >> 24); identical for both spins.
@@ -118,17 +120,25 @@ struct HvPlan {
 HvPlan hv_plan(const edx_sector* s, int vtype);
 HvPlan hv_default_plan(const edx_sector* s, int vtype);
 edx_status hv_validate(const edx_sector* s, int vtype, HvPlan* p);
-// w = H (scale * v); if partial != nullptr the last pass writes per-block
-// partial sums of <scale v, w> (FP64) and plan.col_blocks of them.
-edx_status hv_launch(const edx_sector* s, int vtype, const void* v, void* w,
+// w = H (scale * v), both with column stride ld >= dup; if partial != nullptr
+// the last pass writes per-block partial sums of <scale v, w> (FP64) and
+// plan.col_blocks of them.
+edx_status hv_launch(const edx_sector* s, int vtype, const void* v, void* w, int64_t ld,
                      const double* vscale, double* partial, hipStream_t st,
                      const HvPlan* plan = nullptr);
+edx_status hv_autotune(edx_sector* s, int vtype, const void* v, void* w, int64_t ld, int reps,
+                       hipStream_t st, HvPlan* best, double* best_us);
 int hv_partial_blocks(const edx_sector* s, int vtype);
 
 // ---- krylov.hip
 int elem_blocks(int64_t n);
-edx_status k_start_vector(int vtype, void* u, int64_t n, uint64_t seed,
-                          double* partial, hipStream_t st);
+// random start vector in [-1, 1) of the element with logical index r + c*dup
+// (the same values for every ld); zero in the padding rows
+edx_status k_start_vector(int vtype, void* u, int64_t dup, int64_t ld, int64_t ddw,
+                          uint64_t seed, double* partial, hipStream_t st);
+// y[r + c*dup] = scale * x[r + c*ld] (drops the padding rows)
+edx_status k_unpad_scale(int vtype, const void* x, int64_t ld, int64_t dup, int64_t ddw,
+                         const double* scale, void* y, hipStream_t st);
 // reduce `nslots` sets of `nparts` partials (slot-major, stride kMaxPartials)
 // into out[0..nslots); op: 0 plain sum, 1 Lanczos alpha, 2 Lanczos beta.
 edx_status k_reduce(const double* partial, int nparts, int nslots, double* out,
@@ -188,6 +198,10 @@ void tridiag_vector(const double* a, const double* b, int m, double lam,
                     double* y);
 
 inline int wpad_of(int width) { return width <= 8 ? 8 : (width <= 16 ? 16 : 24); }
+// Column stride of the library's Krylov vectors for a sector with dup rows:
+// rounded up to 32 elements (every column starts on a 128-byte line), dense
+// for short columns where the padding would cost more than it saves.
+inline int64_t vec_ld(int64_t dup) { return dup < 256 ? dup : (dup + 31) / 32 * 32; }
 inline size_t vbytes(int vtype) { return vtype == EDX_F32 ? 4 : 8; }
 inline size_t align_up(size_t x, size_t a = 256) { return (x + a - 1) / a * a; }
 

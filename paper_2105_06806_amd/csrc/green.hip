@@ -7,6 +7,9 @@
 //    spin), times (-1)^N_up for spin down because every spin-up mode precedes
 //    the spin-down modes.  The paper applies the operator on the master rank and
 //    then scatters the vector; here it is a streaming gather on the device.
+//    psi is dense (column stride D_up of the source sector); phi has the
+//    padded column stride of the target sector's Krylov vectors, with zeros
+//    in the padding rows.
 //  * k_cf: the two continued fractions at the Matsubara frequencies
 //    w_n = (2n+1) pi / beta, one thread per frequency, evaluated from the
 //    deepest level up:
@@ -20,16 +23,21 @@ namespace {
 
 template <typename T>
 __global__ __launch_bounds__(256) void k_apply(const T* __restrict__ psi, T* __restrict__ phi,
-                                               int64_t tdup, int64_t tdim, int64_t sdup,
+                                               int64_t tdup, int64_t tld, int64_t tlen,
+                                               int64_t sdup,
                                                const uint32_t* __restrict__ tmap,
                                                const int32_t* __restrict__ srank, int orb,
                                                int spin, int create, int nup) {
   const uint32_t bit = 1u << orb;
   const uint32_t below = bit - 1u;
-  for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < tdim;
+  for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < tlen;
        idx += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t iu = idx % tdup;
-    const int64_t id = idx / tdup;
+    const int64_t id = idx / tld;
+    const int64_t iu = idx - id * tld;
+    if (iu >= tdup) {
+      phi[idx] = T(0);
+      continue;
+    }
     const uint32_t t = tmap[spin == 0 ? iu : id];
     const bool has = (t & bit) != 0u;
     T val = T(0);
@@ -83,18 +91,18 @@ __global__ void k_cf(const double* __restrict__ ap, const double* __restrict__ b
 
 edx_status k_apply_op(const edx_sector* src, const edx_sector* dst, int vtype, const void* psi,
                       void* phi, int orb, int spin, int create, hipStream_t st) {
-  const int64_t n = dst->dim;
+  const int64_t n = dst->vlen;
   const int64_t b = (n + 255) / 256;
   const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(b, 8192));
   const uint32_t* tmap = spin == 0 ? dst->up.map : dst->dw.map;
   const int32_t* srank = spin == 0 ? src->up.rank : src->dw.rank;
   if (vtype == EDX_F64)
     hipLaunchKernelGGL(k_apply<double>, dim3(grid), dim3(256), 0, st, (const double*)psi,
-                       (double*)phi, dst->dup, n, src->dup, tmap, srank, orb, spin, create,
+                       (double*)phi, dst->dup, dst->ld, n, src->dup, tmap, srank, orb, spin, create,
                        src->nup);
   else
     hipLaunchKernelGGL(k_apply<float>, dim3(grid), dim3(256), 0, st, (const float*)psi,
-                       (float*)phi, dst->dup, n, src->dup, tmap, srank, orb, spin, create,
+                       (float*)phi, dst->dup, dst->ld, n, src->dup, tmap, srank, orb, spin, create,
                        src->nup);
   EDX_HIP(hipGetLastError());
   return EDX_OK;

@@ -6,12 +6,12 @@
 // inside a row (stride D_up).  The paper makes the row access local with an MPI
 // transpose (Sec. 3.2).  One GPU holds the whole vector, so instead:
 //
-//  * k_hv_col  -- one block per group of consecutive columns; the columns are
-//                 staged in LDS, so the spin-up gathers hit LDS.  Adds H_d.
-//                 Fused variant: also gathers the spin-down neighbours of each
-//                 element straight from global memory (whole neighbour
-//                 columns, coalesced; pays off when the vector is cache
-//                 resident).
+//  * k_hv_fused -- one pass: a block owns a group of consecutive columns,
+//                 staged in LDS, so the spin-up gathers hit LDS; adds H_d and
+//                 gathers the spin-down neighbours of each element straight
+//                 from global memory (whole neighbour columns, coalesced).
+//  * k_hv_col  -- the column pass of the two-pass plan: as k_hv_fused without
+//                 the spin-down gathers, accumulating into w.
 //  * k_hv_row  -- spin-down part over slabs of R consecutive rows.  A wave
 //                 reads R contiguous elements of each neighbour column.  Blocks
 //                 are numbered so that the blocks of one slab run on one XCD
@@ -23,7 +23,15 @@
 // Two-pass order: k_hv_row writes W = V H_dw^T, then k_hv_col adds
 // H_d o V + H_up V in place and (optionally) the per-block partial sums of
 // <v, w> needed by Lanczos.
+//
+// Column stride: V may be stored with a leading dimension ld >= D_up (the
+// padding rows are neither read nor written).  With ld a multiple of 32
+// elements every column starts on a 128-byte line, so a wave's 256-byte
+// gather from a neighbour column touches two lines instead of three; the
+// gathers are what bounds these kernels (load bandwidth between L2 and the
+// CUs), so the Krylov vectors of the library use such an ld.
 #include <algorithm>
+#include <type_traits>
 #include <vector>
 
 #include "common.cuh"
@@ -34,6 +42,7 @@ namespace edx {
 template <typename T>
 struct HvArgs {
   int64_t dup, ddw;
+  int64_t ld;                         // vector column stride (elements), >= dup
   const uint32_t* __restrict__ hup;   // row-major, stride sup
   const uint32_t* __restrict__ hdw;   // row-major, stride sdw
   int sup, sdw;                       // padded row lengths (8, 16 or 24)
@@ -46,16 +55,16 @@ struct HvArgs {
 };
 
 template <typename T>
-HvArgs<T> make_args(const edx_sector* s);
+HvArgs<T> make_args(const edx_sector* s, int64_t ld);
 
 template <>
-HvArgs<double> make_args<double>(const edx_sector* s) {
-  return HvArgs<double>{s->dup, s->ddw, s->up.hop, s->dw.hop, s->up.wpad, s->dw.wpad,
+HvArgs<double> make_args<double>(const edx_sector* s, int64_t ld) {
+  return HvArgs<double>{s->dup, s->ddw, ld, s->up.hop, s->dw.hop, s->up.wpad, s->dw.wpad,
                         s->up.e64, s->dw.e64, s->up.pat, s->dw.pat, s->amp64, s->w64};
 }
 template <>
-HvArgs<float> make_args<float>(const edx_sector* s) {
-  return HvArgs<float>{s->dup, s->ddw, s->up.hop, s->dw.hop, s->up.wpad, s->dw.wpad,
+HvArgs<float> make_args<float>(const edx_sector* s, int64_t ld) {
+  return HvArgs<float>{s->dup, s->ddw, ld, s->up.hop, s->dw.hop, s->up.wpad, s->dw.wpad,
                        s->up.e32, s->dw.e32, s->up.pat, s->dw.pat, s->amp32, s->w32};
 }
 
@@ -74,7 +83,8 @@ __global__ __launch_bounds__(1024) void k_hv_small(HvArgs<T> a, const T* __restr
   const T sc = vscale ? (T)(*vscale) : T(1);
   for (int i = threadIdx.x; i < kAmpTable; i += blockDim.x) amp[i] = a.amp[i];
   for (int i = threadIdx.x; i < 64; i += blockDim.x) Wt[i] = a.W[i];
-  for (int64_t i = threadIdx.x; i < D; i += blockDim.x) vs[i] = v[i] * sc;
+  for (int64_t i = threadIdx.x; i < D; i += blockDim.x)
+    vs[i] = v[i % a.dup + (i / a.dup) * a.ld] * sc;
   __syncthreads();
   double dot = 0.0;
   for (int64_t idx = threadIdx.x; idx < D; idx += blockDim.x) {
@@ -90,9 +100,12 @@ __global__ __launch_bounds__(1024) void k_hv_small(HvArgs<T> a, const T* __restr
       const uint32_t e = a.hdw[id * a.sdw + k];
       acc += amp[e >> kAmpShift] * vs[iu + (int64_t)(e & kColMask) * a.dup];
     }
-    w[idx] = acc;
+    w[iu + id * a.ld] = acc;
     dot += (double)x * (double)acc;
   }
+  const int64_t pad = a.ld - a.dup;
+  for (int64_t i = threadIdx.x; i < pad * a.ddw; i += blockDim.x)
+    w[a.dup + (i % pad) + (i / pad) * a.ld] = T(0);
   if (partial) {
     const double s = block_sum(dot, red);
     if (threadIdx.x == 0) partial[blockIdx.x] = s;
@@ -106,19 +119,27 @@ __global__ __launch_bounds__(1024) void k_hv_small(HvArgs<T> a, const T* __restr
 // the table loads and the read of w for both are in flight together.
 constexpr int kColMax = 4;   // columns per block held in registers per thread
 
+// nc (<= kColMax) consecutive columns of dup elements, column stride ld, into
+// a dense LDS image; the column of flat index i is found by comparisons.
 template <typename T>
-__device__ __forceinline__ void stage(T* __restrict__ vs, const T* __restrict__ src, int64_t n,
-                                      T sc) {
+__device__ __forceinline__ void stage_cols(T* __restrict__ vs, const T* __restrict__ src, int nc,
+                                           int64_t dup, int64_t ld, T sc) {
+  const int64_t n = (int64_t)nc * dup;
+  const int64_t gap = ld - dup;
+  auto at = [&](int64_t i) {
+    const int64_t c = (int64_t)(i >= dup) + (int64_t)(i >= 2 * dup) + (int64_t)(i >= 3 * dup);
+    return src[i + c * gap];
+  };
   const int bd = blockDim.x;
   int64_t i = threadIdx.x;
   for (; i + 7 * bd < n; i += 8 * bd) {
     T x[8];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) x[u] = src[i + u * bd];
+    for (int u = 0; u < 8; ++u) x[u] = at(i + u * bd);
 #pragma unroll
     for (int u = 0; u < 8; ++u) vs[i + u * bd] = x[u] * sc;
   }
-  for (; i < n; i += bd) vs[i] = src[i] * sc;
+  for (; i < n; i += bd) vs[i] = at(i) * sc;
 }
 
 template <int W>
@@ -132,12 +153,13 @@ __device__ __forceinline__ void load_row(const uint32_t* __restrict__ h, int64_t
   }
 }
 
-template <typename T, int WUP, int WDW, bool FUSE_DW, bool ACCUM>
+// Column pass of the two-pass plan: w += H_d o V + H_up V (w holds V H_dw^T).
+template <typename T, int WUP>
 __global__ __launch_bounds__(1024) void k_hv_col(HvArgs<T> a, const T* __restrict__ v,
                                                  T* __restrict__ w,
                                                  const double* __restrict__ vscale,
                                                  double* __restrict__ partial, int ncol) {
-  constexpr int RPT = FUSE_DW ? 1 : 2;   // rows per thread per iteration
+  constexpr int RPT = 2;   // rows per thread per iteration
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T* amp = reinterpret_cast<T*>(smem_raw);
   T* Wt = amp + kAmpTable;
@@ -149,7 +171,8 @@ __global__ __launch_bounds__(1024) void k_hv_col(HvArgs<T> a, const T* __restric
   const T sc = vscale ? (T)(*vscale) : T(1);
   for (int i = threadIdx.x; i < kAmpTable; i += blockDim.x) amp[i] = a.amp[i];
   for (int i = threadIdx.x; i < 64; i += blockDim.x) Wt[i] = a.W[i];
-  stage(vs, v + j0 * dup, (int64_t)nc * dup, sc);
+  const int64_t ld = a.ld;
+  stage_cols(vs, v + j0 * ld, nc, dup, ld, sc);
   __syncthreads();
   int64_t jc[kColMax];
   T ed[kColMax];
@@ -176,11 +199,9 @@ __global__ __launch_bounds__(1024) void k_hv_col(HvArgs<T> a, const T* __restric
       load_row<WUP>(a.hup, rows[r], e[r]);
       eu[r] = a.eup[rows[r]];
       pu[r] = a.pup[rows[r]] * 8;
-      if (ACCUM) {
 #pragma unroll
-        for (int c = 0; c < kColMax; ++c)
-          wold[r][c] = c < nc ? w[rows[r] + jc[c] * dup] : T(0);
-      }
+      for (int c = 0; c < kColMax; ++c)
+        wold[r][c] = c < nc ? w[rows[r] + jc[c] * ld] : T(0);
     }
 #pragma unroll
     for (int r = 0; r < RPT; ++r) {
@@ -202,25 +223,132 @@ __global__ __launch_bounds__(1024) void k_hv_col(HvArgs<T> a, const T* __restric
         if (c >= nc) break;
         const int64_t j = jc[c];
         const T x = vs[c * dup + iu];
-        T res = acc[c] + (eu[r] + ed[c] + Wt[pu[r] + pd[c]]) * x;
-        if (FUSE_DW) {
-          uint32_t f[WDW];
-#pragma unroll
-          for (int k = 0; k < WDW; ++k) f[k] = a.hdw[j * WDW + k];
-          T g[WDW];
-#pragma unroll
-          for (int k = 0; k < WDW; ++k) g[k] = v[iu + (int64_t)(f[k] & kColMask) * dup];
-          T s2 = T(0);
-#pragma unroll
-          for (int k = 0; k < WDW; ++k) s2 += amp[f[k] >> kAmpShift] * g[k];
-          res += s2 * sc;
-        }
-        if (ACCUM) res += wold[r][c];
-        w[iu + j * dup] = res;
+        const T res = acc[c] + (eu[r] + ed[c] + Wt[pu[r] + pd[c]]) * x + wold[r][c];
+        w[iu + j * ld] = res;
         dot += (double)x * (double)res;
       }
     }
   }
+  // padding rows of the output are defined as zero
+  for (int64_t i = dup + threadIdx.x; i < ld; i += blockDim.x)
+    for (int c = 0; c < nc; ++c) w[i + (j0 + c) * ld] = T(0);
+  if (partial) {
+    const double s = block_sum(dot, red);
+    if (threadIdx.x == 0) partial[blockIdx.x] = s;
+  }
+}
+
+// ---------------------------------------------------------------- fused pass
+// One pass: a block owns NC consecutive columns (staged in LDS); per row it
+// issues the NC * WDW spin-down gathers from global memory first (their table
+// rows, pre-scaled amplitudes and column offsets are block-uniform and loaded
+// once), then does the spin-up hops from LDS and H_d while they are in flight.
+// The last block may own fewer columns: it computes clamped copies and stores
+// only its own.
+// Block-uniform values forced into scalar registers.
+__device__ __forceinline__ float uniform(float x) {
+  return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(x)));
+}
+__device__ __forceinline__ double uniform(double x) {
+  const long long b = __double_as_longlong(x);
+  const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)b);
+  const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(b >> 32));
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+// a pointer into global memory (address space 1: global, not flat, loads)
+template <typename T>
+using gptr = const T __attribute__((address_space(1)))*;
+template <typename T>
+__device__ __forceinline__ gptr<T> uniform(const T* p) {
+  const unsigned long long b = reinterpret_cast<unsigned long long>(p);
+  const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)b);
+  const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(b >> 32));
+  return (gptr<T>)(((unsigned long long)hi << 32) | lo);
+}
+
+template <typename T, int WUP, int WDW, int NC>
+__global__ __launch_bounds__(1024) void k_hv_fused(HvArgs<T> a, const T* __restrict__ v,
+                                                   T* __restrict__ w,
+                                                   const double* __restrict__ vscale,
+                                                   double* __restrict__ partial) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T* amp = reinterpret_cast<T*>(smem_raw);
+  T* Wt = amp + kAmpTable;
+  double* red = reinterpret_cast<double*>(Wt + 64);
+  T* vs = reinterpret_cast<T*>(red + 16);
+  const int64_t dup = a.dup, ld = a.ld;
+  const int64_t j0 = (int64_t)blockIdx.x * NC;
+  const int nc = (int)std::min<int64_t>(NC, a.ddw - j0);
+  const T sc = vscale ? (T)(*vscale) : T(1);
+  for (int i = threadIdx.x; i < kAmpTable; i += blockDim.x) amp[i] = a.amp[i];
+  for (int i = threadIdx.x; i < 64; i += blockDim.x) Wt[i] = a.W[i];
+  stage_cols(vs, v + j0 * ld, nc, dup, ld, sc);
+  gptr<T> gcol[NC][WDW];   // neighbour columns (block-uniform)
+  T gamp[NC][WDW];         // their amplitudes times the vector scale
+  T ed[NC];
+  int pd[NC];
+#pragma unroll
+  for (int c = 0; c < NC; ++c) {
+    const int64_t j = std::min<int64_t>(j0 + c, a.ddw - 1);
+    ed[c] = a.edw[j];
+    pd[c] = a.pdw[j];
+#pragma unroll
+    for (int k = 0; k < WDW; ++k) {
+      const uint32_t f = a.hdw[j * WDW + k];
+      gcol[c][k] = uniform(v + (int64_t)(f & kColMask) * ld);
+      gamp[c][k] = uniform(a.amp[f >> kAmpShift] * sc);
+    }
+  }
+  __syncthreads();
+  double dot = 0.0;
+  // ALL: the block owns NC columns (every block but possibly the last); then
+  // nothing in the row body is conditional and the compiler keeps all
+  // gathers of a row in flight together
+  auto rows = [&](auto all_tag) {
+    constexpr bool ALL = decltype(all_tag)::value;
+    for (int64_t iu = threadIdx.x; iu < dup; iu += blockDim.x) {
+      // the row's own tables first: loads complete in issue order, so the
+      // spin-up part can start before the gathers have arrived
+      uint32_t e[WUP];
+      load_row<WUP>(a.hup, iu, e);
+      const T eu = a.eup[iu];
+      const int pu = a.pup[iu] * 8;
+      const uint32_t iu32 = (uint32_t)iu;
+      T g[NC][WDW];
+#pragma unroll
+      for (int c = 0; c < NC; ++c)
+#pragma unroll
+        for (int k = 0; k < WDW; ++k) g[c][k] = gcol[c][k][iu32];
+      T acc[NC];
+#pragma unroll
+      for (int c = 0; c < NC; ++c) acc[c] = T(0);
+#pragma unroll
+      for (int k = 0; k < WUP; ++k) {
+        const T am = amp[e[k] >> kAmpShift];
+        const int64_t col = e[k] & kColMask;
+#pragma unroll
+        for (int c = 0; c < NC; ++c) acc[c] += am * vs[c * dup + col];
+      }
+#pragma unroll
+      for (int c = 0; c < NC; ++c) {
+        const T x = vs[c * dup + iu];
+        T s2 = T(0);
+#pragma unroll
+        for (int k = 0; k < WDW; ++k) s2 += gamp[c][k] * g[c][k];
+        const T res = acc[c] + (eu + ed[c] + Wt[pu + pd[c]]) * x + s2;
+        if (ALL || c < nc) {
+          w[iu + (j0 + c) * ld] = res;
+          dot += (double)x * (double)res;
+        }
+      }
+    }
+  };
+  if (nc == NC)
+    rows(std::true_type{});
+  else
+    rows(std::false_type{});
+  for (int64_t i = dup + threadIdx.x; i < ld; i += blockDim.x)
+    for (int c = 0; c < nc; ++c) w[i + (j0 + c) * ld] = T(0);
   if (partial) {
     const double s = block_sum(dot, red);
     if (threadIdx.x == 0) partial[blockIdx.x] = s;
@@ -283,8 +411,8 @@ __global__ __launch_bounds__(256) void k_hv_row(HvArgs<T> a, const T* __restrict
     V g1[WDW], g2[WDW];
 #pragma unroll
     for (int k = 0; k < WDW; ++k) {
-      g1[k] = *reinterpret_cast<const V*>(v + iuc + (int64_t)(e1[k] & kColMask) * a.dup);
-      g2[k] = *reinterpret_cast<const V*>(v + iuc + (int64_t)(e2[k] & kColMask) * a.dup);
+      g1[k] = *reinterpret_cast<const V*>(v + iuc + (int64_t)(e1[k] & kColMask) * a.ld);
+      g2[k] = *reinterpret_cast<const V*>(v + iuc + (int64_t)(e2[k] & kColMask) * a.ld);
     }
     V s1 = V(0), s2 = V(0);
 #pragma unroll
@@ -294,8 +422,8 @@ __global__ __launch_bounds__(256) void k_hv_row(HvArgs<T> a, const T* __restrict
     }
     // streaming stores: keep L2 for the slab being gathered
     if (ok) {
-      __builtin_nontemporal_store(s1, reinterpret_cast<V*>(w + iu + j * a.dup));
-      if (has2) __builtin_nontemporal_store(s2, reinterpret_cast<V*>(w + iu + j2 * a.dup));
+      __builtin_nontemporal_store(s1, reinterpret_cast<V*>(w + iu + j * a.ld));
+      if (has2) __builtin_nontemporal_store(s2, reinterpret_cast<V*>(w + iu + j2 * a.ld));
     }
   }
 }
@@ -319,16 +447,19 @@ HvPlan hv_default_plan(const edx_sector* s, int vtype) {
     p.col_blocks = 1;
     return p;
   }
-  // columns per block: fill LDS up to kColLdsBytes, but keep >= ~1024 blocks
-  int c = (int)std::max<size_t>(1, kColLdsBytes / ((size_t)s->dup * sz));
-  c = std::min(c, kColMax);
-  while (c > 1 && (s->ddw + c - 1) / c < 1024) --c;
+  // One fused pass (spin-down neighbours gathered from global memory); it beat
+  // the two-pass plan on every sector measured (Ns = 12..16, Norb = 1..3).
+  // Columns per block: 2, or 3 for columns of 48 KB and more (the spin-up
+  // table row is then reused over more columns), as far as LDS allows and
+  // keeping a block per CU.
+  const size_t colb = (size_t)s->dup * sz;
+  int c = (int)std::max<size_t>(1, kColLdsBytes / colb);
+  c = std::min(c, colb >= 48 * 1024 ? 3 : 2);
+  while (c > 1 && (s->ddw + c - 1) / c < 256) --c;
   p.col_cols = c;
-  p.col_threads = 512;
+  p.col_threads = colb >= 48 * 1024 && c == 3 ? 1024 : 512;
   p.col_blocks = (int)((s->ddw + c - 1) / c);
-  // the fused single pass reads whole neighbour columns from global memory; it
-  // is the right choice while the vector is cache resident
-  p.mode = bytes <= (size_t)32 * 1024 * 1024 ? 2 : 1;
+  p.mode = 2;
   p.row_rows = (s->dup % 2 == 0) ? 128 : 64;
   p.row_cols = 8;
   return p;
@@ -389,33 +520,45 @@ int hv_partial_blocks(const edx_sector* s, int vtype) { return hv_plan(s, vtype)
 namespace {
 
 
-template <typename T, int WUP, int WDW>
-edx_status launch_col(const HvArgs<T>& a, bool fused, int nblk, int nthr, size_t lds,
-                      hipStream_t st, const T* v, T* w, const double* vscale, double* partial,
-                      int ncol) {
-  const void* kern = fused ? (const void*)k_hv_col<T, WUP, WDW, true, false>
-                           : (const void*)k_hv_col<T, WUP, WDW, false, true>;
+template <typename T, int WUP, int WDW, int NC>
+edx_status launch_fused_k(const HvArgs<T>& a, int nblk, int nthr, size_t lds, hipStream_t st,
+                          const T* v, T* w, const double* vscale, double* partial) {
+  const void* kern = (const void*)k_hv_fused<T, WUP, WDW, NC>;
   EDX_HIP(hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-  if (fused)
-    hipLaunchKernelGGL((k_hv_col<T, WUP, WDW, true, false>), dim3(nblk), dim3(nthr), lds, st, a,
-                       v, w, vscale, partial, ncol);
-  else
-    hipLaunchKernelGGL((k_hv_col<T, WUP, WDW, false, true>), dim3(nblk), dim3(nthr), lds, st, a,
-                       v, w, vscale, partial, ncol);
+  hipLaunchKernelGGL((k_hv_fused<T, WUP, WDW, NC>), dim3(nblk), dim3(nthr), lds, st, a, v, w,
+                     vscale, partial);
   EDX_HIP(hipGetLastError());
   return EDX_OK;
+}
+
+template <typename T, int WUP, int WDW>
+edx_status launch_fused_c(const HvArgs<T>& a, int ncol, int nblk, int nthr, size_t lds,
+                          hipStream_t st, const T* v, T* w, const double* vscale,
+                          double* partial) {
+  switch (ncol) {
+    case 1: return launch_fused_k<T, WUP, WDW, 1>(a, nblk, nthr, lds, st, v, w, vscale, partial);
+    case 2: return launch_fused_k<T, WUP, WDW, 2>(a, nblk, nthr, lds, st, v, w, vscale, partial);
+    case 3: return launch_fused_k<T, WUP, WDW, 3>(a, nblk, nthr, lds, st, v, w, vscale, partial);
+    default: return launch_fused_k<T, WUP, WDW, 4>(a, nblk, nthr, lds, st, v, w, vscale, partial);
+  }
 }
 
 template <typename T, int WUP>
 edx_status launch_col_w(const HvArgs<T>& a, bool fused, int nblk, int nthr, size_t lds,
                         hipStream_t st, const T* v, T* w, const double* vscale, double* partial,
                         int ncol) {
-  if (!fused)   // the spin-down width does not enter the accumulate variant
-    return launch_col<T, WUP, 8>(a, false, nblk, nthr, lds, st, v, w, vscale, partial, ncol);
+  if (!fused) {
+    EDX_HIP(hipFuncSetAttribute((const void*)k_hv_col<T, WUP>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    hipLaunchKernelGGL((k_hv_col<T, WUP>), dim3(nblk), dim3(nthr), lds, st, a, v, w, vscale,
+                       partial, ncol);
+    EDX_HIP(hipGetLastError());
+    return EDX_OK;
+  }
   switch (a.sdw) {
-    case 8: return launch_col<T, WUP, 8>(a, true, nblk, nthr, lds, st, v, w, vscale, partial, ncol);
-    case 16: return launch_col<T, WUP, 16>(a, true, nblk, nthr, lds, st, v, w, vscale, partial, ncol);
-    default: return launch_col<T, WUP, 24>(a, true, nblk, nthr, lds, st, v, w, vscale, partial, ncol);
+    case 8: return launch_fused_c<T, WUP, 8>(a, ncol, nblk, nthr, lds, st, v, w, vscale, partial);
+    case 16: return launch_fused_c<T, WUP, 16>(a, ncol, nblk, nthr, lds, st, v, w, vscale, partial);
+    default: return launch_fused_c<T, WUP, 24>(a, ncol, nblk, nthr, lds, st, v, w, vscale, partial);
   }
 }
 
@@ -441,9 +584,9 @@ edx_status launch_row_r(const HvArgs<T>& a, int64_t grid, hipStream_t st, const 
 }
 
 template <typename T>
-edx_status launch_t(const edx_sector* s, const T* v, T* w, const double* vscale,
+edx_status launch_t(const edx_sector* s, const T* v, T* w, int64_t ld, const double* vscale,
                     double* partial, hipStream_t st, const HvPlan& p) {
-  const HvArgs<T> a = make_args<T>(s);
+  const HvArgs<T> a = make_args<T>(s, ld);
   const size_t hdr = smem_header();
   if (p.mode == 0) {
     const size_t lds = hdr + (size_t)s->dim * sizeof(T);
@@ -491,22 +634,27 @@ edx_status launch_t(const edx_sector* s, const T* v, T* w, const double* vscale,
 
 }  // namespace
 
-edx_status hv_launch(const edx_sector* s, int vtype, const void* v, void* w,
+edx_status hv_launch(const edx_sector* s, int vtype, const void* v, void* w, int64_t ld,
                      const double* vscale, double* partial, hipStream_t st,
                      const HvPlan* plan) {
   HvPlan p = plan ? *plan : hv_plan(s, vtype);
+  if (ld < s->dup) {
+    set_error("hv: leading dimension below D_up");
+    return EDX_E_INVALID;
+  }
   // two rows per lane uses 8/16-byte loads: only for 16-byte aligned vectors
+  // whose columns all start on an even element
   if (p.mode == 1 && p.row_rows == 128 &&
-      ((reinterpret_cast<uintptr_t>(v) | reinterpret_cast<uintptr_t>(w)) & 15u))
+      (((reinterpret_cast<uintptr_t>(v) | reinterpret_cast<uintptr_t>(w)) & 15u) || (ld & 1)))
     p.row_rows = 64;
   if (vtype == EDX_F64)
-    return launch_t<double>(s, static_cast<const double*>(v), static_cast<double*>(w), vscale,
+    return launch_t<double>(s, static_cast<const double*>(v), static_cast<double*>(w), ld, vscale,
                             partial, st, p);
-  return launch_t<float>(s, static_cast<const float*>(v), static_cast<float*>(w), vscale,
+  return launch_t<float>(s, static_cast<const float*>(v), static_cast<float*>(w), ld, vscale,
                          partial, st, p);
 }
 
-edx_status hv_autotune(edx_sector* s, int vtype, const void* v, void* w, int reps,
+edx_status hv_autotune(edx_sector* s, int vtype, const void* v, void* w, int64_t ld, int reps,
                        hipStream_t st, HvPlan* best, double* best_us) {
   std::vector<HvPlan> cands;
   auto add = [&](HvPlan p) {
@@ -544,9 +692,9 @@ edx_status hv_autotune(edx_sector* s, int vtype, const void* v, void* w, int rep
   double best_t = 1e300;
   HvPlan bp = cands[0];
   for (const HvPlan& p : cands) {
-    EDX_TRY(hv_launch(s, vtype, v, w, nullptr, nullptr, st, &p));   // warm-up
+    EDX_TRY(hv_launch(s, vtype, v, w, ld, nullptr, nullptr, st, &p));   // warm-up
     EDX_HIP(hipEventRecord(e0, st));
-    for (int r = 0; r < reps; ++r) EDX_TRY(hv_launch(s, vtype, v, w, nullptr, nullptr, st, &p));
+    for (int r = 0; r < reps; ++r) EDX_TRY(hv_launch(s, vtype, v, w, ld, nullptr, nullptr, st, &p));
     EDX_HIP(hipEventRecord(e1, st));
     EDX_HIP(hipEventSynchronize(e1));
     float ms = 0.f;

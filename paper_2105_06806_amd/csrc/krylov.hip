@@ -28,16 +28,23 @@ __device__ __forceinline__ uint64_t splitmix64(uint64_t seed, uint64_t k) {
   return z ^ (z >> 31);
 }
 
+// element (r, c) of a vector with column stride ld draws counter r + c*dup, so
+// the start vector is the same for every ld; padding rows are zero
 template <typename T>
-__global__ __launch_bounds__(kThreads) void k_start(T* __restrict__ u, int64_t n, uint64_t seed,
+__global__ __launch_bounds__(kThreads) void k_start(T* __restrict__ u, int64_t dup, int64_t ld,
+                                                    int64_t n, uint64_t seed,
                                                     double* __restrict__ partial) {
   __shared__ double red[kThreads / 64];
   double acc = 0.0;
   for (int64_t i = blockIdx.x * (int64_t)kThreads + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * kThreads) {
-    const uint64_t z = splitmix64(seed, (uint64_t)i);
-    const double x = (double)(z >> 11) * 0x1.0p-53 * 2.0 - 1.0;
-    const T t = (T)x;
+    const int64_t c = i / ld, r = i - c * ld;
+    T t = T(0);
+    if (r < dup) {
+      const uint64_t z = splitmix64(seed, (uint64_t)(r + c * dup));
+      const double x = (double)(z >> 11) * 0x1.0p-53 * 2.0 - 1.0;
+      t = (T)x;
+    }
     u[i] = t;
     acc += (double)t * (double)t;
   }
@@ -245,15 +252,45 @@ int multi_blocks(int64_t n) { return elem_blocks(n); }
 
 #define PT(x) reinterpret_cast<T*>(x)
 
-edx_status k_start_vector(int vtype, void* u, int64_t n, uint64_t seed, double* partial,
-                          hipStream_t st) {
+edx_status k_start_vector(int vtype, void* u, int64_t dup, int64_t ld, int64_t ddw,
+                          uint64_t seed, double* partial, hipStream_t st) {
+  const int64_t n = ld * ddw;
   const int g = elem_blocks(n);
   if (vtype == EDX_F64)
-    hipLaunchKernelGGL(k_start<double>, dim3(g), dim3(kThreads), 0, st, (double*)u, n, seed,
-                       partial);
+    hipLaunchKernelGGL(k_start<double>, dim3(g), dim3(kThreads), 0, st, (double*)u, dup, ld, n,
+                       seed, partial);
   else
-    hipLaunchKernelGGL(k_start<float>, dim3(g), dim3(kThreads), 0, st, (float*)u, n, seed,
-                       partial);
+    hipLaunchKernelGGL(k_start<float>, dim3(g), dim3(kThreads), 0, st, (float*)u, dup, ld, n,
+                       seed, partial);
+  EDX_HIP(hipGetLastError());
+  return EDX_OK;
+}
+
+namespace {
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_unpad_kernel(const T* __restrict__ x, int64_t ld,
+                                                           int64_t dup, int64_t n,
+                                                           const double* __restrict__ scale,
+                                                           T* __restrict__ y) {
+  const T sc = (T)(*scale);
+  for (int64_t j = blockIdx.x * (int64_t)kThreads + threadIdx.x; j < n;
+       j += (int64_t)gridDim.x * kThreads) {
+    const int64_t c = j / dup, r = j - c * dup;
+    y[j] = x[r + c * ld] * sc;
+  }
+}
+}  // namespace
+
+edx_status k_unpad_scale(int vtype, const void* x, int64_t ld, int64_t dup, int64_t ddw,
+                         const double* scale, void* y, hipStream_t st) {
+  const int64_t n = dup * ddw;
+  const int g = (int)std::max<int64_t>(1, std::min<int64_t>((n + kThreads - 1) / kThreads, 8192));
+  if (vtype == EDX_F64)
+    hipLaunchKernelGGL(k_unpad_kernel<double>, dim3(g), dim3(kThreads), 0, st, (const double*)x,
+                       ld, dup, n, scale, (double*)y);
+  else
+    hipLaunchKernelGGL(k_unpad_kernel<float>, dim3(g), dim3(kThreads), 0, st, (const float*)x, ld,
+                       dup, n, scale, (float*)y);
   EDX_HIP(hipGetLastError());
   return EDX_OK;
 }

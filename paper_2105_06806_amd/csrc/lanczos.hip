@@ -151,6 +151,7 @@ namespace {
 
 struct LanczosWs {
   char* vec = nullptr;       // 3 rotating vectors, or niter+1 basis vectors
+  char* psi = nullptr;       // psi0 accumulator in the padded layout (or nullptr)
   size_t vstride = 0;        // bytes between vectors
   int nvec = 0;
   double* partial = nullptr; // nslots * kMaxPartials (or hv blocks)
@@ -168,9 +169,11 @@ struct LanczosWs {
 
 constexpr int kMaxLmats = 65536;
 
-size_t lanczos_ws_layout(int64_t dim, int vtype, int niter, int reorth, int hv_blocks,
-                         char* base, LanczosWs* L) {
-  const size_t vs = align_up((size_t)dim * vbytes(vtype));
+// vlen: elements per Krylov vector (ld * D_dw); psi_acc: reserve a vector for
+// accumulating psi0 in that layout (when it differs from the dense output)
+size_t lanczos_ws_layout(int64_t vlen, int vtype, int niter, int reorth, int hv_blocks,
+                         bool psi_acc, char* base, LanczosWs* L) {
+  const size_t vs = align_up((size_t)vlen * vbytes(vtype));
   const int nvec = reorth == 2 ? niter + 1 : 3;
   const int slots = reorth == 2 ? std::max(niter + 1, 2) : 2;
   const int pcap = std::max(kMaxPartials, hv_blocks);
@@ -181,6 +184,7 @@ size_t lanczos_ws_layout(int64_t dim, int vtype, int niter, int reorth, int hv_b
     return base ? base + o : nullptr;
   };
   char* vec = take(vs * nvec);
+  char* psi = psi_acc ? take(vs) : nullptr;
   double* partial = (double*)take(sizeof(double) * (size_t)std::max(slots * kMaxPartials, pcap));
   const size_t ns = sizeof(double) * (size_t)(niter + 2);
   double* alpha = (double*)take(ns);
@@ -192,7 +196,7 @@ size_t lanczos_ws_layout(int64_t dim, int vtype, int niter, int reorth, int hv_b
   double* beta2 = (double*)take(ns);
   double* scale2 = (double*)take(ns);
   if (L) {
-    L->vec = vec; L->vstride = vs; L->nvec = nvec; L->partial = partial;
+    L->vec = vec; L->psi = psi; L->vstride = vs; L->nvec = nvec; L->partial = partial;
     L->partial_cap = pcap; L->alpha = alpha; L->beta = beta; L->scale = scale;
     L->coef = coef; L->y = y; L->alpha2 = alpha2; L->beta2 = beta2; L->scale2 = scale2;
   }
@@ -226,9 +230,9 @@ edx_status lanczos_step(const edx_sector* s, int vtype, const LanczosWs& L, int 
                         double* alpha, double* beta, double* scale, void* psi,
                         const double* ycoef, hipStream_t st) {
   const StepBufs b = bufs_for(L, j, reorth);
-  const int64_t n = s->dim;
+  const int64_t n = s->vlen;
   const int hb = hv_partial_blocks(s, vtype);
-  EDX_TRY(hv_launch(s, vtype, b.cur, b.w, scale + j, L.partial, st));
+  EDX_TRY(hv_launch(s, vtype, b.cur, b.w, s->ld, scale + j, L.partial, st));
   EDX_TRY(k_alpha_finish(L.partial, hb, alpha + j, st));
   EDX_TRY(k_update(vtype, b.w, b.cur, scale + j, b.prev, j > 0 ? scale + j - 1 : nullptr,
                    alpha + j, beta + j, n, psi, ycoef, L.partial, st));
@@ -261,8 +265,8 @@ struct StopState {
 }  // namespace
 
 size_t lanczos_workspace_bytes(const edx_sector* s, int vtype, int niter, int reorth) {
-  return lanczos_ws_layout(s->dim, vtype, niter, reorth, hv_partial_blocks(s, vtype), nullptr,
-                           nullptr) + 256;
+  return lanczos_ws_layout(s->vlen, vtype, niter, reorth, hv_partial_blocks(s, vtype),
+                           s->ld != s->dup, nullptr, nullptr) + 256;
 }
 
 edx_status lanczos_ground_state_impl(const edx_sector* s, const edx_lanczos_opts* o, void* ws,
@@ -273,15 +277,15 @@ edx_status lanczos_ground_state_impl(const edx_sector* s, const edx_lanczos_opts
   const int reorth = o->reorth;
   LanczosWs L;
   char* base = reinterpret_cast<char*>(align_up(reinterpret_cast<uintptr_t>(ws)));
-  const size_t need = lanczos_ws_layout(s->dim, vtype, niter, reorth,
-                                        hv_partial_blocks(s, vtype), base, &L);
+  const size_t need = lanczos_ws_layout(s->vlen, vtype, niter, reorth,
+                                        hv_partial_blocks(s, vtype), s->ld != s->dup, base, &L);
   if (need + (size_t)(base - (char*)ws) > ws_bytes) {
     set_error("lanczos: workspace too small (need " + std::to_string(need + 256) + " bytes)");
     return EDX_E_NOMEM;
   }
-  const int64_t n = s->dim;
+  const int64_t n = s->vlen;
   // start vector u_0 and scale_0 = 1/|u_0|
-  EDX_TRY(k_start_vector(vtype, L.vec, n, o->seed, L.partial, st));
+  EDX_TRY(k_start_vector(vtype, L.vec, s->dup, s->ld, s->ddw, o->seed, L.partial, st));
   EDX_TRY(k_beta_finish(L.partial, elem_blocks(n), L.beta, L.scale, st));
   EDX_HIP(hipMemsetAsync(L.beta, 0, sizeof(double), st));   // beta_0 couples nothing
 
@@ -339,6 +343,9 @@ edx_status lanczos_ground_state_impl(const edx_sector* s, const edx_lanczos_opts
   const bool degenerate = m > 1 && E1 > E && (E1 - E) < 1e-9;
 
   if (psi0) {
+    // psi0 is accumulated in the layout of the Krylov vectors, then written
+    // densely (D elements) into the caller's buffer
+    void* acc = L.psi ? (void*)L.psi : psi0;
     if (reorth == 2) {
       std::vector<double> hs(m);
       EDX_HIP(hipMemcpyAsync(hs.data(), L.scale, sizeof(double) * m, hipMemcpyDeviceToHost, st));
@@ -346,24 +353,27 @@ edx_status lanczos_ground_state_impl(const edx_sector* s, const edx_lanczos_opts
       std::vector<double> c(m);
       for (int k = 0; k < m; ++k) c[k] = -y[k] * hs[k];
       EDX_HIP(hipMemcpyAsync(L.coef, c.data(), sizeof(double) * m, hipMemcpyHostToDevice, st));
-      EDX_HIP(hipMemsetAsync(psi0, 0, (size_t)n * vbytes(vtype), st));
-      EDX_TRY(k_multi_axpy(vtype, psi0, L.vec, (int64_t)(L.vstride / vbytes(vtype)), m, L.coef, n,
+      EDX_HIP(hipMemsetAsync(acc, 0, (size_t)n * vbytes(vtype), st));
+      EDX_TRY(k_multi_axpy(vtype, acc, L.vec, (int64_t)(L.vstride / vbytes(vtype)), m, L.coef, n,
                            nullptr, st));
     } else {
       // replay: identical start vector and recurrence, psi += y_j v_j
       EDX_HIP(hipMemcpyAsync(L.y, y.data(), sizeof(double) * m, hipMemcpyHostToDevice, st));
-      EDX_HIP(hipMemsetAsync(psi0, 0, (size_t)n * vbytes(vtype), st));
-      EDX_TRY(k_start_vector(vtype, L.vec, n, o->seed, L.partial, st));
+      EDX_HIP(hipMemsetAsync(acc, 0, (size_t)n * vbytes(vtype), st));
+      EDX_TRY(k_start_vector(vtype, L.vec, s->dup, s->ld, s->ddw, o->seed, L.partial, st));
       EDX_TRY(k_beta_finish(L.partial, elem_blocks(n), L.beta2, L.scale2, st));
       EDX_HIP(hipMemsetAsync(L.beta2, 0, sizeof(double), st));
       for (int j = 0; j < m; ++j)
-        EDX_TRY(lanczos_step(s, vtype, L, j, reorth, L.alpha2, L.beta2, L.scale2, psi0, L.y + j,
+        EDX_TRY(lanczos_step(s, vtype, L, j, reorth, L.alpha2, L.beta2, L.scale2, acc, L.y + j,
                              st));
     }
     // normalise psi0
-    EDX_TRY(k_norm2(vtype, psi0, n, L.partial, st));
+    EDX_TRY(k_norm2(vtype, acc, n, L.partial, st));
     EDX_TRY(k_beta_finish(L.partial, elem_blocks(n), L.coef, L.coef + 1, st));
-    EDX_TRY(k_scale_copy(vtype, psi0, L.coef + 1, psi0, n, st));
+    if (L.psi)
+      EDX_TRY(k_unpad_scale(vtype, acc, s->ld, s->dup, s->ddw, L.coef + 1, psi0, st));
+    else
+      EDX_TRY(k_scale_copy(vtype, psi0, L.coef + 1, psi0, n, st));
     EDX_HIP(hipStreamSynchronize(st));
   }
   *e0 = E;
@@ -396,15 +406,16 @@ size_t green_workspace_bytes(const edx_sector* s, int vtype, int ngf) {
     for (int i = 1; i <= k; ++i) r = r * (nn - k + i) / i;
     return r;
   };
+  // Krylov vectors of a neighbour sector use its padded column stride
   const int64_t cu = comb(ns, s->nup), cd = comb(ns, s->ndw);
   for (int d : {-1, 1}) {
-    dmax = std::max(dmax, comb(ns, s->nup + d) * cd);
-    dmax = std::max(dmax, cu * comb(ns, s->ndw + d));
+    dmax = std::max(dmax, vec_ld(comb(ns, s->nup + d)) * cd);
+    dmax = std::max(dmax, vec_ld(cu) * comb(ns, s->ndw + d));
   }
   // hv partial blocks of a neighbour sector: bounded by its column count
   const int64_t ddw_max = std::max({comb(ns, s->ndw - 1), comb(ns, s->ndw), comb(ns, s->ndw + 1)});
   const int hvb = (int)std::max<int64_t>(kMaxPartials, ddw_max + 8);
-  return lanczos_ws_layout(dmax, vtype, ngf, 0, hvb, nullptr, nullptr) +
+  return lanczos_ws_layout(dmax, vtype, ngf, 0, hvb, false, nullptr, nullptr) +
          sizeof(double) * (2 * kMaxLmats + 4 * (ngf + 1)) + 512;
 }
 
@@ -451,12 +462,12 @@ edx_status green_cf_impl(const edx_sector* gs, const void* psi0, double e0, int 
   for (int br = 0; br < 2; ++br) {
     const edx_sector* t = gs->nb[spin][br];
     LanczosWs L;
-    lanczos_ws_layout(t ? t->dim : 1, vtype, ngf, 0, t ? hv_partial_blocks(t, vtype) : 1, base,
-                      &L);
+    lanczos_ws_layout(t ? t->vlen : 1, vtype, ngf, 0, t ? hv_partial_blocks(t, vtype) : 1, false,
+                      base, &L);
     if (!t) continue;
     EDX_TRY(k_apply_op(gs, t, vtype, psi0, L.vec, orb, spin, br == 0 ? 1 : 0, st));
-    EDX_TRY(k_norm2(vtype, L.vec, t->dim, L.partial, st));
-    EDX_TRY(k_beta_finish(L.partial, elem_blocks(t->dim), L.beta, L.scale, st));
+    EDX_TRY(k_norm2(vtype, L.vec, t->vlen, L.partial, st));
+    EDX_TRY(k_beta_finish(L.partial, elem_blocks(t->vlen), L.beta, L.scale, st));
     double nrm = 0.0;
     EDX_HIP(hipMemcpyAsync(&nrm, L.beta, sizeof(double), hipMemcpyDeviceToHost, st));
     EDX_HIP(hipStreamSynchronize(st));
@@ -487,8 +498,9 @@ edx_status green_cf_impl(const edx_sector* gs, const void* psi0, double e0, int 
   size_t off = 0;
   for (int br = 0; br < 2; ++br) {
     const edx_sector* t = gs->nb[spin][br];
-    off = std::max(off, lanczos_ws_layout(t ? t->dim : 1, vtype, ngf, 0,
-                                          t ? hv_partial_blocks(t, vtype) : 1, nullptr, nullptr));
+    off = std::max(off, lanczos_ws_layout(t ? t->vlen : 1, vtype, ngf, 0,
+                                          t ? hv_partial_blocks(t, vtype) : 1, false, nullptr,
+                                          nullptr));
   }
   gdev = reinterpret_cast<double*>(base + off);
   double* cdev = gdev + 2 * kMaxLmats;

@@ -178,12 +178,16 @@ size_t estimate_footprint(const edx_server_opts& o, const Model& m, int nup, int
            align_up(sizeof(double) * (size_t)std::max<int64_t>(2 * kMaxPartials, cols + 8)) +
            8 * align_up(sizeof(double) * (size_t)(n + 2)) + 4096;
   };
-  size_t bytes = lanc(dim, ddw, niter) + align_up((size_t)dim * vb);
+  // Krylov vectors use the padded column stride; psi0 is accumulated in that
+  // layout (one more vector when it differs) and returned densely
+  const int64_t ld = vec_ld(dup), vlen = ld * ddw;
+  size_t bytes = lanc(vlen, ddw, niter) + (ld != dup ? align_up((size_t)vlen * vb) : 0) +
+                 align_up((size_t)dim * vb);
   if (o.ngf > 0) {
     int64_t dmax = 1;
     for (int d : {-1, 1}) {
-      dmax = std::max(dmax, binom(ns, nup + d) * ddw);
-      dmax = std::max(dmax, dup * binom(ns, ndw + d));
+      dmax = std::max(dmax, vec_ld(binom(ns, nup + d)) * ddw);
+      dmax = std::max(dmax, ld * binom(ns, ndw + d));
     }
     const int64_t cmax = std::max({binom(ns, ndw - 1), ddw, binom(ns, ndw + 1)});
     bytes += lanc(dmax, cmax, o.ngf) + sizeof(double) * (2 * 65536 + 4 * (o.ngf + 1)) + 1024;

@@ -286,6 +286,8 @@ edx_status build_sector_impl(const Model& m, int nup, int ndw, hipStream_t st,
   S->dup = S->up.D;
   S->ddw = S->dw.D;
   S->dim = S->dup * S->ddw;
+  S->ld = vec_ld(S->dup);
+  S->vlen = S->ld * S->ddw;
 
   // signed amplitude table and pattern interaction table
   double amp[kAmpTable];

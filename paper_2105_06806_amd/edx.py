@@ -105,10 +105,11 @@ _SIGS = {
     "edx_sector_dims": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]),
     "edx_sector_hop_nnz": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int32)]),
     "edx_sector_get_tables": (ctypes.c_int, [_P, ctypes.c_int32, _P, _P, _P, _P, _P, _P, _P]),
-    "edx_hv": (ctypes.c_int, [_P, ctypes.c_int, _P, _P, _P]),
+    "edx_sector_ld": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int64)]),
+    "edx_hv": (ctypes.c_int, [_P, ctypes.c_int, _P, _P, ctypes.c_int64, _P]),
     "edx_hv_get_plan": (ctypes.c_int, [_P, ctypes.c_int, ctypes.POINTER(HvPlan)]),
     "edx_hv_set_plan": (ctypes.c_int, [_P, ctypes.c_int, ctypes.POINTER(HvPlan)]),
-    "edx_autotune_hv": (ctypes.c_int, [_P, ctypes.c_int, _P, _P, ctypes.c_int32, _P, ctypes.POINTER(HvPlan), ctypes.POINTER(ctypes.c_double)]),
+    "edx_autotune_hv": (ctypes.c_int, [_P, ctypes.c_int, _P, _P, ctypes.c_int64, ctypes.c_int32, _P, ctypes.POINTER(HvPlan), ctypes.POINTER(ctypes.c_double)]),
     "edx_lanczos_default_opts": (None, [ctypes.POINTER(LanczosOpts)]),
     "edx_workspace_bytes": (ctypes.c_size_t, [_P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]),
     "edx_lanczos_ground_state": (ctypes.c_int, [_P, ctypes.POINTER(LanczosOpts), _P, ctypes.c_size_t, ctypes.POINTER(ctypes.c_double), _P, ctypes.POINTER(LanczosReport), _P]),
@@ -190,6 +191,9 @@ class Sector:
         dup, ddw, dim = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
         _check(lib.edx_sector_dims(handle, ctypes.byref(dup), ctypes.byref(ddw), ctypes.byref(dim)))
         self.dup, self.ddw, self.dim = dup.value, ddw.value, dim.value
+        ld = ctypes.c_int64()
+        _check(lib.edx_sector_ld(handle, ctypes.byref(ld)))
+        self.ld = ld.value   # column stride of the library's own Krylov vectors
 
     def __del__(self):
         h = getattr(self, "handle", None)
@@ -239,14 +243,36 @@ def build_sector(model, nup, ndw, stream=None):
     return Sector(h.value, model, nup, ndw)
 
 
-def hv(sector, v, w, stream=None):
-    """w = H v on the device (tensors of sector.dim elements, same dtype)."""
+def _vec_len(sector, v, w, ld):
     if v.dtype != w.dtype:
         raise TypeError("v and w must have the same dtype")
-    if v.numel() != sector.dim or w.numel() != sector.dim or not v.is_contiguous() or not w.is_contiguous():
-        raise ValueError("v and w must be contiguous with sector.dim elements")
-    _check(lib.edx_hv(sector.handle, _vtype_of(v), _P(v.data_ptr()), _P(w.data_ptr()), _stream_ptr(stream)))
+    n = (ld or sector.dup) * sector.ddw
+    if v.numel() != n or w.numel() != n or not v.is_contiguous() or not w.is_contiguous():
+        raise ValueError(f"v and w must be contiguous with ld * D_dw = {n} elements")
+
+
+def hv(sector, v, w, stream=None, ld=0):
+    """w = H v on the device.  ld = 0: dense tensors of sector.dim elements;
+    otherwise column stride ld >= D_up (ld * D_dw elements, padding rows of w
+    written as zero), e.g. sector.ld."""
+    _vec_len(sector, v, w, ld)
+    _check(lib.edx_hv(sector.handle, _vtype_of(v), _P(v.data_ptr()), _P(w.data_ptr()), int(ld),
+                      _stream_ptr(stream)))
     return w
+
+
+def pad(sector, x, ld=None):
+    """Dense vector (D elements) -> column stride ld (default sector.ld), zero padding."""
+    ld = sector.ld if ld is None else ld
+    out = x.new_zeros(ld * sector.ddw)
+    out.view(sector.ddw, ld)[:, :sector.dup] = x.view(sector.ddw, sector.dup)
+    return out
+
+
+def unpad(sector, x, ld=None):
+    """Column stride ld (default sector.ld) -> dense vector of D elements (a copy)."""
+    ld = sector.ld if ld is None else ld
+    return x.view(sector.ddw, ld)[:, :sector.dup].reshape(-1).clone()
 
 
 def _plan_dict(p):
@@ -270,12 +296,14 @@ def set_plan(sector, vtype, raise_on_error=True, **plan):
     return st
 
 
-def autotune_hv(sector, v, w, reps=5, stream=None):
-    """Time every candidate plan on (v, w) and keep the fastest; returns (plan, us)."""
+def autotune_hv(sector, v, w, reps=5, stream=None, ld=0):
+    """Time every candidate plan on (v, w) (column stride ld as for hv) and keep
+    the fastest; returns (plan, us)."""
+    _vec_len(sector, v, w, ld)
     p = HvPlan()
     us = ctypes.c_double()
-    _check(lib.edx_autotune_hv(sector.handle, _vtype_of(v), _P(v.data_ptr()), _P(w.data_ptr()), int(reps),
-                               _stream_ptr(stream), ctypes.byref(p), ctypes.byref(us)))
+    _check(lib.edx_autotune_hv(sector.handle, _vtype_of(v), _P(v.data_ptr()), _P(w.data_ptr()), int(ld),
+                               int(reps), _stream_ptr(stream), ctypes.byref(p), ctypes.byref(us)))
     return _plan_dict(p), us.value
 
 

@@ -94,9 +94,19 @@ def _set_plan(edx, S, vtype, p):
     return edx.set_plan(S, vtype, raise_on_error=False, **p)
 
 
+def _strided(S, x, ld, fill):
+    """Dense host vector -> column stride ld, `fill` in the padding rows."""
+    out = np.full((S.ddw, ld), fill)
+    out[:, :S.dup] = np.asarray(x).reshape(S.ddw, S.dup)
+    return out.ravel()
+
+
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
 @pytest.mark.parametrize("name,m,sec", HV_CASES, ids=[c[0] for c in HV_CASES])
 def test_hv_every_plan(edx, name, m, sec, dtype):
+    """Every plan, dense and with two padded column strides (odd, and rounded up
+    to 32): the padding rows of v hold NaN (never read), those of w must come
+    back zero."""
     import torch
     H = fock.explicit_hamiltonian(m, *sec)
     S = edx.build_sector(m, *sec)
@@ -104,22 +114,35 @@ def test_hv_every_plan(edx, name, m, sec, dtype):
     ref = H @ x
     tdt = torch.float64 if dtype == "f64" else torch.float32
     vt = edx.F64 if dtype == "f64" else edx.F32
-    v = _cuda(x, tdt)
     tol = (1e-13 if dtype == "f64" else 2e-6) * _hscale(m)
     ran = 0
-    for p in PLANS:
-        st = _set_plan(edx, S, vt, p)
-        if st != 0:
-            assert st in (edx.EDX_E_UNSUPPORTED,), (p, edx.last_error())
-            continue
-        w = torch.full_like(v, float("nan"))
-        edx.hv(S, v, w)
-        torch.cuda.synchronize()
-        got = w.double().cpu().numpy()
-        err = np.abs(got - ref).max()
-        assert err <= tol, (p, err)
-        ran += 1
-    assert ran >= 2
+    for ld in (0, S.dup + 5, (S.dup + 31) // 32 * 32 + 32):
+        lde = ld or S.dup
+        v = _cuda(_strided(S, x, lde, np.nan), tdt)
+        for p in PLANS:
+            st = _set_plan(edx, S, vt, p)
+            if st != 0:
+                assert st in (edx.EDX_E_UNSUPPORTED,), (p, edx.last_error())
+                continue
+            w = torch.full_like(v, float("nan"))
+            edx.hv(S, v, w, ld=ld)
+            torch.cuda.synchronize()
+            got = w.double().cpu().numpy().reshape(S.ddw, lde)
+            err = np.abs(got[:, :S.dup].ravel() - ref).max()
+            assert err <= tol, (ld, p, err)
+            assert np.all(got[:, S.dup:] == 0.0), (ld, p)
+            ran += 1
+    assert ran >= 6
+
+
+def test_sector_ld(edx):
+    for m, sec in [(inputs.workload("ns8")[0], (4, 4)), (inputs.workload("ns12")[0], (6, 6)),
+                   (inputs.make_model(1, 10, 2.5, seed=23), (5, 6))]:
+        S = edx.build_sector(m, *sec)
+        if S.dup < 256:
+            assert S.ld == S.dup
+        else:
+            assert S.ld % 32 == 0 and S.dup <= S.ld < S.dup + 32
 
 
 def test_hv_hermitian(edx):
@@ -144,6 +167,10 @@ def test_hv_rejects_bad_args(edx):
     with pytest.raises(edx.EdxError) as ei:
         edx.hv(S, v, v)
     assert ei.value.status == edx.EDX_E_INVALID
+    w = torch.zeros_like(v)
+    st = edx.lib.edx_hv(S.handle, edx.F64, edx._P(v.data_ptr()), edx._P(w.data_ptr()), S.dup - 1,
+                        None)
+    assert st == edx.EDX_E_INVALID          # column stride below D_up
     with pytest.raises(edx.EdxError) as ei:
         edx.build_sector(m, 9, 4)
     assert ei.value.status == edx.EDX_E_INVALID
@@ -244,25 +271,33 @@ def test_noconv_and_nomem(edx):
 
 @pytest.mark.parametrize("dtype", ["f32", "f64"])
 def test_hv_headline_sector_sampled(edx, dtype):
-    """Ns=16 half filling (D=165,636,900) in the benchmark's launch plan:
-    sampled outputs against the oracle's row-by-row product."""
+    """Ns=16 half filling (D=165,636,900) in the benchmark's layout (column
+    stride S.ld) with the fused plan it selects and the two-pass plan:
+    sampled outputs against the oracle's row-by-row product; padding rows of
+    the output zero."""
     import torch
     m, [sec] = inputs.workload("ns16")
     S = edx.build_sector(m, *sec)
     tdt = torch.float64 if dtype == "f64" else torch.float32
+    vt = edx.F64 if dtype == "f64" else edx.F32
     gen = torch.Generator(device="cuda").manual_seed(5)
-    v = torch.rand(S.dim, dtype=tdt, device="cuda", generator=gen) * 2 - 1
-    w = torch.empty_like(v)
-    edx.hv(S, v, w)
-    torch.cuda.synchronize()
+    vd = torch.rand(S.dim, dtype=tdt, device="cuda", generator=gen) * 2 - 1
+    v = edx.pad(S, vd)
     rows = np.random.default_rng(3).choice(S.dim, size=2000, replace=False)
     rows = np.concatenate([rows, [0, S.dim - 1, S.dup - 1, S.dup]])
     # the oracle needs the neighbours of the sampled rows: pass v to the host
-    vh = v.double().cpu().numpy()
-    ref = fock.hv_rows(m, *sec, vh, rows)
-    got = w.double().cpu().numpy()[rows]
+    ref = fock.hv_rows(m, *sec, vd.double().cpu().numpy(), rows)
+    pos = rows % S.dup + (rows // S.dup) * S.ld
     tol = (1e-13 if dtype == "f64" else 2e-6) * _hscale(m)
-    assert np.abs(got - ref).max() <= tol
+    fused = dict(mode=2, col_cols=3 if dtype == "f32" else 1, col_threads=1024)
+    for plan in (fused, dict(mode=1, col_cols=1, col_threads=512, row_rows=128, row_cols=8)):
+        assert _set_plan(edx, S, vt, plan) == 0, edx.last_error()
+        w = torch.full_like(v, float("nan"))
+        edx.hv(S, v, w, ld=S.ld)
+        torch.cuda.synchronize()
+        got = w[torch.as_tensor(pos, device="cuda")].double().cpu().numpy()
+        assert np.abs(got - ref).max() <= tol, plan
+        assert bool((w.view(S.ddw, S.ld)[:, S.dup:] == 0).all()), plan
 
 
 def _batch_sectors(edx):
