@@ -222,13 +222,15 @@ edx_status edx_green_cf(const edx_sector* gs, const void* psi0, double e0,
 
 /* ---- batched ground states (many sectors, one persistent launch) ----
  * Every job is an independent sector; the ground energy of each follows the
- * recurrence and stop rule of edx_lanczos_ground_state (psi0 is not formed).
- * The paper's counterpart is its parallelism over independent impurity
- * problems (Sec. 5 "Main", inequivalent sites).  One cooperative launch:
- * first the jobs with D >= wide_min_dim, one at a time on all workgroups;
- * then lanes of `lane_wgs` workgroups on one XCD each pull the remaining jobs
- * (largest first) from a device queue.  A job's status is EDX_OK, EDX_E_NOCONV (e0 is the last
- * estimate) or EDX_E_DEVICE (a lane barrier timed out). */
+ * plain recurrence of edx_lanczos_ground_state (psi0 is not formed).  The
+ * paper's counterpart is its parallelism over independent impurity problems
+ * (Sec. 5 "Main", inequivalent sites).  Jobs with D >= wide_min_dim fill the
+ * GPU by themselves: they run first, one after another, through the kernels
+ * and host stop rule of edx_lanczos_ground_state (tol and rtol).  The others
+ * share one cooperative launch: lanes of `lane_wgs` workgroups on one XCD
+ * each pull jobs (largest first) from a device queue and evaluate the tol
+ * stop rule on the device.  A job's status is EDX_OK, EDX_E_NOCONV (e0 is the
+ * last estimate) or EDX_E_DEVICE (a lane barrier timed out). */
 typedef struct {
   double e0;
   double beta_last;
@@ -243,8 +245,9 @@ typedef struct {
   int32_t pad_;
   const int32_t* ccols;   /* [n] columns per column-pass item (1..4), or NULL (1) */
   const int32_t* rcols;   /* [n] columns per row-pass item, or NULL (32)   */
-  int64_t wide_min_dim;   /* jobs with D >= this run first, one at a time on
-                             every workgroup; 0 = 2,000,000; < 0 = none    */
+  int64_t wide_min_dim;   /* jobs with D >= this run first, one at a time
+                             through the whole-GPU kernels; 0 = 2,000,000;
+                             < 0 = none (every job on a lane)              */
 } edx_batch_tiles;
 
 /* Device workspace bytes for n jobs with lanes of lane_wgs workgroups and the
@@ -254,9 +257,10 @@ size_t edx_batch_workspace_bytes(const edx_sector* const* sectors, int32_t n,
                                  int64_t wide_min_dim);
 
 /* Ground energies of n sectors (host array of handles).  opts: niter, vtype,
- * tol, check_every and seed are used (reorth must be 0).  tiles may be NULL
- * (lane_wgs 32).  results: host array of n.  Blocks until done; elapsed_ms
- * (nullable) receives the kernel time. */
+ * tol, check_every and seed are used, and rtol for the whole-GPU jobs
+ * (reorth must be 0).  tiles may be NULL (lane_wgs 32).  results: host array
+ * of n.  Blocks until done; elapsed_ms (nullable) receives the device time
+ * from the first job's start to the last job's end. */
 edx_status edx_batch_ground_state(const edx_sector* const* sectors, int32_t n,
                                   const edx_lanczos_opts* opts,
                                   const edx_batch_tiles* tiles, void* ws,
@@ -264,10 +268,11 @@ edx_status edx_batch_ground_state(const edx_sector* const* sectors, int32_t n,
                                   double* elapsed_ms, void* stream);
 
 /* Project autotuner for the batched launch: per distinct (D_up, D_dw) it
- * times short runs of each (ccols, rcols) candidate, then each lane size with
- * and without the wide phase; writes ccols[n], rcols[n] (host), *lane_wgs and
- * *wide_min_dim.  ws must hold edx_batch_workspace_bytes(..., 8, -1) and
- * (..., 8, 0) bytes. */
+ * times short runs of each (ccols, rcols) candidate on lanes, then each lane
+ * size with each whole-GPU threshold (none, 0.25M, 1M, 2M, 4M, 8M); writes
+ * ccols[n], rcols[n] (host), *lane_wgs and *wide_min_dim.  Candidates whose
+ * workspace exceeds ws_bytes are skipped; ws must hold at least
+ * edx_batch_workspace_bytes(..., 32, -1) bytes. */
 edx_status edx_batch_autotune(const edx_sector* const* sectors, int32_t n,
                               const edx_lanczos_opts* opts, void* ws,
                               size_t ws_bytes, int32_t* ccols, int32_t* rcols,

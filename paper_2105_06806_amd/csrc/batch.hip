@@ -1,7 +1,10 @@
-// Batched ground states of many sectors in one persistent launch.
+// Batched ground states of many sectors.
 //
-// The grid is one workgroup per CU, launched cooperatively so that every
-// workgroup is resident.  Workgroups are grouped into lanes of L workgroups
+// Jobs whose dimension reaches a threshold (wide_min) fill the GPU by
+// themselves: they run first, one after another, through the whole-GPU
+// kernels of the plain path (lanczos.hip).  All other jobs share one
+// persistent launch: the grid is one workgroup per CU, launched cooperatively
+// so that every workgroup is resident.  Workgroups are grouped into lanes of L workgroups
 // that sit on one XCD (workgroup b runs on XCD b % 8), so a lane shares one L2.
 // A lane pulls the next job from a device queue (jobs sorted by decreasing
 // dimension), runs the whole Lanczos recurrence of Sec. 5 "Diagonalization" for
@@ -17,7 +20,10 @@
 // identically in every workgroup of the lane, so no broadcast is needed.
 // Dot products accumulate in FP64 with a fixed reduction order.
 #include <algorithm>
+#include <atomic>
 #include <cmath>
+#include <string>
+#include <thread>
 #include <vector>
 
 #include "common.cuh"
@@ -56,6 +62,11 @@ constexpr int kThreads = 1024;
 constexpr int kWaves = kThreads / 64;
 constexpr long long kSpinLimit = 1ll << 26;
 constexpr int kColMaxB = 4;   // columns per column-pass item held in registers
+constexpr int kMaxBatchIter = 2048;   // niter bound of the batch call
+// Whole-GPU jobs run on this many streams at once (one host thread each), so
+// that one job's kernels fill the gaps while another's host checks its stop
+// rule.
+constexpr int kWideStreams = 3;
 
 __device__ __forceinline__ uint64_t splitmix64(uint64_t seed, uint64_t k) {
   uint64_t z = seed + (k + 1) * 0x9E3779B97F4A7C15ull;
@@ -137,9 +148,7 @@ __device__ double wave_lowest(const double* a, const double* b, int m) {
   return 0.5 * (lo + hi);
 }
 
-// One lane's view: its barrier, partial-sum slots and vectors, and how its
-// members share the row-pass items (a lane spanning all XCDs gives every XCD
-// one contiguous range of slabs so each slab stays in one L2).
+// One lane's view: its barrier, partial-sum slots and vectors.
 struct LaneCtx {
   unsigned* bar;
   int* err;
@@ -148,8 +157,6 @@ struct LaneCtx {
   char* lv;          // 3 vectors
   size_t vstride;
   int L, member;
-  bool xsplit;
-  int xcd, in_xcd, per_xcd;
 };
 
 // The whole Lanczos recurrence of one job on one lane; returns false if a
@@ -197,17 +204,7 @@ __device__ bool solve_job(const BatchJob& J, int jid, BatchOut* __restrict__ out
   const int64_t nchunk = (ddw + J.rcols - 1) / J.rcols;
   const int64_t nrow_items = nslab * nchunk;
   const int64_t ncol_items = (ddw + J.ccols - 1) / J.ccols;
-  int64_t rbeg, rend, rstep;
-  if (C.xsplit) {
-    const int64_t q = (nrow_items + 7) / 8;
-    rbeg = (int64_t)C.xcd * q + C.in_xcd;
-    rend = min(nrow_items, (int64_t)(C.xcd + 1) * q);
-    rstep = C.per_xcd;
-  } else {
-    rbeg = C.member;
-    rend = nrow_items;
-    rstep = L;
-  }
+  const int64_t rbeg = C.member, rend = nrow_items, rstep = L;
 
   for (int j = 0; j < niter; ++j) {
     const T* cur = buf[j % 3];
@@ -366,15 +363,13 @@ __device__ bool solve_job(const BatchJob& J, int jid, BatchOut* __restrict__ out
   return true;
 }
 
-// Phase 1: jobs [0, nwide) one at a time on a lane of every workgroup.
-// Phase 2: jobs [nwide, njobs) on lanes of L workgroups inside one XCD.
+// Jobs [0, njobs) on lanes of L workgroups inside one XCD.
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_batch(
-    const BatchJob* __restrict__ jobs, int nwide, int njobs, BatchOut* __restrict__ out,
+    const BatchJob* __restrict__ jobs, int njobs, BatchOut* __restrict__ out,
     unsigned* __restrict__ ctl, int* __restrict__ slots, int* __restrict__ err,
-    double* __restrict__ parts, char* __restrict__ wide_vecs, size_t wide_vstride,
-    char* __restrict__ vecs, size_t vstride, int L, int lanes_per_xcd, int niter, double tol,
-    int check_every, uint64_t seed) {
+    double* __restrict__ parts, char* __restrict__ vecs, size_t vstride, int L,
+    int lanes_per_xcd, int niter, double tol, int check_every, uint64_t seed) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T* amp = reinterpret_cast<T*>(smem_raw);
   T* Wt = amp + kAmpTable;
@@ -385,51 +380,25 @@ __global__ __launch_bounds__(kThreads) void k_batch(
   T* vs = reinterpret_cast<T*>(tb + (niter + 2));
   const int b = blockIdx.x;
   const int tid = threadIdx.x;
-  const int G = gridDim.x;
-  const int per_xcd = G / 8;
-  unsigned* qwide = ctl;
-  unsigned* qnarrow = ctl + 1;
-  unsigned* bwide = ctl + 2;
-  unsigned* bars = ctl + 3;            // one per narrow lane
-  // ---- phase 1
-  {
-    LaneCtx C{bwide, err, parts, parts + G, wide_vecs, wide_vstride, G, b, true,
-              b & 7, b >> 3, per_xcd};
-    unsigned gen = 0;
-    for (;;) {
-      if (b == 0 && tid == 0) slots[0] = (int)atomicAdd(qwide, 1u);
-      if (!lane_barrier(C.bar, gen, G, err)) return;
-      if (tid == 0) s_job = __hip_atomic_load(slots, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      __syncthreads();
-      const int jid = s_job;
-      if (jid >= nwide) break;
-      if (!solve_job<T>(jobs[jid], jid, out, C, gen, niter, tol, check_every, seed, amp, Wt, red,
-                        ta, tb, vs))
-        return;
-    }
-  }
-  // ---- phase 2
-  {
-    const int xcd = b & 7;
-    const int in_xcd = b >> 3;
-    const int lane = xcd * lanes_per_xcd + in_xcd / L;
-    const int member = in_xcd % L;
-    double* pa = parts + 2 * G + (size_t)lane * 2 * L;
-    LaneCtx C{bars + lane, err, pa, pa + L, vecs + (size_t)lane * 3 * vstride, vstride, L, member,
-              false, xcd, in_xcd, per_xcd};
-    unsigned gen = 0;
-    for (;;) {
-      if (member == 0 && tid == 0) slots[1 + lane] = (int)(nwide + atomicAdd(qnarrow, 1u));
-      if (!lane_barrier(C.bar, gen, L, err)) return;
-      if (tid == 0)
-        s_job = __hip_atomic_load(slots + 1 + lane, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      __syncthreads();
-      const int jid = s_job;
-      if (jid >= njobs) return;
-      if (!solve_job<T>(jobs[jid], jid, out, C, gen, niter, tol, check_every, seed, amp, Wt, red,
-                        ta, tb, vs))
-        return;
-    }
+  unsigned* queue = ctl;
+  unsigned* bars = ctl + 1;            // one per lane
+  const int xcd = b & 7;
+  const int in_xcd = b >> 3;
+  const int lane = xcd * lanes_per_xcd + in_xcd / L;
+  const int member = in_xcd % L;
+  double* pa = parts + (size_t)lane * 2 * L;
+  LaneCtx C{bars + lane, err, pa, pa + L, vecs + (size_t)lane * 3 * vstride, vstride, L, member};
+  unsigned gen = 0;
+  for (;;) {
+    if (member == 0 && tid == 0) slots[lane] = (int)atomicAdd(queue, 1u);
+    if (!lane_barrier(C.bar, gen, L, err)) return;
+    if (tid == 0) s_job = __hip_atomic_load(slots + lane, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __syncthreads();
+    const int jid = s_job;
+    if (jid >= njobs) return;
+    if (!solve_job<T>(jobs[jid], jid, out, C, gen, niter, tol, check_every, seed, amp, Wt, red, ta,
+                      tb, vs))
+      return;
   }
 }
 
@@ -449,27 +418,28 @@ namespace {
 
 struct BatchLayout {
   size_t o_jobs, o_out, o_ctl, o_parts, o_wide, o_vec, total;
-  size_t wide_vstride, vstride;
+  size_t wide_bytes, vstride;
   int nlanes, lanes_per_xcd;
 };
 
-// dmax_wide / dmax_narrow: largest dimension of each phase (0 if empty)
-BatchLayout batch_layout(int n, int vtype, int L, int ncu, int64_t dmax_wide,
-                         int64_t dmax_narrow) {
+// wide_ws: plain Lanczos workspace of the largest job run through the
+// whole-GPU path (0 if none), one per stream; dmax_narrow: largest dimension
+// run in lanes
+BatchLayout batch_layout(int n, int vtype, int L, int ncu, size_t wide_ws, int64_t dmax_narrow) {
   BatchLayout B{};
   const size_t sz = vbytes(vtype);
   B.lanes_per_xcd = std::max(1, ncu / 8 / L);
   B.nlanes = 8 * B.lanes_per_xcd;
-  B.wide_vstride = align_up((size_t)std::max<int64_t>(dmax_wide, 1) * sz);
+  B.wide_bytes = wide_ws;
   B.vstride = align_up((size_t)std::max<int64_t>(dmax_narrow, 1) * sz);
   size_t off = 0;
   auto take = [&](size_t bytes) { size_t o2 = off; off += align_up(bytes); return o2; };
   B.o_jobs = take(sizeof(BatchJob) * n);
   B.o_out = take(sizeof(BatchOut) * n);
-  // ctl: [qwide, qnarrow, barrier_wide, barrier per lane], slots [1 + nlanes], err
-  B.o_ctl = take(sizeof(unsigned) * (3 + B.nlanes) + sizeof(int) * (2 + B.nlanes) + 64);
-  B.o_parts = take(sizeof(double) * (2 * (size_t)ncu + 2 * (size_t)L * B.nlanes));
-  B.o_wide = take(dmax_wide > 0 ? B.wide_vstride * 3 : 0);
+  // ctl: [queue, barrier per lane], slots [nlanes], err
+  B.o_ctl = take(sizeof(unsigned) * (1 + B.nlanes) + sizeof(int) * (1 + B.nlanes) + 64);
+  B.o_parts = take(sizeof(double) * (2 * (size_t)L * B.nlanes));
+  B.o_wide = take(align_up(wide_ws) * kWideStreams);
   B.o_vec = take(dmax_narrow > 0 ? B.vstride * 3 * B.nlanes : 0);
   B.total = off + 256;
   return B;
@@ -500,25 +470,28 @@ edx_status batch_run(const edx_sector* const* secs, int n, const edx_lanczos_opt
     return EDX_E_INVALID;
   }
   if (wide_min == 0) wide_min = batch_wide_default();
-  // job order: the wide phase (D >= wide_min) first, each phase by decreasing D
+  // job order by decreasing D: the whole-GPU jobs (D >= wide_min) first, then
+  // the lane jobs, which lanes take from the queue largest first
   std::vector<int> order(n);
   for (int i = 0; i < n; ++i) order[i] = i;
   std::stable_sort(order.begin(), order.end(),
                    [&](int x, int y) { return secs[x]->dim > secs[y]->dim; });
   int nwide = 0;
-  int64_t dmax_w = 0, dmax_n = 0, colmax = 1;
-  for (int k = 0; k < n; ++k) {
-    const int64_t d = secs[order[k]]->dim;
-    if (wide_min > 0 && d >= wide_min) {
-      ++nwide;
-      dmax_w = std::max(dmax_w, d);
-    } else {
-      dmax_n = std::max(dmax_n, d);
-    }
-  }
-  std::vector<BatchJob> jobs(n);
+  size_t wide_ws = 0;
+  int64_t dmax_n = 0, colmax = 1;
   for (int k = 0; k < n; ++k) {
     const edx_sector* s = secs[order[k]];
+    if (wide_min > 0 && s->dim >= wide_min) {
+      ++nwide;
+      wide_ws = std::max(wide_ws, lanczos_workspace_bytes(s, vtype, o->niter, 0));
+    } else {
+      dmax_n = std::max(dmax_n, s->dim);
+    }
+  }
+  const int nl = n - nwide;
+  std::vector<BatchJob> jobs(nl);
+  for (int k = 0; k < nl; ++k) {
+    const edx_sector* s = secs[order[nwide + k]];
     BatchJob& J = jobs[k];
     J.hup = s->up.hop;
     J.hdw = s->dw.hop;
@@ -532,69 +505,145 @@ edx_status batch_run(const edx_sector* const* secs, int n, const edx_lanczos_opt
     J.ddw = s->ddw;
     J.sup = s->up.wpad;
     J.sdw = s->dw.wpad;
-    J.ccols = std::min(kColMaxB, std::max(1, ccols ? ccols[order[k]] : 1));
-    J.rcols = std::max(1, rcols ? rcols[order[k]] : 32);
+    J.ccols = std::min(kColMaxB, std::max(1, ccols ? ccols[order[nwide + k]] : 1));
+    J.rcols = std::max(1, rcols ? rcols[order[nwide + k]] : 32);
     colmax = std::max(colmax, (int64_t)J.ccols * s->dup);
   }
   const size_t lds = batch_lds_bytes(vtype, colmax, o->niter);
-  if (lds > 160 * 1024) {
+  if (nl > 0 && lds > 160 * 1024) {
     set_error("batch: columns per item do not fit in LDS");
     return EDX_E_UNSUPPORTED;
   }
-  const BatchLayout B = batch_layout(n, vtype, L, ncu, dmax_w, dmax_n);
+  const BatchLayout B = batch_layout(nl, vtype, L, ncu, wide_ws, dmax_n);
   char* base = reinterpret_cast<char*>(align_up(reinterpret_cast<uintptr_t>(ws)));
   if (B.total > ws_bytes) {
     set_error("batch: workspace too small (need " + std::to_string(B.total) + " bytes)");
     return EDX_E_NOMEM;
   }
-  BatchJob* d_jobs = reinterpret_cast<BatchJob*>(base + B.o_jobs);
-  BatchOut* d_out = reinterpret_cast<BatchOut*>(base + B.o_out);
-  unsigned* d_ctl = reinterpret_cast<unsigned*>(base + B.o_ctl);
-  int* d_slots = reinterpret_cast<int*>(d_ctl + 3 + B.nlanes);
-  int* d_err = d_slots + 1 + B.nlanes;
-  double* d_parts = reinterpret_cast<double*>(base + B.o_parts);
-  char* d_wide = base + B.o_wide;
-  char* d_vec = base + B.o_vec;
-  EDX_HIP(hipMemcpyAsync(d_jobs, jobs.data(), sizeof(BatchJob) * n, hipMemcpyHostToDevice, st));
-  EDX_HIP(hipMemsetAsync(d_out, 0, sizeof(BatchOut) * n, st));
-  EDX_HIP(hipMemsetAsync(d_ctl, 0, sizeof(unsigned) * (3 + B.nlanes) + sizeof(int) * (2 + B.nlanes),
-                         st));
-
-  int niter = o->niter;
-  double tol = o->tol;
-  int every = std::max(1, o->check_every);
-  uint64_t seed = o->seed;
-  int njobs = n;
-  size_t wvs = B.wide_vstride, vs = B.vstride;
-  int lpx = B.lanes_per_xcd;
-  void* args[] = {&d_jobs, &nwide, &njobs, &d_out, &d_ctl, &d_slots, &d_err, &d_parts, &d_wide,
-                  &wvs, &d_vec, &vs, &L, &lpx, &niter, &tol, &every, &seed};
-  const void* kern = vtype == EDX_F32 ? (const void*)k_batch<float> : (const void*)k_batch<double>;
-  EDX_HIP(hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-  int per_cu = 0;
-  EDX_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, kThreads, lds));
-  if (per_cu < 1) {
-    set_error("batch: kernel does not fit on a CU");
-    return EDX_E_UNSUPPORTED;
-  }
   hipEvent_t e0, e1;
   EDX_HIP(hipEventCreate(&e0));
   EDX_HIP(hipEventCreate(&e1));
   EDX_HIP(hipEventRecord(e0, st));
-  EDX_HIP(hipLaunchCooperativeKernel(kern, dim3(ncu), dim3(kThreads), args, lds, st));
-  EDX_HIP(hipEventRecord(e1, st));
-  std::vector<BatchOut> hout(n);
+  // whole-GPU jobs: the plain recurrence and stop rule, largest first, on
+  // kWideStreams streams (the caller's and ones created here)
+  if (nwide > 0) {
+    edx_lanczos_opts q = *o;
+    q.reorth = 0;
+    const int nst = std::min(kWideStreams, nwide);
+    std::vector<hipStream_t> sts(nst, st);
+    std::vector<hipEvent_t> done(nst, nullptr);
+    edx_status fail = EDX_OK;
+    for (int t = 1; t < nst && fail == EDX_OK; ++t) {
+      if (hipStreamCreateWithFlags(&sts[t], hipStreamNonBlocking) != hipSuccess ||
+          hipEventCreateWithFlags(&done[t], hipEventDisableTiming) != hipSuccess ||
+          hipStreamWaitEvent(sts[t], e0, 0) != hipSuccess) {
+        set_error("batch: stream set-up failed");
+        fail = EDX_E_DEVICE;
+      }
+    }
+    std::atomic<int> next{0};
+    std::vector<edx_status> tst(nst, EDX_OK);
+    std::vector<std::string> terr(nst);
+    auto worker = [&](int t) {
+      int dev = 0;
+      if (hipGetDevice(&dev) == hipSuccess) (void)hipSetDevice(dev);
+      for (;;) {
+        const int k = next.fetch_add(1);
+        if (k >= nwide) break;
+        const edx_sector* s = secs[order[k]];
+        double e = 0.0;
+        edx_lanczos_report rep{};
+        const edx_status sj = lanczos_ground_state_impl(
+            s, &q, base + B.o_wide + (size_t)t * align_up(B.wide_bytes), B.wide_bytes, &e, nullptr,
+            &rep, sts[t]);
+        if (sj != EDX_OK && sj != EDX_E_NOCONV && sj != EDX_E_DEGENERATE) {
+          tst[t] = sj;
+          terr[t] = std::string("batch: whole-GPU job: ") + edx_last_error();
+          next.store(nwide);
+          break;
+        }
+        edx_batch_result& r = res[order[k]];
+        r.e0 = e;
+        r.beta_last = rep.beta_last;
+        r.iters = rep.iters;
+        r.status = sj == EDX_E_NOCONV ? EDX_E_NOCONV : EDX_OK;
+        r.breakdown = rep.breakdown;
+      }
+    };
+    if (fail == EDX_OK) {
+      std::vector<std::thread> th;
+      for (int t = 1; t < nst; ++t) th.emplace_back(worker, t);
+      worker(0);
+      for (auto& x : th) x.join();
+    }
+    // the caller's stream continues after every helper stream's work
+    for (int t = 1; t < nst; ++t) {
+      if (done[t] && sts[t] != st) {
+        (void)hipEventRecord(done[t], sts[t]);
+        (void)hipStreamWaitEvent(st, done[t], 0);
+      }
+    }
+    for (int t = 1; t < nst; ++t) {
+      if (sts[t] != st) (void)hipStreamSynchronize(sts[t]);
+      if (done[t]) (void)hipEventDestroy(done[t]);
+      if (sts[t] != st) (void)hipStreamDestroy(sts[t]);
+    }
+    for (int t = 0; t < nst && fail == EDX_OK; ++t)
+      if (tst[t] != EDX_OK) {
+        fail = tst[t];
+        set_error(terr[t]);
+      }
+    if (fail != EDX_OK) {
+      (void)hipEventDestroy(e0);
+      (void)hipEventDestroy(e1);
+      return fail;
+    }
+  }
   int herr = 0;
-  EDX_HIP(hipMemcpyAsync(hout.data(), d_out, sizeof(BatchOut) * n, hipMemcpyDeviceToHost, st));
-  EDX_HIP(hipMemcpyAsync(&herr, d_err, sizeof(int), hipMemcpyDeviceToHost, st));
+  std::vector<BatchOut> hout(nl);
+  if (nl > 0) {
+    BatchJob* d_jobs = reinterpret_cast<BatchJob*>(base + B.o_jobs);
+    BatchOut* d_out = reinterpret_cast<BatchOut*>(base + B.o_out);
+    unsigned* d_ctl = reinterpret_cast<unsigned*>(base + B.o_ctl);
+    int* d_slots = reinterpret_cast<int*>(d_ctl + 1 + B.nlanes);
+    int* d_err = d_slots + B.nlanes;
+    double* d_parts = reinterpret_cast<double*>(base + B.o_parts);
+    char* d_vec = base + B.o_vec;
+    EDX_HIP(hipMemcpyAsync(d_jobs, jobs.data(), sizeof(BatchJob) * nl, hipMemcpyHostToDevice, st));
+    EDX_HIP(hipMemsetAsync(d_out, 0, sizeof(BatchOut) * nl, st));
+    EDX_HIP(hipMemsetAsync(d_ctl, 0, sizeof(unsigned) * (1 + B.nlanes) + sizeof(int) * (1 + B.nlanes),
+                           st));
+    int niter = o->niter;
+    double tol = o->tol;
+    int every = std::max(1, o->check_every);
+    uint64_t seed = o->seed;
+    int njobs = nl;
+    size_t vs = B.vstride;
+    int lpx = B.lanes_per_xcd;
+    void* args[] = {&d_jobs, &njobs, &d_out, &d_ctl, &d_slots, &d_err, &d_parts, &d_vec,
+                    &vs, &L, &lpx, &niter, &tol, &every, &seed};
+    const void* kern =
+        vtype == EDX_F32 ? (const void*)k_batch<float> : (const void*)k_batch<double>;
+    EDX_HIP(hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    int per_cu = 0;
+    EDX_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, kThreads, lds));
+    if (per_cu < 1) {
+      set_error("batch: kernel does not fit on a CU");
+      return EDX_E_UNSUPPORTED;
+    }
+    EDX_HIP(hipLaunchCooperativeKernel(kern, dim3(ncu), dim3(kThreads), args, lds, st));
+    EDX_HIP(hipMemcpyAsync(hout.data(), d_out, sizeof(BatchOut) * nl, hipMemcpyDeviceToHost, st));
+    EDX_HIP(hipMemcpyAsync(&herr, d_err, sizeof(int), hipMemcpyDeviceToHost, st));
+  }
+  EDX_HIP(hipEventRecord(e1, st));
   EDX_HIP(hipStreamSynchronize(st));
   float ms = 0.f;
   EDX_HIP(hipEventElapsedTime(&ms, e0, e1));
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   if (elapsed_ms) *elapsed_ms = ms;
-  for (int k = 0; k < n; ++k) {
-    edx_batch_result& r = res[order[k]];
+  for (int k = 0; k < nl; ++k) {
+    edx_batch_result& r = res[order[nwide + k]];
     r.e0 = hout[k].e0;
     r.beta_last = hout[k].beta_last;
     r.iters = hout[k].iters;
@@ -609,9 +658,10 @@ edx_status batch_run(const edx_sector* const* secs, int n, const edx_lanczos_opt
 }
 
 // Autotuner: for every distinct (D_up, D_dw) among the jobs, time a short run
-// (a few Lanczos steps, no stop rule) of up to one job per lane with each
+// (a few Lanczos steps, no stop rule) of up to 8 such jobs on lanes with each
 // candidate (columns per column item, columns per row item) and keep the
-// fastest; then time the whole batch shape with each lane size.
+// fastest; then time the whole batch with each lane size and each threshold
+// for the whole-GPU path.
 edx_status batch_autotune(const edx_sector* const* secs, int n, const edx_lanczos_opts* o,
                           void* ws, size_t ws_bytes, int* ccols, int* rcols, int* lane_wgs,
                           int64_t* wide_min, hipStream_t st) {
@@ -648,9 +698,7 @@ edx_status batch_autotune(const edx_sector* const* secs, int n, const edx_lanczo
       for (int rc : {16, 32, 64}) {
         std::vector<int> c1(sub.size(), cc), r1(sub.size(), rc);
         double ms = 0;
-        // shapes that run in the wide phase are timed there
-        const int64_t wm = sub[0]->dim >= batch_wide_default() ? batch_wide_default() : -1;
-        EDX_TRY(batch_run(sub.data(), (int)sub.size(), &q, c1.data(), r1.data(), L, wm, ws,
+        EDX_TRY(batch_run(sub.data(), (int)sub.size(), &q, c1.data(), r1.data(), L, -1, ws,
                           ws_bytes, res.data(), st, &ms));
         if (ms < best) {
           best = ms;
@@ -668,7 +716,8 @@ edx_status batch_autotune(const edx_sector* const* secs, int n, const edx_lanczo
   double best = 1e300;
   int bl = 32;
   int64_t bw = batch_wide_default();
-  for (int64_t wm : {batch_wide_default(), (int64_t)-1})
+  for (int64_t wm : {(int64_t)-1, (int64_t)250000, (int64_t)1000000, batch_wide_default(),
+                     (int64_t)4000000, (int64_t)8000000})
     for (int l : {8, 16, 32}) {
       if (batch_workspace_bytes(secs, n, o->vtype, l, wm) > ws_bytes) continue;
       double ms = 0;
@@ -687,15 +736,18 @@ edx_status batch_autotune(const edx_sector* const* secs, int n, const edx_lanczo
 size_t batch_workspace_bytes(const edx_sector* const* secs, int n, int vtype, int L,
                              int64_t wide_min) {
   if (wide_min == 0) wide_min = batch_wide_default();
-  int64_t dw = 0, dn = 0;
+  size_t ww = 0;
+  int64_t dn = 0;
+  int nl = 0;
   for (int i = 0; i < n; ++i) {
-    const int64_t d = secs[i]->dim;
-    if (wide_min > 0 && d >= wide_min)
-      dw = std::max(dw, d);
-    else
-      dn = std::max(dn, d);
+    if (wide_min > 0 && secs[i]->dim >= wide_min) {
+      ww = std::max(ww, lanczos_workspace_bytes(secs[i], vtype, kMaxBatchIter, 0));
+    } else {
+      dn = std::max(dn, secs[i]->dim);
+      ++nl;
+    }
   }
-  return batch_layout(n, vtype, L, device_cus(), dw, dn).total;
+  return batch_layout(nl, vtype, L, device_cus(), ww, dn).total;
 }
 
 }  // namespace edx

@@ -192,6 +192,11 @@ edx_status batch_autotune(const edx_sector* const* secs, int n, const edx_lanczo
                           void* ws, size_t ws_bytes, int* ccols, int* rcols, int* lane_wgs,
                           int64_t* wide_min, hipStream_t st);
 
+// ---- lanczos.hip
+size_t lanczos_workspace_bytes(const edx_sector* s, int vtype, int niter, int reorth);
+edx_status lanczos_ground_state_impl(const edx_sector* s, const edx_lanczos_opts* o, void* ws,
+                                     size_t ws_bytes, double* e0, void* psi0,
+                                     edx_lanczos_report* rep, hipStream_t st);
 // ---- lanczos.cpp (host)
 double tridiag_lowest(const double* a, const double* b, int m, int k);
 void tridiag_vector(const double* a, const double* b, int m, double lam,

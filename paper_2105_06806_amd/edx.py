@@ -373,11 +373,12 @@ def _handles(sectors):
 
 
 def batch_workspace_bytes(sectors, vtype="f64", lane_wgs=8, wide_min_dim=None):
-    """Bytes for the batched launch; wide_min_dim None = enough for the
-    autotuner's candidates (with and without the wide phase)."""
+    """Bytes for the batched launch; wide_min_dim None = enough for every
+    whole-GPU threshold the autotuner tries."""
     h = _handles(sectors)
     if wide_min_dim is None:
-        return max(int(lib.edx_batch_workspace_bytes(h, len(sectors), _vt(vtype), lane_wgs, w)) for w in (0, -1))
+        return max(int(lib.edx_batch_workspace_bytes(h, len(sectors), _vt(vtype), lane_wgs, w))
+                   for w in (-1, 250000, 1000000, 2000000, 4000000, 8000000))
     return int(lib.edx_batch_workspace_bytes(h, len(sectors), _vt(vtype), lane_wgs, int(wide_min_dim)))
 
 

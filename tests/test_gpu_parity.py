@@ -343,7 +343,8 @@ def test_batch_autotune_and_lanes(edx):
 
 @pytest.mark.parametrize("wide", [1, 200000])
 def test_batch_wide_phase(edx, wide):
-    """Jobs in the phase that spans every workgroup give the plain results."""
+    """Jobs routed through the whole-GPU path (all of them, or the larger ones)
+    give the plain results."""
     jobs = _batch_sectors(edx)
     secs = [j[2] for j in jobs]
     n = len(secs)
