@@ -55,8 +55,8 @@ def parse():
     ap.add_argument("--full", action="store_true", help="full-size serving sweep")
     ap.add_argument("--tune-reps", type=int, default=3)
     ap.add_argument("--plan", default=None,
-                    help="mode,col_cols,col_threads,row_rows,row_cols of the FP32 headline "
-                         "instead of autotuning (profiling runs)")
+                    help="mode,col_cols,col_threads,row_rows,row_cols[,col_order] of the FP32 "
+                         "headline instead of autotuning (profiling runs)")
     return ap.parse_args()
 
 
@@ -81,19 +81,23 @@ def time_hv(edx, torch, S, v, w, steps, warmup, ld=0):
     return ms, wall
 
 
-def traffic_from_profile():
+def traffic_from_profile(plan):
     """HBM bytes per launch of the headline kernel from the committed counter
-    summary, if it was taken on the current kernel source."""
+    summary, if it was taken on the current kernel source with this plan."""
     if not os.path.exists(PROFILE_PMC):
         return None, None
     txt = open(PROFILE_PMC).read()
     mh = re.search(r"source_sha256:\s*([0-9a-f]{64})", txt)
     mt = re.search(r"traffic_bytes_per_launch:\s*([0-9.eE+]+)", txt)
-    if not mh or not mt:
+    mp = re.search(r"plan:\s*([0-9,]+)", txt)
+    if not mh or not mt or not mp:
         return None, None
     cur = hashlib.sha256(open(HV_SRC, "rb").read()).hexdigest()
     if cur != mh.group(1):
         return None, "stale"
+    keys = ("mode", "col_cols", "col_threads", "row_rows", "row_cols", "col_order")
+    if [int(x) for x in mp.group(1).split(",")] != [int(plan[k]) for k in keys]:
+        return None, "profiled plan " + mp.group(1)
     return float(mt.group(1)), "ok"
 
 
@@ -103,12 +107,13 @@ def cpu_baseline(m, sec, elem_bytes, budget_s=15.0):
     D = 12870 * 12870
     rng = np.random.default_rng(0)
     v = rng.uniform(-1, 1, size=D)
-    n = 20000
+    fock.hv_rows(m, *sec, v, rng.choice(D, size=20000, replace=False))   # warm-up
+    n = 200000
     rows = rng.choice(D, size=n, replace=False)
     t0 = time.perf_counter()
     fock.hv_rows(m, *sec, v, rows)
     dt = time.perf_counter() - t0
-    n2 = int(min(3_000_000, max(n, n * budget_s / max(dt, 1e-3) * 0.8)))
+    n2 = int(min(8_000_000, max(n, n * budget_s / max(dt, 1e-3))))
     rows = rng.choice(D, size=n2, replace=False)
     t0 = time.perf_counter()
     fock.hv_rows(m, *sec, v, rows)
@@ -283,7 +288,7 @@ def main():
         if a.plan and dt_name == "f32":
             f = [int(x) for x in a.plan.split(",")]
             edx.set_plan(S, dt_name, mode=f[0], col_cols=f[1], col_threads=f[2], row_rows=f[3],
-                         row_cols=f[4])
+                         row_cols=f[4], col_order=f[5] if len(f) > 5 else 0)
             plan = edx.get_plan(S, dt_name)
         else:
             plan, tune_us = edx.autotune_hv(S, v, w, reps=a.tune_reps, ld=ld)
@@ -302,7 +307,7 @@ def main():
         del v, w, vd, wd
         torch.cuda.empty_cache()
     r32 = res["f32"]
-    traffic, tstate = traffic_from_profile()
+    traffic, tstate = traffic_from_profile(r32["plan"])
     single = r32["plan"]["mode"] in (0, 2)
     out = {
         "metric": "H·v GB/s & %HBM peak at Ns=16; batched solves/s, p50/p99 vs plain",

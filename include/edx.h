@@ -129,9 +129,13 @@ edx_status edx_hv(const edx_sector* s, edx_vtype vtype, const void* v, void* w,
  * over columns that also gathers the spin-down neighbours from global memory.
  * col_cols: columns per block (1..4) of the column pass; col_threads: 256, 512
  * or 1024; row_rows: rows per slab (16, 32, 64, or 128 = two rows per lane,
- * even D_up only); row_cols: columns per block of the row pass (>= 1). */
+ * even D_up only); row_cols: columns per block of the row pass (>= 1);
+ * col_order (mode 2): which columns a workgroup takes -- 0 consecutive groups
+ * in workgroup order, 1 the groups running at once on one XCD are
+ * consecutive, 2 as 1 over the columns sorted by impurity occupation (so
+ * that concurrently processed columns share more spin-down neighbours). */
 typedef struct {
-  int32_t mode, col_cols, col_threads, row_rows, row_cols;
+  int32_t mode, col_cols, col_threads, row_rows, row_cols, col_order;
 } edx_hv_plan;
 
 /* Current plan of a sector for one vtype (the built-in heuristic until set). */

@@ -178,6 +178,7 @@ edx_status edx_hv_get_plan(const edx_sector* s, edx_vtype vtype, edx_hv_plan* pl
   plan->col_threads = p.col_threads;
   plan->row_rows = p.row_rows;
   plan->row_cols = p.row_cols;
+  plan->col_order = p.col_order;
   return EDX_OK;
 }
 
@@ -190,14 +191,10 @@ edx_status edx_hv_set_plan(edx_sector* s, edx_vtype vtype, const edx_hv_plan* pl
   p.col_threads = plan->col_threads;
   p.row_rows = plan->row_rows;
   p.row_cols = plan->row_cols;
+  p.col_order = plan->col_order;
   EDX_TRY(hv_validate(s, vtype, &p));
   const int k = vtype == EDX_F32 ? 1 : 0;
-  s->plan_v[k][0] = p.mode;
-  s->plan_v[k][1] = p.col_cols;
-  s->plan_v[k][2] = p.col_threads;
-  s->plan_v[k][3] = p.row_rows;
-  s->plan_v[k][4] = p.row_cols;
-  s->plan_v[k][5] = p.col_blocks;
+  s->plan[k] = p;
   s->plan_set[k] = true;
   return EDX_OK;
 }
@@ -218,6 +215,7 @@ edx_status edx_autotune_hv(edx_sector* s, edx_vtype vtype, const void* v, void* 
     best->col_threads = bp.col_threads;
     best->row_rows = bp.row_rows;
     best->row_cols = bp.row_cols;
+    best->col_order = bp.col_order;
   }
   return EDX_OK;
 }

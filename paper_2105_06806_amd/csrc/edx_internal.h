@@ -71,6 +71,17 @@ struct SpinTables {
   uint8_t* pat = nullptr;     // [D] impurity pattern
 };
 
+// Launch plan of edx_hv (see edx_hv_plan).
+struct HvPlan {
+  int mode = 0;      // 0 small (whole sector in LDS), 1 two-pass, 2 fused column
+  int col_cols = 1;  // columns per block in the column pass
+  int col_threads = 512;
+  int row_rows = 64; // rows per slab in the row pass
+  int row_cols = 16; // columns per block in the row pass
+  int col_order = 0; // fused pass: 0 natural, 1 XCD-contiguous, 2 + pattern-sorted
+  int col_blocks = 0;  // blocks of the last pass (partial count)
+};
+
 }  // namespace edx
 
 struct edx_sector {
@@ -92,7 +103,10 @@ struct edx_sector {
   double amp_host[edx::kAmpTable];
   // launch plans of edx_hv per vtype (set by the autotuner or the caller)
   bool plan_set[2] = {false, false};
-  int plan_v[2][6] = {{0}};
+  edx::HvPlan plan[2];
+  // spin-down strings (columns of V) stably sorted by impurity pattern: the
+  // column order of the fused pass with col_order 2
+  int32_t* corder = nullptr;   // [ddw] device
   // lazily built neighbour sectors for the Green's function:
   // [spin][0] = N_s + 1 (particle), [spin][1] = N_s - 1 (hole)
   std::mutex nb_mu;
@@ -109,14 +123,6 @@ size_t sector_table_bytes(int ns, int nup, int ndw);
 void destroy_sector(edx_sector* s);
 
 // ---- hv.hip
-struct HvPlan {
-  int mode = 0;      // 0 small (whole sector in LDS), 1 two-pass, 2 fused column
-  int col_cols = 1;  // columns per block in the column pass
-  int col_threads = 512;
-  int row_rows = 64; // rows per slab in the row pass
-  int row_cols = 16; // columns per block in the row pass
-  int col_blocks = 0;  // blocks of the last pass (partial count)
-};
 HvPlan hv_plan(const edx_sector* s, int vtype);
 HvPlan hv_default_plan(const edx_sector* s, int vtype);
 edx_status hv_validate(const edx_sector* s, int vtype, HvPlan* p);

@@ -142,6 +142,36 @@ __device__ __forceinline__ void stage_cols(T* __restrict__ vs, const T* __restri
   for (; i < n; i += bd) vs[i] = at(i) * sc;
 }
 
+// nc (<= NC) arbitrary columns jc[0..nc) of a vector with column stride ld
+// into a dense LDS image (column c at c * dup).
+template <typename T, int NC>
+__device__ __forceinline__ void stage_list(T* __restrict__ vs, const T* __restrict__ v,
+                                           const int64_t (&jc)[NC], int nc, int64_t dup,
+                                           int64_t ld, T sc) {
+  const int64_t n = (int64_t)nc * dup;
+  auto at = [&](int64_t i) {
+    int64_t base = jc[0] * ld;
+    int64_t off = i;
+#pragma unroll
+    for (int c = 1; c < NC; ++c)
+      if (i >= c * dup) {
+        base = jc[c] * ld;
+        off = i - c * dup;
+      }
+    return v[base + off];
+  };
+  const int bd = blockDim.x;
+  int64_t i = threadIdx.x;
+  for (; i + 7 * bd < n; i += 8 * bd) {
+    T x[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) x[u] = at(i + u * bd);
+#pragma unroll
+    for (int u = 0; u < 8; ++u) vs[i + u * bd] = x[u] * sc;
+  }
+  for (; i < n; i += bd) vs[i] = at(i) * sc;
+}
+
 template <int W>
 __device__ __forceinline__ void load_row(const uint32_t* __restrict__ h, int64_t i,
                                          uint32_t (&e)[W]) {
@@ -270,26 +300,46 @@ template <typename T, int WUP, int WDW, int NC>
 __global__ __launch_bounds__(1024) void k_hv_fused(HvArgs<T> a, const T* __restrict__ v,
                                                    T* __restrict__ w,
                                                    const double* __restrict__ vscale,
-                                                   double* __restrict__ partial) {
+                                                   double* __restrict__ partial, int order,
+                                                   const int32_t* __restrict__ corder) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T* amp = reinterpret_cast<T*>(smem_raw);
   T* Wt = amp + kAmpTable;
   double* red = reinterpret_cast<double*>(Wt + 64);
   T* vs = reinterpret_cast<T*>(red + 16);
   const int64_t dup = a.dup, ld = a.ld;
-  const int64_t j0 = (int64_t)blockIdx.x * NC;
+  // Which columns: group cb = workgroup index (order 0), or XCD-contiguous
+  // numbering (order >= 1): workgroups go round-robin over the 8 XCDs, so
+  // workgroup b takes group x*q + min(x, r) + b/8 (x = b % 8) and the groups
+  // running at once on one XCD are consecutive; their spin-down neighbours
+  // overlap and are served by that XCD's L2.  Order 2 walks the columns
+  // sorted by impurity occupation, where consecutive columns share more
+  // neighbours.
+  int64_t cb = blockIdx.x;
+  if (order >= 1) {
+    const int64_t nblk = gridDim.x, q8 = nblk / 8, r8 = nblk % 8;
+    const int64_t x8 = blockIdx.x % 8;
+    cb = x8 * q8 + std::min<int64_t>(x8, r8) + blockIdx.x / 8;
+  }
+  const int64_t j0 = cb * NC;
   const int nc = (int)std::min<int64_t>(NC, a.ddw - j0);
+  int64_t jc[NC];   // this workgroup's columns (clamped copies past the end)
+#pragma unroll
+  for (int c = 0; c < NC; ++c) {
+    const int64_t jj = std::min<int64_t>(j0 + c, a.ddw - 1);
+    jc[c] = order == 2 ? (int64_t)__builtin_amdgcn_readfirstlane(corder[jj]) : jj;
+  }
   const T sc = vscale ? (T)(*vscale) : T(1);
   for (int i = threadIdx.x; i < kAmpTable; i += blockDim.x) amp[i] = a.amp[i];
   for (int i = threadIdx.x; i < 64; i += blockDim.x) Wt[i] = a.W[i];
-  stage_cols(vs, v + j0 * ld, nc, dup, ld, sc);
+  stage_list<T, NC>(vs, v, jc, nc, dup, ld, sc);
   gptr<T> gcol[NC][WDW];   // neighbour columns (block-uniform)
   T gamp[NC][WDW];         // their amplitudes times the vector scale
   T ed[NC];
   int pd[NC];
 #pragma unroll
   for (int c = 0; c < NC; ++c) {
-    const int64_t j = std::min<int64_t>(j0 + c, a.ddw - 1);
+    const int64_t j = jc[c];
     ed[c] = a.edw[j];
     pd[c] = a.pdw[j];
 #pragma unroll
@@ -337,7 +387,7 @@ __global__ __launch_bounds__(1024) void k_hv_fused(HvArgs<T> a, const T* __restr
         for (int k = 0; k < WDW; ++k) s2 += gamp[c][k] * g[c][k];
         const T res = acc[c] + (eu + ed[c] + Wt[pu + pd[c]]) * x + s2;
         if (ALL || c < nc) {
-          w[iu + (j0 + c) * ld] = res;
+          w[iu + jc[c] * ld] = res;
           dot += (double)x * (double)res;
         }
       }
@@ -348,7 +398,9 @@ __global__ __launch_bounds__(1024) void k_hv_fused(HvArgs<T> a, const T* __restr
   else
     rows(std::false_type{});
   for (int64_t i = dup + threadIdx.x; i < ld; i += blockDim.x)
-    for (int c = 0; c < nc; ++c) w[i + (j0 + c) * ld] = T(0);
+#pragma unroll
+    for (int c = 0; c < NC; ++c)
+      if (c < nc) w[i + jc[c] * ld] = T(0);
   if (partial) {
     const double s = block_sum(dot, red);
     if (threadIdx.x == 0) partial[blockIdx.x] = s;
@@ -460,6 +512,10 @@ HvPlan hv_default_plan(const edx_sector* s, int vtype) {
   p.col_threads = colb >= 48 * 1024 && c == 3 ? 1024 : 512;
   p.col_blocks = (int)((s->ddw + c - 1) / c);
   p.mode = 2;
+  // FP32: XCD-contiguous groups over pattern-sorted columns (L2 reuse of the
+  // spin-down neighbours); FP64 vectors are twice the size and did better
+  // with consecutive workgroups on different XCDs sharing the MALL
+  p.col_order = vtype == EDX_F32 ? 2 : 0;
   p.row_rows = (s->dup % 2 == 0) ? 128 : 64;
   p.row_cols = 8;
   return p;
@@ -477,6 +533,10 @@ edx_status hv_validate(const edx_sector* s, int vtype, HvPlan* p) {
   }
   if (p->mode != 1 && p->mode != 2) {
     set_error("hv plan: mode must be 0, 1 or 2");
+    return EDX_E_INVALID;
+  }
+  if (p->col_order < 0 || p->col_order > 2) {
+    set_error("hv plan: col_order must be 0, 1 or 2");
     return EDX_E_INVALID;
   }
   if (p->col_cols < 1 || p->col_cols > kColMax ||
@@ -505,14 +565,7 @@ edx_status hv_validate(const edx_sector* s, int vtype, HvPlan* p) {
 HvPlan hv_plan(const edx_sector* s, int vtype) {
   const int k = vtype == EDX_F32 ? 1 : 0;
   if (!s->plan_set[k]) return hv_default_plan(s, vtype);
-  HvPlan p;
-  p.mode = s->plan_v[k][0];
-  p.col_cols = s->plan_v[k][1];
-  p.col_threads = s->plan_v[k][2];
-  p.row_rows = s->plan_v[k][3];
-  p.row_cols = s->plan_v[k][4];
-  p.col_blocks = s->plan_v[k][5];
-  return p;
+  return s->plan[k];
 }
 
 int hv_partial_blocks(const edx_sector* s, int vtype) { return hv_plan(s, vtype).col_blocks; }
@@ -520,13 +573,19 @@ int hv_partial_blocks(const edx_sector* s, int vtype) { return hv_plan(s, vtype)
 namespace {
 
 
+struct FusedOrder {
+  int order;
+  const int32_t* corder;
+};
+
 template <typename T, int WUP, int WDW, int NC>
 edx_status launch_fused_k(const HvArgs<T>& a, int nblk, int nthr, size_t lds, hipStream_t st,
-                          const T* v, T* w, const double* vscale, double* partial) {
+                          const T* v, T* w, const double* vscale, double* partial,
+                          FusedOrder fo) {
   const void* kern = (const void*)k_hv_fused<T, WUP, WDW, NC>;
   EDX_HIP(hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
   hipLaunchKernelGGL((k_hv_fused<T, WUP, WDW, NC>), dim3(nblk), dim3(nthr), lds, st, a, v, w,
-                     vscale, partial);
+                     vscale, partial, fo.order, fo.corder);
   EDX_HIP(hipGetLastError());
   return EDX_OK;
 }
@@ -534,19 +593,19 @@ edx_status launch_fused_k(const HvArgs<T>& a, int nblk, int nthr, size_t lds, hi
 template <typename T, int WUP, int WDW>
 edx_status launch_fused_c(const HvArgs<T>& a, int ncol, int nblk, int nthr, size_t lds,
                           hipStream_t st, const T* v, T* w, const double* vscale,
-                          double* partial) {
+                          double* partial, FusedOrder fo) {
   switch (ncol) {
-    case 1: return launch_fused_k<T, WUP, WDW, 1>(a, nblk, nthr, lds, st, v, w, vscale, partial);
-    case 2: return launch_fused_k<T, WUP, WDW, 2>(a, nblk, nthr, lds, st, v, w, vscale, partial);
-    case 3: return launch_fused_k<T, WUP, WDW, 3>(a, nblk, nthr, lds, st, v, w, vscale, partial);
-    default: return launch_fused_k<T, WUP, WDW, 4>(a, nblk, nthr, lds, st, v, w, vscale, partial);
+    case 1: return launch_fused_k<T, WUP, WDW, 1>(a, nblk, nthr, lds, st, v, w, vscale, partial, fo);
+    case 2: return launch_fused_k<T, WUP, WDW, 2>(a, nblk, nthr, lds, st, v, w, vscale, partial, fo);
+    case 3: return launch_fused_k<T, WUP, WDW, 3>(a, nblk, nthr, lds, st, v, w, vscale, partial, fo);
+    default: return launch_fused_k<T, WUP, WDW, 4>(a, nblk, nthr, lds, st, v, w, vscale, partial, fo);
   }
 }
 
 template <typename T, int WUP>
 edx_status launch_col_w(const HvArgs<T>& a, bool fused, int nblk, int nthr, size_t lds,
                         hipStream_t st, const T* v, T* w, const double* vscale, double* partial,
-                        int ncol) {
+                        int ncol, FusedOrder fo) {
   if (!fused) {
     EDX_HIP(hipFuncSetAttribute((const void*)k_hv_col<T, WUP>,
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
@@ -556,9 +615,9 @@ edx_status launch_col_w(const HvArgs<T>& a, bool fused, int nblk, int nthr, size
     return EDX_OK;
   }
   switch (a.sdw) {
-    case 8: return launch_fused_c<T, WUP, 8>(a, ncol, nblk, nthr, lds, st, v, w, vscale, partial);
-    case 16: return launch_fused_c<T, WUP, 16>(a, ncol, nblk, nthr, lds, st, v, w, vscale, partial);
-    default: return launch_fused_c<T, WUP, 24>(a, ncol, nblk, nthr, lds, st, v, w, vscale, partial);
+    case 8: return launch_fused_c<T, WUP, 8>(a, ncol, nblk, nthr, lds, st, v, w, vscale, partial, fo);
+    case 16: return launch_fused_c<T, WUP, 16>(a, ncol, nblk, nthr, lds, st, v, w, vscale, partial, fo);
+    default: return launch_fused_c<T, WUP, 24>(a, ncol, nblk, nthr, lds, st, v, w, vscale, partial, fo);
   }
 }
 
@@ -625,10 +684,11 @@ edx_status launch_t(const edx_sector* s, const T* v, T* w, int64_t ld, const dou
       return EDX_E_INVALID;
   }
   const bool fused = p.mode == 2;
+  const FusedOrder fo{s->corder ? p.col_order : std::min(p.col_order, 1), s->corder};
   switch (a.sup) {
-    case 8: return launch_col_w<T, 8>(a, fused, nblk, nthr, lds, st, v, w, vscale, partial, p.col_cols);
-    case 16: return launch_col_w<T, 16>(a, fused, nblk, nthr, lds, st, v, w, vscale, partial, p.col_cols);
-    default: return launch_col_w<T, 24>(a, fused, nblk, nthr, lds, st, v, w, vscale, partial, p.col_cols);
+    case 8: return launch_col_w<T, 8>(a, fused, nblk, nthr, lds, st, v, w, vscale, partial, p.col_cols, fo);
+    case 16: return launch_col_w<T, 16>(a, fused, nblk, nthr, lds, st, v, w, vscale, partial, p.col_cols, fo);
+    default: return launch_col_w<T, 24>(a, fused, nblk, nthr, lds, st, v, w, vscale, partial, p.col_cols, fo);
   }
 }
 
@@ -671,7 +731,11 @@ edx_status hv_autotune(edx_sector* s, int vtype, const void* v, void* w, int64_t
       p.mode = 2;
       p.col_cols = cc;
       p.col_threads = th;
-      add(p);
+      for (int co : {0, 1, 2}) {
+        HvPlan r = p;
+        r.col_order = co;
+        add(r);
+      }
       for (int rr : {32, 64, 128})
         for (int rc : {8, 32}) {
           HvPlan q = p;
@@ -708,12 +772,7 @@ edx_status hv_autotune(edx_sector* s, int vtype, const void* v, void* w, int64_t
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   const int k = vtype == EDX_F32 ? 1 : 0;
-  s->plan_v[k][0] = bp.mode;
-  s->plan_v[k][1] = bp.col_cols;
-  s->plan_v[k][2] = bp.col_threads;
-  s->plan_v[k][3] = bp.row_rows;
-  s->plan_v[k][4] = bp.row_cols;
-  s->plan_v[k][5] = bp.col_blocks;
+  s->plan[k] = bp;
   s->plan_set[k] = true;
   if (best) *best = bp;
   if (best_us) *best_us = best_t;

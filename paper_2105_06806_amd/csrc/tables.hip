@@ -221,6 +221,7 @@ void destroy_sector(edx_sector* s) {
   dfree(s, s->w64);
   dfree(s, s->w32);
   dfree(s, s->binom);
+  dfree(s, s->corder);
   delete s;
 }
 
@@ -238,6 +239,7 @@ size_t sector_table_bytes(int ns, int nup, int ndw) {
     b += ((size_t)4 << ns) + D * (4 + 24 * 4 + 8 + 4 + 1) + 6 * a;
   }
   b += (kMaxNs + 1) * (kMaxNs + 1) * 4 + 256 * 12 + 64 * 12 + 16 + 8 * kMaxNs + 8 * a;
+  b += (size_t)comb(ns, ndw) * 4 + a;   // column order
   return b;
 }
 
@@ -288,6 +290,20 @@ edx_status build_sector_impl(const Model& m, int nup, int ndw, hipStream_t st,
   S->dim = S->dup * S->ddw;
   S->ld = vec_ld(S->dup);
   S->vlen = S->ld * S->ddw;
+
+  // column order of the fused H.v pass: spin-down strings stably sorted by
+  // impurity pattern (for Norb = 1: impurity empty, then occupied)
+  {
+    std::vector<uint8_t> pat(S->ddw);
+    EDX_HIP(hipMemcpyAsync(pat.data(), S->dw.pat, S->ddw, hipMemcpyDeviceToHost, st));
+    EDX_HIP(hipStreamSynchronize(st));
+    std::vector<int32_t> ord(S->ddw);
+    for (int64_t j = 0; j < S->ddw; ++j) ord[j] = (int32_t)j;
+    std::stable_sort(ord.begin(), ord.end(), [&](int32_t x, int32_t y) { return pat[x] < pat[y]; });
+    EDX_TRY(dalloc(S.get(), &S->corder, ord.size() * sizeof(int32_t)));
+    EDX_HIP(hipMemcpyAsync(S->corder, ord.data(), ord.size() * sizeof(int32_t),
+                           hipMemcpyHostToDevice, st));
+  }
 
   // signed amplitude table and pattern interaction table
   double amp[kAmpTable];

@@ -40,7 +40,7 @@ class _Model(ctypes.Structure):
 class HvPlan(ctypes.Structure):
     _fields_ = [("mode", ctypes.c_int32), ("col_cols", ctypes.c_int32),
                 ("col_threads", ctypes.c_int32), ("row_rows", ctypes.c_int32),
-                ("row_cols", ctypes.c_int32)]
+                ("row_cols", ctypes.c_int32), ("col_order", ctypes.c_int32)]
 
 
 class LanczosOpts(ctypes.Structure):
