@@ -101,6 +101,42 @@ def traffic_from_profile(plan):
     return float(mt.group(1)), "ok"
 
 
+def copy_bandwidth(torch, nbytes=1 << 30, reps=10):
+    """Device-to-device copy GB/s (read + write) of a 1 GiB buffer: the
+    streaming rate this GPU reaches with a plain copy."""
+    x = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda").uniform_()
+    y = torch.empty_like(x)
+    for _ in range(3):
+        y.copy_(x)
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    a.record()
+    for _ in range(reps):
+        y.copy_(x)
+    b.record()
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b) / reps
+    del x, y
+    return 2 * nbytes / (ms * 1e-3) / 1e9
+
+
+def bench_hv_o2(edx, torch, a):
+    """FP32 H.v on the Norb=2, Nbath=7 (Ns=16) half-filled sector."""
+    from paper_2105_06806_amd import inputs
+    m, [sec] = inputs.workload("ns16o2")
+    S = edx.build_sector(m, *sec)
+    gen = torch.Generator(device="cuda").manual_seed(2)
+    v = edx.pad(S, torch.rand(S.dim, dtype=torch.float32, device="cuda", generator=gen) * 2 - 1)
+    w = torch.empty_like(v)
+    plan, _ = edx.autotune_hv(S, v, w, reps=a.tune_reps, ld=S.ld)
+    ms, _ = time_hv(edx, torch, S, v, w, a.steps, a.warmup, ld=S.ld)
+    gbs = S.dim * 8 / (ms.mean() * 1e-3) / 1e9
+    return {"workload": f"H.v, Norb=2 Nbath=7 (Ns=16) 8/8, D={S.dim}, FP32, hop widths "
+                        f"{S.hop_nnz(0)[1]}/{S.hop_nnz(1)[1]}",
+            "us": round(float(ms.mean()) * 1e3, 1), "gbs": round(gbs, 1),
+            "frac": round(gbs / HBM_PEAK_GBS, 4), "plan": plan}
+
+
 def cpu_baseline(m, sec, elem_bytes, budget_s=15.0):
     """The oracle's row-by-row H.v on a bounded sample of output rows, one core."""
     from oracle import fock
@@ -119,10 +155,18 @@ def cpu_baseline(m, sec, elem_bytes, budget_s=15.0):
     fock.hv_rows(m, *sec, v, rows)
     dt = time.perf_counter() - t0
     rate = n2 / dt
+    cpu = "unknown CPU"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                cpu = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
     return {"value": round(rate * elem_bytes / 1e9, 4), "unit": "GB/s", "cores": 1, "kind": "oracle",
             "sample": f"{n2} random output rows of the Ns=16 8/8 sector (FP64, second quantisation "
-                      f"per row), {dt:.1f} s; value = rows/s x {elem_bytes} B (the GPU's algorithmic "
-                      f"bytes per FP32 element)",
+                      f"per row), {dt:.1f} s on one core of {cpu} ({os.cpu_count()} visible); "
+                      f"value = rows/s x {elem_bytes} B (the GPU's algorithmic bytes per FP32 element)",
             "rows_per_s": round(rate, 1), "full_hv_s_extrapolated": round(D / rate, 1)}
 
 
@@ -300,6 +344,7 @@ def main():
         vd, wd = edx.unpad(S, v), torch.empty(D, dtype=tdt, device="cuda")
         msd, _ = time_hv(edx, torch, S, vd, wd, max(5, a.steps // 5), 2)
         res[dt_name] = {"ms_mean": float(ms.mean()), "ms_min": float(ms.min()), "wall_s": wall,
+                        "ms_median": float(np.median(ms)),
                         "plan": plan, "gbs": alg / (ms.mean() * 1e-3) / 1e9, "alg_bytes": alg,
                         "dense_us": float(msd.mean()) * 1e3}
         log(f"{dt_name}: {ms.mean() * 1e3:.1f} us/H.v, {res[dt_name]['gbs']:.0f} GB/s algorithmic "
@@ -308,6 +353,8 @@ def main():
         torch.cuda.empty_cache()
     r32 = res["f32"]
     traffic, tstate = traffic_from_profile(r32["plan"])
+    copy_gbs = copy_bandwidth(torch)
+    log(f"copy: {copy_gbs:.0f} GB/s")
     single = r32["plan"]["mode"] in (0, 2)
     out = {
         "metric": "H·v GB/s & %HBM peak at Ns=16; batched solves/s, p50/p99 vs plain",
@@ -336,9 +383,21 @@ def main():
                      "traffic": traffic if single else None,
                      "kernel": "k_hv_fused<float,8,8,3>" if single else "k_hv_row + k_hv_col",
                      "traffic_source": tstate},
+        # the three views of the headline: algorithmic bytes / time, counter
+        # (MALL/HBM-side) bytes / time, each against 8 TB/s and a plain copy
+        "bandwidth": {
+            "effective_gbs": round(r32["gbs"], 1),
+            "hbm_side_gbs": round(traffic / (r32["ms_mean"] * 1e-3) / 1e9, 1)
+            if (traffic and single) else None,
+            "copy_gbs": round(copy_gbs, 1),
+            "effective_frac_of_copy": round(r32["gbs"] / copy_gbs, 4),
+            "hbm_side_frac_of_peak": round(traffic / (r32["ms_mean"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
+            if (traffic and single) else None,
+            "median_us": round(r32["ms_median"] * 1e3, 1)},
     }
     if not a.quick:
-        for name, fn in (("ns12", lambda: bench_ns12(edx)), ("ns15o3", lambda: bench_ns15o3(edx)),
+        for name, fn in (("hv_ns16o2", lambda: bench_hv_o2(edx, torch, a)),
+                         ("ns12", lambda: bench_ns12(edx)), ("ns15o3", lambda: bench_ns15o3(edx)),
                          ("batch", lambda: bench_batch(edx, torch)),
                          ("serve", lambda: bench_serve(edx, torch, a.full))):
             t0 = time.perf_counter()

@@ -304,6 +304,31 @@ def test_hv_headline_sector_sampled(edx, dtype):
         assert bool((w.view(S.ddw, S.ld)[:, S.dup:] == 0).all()), plan
 
 
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_hv_ns16_two_orbital_sampled(edx, dtype):
+    """Norb=2, Nbath=7 (Ns=16) half filling, the second H.v headline sector
+    (wider hop rows): default plan on the padded layout, sampled outputs
+    against the oracle's row-by-row product."""
+    import torch
+    m, [sec] = inputs.workload("ns16o2")
+    S = edx.build_sector(m, *sec)
+    tdt = torch.float64 if dtype == "f64" else torch.float32
+    gen = torch.Generator(device="cuda").manual_seed(6)
+    vd = torch.rand(S.dim, dtype=tdt, device="cuda", generator=gen) * 2 - 1
+    v = edx.pad(S, vd)
+    w = torch.full_like(v, float("nan"))
+    edx.hv(S, v, w, ld=S.ld)
+    torch.cuda.synchronize()
+    rows = np.random.default_rng(4).choice(S.dim, size=1500, replace=False)
+    rows = np.concatenate([rows, [0, S.dim - 1, S.dup - 1, S.dup]])
+    ref = fock.hv_rows(m, *sec, vd.double().cpu().numpy(), rows)
+    pos = rows % S.dup + (rows // S.dup) * S.ld
+    got = w[torch.as_tensor(pos, device="cuda")].double().cpu().numpy()
+    tol = (1e-13 if dtype == "f64" else 2e-6) * _hscale(m)
+    assert np.abs(got - ref).max() <= tol
+    assert bool((w.view(S.ddw, S.ld)[:, S.dup:] == 0).all())
+
+
 def _batch_sectors(edx):
     """Mixed sizes: Ns=8, 10 and 12 sectors of several bath sets."""
     jobs = []

@@ -93,7 +93,7 @@ def test_explicit_equals_kron_decomposition(m, sec):
     assert np.allclose(K.matvec(x), H @ x, rtol=0, atol=1e-12)
 
 
-@pytest.mark.parametrize("m,sec", KRON_CASES[:3])
+@pytest.mark.parametrize("m,sec", KRON_CASES)
 def test_sampled_rows(m, sec):
     H = fock.explicit_hamiltonian(m, *sec)
     x = np.random.default_rng(1).standard_normal(H.shape[0])
