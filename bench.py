@@ -88,17 +88,17 @@ def traffic_from_profile(plan):
         return None, None
     txt = open(PROFILE_PMC).read()
     mh = re.search(r"source_sha256:\s*([0-9a-f]{64})", txt)
-    mt = re.search(r"traffic_bytes_per_launch:\s*([0-9.eE+]+)", txt)
-    mp = re.search(r"plan:\s*([0-9,]+)", txt)
-    if not mh or not mt or not mp:
+    if not mh:
         return None, None
     cur = hashlib.sha256(open(HV_SRC, "rb").read()).hexdigest()
     if cur != mh.group(1):
         return None, "stale"
     keys = ("mode", "col_cols", "col_threads", "row_rows", "row_cols", "col_order")
-    if [int(x) for x in mp.group(1).split(",")] != [int(plan[k]) for k in keys]:
-        return None, "profiled plan " + mp.group(1)
-    return float(mt.group(1)), "ok"
+    want = ",".join(str(int(plan[k])) for k in keys)
+    for mp in re.finditer(r"traffic\[([0-9,]+)\]:\s*([0-9.eE+]+)", txt):
+        if mp.group(1) == want:
+            return float(mp.group(2)), "ok"
+    return None, "plan not profiled"
 
 
 def copy_bandwidth(torch, nbytes=1 << 30, reps=10):
