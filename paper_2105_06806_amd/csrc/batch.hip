@@ -529,6 +529,9 @@ edx_status batch_run(const edx_sector* const* secs, int n, const edx_lanczos_opt
   if (nwide > 0) {
     edx_lanczos_opts q = *o;
     q.reorth = 0;
+    // helper threads start on device 0: they are given the caller's device
+    int dev = 0;
+    EDX_HIP(hipGetDevice(&dev));
     const int nst = std::min(kWideStreams, nwide);
     std::vector<hipStream_t> sts(nst, st);
     std::vector<hipEvent_t> done(nst, nullptr);
@@ -545,8 +548,12 @@ edx_status batch_run(const edx_sector* const* secs, int n, const edx_lanczos_opt
     std::vector<edx_status> tst(nst, EDX_OK);
     std::vector<std::string> terr(nst);
     auto worker = [&](int t) {
-      int dev = 0;
-      if (hipGetDevice(&dev) == hipSuccess) (void)hipSetDevice(dev);
+      if (t > 0 && hipSetDevice(dev) != hipSuccess) {
+        tst[t] = EDX_E_DEVICE;
+        terr[t] = "batch: hipSetDevice failed in a helper thread";
+        next.store(nwide);
+        return;
+      }
       for (;;) {
         const int k = next.fetch_add(1);
         if (k >= nwide) break;
