@@ -10,9 +10,12 @@ design notes):
     norb + a*nbath + nu;
   * sector index i = i_up + i_dw * D_up (0-based; eq. SectorIndxDecomp read
     with the spin-down offset that eq. Vmatrix states);
-  * H is eq. Ham1 restricted to the normal bath and the density-density
-    interaction, with plain U n_up n_dw (no Hartree constant) and the chemical
-    potential acting on the impurity only.
+  * H is eq. Ham1 restricted to the normal bath, with plain U n_up n_dw (no
+    Hartree constant) and the chemical potential acting on the impurity only;
+    the spin-exchange and pair-hopping terms of eq. Ham1 (couplings Jx, Jp,
+    default 0) act on the impurity orbitals exactly as printed there:
+      - Jx sum_{a != b} d+_{a up} d_{a dw} d+_{b dw} d_{b up}
+      + Jp sum_{a != b} d+_{a up} d+_{a dw} d_{b dw} d_{b up}.
 """
 from __future__ import annotations
 
@@ -152,6 +155,40 @@ def hopping_terms(model):
     return out
 
 
+def nondiagonal_terms(model):
+    """The spin-exchange and pair-hopping operators of eq. Ham1 as
+    (amplitude, [(mode, creator?), ...] listed left to right), for every
+    ordered pair of distinct impurity orbitals."""
+    ns, norb = ns_of(model), model["norb"]
+    jx, jp = float(model.get("Jx", 0.0)), float(model.get("Jp", 0.0))
+    up = lambda a: a
+    dw = lambda a: a + ns
+    out = []
+    for a in range(norb):
+        for b in range(norb):
+            if a == b:
+                continue
+            if jx != 0.0:
+                out.append((-jx, [(up(a), True), (dw(a), False), (dw(b), True), (up(b), False)]))
+            if jp != 0.0:
+                out.append((jp, [(up(a), True), (dw(a), True), (dw(b), False), (up(b), False)]))
+    return out
+
+
+def apply_product(I, ops):
+    """A product of creators/annihilators (listed left to right) applied to
+    |I>: the rightmost acts first.  Returns (valid, I_new, sign)."""
+    valid = np.ones(I.shape, dtype=bool)
+    sign = np.ones(I.shape, dtype=np.int64)
+    cur = I.copy()
+    for (m, creator) in reversed(ops):
+        ok, nxt, sg = (apply_cdag if creator else apply_c)(cur, m)
+        valid &= ok
+        sign *= sg
+        cur = np.where(ok, nxt, cur)
+    return valid, cur, sign
+
+
 def explicit_hamiltonian(model, nup, ndw):
     """Sector Hamiltonian H_S as CSR, built term by term on full 2Ns-bit strings.
 
@@ -167,6 +204,12 @@ def explicit_hamiltonian(model, nup, ndw):
         rows.append(_index_of(up, dw, ns, Inew[j]))
         cols.append(j)
         vals.append(V * sgn[j].astype(np.float64))
+    for (amp, ops) in nondiagonal_terms(model):
+        valid, Inew, sgn = apply_product(I, ops)
+        j = np.nonzero(valid)[0]
+        rows.append(_index_of(up, dw, ns, Inew[j]))
+        cols.append(j)
+        vals.append(amp * sgn[j].astype(np.float64))
     H = sp.coo_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))),
                       shape=(D, D)).tocsr()
     H.sum_duplicates()
@@ -189,6 +232,12 @@ def hv_rows(model, nup, ndw, v, rows):
         k = np.nonzero(valid)[0]
         j = _index_of(up, dw, ns, Inew[k])
         out[k] += V * sgn[k] * v[j]
+    # H is symmetric: row i of the interaction terms is the operator applied to |i>
+    for (amp, ops) in nondiagonal_terms(model):
+        valid, Inew, sgn = apply_product(I, ops)
+        k = np.nonzero(valid)[0]
+        j = _index_of(up, dw, ns, Inew[k])
+        out[k] += amp * sgn[k] * v[j]
     return out
 
 

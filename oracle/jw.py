@@ -52,6 +52,13 @@ def fock_hamiltonian(model):
                 H += model["Ust"] * n[a] @ n[ns + b]
         for b in range(a + 1, norb):
             H += (model["Ust"] - model["Jh"]) * (n[a] @ n[b] + n[ns + a] @ n[ns + b])
+    # spin exchange and pair hopping (eq. Ham1), products of the matrices above
+    jx, jp = model.get("Jx", 0.0), model.get("Jp", 0.0)
+    for a in range(norb):
+        for b in range(norb):
+            if a != b:
+                H -= jx * cd[a] @ c[ns + a] @ cd[ns + b] @ c[b]
+                H += jp * cd[a] @ cd[ns + a] @ c[ns + b] @ c[b]
     return H, c
 
 

@@ -64,6 +64,10 @@ class KronH:
     """Matrix-free H for one sector built from the per-spin factors."""
 
     def __init__(self, model, nup, ndw):
+        if model.get("Jx", 0.0) != 0.0 or model.get("Jp", 0.0) != 0.0:
+            # spin exchange and pair hopping move electrons of both spins at once:
+            # not a Kronecker sum (use fock.explicit_hamiltonian / hv_rows)
+            raise ValueError("KronH covers the density-density interaction only")
         self.Hup = spin_hamiltonian(model, nup, 0)
         self.Hdw = spin_hamiltonian(model, ndw, 1)
         Eu, pu = spin_diagonal(model, nup)

@@ -56,9 +56,11 @@ def _plain_bath(rng, nbath, elo, ehi, vlo, vhi):
 
 
 def make_model(norb, nbath, U, Ust=None, Jh=0.0, eps_imp=None, xmu=0.0,
-               seed=0, symmetric=True, elo=-1.0, ehi=1.0, vlo=0.2, vhi=0.6):
+               seed=0, symmetric=True, elo=-1.0, ehi=1.0, vlo=0.2, vhi=0.6, Jx=0.0, Jp=0.0):
     """Draw one bath realisation.  ``eps_imp`` defaults to the half-filling
-    Hartree shift -(U/2 + (norb-1)(2U'-J)/2), which is -U/2 for norb=1."""
+    Hartree shift -(U/2 + (norb-1)(2U'-J)/2), which is -U/2 for norb=1.
+    ``Jx``, ``Jp``: spin-exchange and pair-hopping couplings (0: density-density
+    interaction only)."""
     rng = np.random.default_rng(seed)
     if Ust is None:
         Ust = U - 2.0 * Jh
@@ -74,6 +76,7 @@ def make_model(norb, nbath, U, Ust=None, Jh=0.0, eps_imp=None, xmu=0.0,
         "eps_imp": np.full(norb, float(eps_imp)), "xmu": float(xmu),
         "eps_bath": eb, "vhyb": vb,
         "U": float(U), "Ust": float(Ust), "Jh": float(Jh),
+        "Jx": float(Jx), "Jp": float(Jp),
     }
 
 
