@@ -56,8 +56,12 @@ typedef enum {
 /* storage type of v, w, Krylov vectors and psi0; scalars are always FP64 */
 typedef enum { EDX_F64 = 0, EDX_F32 = 1 } edx_vtype;
 
-/* Normal-bath impurity model, density-density part of eq. Ham1
- * (J_X = J_P = 0).  Ns = norb*(nbath+1) must be <= 24, norb <= 3. */
+/* Normal-bath impurity model of eq. Ham1: one-body levels, hybridisation,
+ * the density-density interaction, and the spin-exchange and pair-hopping
+ * terms  - Jx sum_{a!=b} d+_{a up} d_{a dw} d+_{b dw} d_{b up}
+ *        + Jp sum_{a!=b} d+_{a up} d+_{a dw} d_{b dw} d_{b up}
+ * on the impurity orbitals (Jx = Jp = 0: density-density only).
+ * Ns = norb*(nbath+1) must be <= 24, norb <= 3. */
 typedef struct {
   int32_t norb;
   int32_t nbath;
@@ -68,6 +72,8 @@ typedef struct {
   double Ust;              /* U': inter-orbital opposite spin            */
   double Jh;               /* J: same-spin inter-orbital gets U' - J     */
   double xmu;              /* chemical potential on the impurity levels  */
+  double Jx;               /* spin exchange J_X                          */
+  double Jp;               /* pair hopping J_P                           */
 } edx_model;
 
 typedef struct edx_sector edx_sector;

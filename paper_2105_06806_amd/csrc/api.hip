@@ -55,6 +55,8 @@ static edx_status check_model(const edx_model* m, Model* out) {
   out->Ust = m->Ust;
   out->Jh = m->Jh;
   out->xmu = m->xmu;
+  out->Jx = m->Jx;
+  out->Jp = m->Jp;
   for (double x : out->eps_imp)
     if (!std::isfinite(x)) return invalid("non-finite eps_imp");
   for (double x : out->eps_bath)
@@ -62,7 +64,7 @@ static edx_status check_model(const edx_model* m, Model* out) {
   for (double x : out->vhyb)
     if (!std::isfinite(x)) return invalid("non-finite vhyb");
   if (!std::isfinite(m->U) || !std::isfinite(m->Ust) || !std::isfinite(m->Jh) ||
-      !std::isfinite(m->xmu))
+      !std::isfinite(m->xmu) || !std::isfinite(m->Jx) || !std::isfinite(m->Jp))
     return invalid("non-finite interaction parameter");
   return EDX_OK;
 }

@@ -458,6 +458,12 @@ int device_cus() {
 
 int64_t batch_wide_default() { return 2000000; }
 
+// Jobs of the whole-GPU path: D >= wide_min, and every sector with spin
+// exchange or pair hopping (the lanes implement the spin-separable H only).
+static bool is_wide(const edx_sector* s, int64_t wide_min) {
+  return s->nd || (wide_min > 0 && s->dim >= wide_min);
+}
+
 edx_status batch_run(const edx_sector* const* secs, int n, const edx_lanczos_opts* o,
                      const int* ccols, const int* rcols, int L, int64_t wide_min, void* ws,
                      size_t ws_bytes, edx_batch_result* res, hipStream_t st,
@@ -474,14 +480,16 @@ edx_status batch_run(const edx_sector* const* secs, int n, const edx_lanczos_opt
   // the lane jobs, which lanes take from the queue largest first
   std::vector<int> order(n);
   for (int i = 0; i < n; ++i) order[i] = i;
-  std::stable_sort(order.begin(), order.end(),
-                   [&](int x, int y) { return secs[x]->dim > secs[y]->dim; });
+  std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
+    const bool wx = is_wide(secs[x], wide_min), wy = is_wide(secs[y], wide_min);
+    return wx != wy ? wx : secs[x]->dim > secs[y]->dim;
+  });
   int nwide = 0;
   size_t wide_ws = 0;
   int64_t dmax_n = 0, colmax = 1;
   for (int k = 0; k < n; ++k) {
     const edx_sector* s = secs[order[k]];
-    if (wide_min > 0 && s->dim >= wide_min) {
+    if (is_wide(s, wide_min)) {
       ++nwide;
       wide_ws = std::max(wide_ws, lanczos_workspace_bytes(s, vtype, o->niter, 0));
     } else {
@@ -747,7 +755,7 @@ size_t batch_workspace_bytes(const edx_sector* const* secs, int n, int vtype, in
   int64_t dn = 0;
   int nl = 0;
   for (int i = 0; i < n; ++i) {
-    if (wide_min > 0 && secs[i]->dim >= wide_min) {
+    if (is_wide(secs[i], wide_min)) {
       ww = std::max(ww, lanczos_workspace_bytes(secs[i], vtype, kMaxBatchIter, 0));
     } else {
       dn = std::max(dn, secs[i]->dim);

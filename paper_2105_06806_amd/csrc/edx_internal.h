@@ -21,6 +21,7 @@ constexpr uint32_t kPadPair = 0x7Fu;         // pair index of padding entries
 constexpr int kAmpTable = 256;               // signed amplitude per (pair, sign)
 constexpr int kMaxPartials = 2048;           // partial sums per reduction
 constexpr int kReduceSlots = 8;              // dots reduced by one kernel
+constexpr int kNdMaxBlocks = 2048;           // workgroups of the H_nd pass
 
 void set_error(const std::string& msg);
 
@@ -54,6 +55,7 @@ struct Model {
   int norb = 0, nbath = 0, ns = 0;
   std::vector<double> eps_imp, eps_bath, vhyb;
   double U = 0, Ust = 0, Jh = 0, xmu = 0;
+  double Jx = 0, Jp = 0;   // spin exchange, pair hopping (eq. Ham1)
 };
 
 // Tables of one spin species of a sector, device resident.
@@ -89,6 +91,7 @@ struct edx_sector {
   edx::Allocator alloc;      // where the device tables came from
   int nup = 0, ndw = 0;
   int64_t dup = 0, ddw = 0, dim = 0;
+  bool nd = false;           // spin exchange / pair hopping present (norb >= 2)
   int64_t ld = 0;            // column stride of the library's Krylov vectors
   int64_t vlen = 0;          // ld * ddw elements per Krylov vector
   int device = 0;

@@ -480,6 +480,88 @@ __global__ __launch_bounds__(256) void k_hv_row(HvArgs<T> a, const T* __restrict
   }
 }
 
+// ---------------------------------------------------------------- H_nd pass
+// Spin exchange and pair hopping of eq. Ham1 (impurity orbitals a != b):
+//   X_ab = d+_{a up} d_{a dw} d+_{b dw} d_{b up}   (amplitude -Jx)
+//   P_ab = d+_{a up} d+_{a dw} d_{b dw} d_{b up}   (amplitude +Jp)
+// They move electrons of both spins at once, so they are no Kronecker sum:
+// this pass adds them to w after the spin-separable passes.  H is real
+// symmetric, so row i of the term is the operator applied to |i>: for output
+// element (s_up, s_dw) every term whose occupations allow it gives one source
+// element (rank_up(s_up'), rank_dw(s_dw')), with the sign of Sec. 2.3 taken
+// operator by operator (right to left) on the full string, up modes first.
+// The N_up - 1 spin-up electrons that every spin-down operator of a term
+// passes appear twice and cancel, so only per-spin parities below the
+// touched levels remain.  The impurity levels are the lowest bits, so the
+// source ranks are close to the output's and the gathers hit in cache.
+template <typename T>
+struct NdArgs {
+  int64_t dup, ddw, ld;
+  const uint32_t* __restrict__ mapup;
+  const uint32_t* __restrict__ mapdw;
+  const int32_t* __restrict__ rankup;
+  const int32_t* __restrict__ rankdw;
+  int norb;
+  T jx, jp;
+};
+
+__device__ __forceinline__ int parity_below(uint32_t s, int m) {
+  return __popc(s & ((1u << m) - 1u)) & 1;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_hv_nd(NdArgs<T> a, const T* __restrict__ v,
+                                               T* __restrict__ w,
+                                               const double* __restrict__ vscale,
+                                               double* __restrict__ partial) {
+  __shared__ double red[16];
+  const T sc = vscale ? (T)(*vscale) : T(1);
+  double dot = 0.0;
+  for (int64_t j = blockIdx.x; j < a.ddw; j += gridDim.x) {
+    const uint32_t sd = a.mapdw[j];
+    for (int64_t i = threadIdx.x; i < a.dup; i += blockDim.x) {
+      const uint32_t su = a.mapup[i];
+      T acc = T(0);
+      for (int p = 0; p < a.norb; ++p) {
+        for (int q = 0; q < a.norb; ++q) {
+          if (p == q) continue;
+          const uint32_t bp = 1u << p, bq = 1u << q;
+          // X_pq: d_{q up}, d+_{q dw}, d_{p dw}, d+_{p up}
+          if (a.jx != T(0) && (su & bq) && !(su & bp) && (sd & bp) && !(sd & bq)) {
+            const uint32_t su1 = su ^ bq, sd1 = sd | bq;
+            const int par = parity_below(su, q) ^ parity_below(sd, q) ^ parity_below(sd1, p) ^
+                            parity_below(su1, p);
+            const int64_t src = (int64_t)a.rankup[su1 | bp] + (int64_t)a.rankdw[sd1 ^ bp] * a.ld;
+            const T x = v[src];
+            acc += par ? a.jx * x : -a.jx * x;
+          }
+          // P_pq: d_{q up}, d_{q dw}, d+_{p dw}, d+_{p up}
+          if (a.jp != T(0) && (su & bq) && (sd & bq) && !(su & bp) && !(sd & bp)) {
+            const uint32_t su1 = su ^ bq, sd1 = sd ^ bq;
+            const int par = parity_below(su, q) ^ parity_below(sd, q) ^ parity_below(sd1, p) ^
+                            parity_below(su1, p);
+            const int64_t src = (int64_t)a.rankup[su1 | bp] + (int64_t)a.rankdw[sd1 | bp] * a.ld;
+            const T x = v[src];
+            acc += par ? -a.jp * x : a.jp * x;
+          }
+        }
+      }
+      const int64_t e = i + j * a.ld;
+      const T add = acc * sc;
+      w[e] += add;
+      if (partial) dot += (double)(v[e] * sc) * (double)add;
+    }
+  }
+  if (partial) {
+    const double s2 = block_sum(dot, red);
+    if (threadIdx.x == 0) partial[blockIdx.x] = s2;
+  }
+}
+
+int nd_blocks(const edx_sector* s) {
+  return s->nd ? (int)std::min<int64_t>(s->ddw, kNdMaxBlocks) : 0;
+}
+
 // ---------------------------------------------------------------- planning
 namespace {
 
@@ -568,7 +650,11 @@ HvPlan hv_plan(const edx_sector* s, int vtype) {
   return s->plan[k];
 }
 
-int hv_partial_blocks(const edx_sector* s, int vtype) { return hv_plan(s, vtype).col_blocks; }
+// partial sums of <v, Hv>: the last spin-separable pass's blocks, then the
+// H_nd pass's
+int hv_partial_blocks(const edx_sector* s, int vtype) {
+  return hv_plan(s, vtype).col_blocks + nd_blocks(s);
+}
 
 namespace {
 
@@ -708,10 +794,27 @@ edx_status hv_launch(const edx_sector* s, int vtype, const void* v, void* w, int
       (((reinterpret_cast<uintptr_t>(v) | reinterpret_cast<uintptr_t>(w)) & 15u) || (ld & 1)))
     p.row_rows = 64;
   if (vtype == EDX_F64)
-    return launch_t<double>(s, static_cast<const double*>(v), static_cast<double*>(w), ld, vscale,
-                            partial, st, p);
-  return launch_t<float>(s, static_cast<const float*>(v), static_cast<float*>(w), ld, vscale,
-                         partial, st, p);
+    EDX_TRY(launch_t<double>(s, static_cast<const double*>(v), static_cast<double*>(w), ld,
+                             vscale, partial, st, p));
+  else
+    EDX_TRY(launch_t<float>(s, static_cast<const float*>(v), static_cast<float*>(w), ld, vscale,
+                            partial, st, p));
+  if (!s->nd) return EDX_OK;
+  const int nb = nd_blocks(s);
+  double* pnd = partial ? partial + p.col_blocks : nullptr;
+  if (vtype == EDX_F64) {
+    const NdArgs<double> na{s->dup, s->ddw, ld, s->up.map, s->dw.map, s->up.rank, s->dw.rank,
+                            s->model.norb, s->model.Jx, s->model.Jp};
+    hipLaunchKernelGGL(k_hv_nd<double>, dim3(nb), dim3(256), 0, st, na,
+                       static_cast<const double*>(v), static_cast<double*>(w), vscale, pnd);
+  } else {
+    const NdArgs<float> na{s->dup, s->ddw, ld, s->up.map, s->dw.map, s->up.rank, s->dw.rank,
+                           s->model.norb, (float)s->model.Jx, (float)s->model.Jp};
+    hipLaunchKernelGGL(k_hv_nd<float>, dim3(nb), dim3(256), 0, st, na,
+                       static_cast<const float*>(v), static_cast<float*>(w), vscale, pnd);
+  }
+  EDX_HIP(hipGetLastError());
+  return EDX_OK;
 }
 
 edx_status hv_autotune(edx_sector* s, int vtype, const void* v, void* w, int64_t ld, int reps,

@@ -414,7 +414,7 @@ size_t green_workspace_bytes(const edx_sector* s, int vtype, int ngf) {
   }
   // hv partial blocks of a neighbour sector: bounded by its column count
   const int64_t ddw_max = std::max({comb(ns, s->ndw - 1), comb(ns, s->ndw), comb(ns, s->ndw + 1)});
-  const int hvb = (int)std::max<int64_t>(kMaxPartials, ddw_max + 8);
+  const int hvb = (int)std::max<int64_t>(kMaxPartials, ddw_max + 8 + kNdMaxBlocks);
   return lanczos_ws_layout(dmax, vtype, ngf, 0, hvb, false, nullptr, nullptr) +
          sizeof(double) * (2 * kMaxLmats + 4 * (ngf + 1)) + 512;
 }

@@ -16,6 +16,7 @@
 #include <algorithm>
 #include <atomic>
 #include <chrono>
+#include <cmath>
 #include <condition_variable>
 #include <cstring>
 #include <deque>
@@ -175,7 +176,8 @@ size_t estimate_footprint(const edx_server_opts& o, const Model& m, int nup, int
   const int niter = o.lanczos.niter;
   auto lanc = [&](int64_t d, int64_t cols, int n) {
     return align_up((size_t)d * vb) * 3 +
-           align_up(sizeof(double) * (size_t)std::max<int64_t>(2 * kMaxPartials, cols + 8)) +
+           align_up(sizeof(double) * (size_t)std::max<int64_t>(2 * kMaxPartials,
+                                                               cols + 8 + kNdMaxBlocks)) +
            8 * align_up(sizeof(double) * (size_t)(n + 2)) + 4096;
   };
   // Krylov vectors use the padded column stride; psi0 is accumulated in that
@@ -353,6 +355,12 @@ edx_status edx_server_submit(edx_server* S, const edx_model* model, int32_t nup,
   m.Ust = model->Ust;
   m.Jh = model->Jh;
   m.xmu = model->xmu;
+  m.Jx = model->Jx;
+  m.Jp = model->Jp;
+  if (!std::isfinite(m.Jx) || !std::isfinite(m.Jp)) {
+    set_error("server: non-finite interaction parameter");
+    return EDX_E_INVALID;
+  }
   R->nup = nup;
   R->ndw = ndw;
   R->footprint = estimate_footprint(S->opts, m, nup, ndw);

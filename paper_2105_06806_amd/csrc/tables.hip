@@ -290,6 +290,7 @@ edx_status build_sector_impl(const Model& m, int nup, int ndw, hipStream_t st,
   S->dim = S->dup * S->ddw;
   S->ld = vec_ld(S->dup);
   S->vlen = S->ld * S->ddw;
+  S->nd = m.norb >= 2 && (m.Jx != 0.0 || m.Jp != 0.0);
 
   // column order of the fused H.v pass: spin-down strings stably sorted by
   // impurity pattern (for Norb = 1: impurity empty, then occupied)

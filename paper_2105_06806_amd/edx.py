@@ -34,7 +34,8 @@ class _Model(ctypes.Structure):
                 ("eps_bath", ctypes.POINTER(ctypes.c_double)),
                 ("vhyb", ctypes.POINTER(ctypes.c_double)),
                 ("U", ctypes.c_double), ("Ust", ctypes.c_double),
-                ("Jh", ctypes.c_double), ("xmu", ctypes.c_double)]
+                ("Jh", ctypes.c_double), ("xmu", ctypes.c_double),
+                ("Jx", ctypes.c_double), ("Jp", ctypes.c_double)]
 
 
 class HvPlan(ctypes.Structure):
@@ -232,7 +233,8 @@ def _model_struct(m):
         return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
 
     s = _Model(int(m["norb"]), int(m["nbath"]), arr(m["eps_imp"]), arr(m["eps_bath"]),
-               arr(m["vhyb"]), float(m["U"]), float(m["Ust"]), float(m["Jh"]), float(m["xmu"]))
+               arr(m["vhyb"]), float(m["U"]), float(m["Ust"]), float(m["Jh"]), float(m["xmu"]),
+               float(m.get("Jx", 0.0)), float(m.get("Jp", 0.0)))
     return s, keep
 
 

@@ -77,6 +77,11 @@ HV_CASES = [
     ("ns11", inputs.make_model(1, 10, 2.5, seed=23, symmetric=False), (5, 6)),
     ("ns12", inputs.workload("ns12")[0], (6, 6)),
     ("ns7_odd", inputs.make_model(1, 6, 1.7, seed=24, symmetric=False), (3, 3)),
+    # spin exchange and pair hopping (the separate H_nd pass)
+    ("o2_kanamori", inputs.make_model(2, 4, 3.0, Jh=0.5, seed=25, symmetric=False, Jx=0.5, Jp=0.5),
+     (5, 5)),
+    ("o3_nd", inputs.make_model(3, 2, 3.0, Jh=0.6, seed=26, symmetric=False, Jx=0.45, Jp=-0.3),
+     (5, 4)),
 ]
 
 PLANS = [
@@ -327,6 +332,100 @@ def test_hv_ns16_two_orbital_sampled(edx, dtype):
     tol = (1e-13 if dtype == "f64" else 2e-6) * _hscale(m)
     assert np.abs(got - ref).max() <= tol
     assert bool((w.view(S.ddw, S.ld)[:, S.dup:] == 0).all())
+
+
+ND_CASES = [
+    ("o2", inputs.make_model(2, 2, 3.0, Jh=0.5, seed=31, symmetric=False, Jx=0.5, Jp=0.5), (3, 3)),
+    ("o3", inputs.make_model(3, 1, 3.0, Jh=0.5, seed=32, symmetric=False, Jx=0.5, Jp=0.5), (3, 3)),
+    ("o3_odd", inputs.make_model(3, 1, 2.5, Jh=0.4, seed=33, symmetric=False, Jx=0.3, Jp=0.2),
+     (3, 2)),
+]
+
+
+def test_nd_ground_state_larger(edx):
+    """Norb=2, Nbath=4 (Ns=10) 5/5 with full Kanamori: E0 against ARPACK on the
+    explicit sector matrix, FP64 and FP32."""
+    m = inputs.make_model(2, 4, 3.0, Jh=0.5, seed=35, symmetric=False, Jx=0.5, Jp=0.5)
+    sec = (5, 5)
+    E0, _ = spectra.arpack_lowest(fock.explicit_hamiltonian(m, *sec))
+    S = edx.build_sector(m, *sec)
+    e64 = edx.lanczos_ground_state(S, want_psi=False, niter=500, tol=1e-14, seed=2,
+                                   allow=(edx.EDX_E_DEGENERATE,))[0]
+    assert abs(e64 - E0) <= 1e-10 * abs(E0)
+    e32 = edx.lanczos_ground_state(S, want_psi=False, vtype="f32", niter=500, tol=1e-9, seed=2,
+                                   allow=(edx.EDX_E_DEGENERATE, edx.EDX_E_NOCONV))[0]
+    assert abs(e32 - E0) <= 1e-5 * abs(E0)
+
+
+@pytest.mark.parametrize("name,m,sec", ND_CASES, ids=[c[0] for c in ND_CASES])
+def test_nd_ground_state_and_green(edx, name, m, sec):
+    """Kanamori-type models with spin exchange and pair hopping: E0 against the
+    dense spectrum, psi0 overlap, and G of every orbital against the exact
+    Lehmann sum (G_up + G_dw where the ground level is degenerate)."""
+    H = fock.explicit_hamiltonian(m, *sec).toarray()
+    w, V = np.linalg.eigh(H)
+    S = edx.build_sector(m, *sec)
+    e0, psi, rep, st = edx.lanczos_ground_state(S, niter=400, tol=1e-14, rtol=1e-11, seed=8,
+                                                allow=(edx.EDX_E_DEGENERATE,))
+    assert abs(e0 - w[0]) <= 1e-10 * abs(w[0])
+    degenerate = w[1] - w[0] < 1e-9
+    if not degenerate:
+        assert abs(abs(psi.cpu().numpy() @ V[:, 0]) - 1) < 1e-8
+    beta, lm = 40.0, 128
+    z = 1j * green.matsubara(beta, lm)
+    for orb in range(m["norb"]):
+        G = [edx.green_cf(S, psi, e0, orb, sp, ngf=300, beta=beta, lmats=lm)[0] for sp in (0, 1)]
+        if degenerate:
+            got = G[0] + G[1]
+            ref = sum(green.lehmann_exact(m, *sec, orb, sp, z)[0] for sp in (0, 1))
+            assert np.abs(got - ref).max() <= 1e-8 * np.abs(ref).max(), orb
+        else:
+            for sp in (0, 1):
+                ref = green.lehmann_exact(m, *sec, orb, sp, z)[0]
+                assert np.abs(G[sp] - ref).max() <= 1e-8 * np.abs(ref).max(), (orb, sp)
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_nd_large_sector_sampled(edx, dtype):
+    """Norb=3, Nbath=4 (Ns=15) 7/7, D=41.4M, with Jx = Jp = J (full Kanamori):
+    default plan on the padded layout, sampled outputs against the oracle's
+    row-by-row product, padding rows zero."""
+    import torch
+    m = inputs.make_model(3, 4, 3.0, Jh=0.5, seed=34, symmetric=False, elo=-2.0, ehi=2.0,
+                          vlo=0.1, vhi=0.5, Jx=0.5, Jp=0.5)
+    sec = (7, 7)
+    S = edx.build_sector(m, *sec)
+    tdt = torch.float64 if dtype == "f64" else torch.float32
+    gen = torch.Generator(device="cuda").manual_seed(9)
+    vd = torch.rand(S.dim, dtype=tdt, device="cuda", generator=gen) * 2 - 1
+    v = edx.pad(S, vd)
+    w = torch.full_like(v, float("nan"))
+    edx.hv(S, v, w, ld=S.ld)
+    torch.cuda.synchronize()
+    rows = np.random.default_rng(5).choice(S.dim, size=1500, replace=False)
+    rows = np.concatenate([rows, [0, S.dim - 1, S.dup - 1, S.dup]])
+    ref = fock.hv_rows(m, *sec, vd.double().cpu().numpy(), rows)
+    pos = rows % S.dup + (rows // S.dup) * S.ld
+    got = w[torch.as_tensor(pos, device="cuda")].double().cpu().numpy()
+    tol = (1e-13 if dtype == "f64" else 2e-6) * (_hscale(m) + 4 * 0.5 * 6)
+    assert np.abs(got - ref).max() <= tol
+    assert bool((w.view(S.ddw, S.ld)[:, S.dup:] == 0).all())
+
+
+def test_batch_routes_nd_jobs(edx):
+    """Jobs with spin exchange / pair hopping run through the whole-GPU path
+    inside a batch and give the plain results; the others still use lanes."""
+    jobs = []
+    for k in range(3):
+        m = inputs.make_model(2, 3, 3.0, Jh=0.5, seed=60 + k, symmetric=False, Jx=0.5 * (k != 1),
+                              Jp=0.5 * (k != 1))
+        for sec in [(4, 4), (3, 4), (4, 5)]:
+            jobs.append(edx.build_sector(m, *sec))
+    res, _ = edx.batch_ground_state(jobs, vtype="f64", niter=400, tol=1e-12, seed=9)
+    for S, r in zip(jobs, res):
+        e_plain = edx.lanczos_ground_state(S, want_psi=False, niter=400, tol=1e-12, seed=9,
+                                           allow=(edx.EDX_E_DEGENERATE,))[0]
+        assert r["status"] == 0 and abs(r["e0"] - e_plain) <= 1e-10 * abs(e_plain)
 
 
 def _batch_sectors(edx):
