@@ -154,6 +154,32 @@ def _cpu_rows_worker(args):
     return n, time.perf_counter() - t0
 
 
+def bench_hv_kanamori(edx, torch, a):
+    """FP32 H.v with spin exchange and pair hopping (Jx = Jp = J) on the
+    Norb=2 Ns=16 and Norb=3 Ns=15 half-filled sectors, and the same models
+    without them (density-density only)."""
+    from paper_2105_06806_amd import inputs
+    out = {}
+    for name in ("ns16o2", "ns15o3"):
+        m0, [sec] = inputs.workload(name)
+        row = {}
+        for tag, m in (("kanamori", dict(m0, Jx=m0["Jh"], Jp=m0["Jh"])), ("density_density", m0)):
+            S = edx.build_sector(m, *sec)
+            gen = torch.Generator(device="cuda").manual_seed(3)
+            v = edx.pad(S, torch.rand(S.dim, dtype=torch.float32, device="cuda", generator=gen) * 2 - 1)
+            w = torch.empty_like(v)
+            plan, _ = edx.autotune_hv(S, v, w, reps=a.tune_reps, ld=S.ld)
+            ms, _ = time_hv(edx, torch, S, v, w, max(10, a.steps // 2), a.warmup, ld=S.ld)
+            row[tag] = {"us": round(float(ms.mean()) * 1e3, 1),
+                        "gbs": round(S.dim * 8 / (ms.mean() * 1e-3) / 1e9, 1), "plan": plan}
+            del v, w
+            torch.cuda.empty_cache()
+        row["workload"] = (f"H.v {name} {sec[0]}/{sec[1]} D={S.dim} FP32, U={m0['U']}, "
+                           f"J=Jx=Jp={m0['Jh']} (kanamori) vs Jx=Jp=0")
+        out[name] = row
+    return out
+
+
 def cpu_baseline(m, sec, elem_bytes, budget_s=15.0, max_procs=16):
     """The oracle's row-by-row H.v on a bounded sample of output rows: one core
     (calibration), then one oracle process per core (up to max_procs, the host
@@ -429,6 +455,7 @@ def main():
     }
     if not a.quick:
         for name, fn in (("hv_ns16o2", lambda: bench_hv_o2(edx, torch, a)),
+                         ("hv_kanamori", lambda: bench_hv_kanamori(edx, torch, a)),
                          ("ns12", lambda: bench_ns12(edx)), ("ns15o3", lambda: bench_ns15o3(edx)),
                          ("batch", lambda: bench_batch(edx, torch)),
                          ("serve", lambda: bench_serve(edx, torch, a.full))):

@@ -110,6 +110,14 @@ struct edx_sector {
   // spin-down strings (columns of V) stably sorted by impurity pattern: the
   // column order of the fused pass with col_order 2
   int32_t* corder = nullptr;   // [ddw] device
+  // spin exchange / pair hopping terms by impurity-pattern pair (pu, pd):
+  // entries nd_off[pu * P + pd] .. nd_off[pu * P + pd + 1] (P = 2^norb) give the
+  // source offsets (rows du, columns dd) and signed amplitudes
+  int32_t* nd_off = nullptr;   // [P*P + 1] device
+  int32_t* nd_du = nullptr;    // [terms]
+  int32_t* nd_dd = nullptr;
+  double* nd_amp64 = nullptr;
+  float* nd_amp32 = nullptr;
   // lazily built neighbour sectors for the Green's function:
   // [spin][0] = N_s + 1 (particle), [spin][1] = N_s - 1 (hole)
   std::mutex nb_mu;
@@ -123,6 +131,9 @@ edx_status build_sector_impl(const Model& m, int nup, int ndw, hipStream_t st,
                              edx_sector** out, const Allocator* a = nullptr);
 // upper bound of the device bytes build_sector_impl takes from an allocator
 size_t sector_table_bytes(int ns, int nup, int ndw);
+// H_nd term table of a sector with spin exchange / pair hopping
+edx_status build_nd_terms(edx_sector* S, const Model& m, const std::vector<int32_t>& binom,
+                          hipStream_t st);
 void destroy_sector(edx_sector* s);
 
 // ---- hv.hip

@@ -481,75 +481,89 @@ __global__ __launch_bounds__(256) void k_hv_row(HvArgs<T> a, const T* __restrict
 }
 
 // ---------------------------------------------------------------- H_nd pass
-// Spin exchange and pair hopping of eq. Ham1 (impurity orbitals a != b):
-//   X_ab = d+_{a up} d_{a dw} d+_{b dw} d_{b up}   (amplitude -Jx)
-//   P_ab = d+_{a up} d+_{a dw} d_{b dw} d_{b up}   (amplitude +Jp)
-// They move electrons of both spins at once, so they are no Kronecker sum:
-// this pass adds them to w after the spin-separable passes.  H is real
-// symmetric, so row i of the term is the operator applied to |i>: for output
-// element (s_up, s_dw) every term whose occupations allow it gives one source
-// element (rank_up(s_up'), rank_dw(s_dw')), with the sign of Sec. 2.3 taken
-// operator by operator (right to left) on the full string, up modes first.
-// The N_up - 1 spin-up electrons that every spin-down operator of a term
-// passes appear twice and cancel, so only per-spin parities below the
-// touched levels remain.  The impurity levels are the lowest bits, so the
-// source ranks are close to the output's and the gathers hit in cache.
+// Spin exchange and pair hopping of eq. Ham1 (impurity orbitals p != q) move
+// electrons of both spins at once, so they are no Kronecker sum: this pass
+// adds them to w after the spin-separable passes.  H is real symmetric, so
+// row i of these terms is the operators applied to |i>; whether a term acts,
+// its sign and the index shift of the source element depend only on the
+// impurity patterns of the row and column strings (the sector build tabulates
+// them per pattern pair, see tables.hip), so an output element reads its
+// row's pattern byte and gathers one nearby source element per term.
 template <typename T>
 struct NdArgs {
   int64_t dup, ddw, ld;
-  const uint32_t* __restrict__ mapup;
-  const uint32_t* __restrict__ mapdw;
-  const int32_t* __restrict__ rankup;
-  const int32_t* __restrict__ rankdw;
-  int norb;
-  T jx, jp;
+  const uint8_t* __restrict__ pup;
+  const uint8_t* __restrict__ pdw;
+  const int32_t* __restrict__ off;   // [P*P + 1]
+  const int32_t* __restrict__ du;
+  const int32_t* __restrict__ dd;
+  const T* __restrict__ amp;
+  int P;
 };
 
-__device__ __forceinline__ int parity_below(uint32_t s, int m) {
-  return __popc(s & ((1u << m) - 1u)) & 1;
-}
+constexpr int kNdMaxTerms = 64 * 12;   // pattern pairs (norb <= 3) x terms per pair
+constexpr int kNdRows = 4;             // rows per thread per iteration (loads in flight)
+constexpr int64_t kNdPatLds = 96 * 1024;   // row patterns staged in LDS up to this many rows
 
+// The term table and (when D_up <= kNdPatLds) every row's impurity pattern
+// are staged in LDS, so the only global loads left are the source gathers
+// and the read-modify-write of w, issued together.
 template <typename T>
 __global__ __launch_bounds__(256) void k_hv_nd(NdArgs<T> a, const T* __restrict__ v,
                                                T* __restrict__ w,
                                                const double* __restrict__ vscale,
                                                double* __restrict__ partial) {
   __shared__ double red[16];
+  __shared__ int s_off[65];
+  __shared__ int s_du[kNdMaxTerms];
+  __shared__ int s_dd[kNdMaxTerms];
+  __shared__ T s_amp[kNdMaxTerms];
+  extern __shared__ uint8_t s_pat[];
+  const bool pat_lds = a.dup <= kNdPatLds;
+  const int npp = a.P * a.P;
+  for (int k = threadIdx.x; k <= npp; k += blockDim.x) s_off[k] = a.off[k];
+  if (pat_lds)
+    for (int64_t i = threadIdx.x; i < a.dup; i += blockDim.x) s_pat[i] = a.pup[i];
+  __syncthreads();
+  const int nt = s_off[npp];
+  for (int k = threadIdx.x; k < nt; k += blockDim.x) {
+    s_du[k] = a.du[k];
+    s_dd[k] = a.dd[k];
+    s_amp[k] = a.amp[k];
+  }
+  __syncthreads();
   const T sc = vscale ? (T)(*vscale) : T(1);
   double dot = 0.0;
+  const int64_t step = (int64_t)blockDim.x * kNdRows;
   for (int64_t j = blockIdx.x; j < a.ddw; j += gridDim.x) {
-    const uint32_t sd = a.mapdw[j];
-    for (int64_t i = threadIdx.x; i < a.dup; i += blockDim.x) {
-      const uint32_t su = a.mapup[i];
-      T acc = T(0);
-      for (int p = 0; p < a.norb; ++p) {
-        for (int q = 0; q < a.norb; ++q) {
-          if (p == q) continue;
-          const uint32_t bp = 1u << p, bq = 1u << q;
-          // X_pq: d_{q up}, d+_{q dw}, d_{p dw}, d+_{p up}
-          if (a.jx != T(0) && (su & bq) && !(su & bp) && (sd & bp) && !(sd & bq)) {
-            const uint32_t su1 = su ^ bq, sd1 = sd | bq;
-            const int par = parity_below(su, q) ^ parity_below(sd, q) ^ parity_below(sd1, p) ^
-                            parity_below(su1, p);
-            const int64_t src = (int64_t)a.rankup[su1 | bp] + (int64_t)a.rankdw[sd1 ^ bp] * a.ld;
-            const T x = v[src];
-            acc += par ? a.jx * x : -a.jx * x;
-          }
-          // P_pq: d_{q up}, d_{q dw}, d+_{p dw}, d+_{p up}
-          if (a.jp != T(0) && (su & bq) && (sd & bq) && !(su & bp) && !(sd & bp)) {
-            const uint32_t su1 = su ^ bq, sd1 = sd ^ bq;
-            const int par = parity_below(su, q) ^ parity_below(sd, q) ^ parity_below(sd1, p) ^
-                            parity_below(su1, p);
-            const int64_t src = (int64_t)a.rankup[su1 | bp] + (int64_t)a.rankdw[sd1 | bp] * a.ld;
-            const T x = v[src];
-            acc += par ? -a.jp * x : a.jp * x;
-          }
+    const int pd = a.pdw[j];
+    const T* __restrict__ vcol = v + j * a.ld;
+    T* __restrict__ wcol = w + j * a.ld;
+    for (int64_t i0 = threadIdx.x; i0 < a.dup; i0 += step) {
+      int t0[kNdRows], t1[kNdRows];
+      T wold[kNdRows];
+#pragma unroll
+      for (int r = 0; r < kNdRows; ++r) {
+        const int64_t i = i0 + (int64_t)r * blockDim.x;
+        t0[r] = t1[r] = 0;
+        if (i < a.dup) {
+          const int key = (pat_lds ? (int)s_pat[i] : (int)a.pup[i]) * a.P + pd;
+          t0[r] = s_off[key];
+          t1[r] = s_off[key + 1];
         }
+        wold[r] = t1[r] > t0[r] ? wcol[i] : T(0);
       }
-      const int64_t e = i + j * a.ld;
-      const T add = acc * sc;
-      w[e] += add;
-      if (partial) dot += (double)(v[e] * sc) * (double)add;
+#pragma unroll
+      for (int r = 0; r < kNdRows; ++r) {
+        if (t1[r] == t0[r]) continue;
+        const int64_t i = i0 + (int64_t)r * blockDim.x;
+        T acc = T(0);
+        for (int t = t0[r]; t < t1[r]; ++t)
+          acc += s_amp[t] * vcol[i + s_du[t] + (int64_t)s_dd[t] * a.ld];
+        const T add = acc * sc;
+        wcol[i] = wold[r] + add;
+        if (partial) dot += (double)(vcol[i] * sc) * (double)add;
+      }
     }
   }
   if (partial) {
@@ -802,15 +816,17 @@ edx_status hv_launch(const edx_sector* s, int vtype, const void* v, void* w, int
   if (!s->nd) return EDX_OK;
   const int nb = nd_blocks(s);
   double* pnd = partial ? partial + p.col_blocks : nullptr;
+  const int P = 1 << s->model.norb;
+  const size_t patlds = s->dup <= kNdPatLds ? (size_t)s->dup : 0;
   if (vtype == EDX_F64) {
-    const NdArgs<double> na{s->dup, s->ddw, ld, s->up.map, s->dw.map, s->up.rank, s->dw.rank,
-                            s->model.norb, s->model.Jx, s->model.Jp};
-    hipLaunchKernelGGL(k_hv_nd<double>, dim3(nb), dim3(256), 0, st, na,
+    const NdArgs<double> na{s->dup, s->ddw, ld, s->up.pat, s->dw.pat, s->nd_off, s->nd_du,
+                            s->nd_dd, s->nd_amp64, P};
+    hipLaunchKernelGGL(k_hv_nd<double>, dim3(nb), dim3(256), patlds, st, na,
                        static_cast<const double*>(v), static_cast<double*>(w), vscale, pnd);
   } else {
-    const NdArgs<float> na{s->dup, s->ddw, ld, s->up.map, s->dw.map, s->up.rank, s->dw.rank,
-                           s->model.norb, (float)s->model.Jx, (float)s->model.Jp};
-    hipLaunchKernelGGL(k_hv_nd<float>, dim3(nb), dim3(256), 0, st, na,
+    const NdArgs<float> na{s->dup, s->ddw, ld, s->up.pat, s->dw.pat, s->nd_off, s->nd_du,
+                           s->nd_dd, s->nd_amp32, P};
+    hipLaunchKernelGGL(k_hv_nd<float>, dim3(nb), dim3(256), patlds, st, na,
                        static_cast<const float*>(v), static_cast<float*>(w), vscale, pnd);
   }
   EDX_HIP(hipGetLastError());

@@ -222,7 +222,82 @@ void destroy_sector(edx_sector* s) {
   dfree(s, s->w32);
   dfree(s, s->binom);
   dfree(s, s->corder);
+  dfree(s, s->nd_off);
+  dfree(s, s->nd_du);
+  dfree(s, s->nd_dd);
+  dfree(s, s->nd_amp64);
+  dfree(s, s->nd_amp32);
   delete s;
+}
+
+// Spin exchange X_pq = d+_{p up} d_{p dw} d+_{q dw} d_{q up} (amplitude -Jx)
+// and pair hopping P_pq = d+_{p up} d+_{p dw} d_{q dw} d_{q up} (+Jp) of eq.
+// Ham1, p != q impurity orbitals, applied to a basis state: whether a term
+// acts, its sign and the index shift of the result depend only on the two
+// impurity patterns (the lowest norb bits of each spin string).  Sign: the
+// operators act right to left on the full string (spin-up modes first), each
+// contributing (-1)^(occupied modes below it); both spin-down operators pass
+// the same N_up - 1 spin-up electrons, which cancels, leaving per-spin
+// parities below impurity levels.  Index shift: a term keeps the number of
+// occupied impurity levels of each spin, so every bath bit keeps its position
+// in the colex sum sum_k C(c_k, k) and the rank changes by the difference of
+// the impurity bits' own terms.
+namespace {
+int low_rank(uint32_t pat, const std::vector<int32_t>& binom) {
+  int r = 0, k = 1;
+  for (int c = 0; c < 8; ++c)
+    if (pat & (1u << c)) r += binom[c * (kMaxNs + 1) + k++];
+  return r;
+}
+int below(uint32_t s, int m) { return __builtin_popcount(s & ((1u << m) - 1u)) & 1; }
+}  // namespace
+
+edx_status build_nd_terms(edx_sector* S, const Model& m, const std::vector<int32_t>& binom,
+                          hipStream_t st) {
+  const int P = 1 << m.norb;
+  std::vector<int32_t> off(P * P + 1, 0), du, dd;
+  std::vector<double> amp;
+  for (int pu = 0; pu < P; ++pu)
+    for (int pd = 0; pd < P; ++pd) {
+      for (int p = 0; p < m.norb; ++p)
+        for (int q = 0; q < m.norb; ++q) {
+          if (p == q) continue;
+          const uint32_t bp = 1u << p, bq = 1u << q;
+          const uint32_t u = (uint32_t)pu, d = (uint32_t)pd;
+          if (m.Jx != 0.0 && (u & bq) && !(u & bp) && (d & bp) && !(d & bq)) {
+            const int par = below(u, q) ^ below(d, q) ^ below(d | bq, p) ^ below(u ^ bq, p);
+            du.push_back(low_rank((u ^ bq) | bp, binom) - low_rank(u, binom));
+            dd.push_back(low_rank((d | bq) ^ bp, binom) - low_rank(d, binom));
+            amp.push_back(par ? m.Jx : -m.Jx);
+          }
+          if (m.Jp != 0.0 && (u & bq) && (d & bq) && !(u & bp) && !(d & bp)) {
+            const int par = below(u, q) ^ below(d, q) ^ below(d ^ bq, p) ^ below(u ^ bq, p);
+            du.push_back(low_rank((u ^ bq) | bp, binom) - low_rank(u, binom));
+            dd.push_back(low_rank((d ^ bq) | bp, binom) - low_rank(d, binom));
+            amp.push_back(par ? -m.Jp : m.Jp);
+          }
+        }
+      off[pu * P + pd + 1] = (int32_t)du.size();
+    }
+  const size_t nt = std::max<size_t>(1, du.size());
+  du.resize(nt, 0);
+  dd.resize(nt, 0);
+  amp.resize(nt, 0.0);
+  std::vector<float> ampf(amp.begin(), amp.end());
+  EDX_TRY(dalloc(S, &S->nd_off, off.size() * sizeof(int32_t)));
+  EDX_TRY(dalloc(S, &S->nd_du, nt * sizeof(int32_t)));
+  EDX_TRY(dalloc(S, &S->nd_dd, nt * sizeof(int32_t)));
+  EDX_TRY(dalloc(S, &S->nd_amp64, nt * sizeof(double)));
+  EDX_TRY(dalloc(S, &S->nd_amp32, nt * sizeof(float)));
+  EDX_HIP(hipMemcpyAsync(S->nd_off, off.data(), off.size() * sizeof(int32_t),
+                         hipMemcpyHostToDevice, st));
+  EDX_HIP(hipMemcpyAsync(S->nd_du, du.data(), nt * sizeof(int32_t), hipMemcpyHostToDevice, st));
+  EDX_HIP(hipMemcpyAsync(S->nd_dd, dd.data(), nt * sizeof(int32_t), hipMemcpyHostToDevice, st));
+  EDX_HIP(hipMemcpyAsync(S->nd_amp64, amp.data(), nt * sizeof(double), hipMemcpyHostToDevice, st));
+  EDX_HIP(hipMemcpyAsync(S->nd_amp32, ampf.data(), nt * sizeof(float), hipMemcpyHostToDevice, st));
+  // the host vectors go out of scope: finish the copies first
+  EDX_HIP(hipStreamSynchronize(st));
+  return EDX_OK;
 }
 
 size_t sector_table_bytes(int ns, int nup, int ndw) {
@@ -240,6 +315,7 @@ size_t sector_table_bytes(int ns, int nup, int ndw) {
   }
   b += (kMaxNs + 1) * (kMaxNs + 1) * 4 + 256 * 12 + 64 * 12 + 16 + 8 * kMaxNs + 8 * a;
   b += (size_t)comb(ns, ndw) * 4 + a;   // column order
+  b += 6 * a + 65 * 4 + 64 * 12 * (4 + 4 + 8 + 4);   // H_nd term table
   return b;
 }
 
@@ -291,6 +367,7 @@ edx_status build_sector_impl(const Model& m, int nup, int ndw, hipStream_t st,
   S->ld = vec_ld(S->dup);
   S->vlen = S->ld * S->ddw;
   S->nd = m.norb >= 2 && (m.Jx != 0.0 || m.Jp != 0.0);
+  if (S->nd) EDX_TRY(build_nd_terms(S.get(), m, binom, st));
 
   // column order of the fused H.v pass: spin-down strings stably sorted by
   // impurity pattern (for Norb = 1: impurity empty, then occupied)
