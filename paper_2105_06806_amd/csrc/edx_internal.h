@@ -118,6 +118,7 @@ struct edx_sector {
   int32_t* nd_dd = nullptr;
   double* nd_amp64 = nullptr;
   float* nd_amp32 = nullptr;
+  int nd_nt = 0;               // number of terms in the table
   // lazily built neighbour sectors for the Green's function:
   // [spin][0] = N_s + 1 (particle), [spin][1] = N_s - 1 (hole)
   std::mutex nb_mu;

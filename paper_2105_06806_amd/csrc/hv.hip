@@ -296,18 +296,63 @@ __device__ __forceinline__ gptr<T> uniform(const T* p) {
   return (gptr<T>)(((unsigned long long)hi << 32) | lo);
 }
 
-template <typename T, int WUP, int WDW, int NC>
+// Spin-exchange / pair-hopping term table of a sector (see k_hv_nd): per
+// impurity-pattern pair, the row and column shifts of the source element
+// and the signed amplitude.
+template <typename T>
+struct NdTab {
+  const int32_t* off;   // [P*P + 1]
+  const int32_t* du;
+  const int32_t* dd;
+  const T* amp;
+  int P, nt;
+};
+
+template <typename T>
+const T* nd_amp(const edx_sector* s);
+template <>
+const double* nd_amp<double>(const edx_sector* s) { return s->nd_amp64; }
+template <>
+const float* nd_amp<float>(const edx_sector* s) { return s->nd_amp32; }
+
+__host__ __device__ constexpr size_t al16(size_t x) { return (x + 15) & ~(size_t)15; }
+
+// LDS bytes of a staged term table
+inline size_t nd_tab_lds(int P, int nt, size_t tsz) {
+  return al16((size_t)(P * P + 1) * 4) + al16((size_t)nt * 8) + al16((size_t)nt * tsz);
+}
+
+template <typename T, int WUP, int WDW, int NC, bool ND>
 __global__ __launch_bounds__(1024) void k_hv_fused(HvArgs<T> a, const T* __restrict__ v,
                                                    T* __restrict__ w,
                                                    const double* __restrict__ vscale,
                                                    double* __restrict__ partial, int order,
-                                                   const int32_t* __restrict__ corder) {
+                                                   const int32_t* __restrict__ corder,
+                                                   NdTab<T> nd) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T* amp = reinterpret_cast<T*>(smem_raw);
   T* Wt = amp + kAmpTable;
   double* red = reinterpret_cast<double*>(Wt + 64);
   T* vs = reinterpret_cast<T*>(red + 16);
   const int64_t dup = a.dup, ld = a.ld;
+  // with ND the spin-exchange / pair-hopping table follows the columns:
+  // offsets, (row shift, column shift) pairs, amplitudes
+  int* n_off = nullptr;
+  int2* n_dud = nullptr;
+  T* n_amp = nullptr;
+  if (ND) {
+    unsigned char* q = reinterpret_cast<unsigned char*>(vs + NC * dup);
+    q = reinterpret_cast<unsigned char*>(al16(reinterpret_cast<uintptr_t>(q)));
+    n_off = reinterpret_cast<int*>(q);
+    n_dud = reinterpret_cast<int2*>(q + al16((size_t)(nd.P * nd.P + 1) * 4));
+    n_amp = reinterpret_cast<T*>(reinterpret_cast<unsigned char*>(n_dud) +
+                                 al16((size_t)nd.nt * 8));
+    for (int k = threadIdx.x; k <= nd.P * nd.P; k += blockDim.x) n_off[k] = nd.off[k];
+    for (int k = threadIdx.x; k < nd.nt; k += blockDim.x) {
+      n_dud[k] = make_int2(nd.du[k], nd.dd[k]);
+      n_amp[k] = nd.amp[k];
+    }
+  }
   // Which columns: group cb = workgroup index (order 0), or XCD-contiguous
   // numbering (order >= 1): workgroups go round-robin over the 8 XCDs, so
   // workgroup b takes group x*q + min(x, r) + b/8 (x = b % 8) and the groups
@@ -362,7 +407,8 @@ __global__ __launch_bounds__(1024) void k_hv_fused(HvArgs<T> a, const T* __restr
       uint32_t e[WUP];
       load_row<WUP>(a.hup, iu, e);
       const T eu = a.eup[iu];
-      const int pu = a.pup[iu] * 8;
+      const int patu = a.pup[iu];
+      const int pu = patu * 8;
       const uint32_t iu32 = (uint32_t)iu;
       T g[NC][WDW];
 #pragma unroll
@@ -385,7 +431,18 @@ __global__ __launch_bounds__(1024) void k_hv_fused(HvArgs<T> a, const T* __restr
         T s2 = T(0);
 #pragma unroll
         for (int k = 0; k < WDW; ++k) s2 += gamp[c][k] * g[c][k];
-        const T res = acc[c] + (eu + ed[c] + Wt[pu + pd[c]]) * x + s2;
+        T res = acc[c] + (eu + ed[c] + Wt[pu + pd[c]]) * x + s2;
+        if constexpr (ND) {
+          // spin exchange / pair hopping: sources near (iu, jc[c])
+          const int key = patu * nd.P + pd[c];
+          const int t1 = n_off[key + 1];
+          T sn = T(0);
+          for (int t = n_off[key]; t < t1; ++t) {
+            const int2 sh = n_dud[t];
+            sn += n_amp[t] * v[iu + sh.x + (jc[c] + sh.y) * ld];
+          }
+          res += sn * sc;
+        }
         if (ALL || c < nc) {
           w[iu + jc[c] * ld] = res;
           dot += (double)x * (double)res;
@@ -601,7 +658,8 @@ HvPlan hv_default_plan(const edx_sector* s, int vtype) {
   // table row is then reused over more columns), as far as LDS allows and
   // keeping a block per CU.
   const size_t colb = (size_t)s->dup * sz;
-  int c = (int)std::max<size_t>(1, kColLdsBytes / colb);
+  const size_t ndl = s->nd ? 16 + nd_tab_lds(1 << s->model.norb, s->nd_nt, sz) : 0;
+  int c = (int)std::max<size_t>(1, (kColLdsBytes - ndl) / colb);
   c = std::min(c, colb >= 48 * 1024 ? 3 : 2);
   while (c > 1 && (s->ddw + c - 1) / c < 256) --c;
   p.col_cols = c;
@@ -650,7 +708,9 @@ edx_status hv_validate(const edx_sector* s, int vtype, HvPlan* p) {
     set_error("hv plan: row_rows = 128 (two rows per lane) needs an even D_up");
     return EDX_E_UNSUPPORTED;
   }
-  if (smem_header() + (size_t)p->col_cols * s->dup * sz > 160 * 1024) {
+  const size_t ndl = (s->nd && p->mode == 2)
+                         ? 16 + nd_tab_lds(1 << s->model.norb, s->nd_nt, sz) : 0;
+  if (smem_header() + (size_t)p->col_cols * s->dup * sz + ndl > 160 * 1024) {
     set_error("hv plan: columns do not fit in LDS");
     return EDX_E_UNSUPPORTED;
   }
@@ -667,33 +727,47 @@ HvPlan hv_plan(const edx_sector* s, int vtype) {
 // partial sums of <v, Hv>: the last spin-separable pass's blocks, then the
 // H_nd pass's
 int hv_partial_blocks(const edx_sector* s, int vtype) {
-  return hv_plan(s, vtype).col_blocks + nd_blocks(s);
+  const HvPlan p = hv_plan(s, vtype);
+  return p.col_blocks + (p.mode == 2 ? 0 : nd_blocks(s));
 }
 
 namespace {
 
 
+template <typename T>
 struct FusedOrder {
   int order;
   const int32_t* corder;
+  NdTab<T> nd;   // nd.nt = 0: no spin exchange / pair hopping in this pass
 };
+
+template <typename T, int WUP, int WDW, int NC, bool ND>
+edx_status launch_fused_n(const HvArgs<T>& a, int nblk, int nthr, size_t lds, hipStream_t st,
+                          const T* v, T* w, const double* vscale, double* partial,
+                          FusedOrder<T> fo, const NdTab<T>& nd) {
+  const void* kern = (const void*)k_hv_fused<T, WUP, WDW, NC, ND>;
+  EDX_HIP(hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  hipLaunchKernelGGL((k_hv_fused<T, WUP, WDW, NC, ND>), dim3(nblk), dim3(nthr), lds, st, a, v,
+                     w, vscale, partial, fo.order, fo.corder, nd);
+  EDX_HIP(hipGetLastError());
+  return EDX_OK;
+}
 
 template <typename T, int WUP, int WDW, int NC>
 edx_status launch_fused_k(const HvArgs<T>& a, int nblk, int nthr, size_t lds, hipStream_t st,
                           const T* v, T* w, const double* vscale, double* partial,
-                          FusedOrder fo) {
-  const void* kern = (const void*)k_hv_fused<T, WUP, WDW, NC>;
-  EDX_HIP(hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-  hipLaunchKernelGGL((k_hv_fused<T, WUP, WDW, NC>), dim3(nblk), dim3(nthr), lds, st, a, v, w,
-                     vscale, partial, fo.order, fo.corder);
-  EDX_HIP(hipGetLastError());
-  return EDX_OK;
+                          FusedOrder<T> fo) {
+  if (fo.nd.nt > 0)
+    return launch_fused_n<T, WUP, WDW, NC, true>(a, nblk, nthr, lds, st, v, w, vscale, partial,
+                                                 fo, fo.nd);
+  return launch_fused_n<T, WUP, WDW, NC, false>(a, nblk, nthr, lds, st, v, w, vscale, partial,
+                                                fo, fo.nd);
 }
 
 template <typename T, int WUP, int WDW>
 edx_status launch_fused_c(const HvArgs<T>& a, int ncol, int nblk, int nthr, size_t lds,
                           hipStream_t st, const T* v, T* w, const double* vscale,
-                          double* partial, FusedOrder fo) {
+                          double* partial, FusedOrder<T> fo) {
   switch (ncol) {
     case 1: return launch_fused_k<T, WUP, WDW, 1>(a, nblk, nthr, lds, st, v, w, vscale, partial, fo);
     case 2: return launch_fused_k<T, WUP, WDW, 2>(a, nblk, nthr, lds, st, v, w, vscale, partial, fo);
@@ -705,7 +779,7 @@ edx_status launch_fused_c(const HvArgs<T>& a, int ncol, int nblk, int nthr, size
 template <typename T, int WUP>
 edx_status launch_col_w(const HvArgs<T>& a, bool fused, int nblk, int nthr, size_t lds,
                         hipStream_t st, const T* v, T* w, const double* vscale, double* partial,
-                        int ncol, FusedOrder fo) {
+                        int ncol, FusedOrder<T> fo) {
   if (!fused) {
     EDX_HIP(hipFuncSetAttribute((const void*)k_hv_col<T, WUP>,
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
@@ -757,7 +831,14 @@ edx_status launch_t(const edx_sector* s, const T* v, T* w, int64_t ld, const dou
     return EDX_OK;
   }
   if (p.col_cols > kColMax || p.col_cols < 1) return EDX_E_INVALID;
-  const size_t lds = hdr + (size_t)p.col_cols * s->dup * sizeof(T);
+  // the fused pass also applies spin exchange / pair hopping from a staged table
+  NdTab<T> nd{nullptr, nullptr, nullptr, nullptr, 1 << s->model.norb, 0};
+  size_t ndl = 0;
+  if (s->nd && p.mode == 2) {
+    nd = NdTab<T>{s->nd_off, s->nd_du, s->nd_dd, nd_amp<T>(s), 1 << s->model.norb, s->nd_nt};
+    ndl = 16 + nd_tab_lds(nd.P, nd.nt, sizeof(T));
+  }
+  const size_t lds = hdr + (size_t)p.col_cols * s->dup * sizeof(T) + ndl;
   const int nthr = p.col_threads;
   if (lds > 160 * 1024) {
     set_error("hv: column does not fit in LDS (D_up too large)");
@@ -784,7 +865,7 @@ edx_status launch_t(const edx_sector* s, const T* v, T* w, int64_t ld, const dou
       return EDX_E_INVALID;
   }
   const bool fused = p.mode == 2;
-  const FusedOrder fo{s->corder ? p.col_order : std::min(p.col_order, 1), s->corder};
+  const FusedOrder<T> fo{s->corder ? p.col_order : std::min(p.col_order, 1), s->corder, nd};
   switch (a.sup) {
     case 8: return launch_col_w<T, 8>(a, fused, nblk, nthr, lds, st, v, w, vscale, partial, p.col_cols, fo);
     case 16: return launch_col_w<T, 16>(a, fused, nblk, nthr, lds, st, v, w, vscale, partial, p.col_cols, fo);
@@ -813,7 +894,7 @@ edx_status hv_launch(const edx_sector* s, int vtype, const void* v, void* w, int
   else
     EDX_TRY(launch_t<float>(s, static_cast<const float*>(v), static_cast<float*>(w), ld, vscale,
                             partial, st, p));
-  if (!s->nd) return EDX_OK;
+  if (!s->nd || p.mode == 2) return EDX_OK;
   const int nb = nd_blocks(s);
   double* pnd = partial ? partial + p.col_blocks : nullptr;
   const int P = 1 << s->model.norb;

@@ -279,6 +279,7 @@ edx_status build_nd_terms(edx_sector* S, const Model& m, const std::vector<int32
         }
       off[pu * P + pd + 1] = (int32_t)du.size();
     }
+  S->nd_nt = (int)du.size();
   const size_t nt = std::max<size_t>(1, du.size());
   du.resize(nt, 0);
   dd.resize(nt, 0);
