@@ -67,10 +67,54 @@ def spin_strings(nbit, n):
     return np.array(vals, dtype=np.uint64)
 
 
-def sector_states(ns, nup, ndw):
-    """Full Fock integers of the sector in sector order (i_up fastest)."""
-    up = spin_strings(ns, nup)
-    dw = spin_strings(ns, ndw)
+def orbital_levels(model, a):
+    """The Nbit = Nbath + 1 levels of orbital a: its impurity level, then its
+    bath levels in order (orbital-resolved quantum numbers, Sec. 2.2)."""
+    norb, nbath = model["norb"], model["nbath"]
+    return [a] + [norb + a * nbath + nu for nu in range(nbath)]
+
+
+def orbital_spin_strings(model, counts):
+    """Strings of one spin with counts[a] electrons in orbital a's levels, in the
+    order of eq. SectorIndxDecomp: i = i_1 + D_1 (i_2 + D_2 (...)), i_a the
+    position of orbital a's Nbit-bit string in that orbital's ascending
+    listing (orbital 1 fastest)."""
+    norb, nbath = model["norb"], model["nbath"]
+    per = []
+    for a in range(norb):
+        lv = orbital_levels(model, a)
+        loc = spin_strings(nbath + 1, counts[a])          # ascending Nbit-bit strings
+        full = []
+        for x in loc:
+            f = 0
+            for k in range(nbath + 1):
+                if (int(x) >> k) & 1:
+                    f |= 1 << lv[k]
+            full.append(f)
+        per.append(full)
+    out = [0]
+    for a in range(norb):                                  # orbital a varies slower than a-1
+        out = [prev | x for x in per[a] for prev in out]
+    return np.array(out, dtype=np.uint64)
+
+
+def spin_basis(model, spec):
+    """Strings of one spin for a sector spec: an int N (total-N sector,
+    ascending listing) or a sequence of per-orbital counts."""
+    if np.ndim(spec) == 0:
+        return spin_strings(ns_of(model), int(spec))
+    return orbital_spin_strings(model, [int(x) for x in spec])
+
+
+def sector_states(ns, nup, ndw, model=None):
+    """Full Fock integers of the sector in sector order (i_up fastest).  With a
+    model, nup/ndw may be per-orbital count sequences."""
+    if model is None:
+        up = spin_strings(ns, nup)
+        dw = spin_strings(ns, ndw)
+    else:
+        up = spin_basis(model, nup)
+        dw = spin_basis(model, ndw)
     I = (up[None, :] + (dw[:, None] << np.uint64(ns))).ravel()
     return up, dw, I
 
@@ -135,11 +179,17 @@ def diagonal(model, I):
     return d
 
 
+def _lookup(strings, x):
+    """Positions of the values x in the (not necessarily sorted) string list."""
+    order = np.argsort(strings, kind="stable")
+    return order[np.searchsorted(strings[order], x)]
+
+
 def _index_of(up, dw, ns, Inew):
     """Sector index i_up + i_dw*D_up of Fock integers known to lie in the sector."""
     mask = np.uint64((1 << ns) - 1)
-    iu = np.searchsorted(up, Inew & mask)
-    idw = np.searchsorted(dw, Inew >> np.uint64(ns))
+    iu = _lookup(up, Inew & mask)
+    idw = _lookup(dw, Inew >> np.uint64(ns))
     return iu.astype(np.int64) + idw.astype(np.int64) * len(up)
 
 
@@ -193,9 +243,10 @@ def explicit_hamiltonian(model, nup, ndw):
     """Sector Hamiltonian H_S as CSR, built term by term on full 2Ns-bit strings.
 
     Does not use the spin factorisation: every sign is the full-string sign of
-    Sec. 2.3.  H[i, j] = <i|H|j>."""
+    Sec. 2.3.  H[i, j] = <i|H|j>.  nup/ndw: electron counts, or per-orbital
+    count sequences (orbital-resolved sector)."""
     ns = ns_of(model)
-    up, dw, I = sector_states(ns, nup, ndw)
+    up, dw, I = sector_states(ns, nup, ndw, model)
     D = I.size
     rows, cols, vals = [np.arange(D)], [np.arange(D)], [diagonal(model, I)]
     for (ma, mb, V) in hopping_terms(model):
@@ -220,8 +271,8 @@ def hv_rows(model, nup, ndw, v, rows):
     """(H v)[rows] computed row by row from second quantisation, for sectors too
     large to store H.  H is real symmetric, so row i of H is H|i>."""
     ns = ns_of(model)
-    up = spin_strings(ns, nup)
-    dw = spin_strings(ns, ndw)
+    up = spin_basis(model, nup)
+    dw = spin_basis(model, ndw)
     rows = np.asarray(rows, dtype=np.int64)
     iu, idw = rows % len(up), rows // len(up)
     I = up[iu] + (dw[idw] << np.uint64(ns))

@@ -35,9 +35,21 @@ def apply_operator(model, nup, ndw, psi, orb, spin, kind):
     ns = fock.ns_of(model)
     m = orb + spin * ns
     d = 1 if kind == "cdag" else -1
-    tgt = (nup + d, ndw) if spin == 0 else (nup, ndw + d)
-    up, dw, I = fock.sector_states(ns, nup, ndw)
-    tup, tdw, _ = fock.sector_states(ns, *tgt)
+
+    def shifted(spec):
+        if np.ndim(spec) == 0:
+            return spec + d
+        t = list(spec)
+        t[orb] += d                     # orbital-resolved: only orbital orb changes
+        return tuple(t)
+
+    tgt = (shifted(nup), ndw) if spin == 0 else (nup, shifted(ndw))
+    bad = lambda spec: (np.ndim(spec) == 0 and not 0 <= spec <= ns) or \
+        (np.ndim(spec) > 0 and not all(0 <= x <= model["nbath"] + 1 for x in spec))
+    if bad(tgt[0]) or bad(tgt[1]):
+        return tgt, np.zeros(0)
+    up, dw, I = fock.sector_states(ns, nup, ndw, model)
+    tup, tdw, _ = fock.sector_states(ns, *tgt, model)
     Dt = len(tup) * len(tdw)
     phi = np.zeros(Dt)
     if Dt == 0:
