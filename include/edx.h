@@ -87,6 +87,20 @@ typedef struct edx_server edx_server;
 edx_status edx_build_sector(const edx_model* model, int32_t nup, int32_t ndw,
                             void* stream, edx_sector** out);
 
+/* Orbital-resolved sector (Sec. 2.2, eqs. Fock_decomp and Irelation with
+ * N_ud = N_alpha; Sec. 2.3, the split of H_sigma into per-orbital terms):
+ * nup[a], ndw[a] (host, [norb]) electrons of each spin among orbital a's
+ * N_bit = nbath + 1 levels (its impurity level, then its bath levels).  Per
+ * spin, orbital a's local string has its ascending (colex) position r_a and
+ * the string index is r_1 + D_1 (r_2 + D_2 r_3), D_a = C(nbath+1, counts[a]).
+ * The sector is used like one from edx_build_sector (the same H.v, Lanczos and
+ * Green's function entry points); its Green's function neighbours change
+ * only orbital orb's count.  The conservation needs H_nd = 0: Jx or Jp != 0
+ * -> EDX_E_UNSUPPORTED; a count outside [0, nbath+1] or a NULL array ->
+ * EDX_E_INVALID. */
+edx_status edx_build_sector_orbital(const edx_model* model, const int32_t* nup,
+                                    const int32_t* ndw, void* stream, edx_sector** out);
+
 void edx_sector_destroy(edx_sector* s);
 
 /* D_up, D_dw and D = D_up * D_dw of a sector (eq. nud_dimension). */

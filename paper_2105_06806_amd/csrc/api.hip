@@ -96,6 +96,30 @@ edx_status edx_build_sector(const edx_model* model, int32_t nup, int32_t ndw, vo
   return build_sector_impl(m, nup, ndw, static_cast<hipStream_t>(stream), out);
 }
 
+edx_status edx_build_sector_orbital(const edx_model* model, const int32_t* nup,
+                                    const int32_t* ndw, void* stream, edx_sector** out) {
+  if (!out) return invalid("out is NULL");
+  *out = nullptr;
+  if (!nup || !ndw) return invalid("nup/ndw arrays are NULL");
+  Model m;
+  EDX_TRY(check_model(model, &m));
+  if (m.Jx != 0.0 || m.Jp != 0.0) {
+    set_error("orbital-resolved sectors need Jx = Jp = 0 (H_nd mixes orbital counts)");
+    return EDX_E_UNSUPPORTED;
+  }
+  int cu[kMaxNorb] = {0, 0, 0}, cd[kMaxNorb] = {0, 0, 0};
+  int su = 0, sd = 0;
+  for (int a = 0; a < m.norb; ++a) {
+    if (nup[a] < 0 || ndw[a] < 0 || nup[a] > m.nbath + 1 || ndw[a] > m.nbath + 1)
+      return invalid("per-orbital counts must be in [0, nbath + 1]");
+    cu[a] = nup[a];
+    cd[a] = ndw[a];
+    su += cu[a];
+    sd += cd[a];
+  }
+  return build_sector_impl(m, su, sd, static_cast<hipStream_t>(stream), out, nullptr, cu, cd);
+}
+
 void edx_sector_destroy(edx_sector* s) { destroy_sector(s); }
 
 edx_status edx_sector_dims(const edx_sector* s, int64_t* dup, int64_t* ddw, int64_t* dim) {

@@ -61,6 +61,8 @@ struct Model {
 // Tables of one spin species of a sector, device resident.
 struct SpinTables {
   int n = 0;              // electrons of this spin
+  bool orb = false;       // orbital-resolved: counts[a] electrons in orbital a
+  int counts[kMaxNorb] = {0, 0, 0};
   int64_t D = 0;          // number of strings
   int width = 0;          // max hops in any row
   int wpad = 8;           // row stride of the hop table: 8, 16 or 24 entries
@@ -120,16 +122,22 @@ struct edx_sector {
   float* nd_amp32 = nullptr;
   int nd_nt = 0;               // number of terms in the table
   // lazily built neighbour sectors for the Green's function:
-  // [spin][0] = N_s + 1 (particle), [spin][1] = N_s - 1 (hole)
+  // [spin][0] = N_s + 1 (particle), [spin][1] = N_s - 1 (hole); for an
+  // orbital-resolved sector per orbital: [spin][orb][branch]
   std::mutex nb_mu;
   edx_sector* nb[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
+  edx_sector* nb_orb[2][edx::kMaxNorb][2] = {};
+  bool orb = false;          // orbital-resolved sector (per-orbital counts)
 };
 
 namespace edx {
 
 // ---- tables.hip
+// cup/cdw (both or neither): per-orbital electron counts of an orbital-resolved
+// sector (nup/ndw are then their sums)
 edx_status build_sector_impl(const Model& m, int nup, int ndw, hipStream_t st,
-                             edx_sector** out, const Allocator* a = nullptr);
+                             edx_sector** out, const Allocator* a = nullptr,
+                             const int* cup = nullptr, const int* cdw = nullptr);
 // upper bound of the device bytes build_sector_impl takes from an allocator
 size_t sector_table_bytes(int ns, int nup, int ndw);
 // H_nd term table of a sector with spin exchange / pair hopping

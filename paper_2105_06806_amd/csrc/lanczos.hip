@@ -421,17 +421,40 @@ size_t green_workspace_bytes(const edx_sector* s, int vtype, int ngf) {
 
 namespace {
 
-edx_status ensure_neighbours(const edx_sector* gs, int spin, hipStream_t st) {
+// Sectors reached by d+_{orb,spin} (k = 0) and d_{orb,spin} (k = 1): total
+// counts N_spin +- 1, or, in an orbital-resolved sector, orbital orb's count of
+// that spin +- 1 (the other orbitals' counts are untouched).
+edx_sector* const* neighbour_slot(const edx_sector* gs, int orb, int spin) {
+  return gs->orb ? gs->nb_orb[spin][orb] : gs->nb[spin];
+}
+
+edx_status ensure_neighbours(const edx_sector* gs, int orb, int spin, hipStream_t st) {
   edx_sector* g = const_cast<edx_sector*>(gs);
   std::lock_guard<std::mutex> lk(g->nb_mu);
-  const int n0 = spin == 0 ? gs->nup : gs->ndw;
+  edx_sector** slot = g->orb ? g->nb_orb[spin][orb] : g->nb[spin];
+  const Allocator* alloc = gs->alloc.alloc ? &gs->alloc : nullptr;
   for (int k = 0; k < 2; ++k) {
-    const int nn = n0 + (k == 0 ? 1 : -1);
-    if (g->nb[spin][k] || nn < 0 || nn > gs->model.ns) continue;
+    const int d = k == 0 ? 1 : -1;
+    if (slot[k]) continue;
     edx_sector* t = nullptr;
-    EDX_TRY(build_sector_impl(gs->model, spin == 0 ? nn : gs->nup, spin == 0 ? gs->ndw : nn, st,
-                              &t, gs->alloc.alloc ? &gs->alloc : nullptr));
-    g->nb[spin][k] = t;
+    if (gs->orb) {
+      int cu[kMaxNorb], cd[kMaxNorb];
+      for (int a = 0; a < kMaxNorb; ++a) {
+        cu[a] = gs->up.counts[a];
+        cd[a] = gs->dw.counts[a];
+      }
+      int* c = spin == 0 ? cu : cd;
+      c[orb] += d;
+      if (c[orb] < 0 || c[orb] > gs->model.nbath + 1) continue;
+      EDX_TRY(build_sector_impl(gs->model, gs->nup + (spin == 0 ? d : 0),
+                                gs->ndw + (spin == 1 ? d : 0), st, &t, alloc, cu, cd));
+    } else {
+      const int nn = (spin == 0 ? gs->nup : gs->ndw) + d;
+      if (nn < 0 || nn > gs->model.ns) continue;
+      EDX_TRY(build_sector_impl(gs->model, spin == 0 ? nn : gs->nup, spin == 0 ? gs->ndw : nn,
+                                st, &t, alloc));
+    }
+    slot[k] = t;
   }
   return EDX_OK;
 }
@@ -452,7 +475,8 @@ edx_status green_cf_impl(const edx_sector* gs, const void* psi0, double e0, int 
     set_error("green: workspace too small (need " + std::to_string(need) + " bytes)");
     return EDX_E_NOMEM;
   }
-  EDX_TRY(ensure_neighbours(gs, spin, st));
+  EDX_TRY(ensure_neighbours(gs, orb, spin, st));
+  edx_sector* const* nbs = neighbour_slot(gs, orb, spin);
   char* base = reinterpret_cast<char*>(align_up(reinterpret_cast<uintptr_t>(ws)));
   double* gdev = nullptr;
   double w[2] = {0.0, 0.0};
@@ -460,7 +484,7 @@ edx_status green_cf_impl(const edx_sector* gs, const void* psi0, double e0, int 
   std::vector<double> ha[2], hb[2];
   // the two branches run one after the other in the same workspace
   for (int br = 0; br < 2; ++br) {
-    const edx_sector* t = gs->nb[spin][br];
+    const edx_sector* t = nbs[br];
     LanczosWs L;
     lanczos_ws_layout(t ? t->vlen : 1, vtype, ngf, 0, t ? hv_partial_blocks(t, vtype) : 1, false,
                       base, &L);
@@ -497,7 +521,7 @@ edx_status green_cf_impl(const edx_sector* gs, const void* psi0, double e0, int 
   // G and the staged coefficients sit after the larger of the two layouts
   size_t off = 0;
   for (int br = 0; br < 2; ++br) {
-    const edx_sector* t = gs->nb[spin][br];
+    const edx_sector* t = nbs[br];
     off = std::max(off, lanczos_ws_layout(t ? t->vlen : 1, vtype, ngf, 0,
                                           t ? hv_partial_blocks(t, vtype) : 1, false, nullptr,
                                           nullptr));

@@ -49,6 +49,46 @@ __global__ void k_rank_map(int ns, int n, const int32_t* __restrict__ binom,
   }
 }
 
+// Orbital-resolved basis (quantum numbers conserved per orbital, Sec. 2.2):
+// strings with c[a] electrons among orbital a's levels (its impurity level,
+// then its bath levels), indexed as in eq. SectorIndxDecomp: orbital a's
+// Nbit-bit string has its colex position r_a among strings with c[a] bits and
+// index = sum_a r_a * radix[a], radix[a] = prod_{b<a} C(Nbit, c[b]).
+struct OrbCounts {
+  int c[kMaxNorb];
+  int64_t radix[kMaxNorb];
+};
+
+__global__ void k_rank_map_orb(int ns, int norb, int nbath, OrbCounts oc,
+                               const int32_t* __restrict__ binom, int32_t* __restrict__ rank,
+                               uint32_t* __restrict__ map) {
+  const uint32_t total = 1u << ns;
+  const uint32_t bmask = nbath >= 32 ? 0xFFFFFFFFu : ((1u << nbath) - 1u);
+  for (uint32_t s = blockIdx.x * blockDim.x + threadIdx.x; s < total;
+       s += gridDim.x * blockDim.x) {
+    int64_t idx = 0;
+    bool ok = true;
+    for (int a = 0; a < norb && ok; ++a) {
+      const uint32_t loc = ((s >> a) & 1u) | (((s >> (norb + a * nbath)) & bmask) << 1);
+      if (__popc(loc) != oc.c[a]) {
+        ok = false;
+        break;
+      }
+      int32_t r = 0;
+      int k = 1;
+      uint32_t x = loc;
+      while (x) {
+        r += binom[(__ffs(x) - 1) * (kMaxNs + 1) + k];
+        ++k;
+        x &= x - 1;
+      }
+      idx += (int64_t)r * oc.radix[a];
+    }
+    rank[s] = ok ? (int32_t)idx : -1;
+    if (ok) map[idx] = s;
+  }
+}
+
 __device__ __forceinline__ int hops_of_row(uint32_t s, int norb, int nbath) {
   int cnt = 0;
   for (int a = 0; a < norb; ++a) {
@@ -149,24 +189,37 @@ int grid_for(int64_t n, int threads) {
   return (int)std::max<int64_t>(1, std::min<int64_t>(b, 4096));
 }
 
-edx_status build_spin(edx_sector* S, SpinTables& T, int n, const double* d_elev,
-                      hipStream_t st) {
+edx_status build_spin(edx_sector* S, SpinTables& T, int n, const int* counts,
+                      const double* d_elev, hipStream_t st) {
   const Model& m = S->model;
   T.n = n;
-  int64_t D = 1;
-  {
-    // C(ns, n) from Pascal's triangle
-    std::vector<int64_t> row(m.ns + 1, 0);
-    row[0] = 1;
-    for (int r = 1; r <= m.ns; ++r)
-      for (int k = r; k >= 1; --k) row[k] += row[k - 1];
-    D = row[n];
+  // C(r, k) from Pascal's triangle
+  std::vector<std::vector<int64_t>> C(m.ns + 1, std::vector<int64_t>(m.ns + 1, 0));
+  for (int r = 0; r <= m.ns; ++r) {
+    C[r][0] = 1;
+    for (int k = 1; k <= r; ++k) C[r][k] = C[r - 1][k - 1] + (k <= r - 1 ? C[r - 1][k] : 0);
+  }
+  int64_t D = C[m.ns][n];
+  OrbCounts oc{};
+  if (counts) {
+    T.orb = true;
+    D = 1;
+    for (int a = 0; a < m.norb; ++a) {
+      T.counts[a] = counts[a];
+      oc.c[a] = counts[a];
+      oc.radix[a] = D;
+      D *= C[m.nbath + 1][counts[a]];
+    }
   }
   T.D = D;
   const size_t total = size_t(1) << m.ns;
   EDX_TRY(dalloc(S, &T.rank, total * sizeof(int32_t)));
   EDX_TRY(dalloc(S, &T.map, D * sizeof(uint32_t)));
-  k_rank_map<<<grid_for(total, 256), 256, 0, st>>>(m.ns, n, S->binom, T.rank, T.map);
+  if (counts)
+    k_rank_map_orb<<<grid_for(total, 256), 256, 0, st>>>(m.ns, m.norb, m.nbath, oc, S->binom,
+                                                         T.rank, T.map);
+  else
+    k_rank_map<<<grid_for(total, 256), 256, 0, st>>>(m.ns, n, S->binom, T.rank, T.map);
   EDX_HIP(hipGetLastError());
 
   int* d_width = nullptr;
@@ -212,7 +265,10 @@ void free_spin(edx_sector* S, SpinTables& T) {
 void destroy_sector(edx_sector* s) {
   if (!s) return;
   for (int sp = 0; sp < 2; ++sp)
-    for (int k = 0; k < 2; ++k) destroy_sector(s->nb[sp][k]);
+    for (int k = 0; k < 2; ++k) {
+      destroy_sector(s->nb[sp][k]);
+      for (int a = 0; a < kMaxNorb; ++a) destroy_sector(s->nb_orb[sp][a][k]);
+    }
   const bool shared = (s->dw.map == s->up.map);
   free_spin(s, s->up);
   if (!shared) free_spin(s, s->dw);
@@ -321,7 +377,8 @@ size_t sector_table_bytes(int ns, int nup, int ndw) {
 }
 
 edx_status build_sector_impl(const Model& m, int nup, int ndw, hipStream_t st,
-                             edx_sector** out, const Allocator* alloc) {
+                             edx_sector** out, const Allocator* alloc, const int* cup,
+                             const int* cdw) {
   std::unique_ptr<edx_sector, void (*)(edx_sector*)> S(new edx_sector(), destroy_sector);
   if (alloc) S->alloc = *alloc;
   S->model = m;
@@ -350,12 +407,16 @@ edx_status build_sector_impl(const Model& m, int nup, int ndw, hipStream_t st,
   EDX_HIP(hipMemcpyAsync(d_elev, elev.data(), m.ns * sizeof(double),
                          hipMemcpyHostToDevice, st));
 
-  edx_status rc = build_spin(S.get(), S->up, nup, d_elev, st);
+  S->orb = cup != nullptr;
+  bool same = ndw == nup;
+  if (S->orb)
+    for (int a = 0; a < m.norb; ++a) same = same && cup[a] == cdw[a];
+  edx_status rc = build_spin(S.get(), S->up, nup, cup, d_elev, st);
   if (rc == EDX_OK) {
-    if (ndw == nup) {
+    if (same) {
       S->dw = S->up;   // identical tables, shared
     } else {
-      rc = build_spin(S.get(), S->dw, ndw, d_elev, st);
+      rc = build_spin(S.get(), S->dw, ndw, cdw, d_elev, st);
     }
   }
   if (rc != EDX_OK) {

@@ -102,6 +102,7 @@ class GfReport(ctypes.Structure):
 _P = ctypes.c_void_p
 _SIGS = {
     "edx_build_sector": (ctypes.c_int, [ctypes.POINTER(_Model), ctypes.c_int32, ctypes.c_int32, _P, ctypes.POINTER(_P)]),
+    "edx_build_sector_orbital": (ctypes.c_int, [ctypes.POINTER(_Model), _P, _P, _P, ctypes.POINTER(_P)]),
     "edx_sector_destroy": (None, [_P]),
     "edx_sector_dims": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]),
     "edx_sector_hop_nnz": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int32)]),
@@ -243,6 +244,23 @@ def build_sector(model, nup, ndw, stream=None):
     h = _P()
     _check(lib.edx_build_sector(ctypes.byref(ms), int(nup), int(ndw), _stream_ptr(stream), ctypes.byref(h)))
     return Sector(h.value, model, nup, ndw)
+
+
+def build_sector_orbital(model, nup, ndw, stream=None):
+    """Orbital-resolved sector: nup[a], ndw[a] electrons of each spin in
+    orbital a (see edx_build_sector_orbital)."""
+    norb = int(model["norb"])
+    if len(nup) != norb or len(ndw) != norb:
+        raise ValueError(f"nup and ndw need {norb} per-orbital counts")
+    ms, keep = _model_struct(model)
+    cu = (ctypes.c_int32 * norb)(*[int(x) for x in nup])
+    cd = (ctypes.c_int32 * norb)(*[int(x) for x in ndw])
+    h = _P()
+    _check(lib.edx_build_sector_orbital(ctypes.byref(ms), ctypes.cast(cu, _P), ctypes.cast(cd, _P),
+                                        _stream_ptr(stream), ctypes.byref(h)))
+    s = Sector(h.value, model, sum(nup), sum(ndw))
+    s.counts = (tuple(int(x) for x in nup), tuple(int(x) for x in ndw))
+    return s
 
 
 def _vec_len(sector, v, w, ld):

@@ -27,6 +27,13 @@ def edx():
     return E
 
 
+def _build(edx, m, sec):
+    """Total-N sector (nup, ndw) or orbital-resolved sector (count tuples)."""
+    if np.ndim(sec[0]) > 0:
+        return edx.build_sector_orbital(m, sec[0], sec[1])
+    return edx.build_sector(m, *sec)
+
+
 def _cuda(x, dtype):
     import torch
     return torch.as_tensor(np.ascontiguousarray(x), dtype=dtype, device="cuda")
@@ -82,6 +89,11 @@ HV_CASES = [
      (5, 5)),
     ("o3_nd", inputs.make_model(3, 2, 3.0, Jh=0.6, seed=26, symmetric=False, Jx=0.45, Jp=-0.3),
      (5, 4)),
+    # orbital-resolved sectors (per-orbital counts of each spin)
+    ("orb2", inputs.make_model(2, 4, 3.0, Jh=0.5, seed=27, symmetric=False), ((2, 3), (3, 2))),
+    ("orb3", inputs.make_model(3, 3, 3.0, Jh=0.5, seed=28, symmetric=False),
+     ((2, 1, 3), (2, 2, 2))),
+    ("orb2_edge", inputs.make_model(2, 4, 2.0, seed=29, symmetric=False), ((0, 5), (5, 1))),
 ]
 
 PLANS = [
@@ -117,7 +129,7 @@ def test_hv_every_plan(edx, name, m, sec, dtype):
     back zero."""
     import torch
     H = fock.explicit_hamiltonian(m, *sec)
-    S = edx.build_sector(m, *sec)
+    S = _build(edx, m, sec)
     x = inputs.random_vector(S.dim, seed=99)
     ref = H @ x
     tdt = torch.float64 if dtype == "f64" else torch.float32
@@ -527,3 +539,112 @@ def test_server_admission_and_errors(edx):
     st = srv.stats()
     assert st["pending"] == 0 and st["running"] == 0
     srv.close()
+
+
+# ---- orbital-resolved sectors (quantum numbers conserved per orbital)
+
+ORB_CASES = [
+    ("o2", inputs.make_model(2, 3, 3.0, Jh=0.5, seed=51, symmetric=False), ((2, 1), (1, 2))),
+    ("o2_same", inputs.make_model(2, 3, 3.0, Jh=0.5, seed=51, symmetric=False), ((2, 2), (2, 2))),
+    ("o3", inputs.make_model(3, 2, 2.5, Jh=0.4, seed=52, symmetric=False), ((1, 2, 1), (2, 1, 1))),
+    ("o3_edge", inputs.make_model(3, 2, 2.5, Jh=0.4, seed=53, symmetric=False),
+     ((0, 3, 1), (3, 0, 2))),
+]
+
+
+@pytest.mark.parametrize("name,m,sec", ORB_CASES, ids=[c[0] for c in ORB_CASES])
+def test_orbital_tables_and_dims(edx, name, m, sec):
+    """Per-spin string listing of an orbital-resolved sector bit-exact against
+    the oracle's mixed-radix listing; D_sigma = prod_a C(Nbath+1, n_a)."""
+    S = edx.build_sector_orbital(m, *sec)
+    nb = m["nbath"] + 1
+    for spin in (0, 1):
+        t = S.tables(spin)
+        assert len(t["map"]) == math.prod(math.comb(nb, c) for c in sec[spin])
+        assert np.array_equal(t["map"], fock.spin_basis(m, sec[spin]).astype(np.uint32))
+    assert S.nup == sum(sec[0]) and S.ndw == sum(sec[1])
+
+
+@pytest.mark.parametrize("name,m,sec", ORB_CASES, ids=[c[0] for c in ORB_CASES])
+def test_orbital_ground_state_and_green(edx, name, m, sec):
+    """E0 and psi0 against the dense spectrum of the orbital sector; G of every
+    orbital and spin against the exact Lehmann sum over the neighbouring
+    orbital sectors (only orbital orb's count changes)."""
+    H = fock.explicit_hamiltonian(m, *sec).toarray()
+    w, V = np.linalg.eigh(H)
+    S = edx.build_sector_orbital(m, *sec)
+    e0, psi, rep, st = edx.lanczos_ground_state(S, niter=300, tol=1e-14, rtol=1e-11, seed=4,
+                                                allow=(edx.EDX_E_DEGENERATE,))
+    assert abs(e0 - w[0]) <= 1e-10 * abs(w[0])
+    assert w[1] - w[0] > 1e-8, "pick a case with a unique ground state"
+    assert abs(abs(psi.cpu().numpy() @ V[:, 0]) - 1) < 1e-8
+    beta, lm = 40.0, 128
+    z = 1j * green.matsubara(beta, lm)
+    for orb in range(m["norb"]):
+        for sp in (0, 1):
+            G, gr = edx.green_cf(S, psi, e0, orb, sp, ngf=200, beta=beta, lmats=lm)
+            ref = green.lehmann_exact(m, *sec, orb, sp, z)[0]
+            assert np.abs(G - ref).max() <= 1e-8 * np.abs(ref).max(), (orb, sp)
+
+
+def test_orbital_sectors_partition_total_sector(edx):
+    """Norb=2, Nbath=5 (Ns=12), N_up = N_dw = 6: the orbital sectors with
+    per-orbital counts summing to (6, 6) split the total-N sector, so their
+    dimensions add up to it and the lowest of their ground energies is its
+    ground energy (all on the GPU, FP64)."""
+    m = inputs.make_model(2, 5, 3.0, Jh=0.5, seed=54, symmetric=False)
+    T = edx.build_sector(m, 6, 6)
+    eT = edx.lanczos_ground_state(T, want_psi=False, niter=500, tol=1e-13, seed=1,
+                                  allow=(edx.EDX_E_DEGENERATE,))[0]
+    dims, es = 0, []
+    for a in range(7):
+        for b in range(7):
+            S = edx.build_sector_orbital(m, (a, 6 - a), (b, 6 - b))
+            dims += S.dim
+            es.append(edx.lanczos_ground_state(S, want_psi=False, niter=500, tol=1e-13, seed=1,
+                                               allow=(edx.EDX_E_DEGENERATE,))[0])
+    assert dims == T.dim
+    assert abs(min(es) - eT) <= 1e-9 * abs(eT)
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_orbital_ns16_sampled(edx, dtype):
+    """Norb=2, Nbath=7 (Ns=16) orbital sector (4,4)/(4,4), D = 70^4 = 24M:
+    default plan on the padded layout, sampled outputs against the oracle's
+    row-by-row product."""
+    import torch
+    m, _ = inputs.workload("ns16o2")
+    sec = ((4, 4), (4, 4))
+    S = edx.build_sector_orbital(m, *sec)
+    assert S.dim == 70 ** 4
+    tdt = torch.float64 if dtype == "f64" else torch.float32
+    gen = torch.Generator(device="cuda").manual_seed(8)
+    vd = torch.rand(S.dim, dtype=tdt, device="cuda", generator=gen) * 2 - 1
+    v = edx.pad(S, vd)
+    w = torch.full_like(v, float("nan"))
+    edx.hv(S, v, w, ld=S.ld)
+    torch.cuda.synchronize()
+    rows = np.random.default_rng(9).choice(S.dim, size=1500, replace=False)
+    rows = np.concatenate([rows, [0, S.dim - 1, S.dup - 1, S.dup]])
+    ref = fock.hv_rows(m, *sec, vd.double().cpu().numpy(), rows)
+    pos = rows % S.dup + (rows // S.dup) * S.ld
+    got = w[torch.as_tensor(pos, device="cuda")].double().cpu().numpy()
+    tol = (1e-13 if dtype == "f64" else 2e-6) * _hscale(m)
+    assert np.abs(got - ref).max() <= tol
+    assert bool((w.view(S.ddw, S.ld)[:, S.dup:] == 0).all())
+
+
+def test_orbital_rejects(edx):
+    m = inputs.make_model(2, 3, 3.0, Jh=0.5, seed=55, symmetric=False)
+    with pytest.raises(edx.EdxError) as e:
+        edx.build_sector_orbital(m, (5, 1), (1, 1))
+    assert e.value.status == edx.EDX_E_INVALID
+    with pytest.raises(edx.EdxError) as e:
+        edx.build_sector_orbital(m, (-1, 1), (1, 1))
+    assert e.value.status == edx.EDX_E_INVALID
+    with pytest.raises(ValueError):
+        edx.build_sector_orbital(m, (1, 1, 1), (1, 1))
+    mk = inputs.make_model(2, 3, 3.0, Jh=0.5, seed=55, symmetric=False, Jx=0.5, Jp=0.5)
+    with pytest.raises(edx.EdxError) as e:
+        edx.build_sector_orbital(mk, (2, 1), (1, 2))
+    assert e.value.status == edx.EDX_E_UNSUPPORTED
