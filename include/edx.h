@@ -214,6 +214,40 @@ edx_status edx_lanczos_ground_state(const edx_sector* s,
                                     size_t ws_bytes, double* e0, void* psi0,
                                     edx_lanczos_report* rep, void* stream);
 
+/* ---- several low-lying states (Sec. 5 "Eigenspace class": lanc_nstates_*)
+ * The k lowest eigenpairs of one sector by Lanczos with full
+ * re-orthogonalisation and locking: each run starts from a random vector
+ * (SplitMix64, seed + run) orthogonal to the states locked so far, keeps
+ * every new Krylov vector orthogonal to them and to the run's own basis
+ * (classical Gram-Schmidt twice), and locks the lowest Ritz pairs whose
+ * residual beta_m |y_{m-1}| <= rtol max(1, |theta|) (tol when rtol = 0; FP32
+ * floor as for the ground state).  A run that reaches niter restarts from
+ * its unconverged wanted Ritz vectors.  A run from one start vector sees one
+ * vector per degenerate eigenspace; the locking finds the other copies in
+ * later runs, and with verify = 1 a last run checks that the lowest state
+ * orthogonal to all k locked ones lies at or above the k-th energy (a lower
+ * one replaces the highest and the check repeats).  k is clipped to D.
+ * e (host, [k]) ascending; psi (device, nullable) receives the k normalised
+ * vectors, dense, one after another (k * D elements of opts->vtype).
+ * opts->reorth is ignored.  EDX_OK, or EDX_E_NOCONV with the states found. */
+typedef struct {
+  int32_t nfound;       /* states returned (k clipped to D)                 */
+  int32_t runs;         /* Lanczos runs (restarts and the check included)   */
+  int32_t iters;        /* Lanczos steps over all runs                      */
+  int32_t verified;     /* 1 if the check run passed (or verify = 0)        */
+  double resid_max;     /* largest residual estimate of a locked pair       */
+} edx_lowest_report;
+
+#define EDX_MAX_STATES 64
+
+size_t edx_lowest_workspace_bytes(const edx_sector* s, int32_t vtype, int32_t niter,
+                                  int32_t k);
+
+edx_status edx_lanczos_lowest(const edx_sector* s, int32_t k,
+                              const edx_lanczos_opts* opts, int32_t verify,
+                              void* ws, size_t ws_bytes, double* e, void* psi,
+                              edx_lowest_report* rep, void* stream);
+
 typedef struct {
   int32_t ngf;     /* Krylov depth per branch (lanc_ngfiter), default 200 */
   int32_t lmats;   /* number of Matsubara frequencies                   */
@@ -243,6 +277,71 @@ edx_status edx_green_cf(const edx_sector* gs, const void* psi0, double e0,
                         int32_t orb, int32_t spin, const edx_gf_opts* opts,
                         void* ws, size_t ws_bytes, double* g_host,
                         edx_gf_report* rep, void* stream);
+
+/* ---- finite temperature: the eigenstate list (Sec. 5 "Eigenspace class"
+ * and the thermal form of "Dynamical correlation functions") ----
+ * An edx_espace holds the low-lying states of a fixed set of nsec sectors.
+ * edx_espace_diag asks sector i for its next_i lowest states
+ * (edx_lanczos_lowest, next_i = nstates_sector at first), merges them into one
+ * list ordered by energy (ties: sector, then state), E0 = the lowest, and
+ * keeps the states with exp(-beta (E - E0)) >= cutoff, at most nstates_total
+ * of them (the printed inequality is read as "drop the states whose factor is
+ * below the cutoff").  Annealing: a sector whose computed states were all kept
+ * asks for nstates_step more at the next call, any other one for the number
+ * it kept (at least 1, at most EDX_MAX_STATES); repeated calls settle the
+ * distribution.  Kept vectors stay in device memory owned by the espace (one
+ * allocation per sector that keeps a state); the sector handles are not owned
+ * and must outlive the espace's use of them.  nstates_total = 1 is T = 0. */
+typedef struct edx_espace edx_espace;
+
+typedef struct {
+  double beta;             /* inverse temperature, k_B = 1 (default 1000)      */
+  double cutoff;           /* Boltzmann factor cutoff (default 1e-9)           */
+  int32_t nstates_sector;  /* first request per sector (default 2)             */
+  int32_t nstates_total;   /* most states in the list (default 1 = T = 0)      */
+  int32_t nstates_step;    /* annealing increment (default 2)                  */
+  int32_t verify;          /* check run of edx_lanczos_lowest (default 1)      */
+} edx_espace_opts;
+
+void edx_espace_default_opts(edx_espace_opts* o);
+edx_status edx_espace_create(const edx_espace_opts* o, int32_t nsec, edx_espace** out);
+void edx_espace_destroy(edx_espace* E);
+
+/* Workspace for edx_espace_diag with these sectors and the current requests. */
+size_t edx_espace_diag_workspace_bytes(const edx_espace* E, edx_sector* const* secs,
+                                       int32_t nsec, int32_t vtype, int32_t niter);
+
+/* Diagonalise every sector (secs[i] is slot i; nsec as at creation) and
+ * rebuild the list; the previous list and its vectors are released first.
+ * opts as for edx_lanczos_lowest; the vectors have opts->vtype.  Stops at the
+ * first sector that fails (its status is returned, the list is left empty). */
+edx_status edx_espace_diag(edx_espace* E, edx_sector* const* secs, int32_t nsec,
+                           const edx_lanczos_opts* opts, void* ws, size_t ws_bytes,
+                           void* stream);
+
+/* Kept states, E0 and Z = sum of exp(-beta (E_n - E0)) over them. */
+edx_status edx_espace_info(const edx_espace* E, int32_t* nstates, double* e0, double* z);
+
+/* State i of the list (ascending energy): energy, sector slot, weight
+ * exp(-beta (E - E0)) / Z and its dense device vector (owned by E). */
+edx_status edx_espace_state(const edx_espace* E, int32_t i, double* e, int32_t* sec,
+                            double* weight, const void** psi);
+
+/* Per sector: states computed and kept by the last diag, next request. */
+edx_status edx_espace_sector(const edx_espace* E, int32_t sec, int32_t* computed,
+                             int32_t* kept, int32_t* next);
+
+/* Workspace for edx_espace_green (the largest Green's function workspace over
+ * the sectors that keep a state). */
+size_t edx_espace_green_workspace_bytes(const edx_espace* E, int32_t ngf);
+
+/* Thermal impurity G(i w_n) = sum_n w_n G_n, w_n = exp(-beta (E_n - E0)) / Z,
+ * over the kept states; G_n is edx_green_cf of state n with its own energy
+ * E_n as the reference (poles at E_m - E_n).  opts->beta must equal the
+ * espace's beta and opts->vtype the vectors' type. */
+edx_status edx_espace_green(edx_espace* E, int32_t orb, int32_t spin,
+                            const edx_gf_opts* opts, void* ws, size_t ws_bytes,
+                            double* g_host, void* stream);
 
 /* ---- batched ground states (many sectors, one persistent launch) ----
  * Every job is an independent sector; the ground energy of each follows the

@@ -15,15 +15,6 @@ thread_local std::string g_last_error;
 
 void set_error(const std::string& msg) { g_last_error = msg; }
 
-size_t lanczos_workspace_bytes(const edx_sector* s, int vtype, int niter, int reorth);
-size_t green_workspace_bytes(const edx_sector* s, int vtype, int ngf);
-edx_status lanczos_ground_state_impl(const edx_sector* s, const edx_lanczos_opts* o, void* ws,
-                                     size_t ws_bytes, double* e0, void* psi0,
-                                     edx_lanczos_report* rep, hipStream_t st);
-edx_status green_cf_impl(const edx_sector* gs, const void* psi0, double e0, int orb, int spin,
-                         const edx_gf_opts* o, void* ws, size_t ws_bytes, double* g_host,
-                         edx_gf_report* rep, hipStream_t st);
-
 static edx_status invalid(const std::string& msg) {
   set_error(msg);
   return EDX_E_INVALID;
@@ -276,6 +267,25 @@ edx_status edx_lanczos_ground_state(const edx_sector* s, const edx_lanczos_opts*
   if (!(opts->tol >= 0.0) || !(opts->rtol >= 0.0)) return invalid("tol/rtol must be >= 0");
   return lanczos_ground_state_impl(s, opts, ws, ws_bytes, e0, psi0, rep,
                                    static_cast<hipStream_t>(stream));
+}
+
+size_t edx_lowest_workspace_bytes(const edx_sector* s, int32_t vtype, int32_t niter, int32_t k) {
+  if (!s || !valid_vtype(vtype) || niter < 1 || k < 1 || k > EDX_MAX_STATES) return 0;
+  return lowest_workspace_bytes(s, vtype, niter, k);
+}
+
+edx_status edx_lanczos_lowest(const edx_sector* s, int32_t k, const edx_lanczos_opts* opts,
+                              int32_t verify, void* ws, size_t ws_bytes, double* e, void* psi,
+                              edx_lowest_report* rep, void* stream) {
+  EDX_TRY(check_sector(s));
+  if (!opts || !e || !ws) return invalid("opts, e and ws must be non-NULL");
+  if (k < 1 || k > EDX_MAX_STATES) return invalid("k must be in [1, 64]");
+  if (!valid_vtype(opts->vtype)) return invalid("vtype must be EDX_F64 or EDX_F32");
+  if (opts->niter < 1 || opts->niter > 4096) return invalid("niter must be in [1, 4096]");
+  if (!(opts->tol >= 0.0) || !(opts->rtol >= 0.0) || !(opts->tol > 0.0 || opts->rtol > 0.0))
+    return invalid("tol/rtol must be >= 0, one of them > 0");
+  return lowest_states_impl(s, k, opts, verify, ws, ws_bytes, e, psi, rep,
+                            static_cast<hipStream_t>(stream));
 }
 
 edx_status edx_green_cf(const edx_sector* gs, const void* psi0, double e0, int32_t orb,

@@ -226,6 +226,14 @@ size_t lanczos_workspace_bytes(const edx_sector* s, int vtype, int niter, int re
 edx_status lanczos_ground_state_impl(const edx_sector* s, const edx_lanczos_opts* o, void* ws,
                                      size_t ws_bytes, double* e0, void* psi0,
                                      edx_lanczos_report* rep, hipStream_t st);
+size_t lowest_workspace_bytes(const edx_sector* s, int vtype, int niter, int k);
+edx_status lowest_states_impl(const edx_sector* s, int k, const edx_lanczos_opts* o, int verify,
+                              void* ws, size_t ws_bytes, double* e, void* psi,
+                              edx_lowest_report* rep, hipStream_t st);
+size_t green_workspace_bytes(const edx_sector* s, int vtype, int ngf);
+edx_status green_cf_impl(const edx_sector* gs, const void* psi0, double e0, int orb, int spin,
+                         const edx_gf_opts* o, void* ws, size_t ws_bytes, double* g_host,
+                         edx_gf_report* rep, hipStream_t st);
 // ---- lanczos.cpp (host)
 double tridiag_lowest(const double* a, const double* b, int m, int k);
 void tridiag_vector(const double* a, const double* b, int m, double lam,

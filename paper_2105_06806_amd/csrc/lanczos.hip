@@ -228,7 +228,8 @@ StepBufs bufs_for(const LanczosWs& L, int j, int reorth) {
 // psi += y_j v_j (replay).
 edx_status lanczos_step(const edx_sector* s, int vtype, const LanczosWs& L, int j, int reorth,
                         double* alpha, double* beta, double* scale, void* psi,
-                        const double* ycoef, hipStream_t st) {
+                        const double* ycoef, hipStream_t st, const char* locked = nullptr,
+                        int nlock = 0) {
   const StepBufs b = bufs_for(L, j, reorth);
   const int64_t n = s->vlen;
   const int hb = hv_partial_blocks(s, vtype);
@@ -243,7 +244,14 @@ edx_status lanczos_step(const edx_sector* s, int vtype, const LanczosWs& L, int 
     EDX_TRY(k_axpy2(vtype, b.w, b.cur, L.coef, scale + j, b.prev, L.coef + 1,
                     j > 0 ? scale + j - 1 : nullptr, n, L.partial, st));
   } else if (reorth == 2) {
+    const int64_t ldv = (int64_t)(L.vstride / vbytes(vtype));
     for (int pass = 0; pass < 2; ++pass) {
+      if (nlock > 0) {
+        // deflation: the locked (orthonormal) eigenvectors are projected out
+        EDX_TRY(k_multi_dot(vtype, locked, ldv, nlock, b.w, n, L.partial, st));
+        EDX_TRY(k_reduce_strided(L.partial, multi_blocks(n), kMaxPartials, nlock, L.coef, st));
+        EDX_TRY(k_multi_axpy(vtype, b.w, locked, ldv, nlock, L.coef, n, L.partial, st));
+      }
       EDX_TRY(k_multi_dot(vtype, L.vec, (int64_t)(L.vstride / vbytes(vtype)), j + 1, b.w, n,
                           L.partial, st));
       EDX_TRY(k_reduce_strided(L.partial, multi_blocks(n), kMaxPartials, j + 1, L.coef, st));
@@ -392,6 +400,243 @@ edx_status lanczos_ground_state_impl(const edx_sector* s, const edx_lanczos_opts
     return EDX_E_NOCONV;
   }
   if (degenerate) return EDX_E_DEGENERATE;
+  return EDX_OK;
+}
+
+// ---------------------------------------------------------------- low-lying states
+// Workspace: the Lanczos basis of one run (full re-orthogonalisation) and k + 1
+// vectors after it: k locked eigenvectors (orthonormal, padded layout) and one
+// staging slot for a Ritz vector that is not locked yet.
+namespace {
+
+size_t lowest_ws_layout(int64_t vlen, int vtype, int niter, int k, int hvb, char* base,
+                        LanczosWs* L, char** locked) {
+  const int nit = std::max(niter, k + 1);   // scalar arrays and dot slots cover k
+  const size_t off = lanczos_ws_layout(vlen, vtype, nit, 2, hvb, false, base, L);
+  if (locked) *locked = base ? base + off : nullptr;
+  return off + align_up((size_t)vlen * vbytes(vtype)) * (size_t)(k + 1);
+}
+
+// w -= sum_k <x_k, w> x_k over nl orthonormal x_k, twice; L.partial then holds
+// the partial sums of |w|^2 (multi_blocks(n) of them)
+edx_status project_out(int vtype, void* w, const char* X, const LanczosWs& L, int nl, int64_t n,
+                       hipStream_t st) {
+  const int64_t ldv = (int64_t)(L.vstride / vbytes(vtype));
+  for (int pass = 0; pass < 2; ++pass) {
+    EDX_TRY(k_multi_dot(vtype, X, ldv, nl, w, n, L.partial, st));
+    EDX_TRY(k_reduce_strided(L.partial, multi_blocks(n), kMaxPartials, nl, L.coef, st));
+    EDX_TRY(k_multi_axpy(vtype, w, X, ldv, nl, L.coef, n, L.partial, st));
+  }
+  return EDX_OK;
+}
+
+// out = sum_i c_i sum_j y_i[j] v_j over the run's basis (v_j = scale_j u_j)
+edx_status ritz_combination(int vtype, const LanczosWs& L, int m, const std::vector<double>& hs,
+                            const std::vector<std::vector<double>>& ys,
+                            const std::vector<double>& c, void* out, int64_t n, hipStream_t st) {
+  std::vector<double> coef(m, 0.0);
+  for (size_t i = 0; i < ys.size(); ++i)
+    for (int j = 0; j < m; ++j) coef[j] -= c[i] * ys[i][j] * hs[j];
+  EDX_HIP(hipMemcpyAsync(L.coef, coef.data(), sizeof(double) * m, hipMemcpyHostToDevice, st));
+  EDX_HIP(hipMemsetAsync(out, 0, (size_t)n * vbytes(vtype), st));
+  EDX_TRY(k_multi_axpy(vtype, out, L.vec, (int64_t)(L.vstride / vbytes(vtype)), m, L.coef, n,
+                       nullptr, st));
+  EDX_HIP(hipStreamSynchronize(st));   // coef is a host temporary
+  return EDX_OK;
+}
+
+}  // namespace
+
+size_t lowest_workspace_bytes(const edx_sector* s, int vtype, int niter, int k) {
+  k = (int)std::min<int64_t>(std::max(k, 1), s->dim);
+  return lowest_ws_layout(s->vlen, vtype, niter, k, hv_partial_blocks(s, vtype), nullptr, nullptr,
+                          nullptr) + 256;
+}
+
+edx_status lowest_states_impl(const edx_sector* s, int k, const edx_lanczos_opts* o, int verify,
+                              void* ws, size_t ws_bytes, double* e_out, void* psi_out,
+                              edx_lowest_report* rep, hipStream_t st) {
+  const int vtype = o->vtype;
+  const int niter = o->niter;
+  k = (int)std::min<int64_t>(k, s->dim);
+  LanczosWs L;
+  char* X = nullptr;
+  char* base = reinterpret_cast<char*>(align_up(reinterpret_cast<uintptr_t>(ws)));
+  const size_t need = lowest_ws_layout(s->vlen, vtype, niter, k, hv_partial_blocks(s, vtype),
+                                       base, &L, &X);
+  if (need + (size_t)(base - (char*)ws) > ws_bytes) {
+    set_error("lanczos_lowest: workspace too small (need " + std::to_string(need + 256) +
+              " bytes)");
+    return EDX_E_NOMEM;
+  }
+  const int64_t n = s->vlen;
+  const size_t vs = L.vstride;
+  const double rtol = o->rtol > 0.0 ? o->rtol : o->tol;
+  std::vector<double> E;            // energies of the locked states, slot order
+  std::vector<double> ha(niter + 2), hb(niter + 2), hs(niter + 2);
+  bool from_staging = false;        // next run starts from the staging slot
+  bool verified = verify == 0;
+  int runs = 0, iters = 0;
+  double resid_max = 0.0;
+  const int max_runs = 4 * k + 8;
+  auto slot = [&](int i) { return X + (size_t)i * vs; };
+
+  while (runs < max_runs) {
+    const int nl = (int)E.size();
+    const bool checking = nl >= k;
+    if (checking && (verified || nl >= s->dim)) {
+      verified = true;
+      break;
+    }
+    const int want = checking ? 1 : k - nl;
+    char* stage = slot(nl);         // first free slot (slot k while checking)
+    // start vector, orthogonal to the locked states
+    if (from_staging) {
+      EDX_HIP(hipMemcpyAsync(L.vec, stage, (size_t)n * vbytes(vtype), hipMemcpyDeviceToDevice,
+                             st));
+      if (nl == 0) EDX_TRY(k_norm2(vtype, L.vec, n, L.partial, st));
+    } else {
+      EDX_TRY(k_start_vector(vtype, L.vec, s->dup, s->ld, s->ddw,
+                             o->seed + 0x9E3779B97F4A7C15ull * (uint64_t)runs, L.partial, st));
+    }
+    if (nl > 0) EDX_TRY(project_out(vtype, L.vec, X, L, nl, n, st));
+    EDX_TRY(k_beta_finish(L.partial, elem_blocks(n), L.beta, L.scale, st));
+    EDX_HIP(hipMemsetAsync(L.beta, 0, sizeof(double), st));
+    ++runs;
+
+    // Lanczos run with full re-orthogonalisation and deflation
+    int m = 0, done = 0;
+    double tnorm = 0.0;
+    std::vector<double> theta;
+    std::vector<std::vector<double>> ys;
+    std::vector<double> res;
+    int nconv = 0;
+    const int every = std::max(1, o->check_every);
+    while (done < niter && m == 0) {
+      const int upto = (int)std::min<int64_t>({(int64_t)niter, (int64_t)done + every,
+                                               s->dim - nl});
+      for (int j = done; j < upto; ++j)
+        EDX_TRY(lanczos_step(s, vtype, L, j, 2, L.alpha, L.beta, L.scale, nullptr, nullptr, st,
+                             X, nl));
+      EDX_HIP(hipMemcpyAsync(ha.data(), L.alpha, sizeof(double) * upto, hipMemcpyDeviceToHost,
+                             st));
+      EDX_HIP(hipMemcpyAsync(hb.data(), L.beta, sizeof(double) * (upto + 1),
+                             hipMemcpyDeviceToHost, st));
+      EDX_HIP(hipStreamSynchronize(st));
+      for (int j = done; j < upto; ++j) tnorm = std::max(tnorm, std::fabs(ha[j]) + hb[j] + hb[j + 1]);
+      const int mm = upto;
+      const bool bd = !(hb[mm] > 1e-12 * tnorm) || mm >= s->dim - nl;
+      const double floor32 = vtype == EDX_F32 ? 2.0 * 1.1920929e-7 * tnorm : 0.0;
+      const int w = std::min(want, mm);
+      theta.assign(w, 0.0);
+      ys.assign(w, std::vector<double>(mm));
+      res.assign(w, 0.0);
+      nconv = 0;
+      bool lead = true;
+      for (int i = 0; i < w; ++i) {
+        theta[i] = tridiag_lowest(ha.data(), hb.data() + 1, mm, i);
+        tridiag_vector(ha.data(), hb.data() + 1, mm, theta[i], ys[i].data());
+        res[i] = bd ? 0.0 : hb[mm] * std::fabs(ys[i][mm - 1]);
+        const bool ok = res[i] <= std::max(rtol * std::max(1.0, std::fabs(theta[i])), floor32);
+        lead = lead && ok;
+        if (lead) ++nconv;
+      }
+      if (nconv == want || bd || upto == niter) m = mm;
+      done = upto;
+    }
+    iters += m;
+    // orthonormalise the Ritz coefficient vectors (modified Gram-Schmidt):
+    // a tight cluster of Ritz values can give nearly parallel inverse-iteration vectors
+    for (size_t i = 0; i < ys.size(); ++i) {
+      for (size_t q = 0; q < i; ++q) {
+        double d = 0.0;
+        for (int j = 0; j < m; ++j) d += ys[q][j] * ys[i][j];
+        for (int j = 0; j < m; ++j) ys[i][j] -= d * ys[q][j];
+      }
+      double nn = 0.0;
+      for (int j = 0; j < m; ++j) nn += ys[i][j] * ys[i][j];
+      nn = std::sqrt(nn);
+      for (int j = 0; j < m; ++j) ys[i][j] /= nn;
+    }
+    EDX_HIP(hipMemcpyAsync(hs.data(), L.scale, sizeof(double) * m, hipMemcpyDeviceToHost, st));
+    EDX_HIP(hipStreamSynchronize(st));
+
+    // lock the converged leading pairs (or, while checking, test the lowest)
+    int locked_now = 0;
+    for (int i = 0; i < nconv; ++i) {
+      if (checking) {
+        const double emax = *std::max_element(E.begin(), E.end());
+        const double delta = std::max(10.0 * rtol * std::max(1.0, std::fabs(emax)), 1e-12) +
+                             (vtype == EDX_F32 ? 4.0 * 1.1920929e-7 * tnorm : 0.0);
+        if (theta[0] >= emax - delta) {
+          verified = true;
+          break;
+        }
+      }
+      char* dst = slot((int)E.size());
+      EDX_TRY(ritz_combination(vtype, L, m, hs, {ys[i]}, {1.0}, dst, n, st));
+      if (!E.empty()) {
+        EDX_TRY(project_out(vtype, dst, X, L, (int)E.size(), n, st));
+      } else {
+        EDX_TRY(k_norm2(vtype, dst, n, L.partial, st));
+      }
+      EDX_TRY(k_beta_finish(L.partial, elem_blocks(n), L.coef, L.coef + 1, st));
+      double nrm = 0.0;
+      EDX_HIP(hipMemcpyAsync(&nrm, L.coef, sizeof(double), hipMemcpyDeviceToHost, st));
+      EDX_HIP(hipStreamSynchronize(st));
+      if (!(nrm > 0.5)) break;   // not independent of the locked states: leave it
+      EDX_TRY(k_scale_copy(vtype, dst, L.coef + 1, dst, n, st));
+      if (checking) {
+        // replaces the highest locked state
+        const int hi = (int)(std::max_element(E.begin(), E.end()) - E.begin());
+        EDX_HIP(hipMemcpyAsync(slot(hi), dst, (size_t)n * vbytes(vtype), hipMemcpyDeviceToDevice,
+                               st));
+        E[hi] = theta[i];
+      } else {
+        E.push_back(theta[i]);
+      }
+      resid_max = std::max(resid_max, res[i]);
+      ++locked_now;
+      if (checking) break;
+    }
+    if (verified && checking) break;
+    // restart from the wanted Ritz vectors that did not converge
+    from_staging = false;
+    const int wl = (int)ys.size();
+    if (locked_now < wl && (int)E.size() < s->dim) {
+      std::vector<std::vector<double>> rest(ys.begin() + locked_now, ys.end());
+      const int free_slot = std::min((int)E.size(), k);
+      EDX_TRY(ritz_combination(vtype, L, m, hs, rest, std::vector<double>(rest.size(), 1.0),
+                               slot(free_slot), n, st));
+      from_staging = true;
+    }
+  }
+  const int nf = (int)E.size();
+  std::vector<int> order(nf);
+  for (int i = 0; i < nf; ++i) order[i] = i;
+  std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return E[x] < E[y]; });
+  for (int i = 0; i < nf; ++i) e_out[i] = E[order[i]];
+  if (psi_out && nf > 0) {
+    const double one = 1.0;
+    EDX_HIP(hipMemcpyAsync(L.coef + 2, &one, sizeof(double), hipMemcpyHostToDevice, st));
+    for (int i = 0; i < nf; ++i) {
+      char* dst = reinterpret_cast<char*>(psi_out) + (size_t)i * s->dim * vbytes(vtype);
+      EDX_TRY(k_unpad_scale(vtype, slot(order[i]), s->ld, s->dup, s->ddw, L.coef + 2, dst, st));
+    }
+  }
+  EDX_HIP(hipStreamSynchronize(st));
+  if (rep) {
+    rep->nfound = nf;
+    rep->runs = runs;
+    rep->iters = iters;
+    rep->verified = verified ? 1 : 0;
+    rep->resid_max = resid_max;
+  }
+  if (nf < k || !verified) {
+    set_error("lanczos_lowest: " + std::to_string(nf) + " of " + std::to_string(k) +
+              " states converged" + (verified ? "" : " (check run not passed)"));
+    return EDX_E_NOCONV;
+  }
   return EDX_OK;
 }
 

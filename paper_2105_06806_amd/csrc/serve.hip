@@ -29,15 +29,6 @@
 
 namespace edx {
 
-size_t lanczos_workspace_bytes(const edx_sector* s, int vtype, int niter, int reorth);
-size_t green_workspace_bytes(const edx_sector* s, int vtype, int ngf);
-edx_status lanczos_ground_state_impl(const edx_sector* s, const edx_lanczos_opts* o, void* ws,
-                                     size_t ws_bytes, double* e0, void* psi0,
-                                     edx_lanczos_report* rep, hipStream_t st);
-edx_status green_cf_impl(const edx_sector* gs, const void* psi0, double e0, int orb, int spin,
-                         const edx_gf_opts* o, void* ws, size_t ws_bytes, double* g_host,
-                         edx_gf_report* rep, hipStream_t st);
-
 namespace {
 
 constexpr int kMaxSkips = 8;

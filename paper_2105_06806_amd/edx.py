@@ -58,6 +58,18 @@ class LanczosReport(ctypes.Structure):
                 ("beta_last", ctypes.c_double), ("resid", ctypes.c_double)]
 
 
+class LowestReport(ctypes.Structure):
+    _fields_ = [("nfound", ctypes.c_int32), ("runs", ctypes.c_int32),
+                ("iters", ctypes.c_int32), ("verified", ctypes.c_int32),
+                ("resid_max", ctypes.c_double)]
+
+
+class EspaceOpts(ctypes.Structure):
+    _fields_ = [("beta", ctypes.c_double), ("cutoff", ctypes.c_double),
+                ("nstates_sector", ctypes.c_int32), ("nstates_total", ctypes.c_int32),
+                ("nstates_step", ctypes.c_int32), ("verify", ctypes.c_int32)]
+
+
 class BatchResult(ctypes.Structure):
     _fields_ = [("e0", ctypes.c_double), ("beta_last", ctypes.c_double),
                 ("iters", ctypes.c_int32), ("status", ctypes.c_int32),
@@ -115,6 +127,18 @@ _SIGS = {
     "edx_lanczos_default_opts": (None, [ctypes.POINTER(LanczosOpts)]),
     "edx_workspace_bytes": (ctypes.c_size_t, [_P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]),
     "edx_lanczos_ground_state": (ctypes.c_int, [_P, ctypes.POINTER(LanczosOpts), _P, ctypes.c_size_t, ctypes.POINTER(ctypes.c_double), _P, ctypes.POINTER(LanczosReport), _P]),
+    "edx_lowest_workspace_bytes": (ctypes.c_size_t, [_P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]),
+    "edx_lanczos_lowest": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.POINTER(LanczosOpts), ctypes.c_int32, _P, ctypes.c_size_t, _P, _P, ctypes.POINTER(LowestReport), _P]),
+    "edx_espace_default_opts": (None, [ctypes.POINTER(EspaceOpts)]),
+    "edx_espace_create": (ctypes.c_int, [ctypes.POINTER(EspaceOpts), ctypes.c_int32, ctypes.POINTER(_P)]),
+    "edx_espace_destroy": (None, [_P]),
+    "edx_espace_diag_workspace_bytes": (ctypes.c_size_t, [_P, _P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]),
+    "edx_espace_diag": (ctypes.c_int, [_P, _P, ctypes.c_int32, ctypes.POINTER(LanczosOpts), _P, ctypes.c_size_t, _P]),
+    "edx_espace_info": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]),
+    "edx_espace_state": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_P)]),
+    "edx_espace_sector": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]),
+    "edx_espace_green_workspace_bytes": (ctypes.c_size_t, [_P, ctypes.c_int32]),
+    "edx_espace_green": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(GfOpts), _P, ctypes.c_size_t, _P, _P]),
     "edx_green_cf": (ctypes.c_int, [_P, _P, ctypes.c_double, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(GfOpts), _P, ctypes.c_size_t, _P, ctypes.POINTER(GfReport), _P]),
     "edx_batch_workspace_bytes": (ctypes.c_size_t, [_P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int64]),
     "edx_batch_ground_state": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.POINTER(LanczosOpts), ctypes.POINTER(BatchTiles), _P, ctypes.c_size_t, ctypes.POINTER(BatchResult), ctypes.POINTER(ctypes.c_double), _P]),
@@ -386,6 +410,94 @@ def green_cf(sector, psi0, e0, orb=0, spin=0, ngf=200, beta=200.0, lmats=4096, w
         n = rep.np if k.endswith("_p") else rep.nh
         r[k] = b[: n if k.startswith("alpha") else max(n - 1, 0)].copy()
     return g[0::2] + 1j * g[1::2], r
+
+
+def lanczos_lowest(sector, k, verify=1, want_psi=True, ws=None, stream=None, allow=(EDX_OK,), **kw):
+    """k lowest eigenpairs: (energies numpy [nfound], psi tensor [nfound, D] or
+    None, report dict, status)."""
+    o = lanczos_opts(**kw)
+    need = int(lib.edx_lowest_workspace_bytes(sector.handle, o.vtype, o.niter, int(k)))
+    if need == 0:
+        raise ValueError("bad arguments for edx_lowest_workspace_bytes")
+    if ws is None:
+        ws = alloc_workspace(need)
+    kk = min(int(k), sector.dim)
+    e = np.zeros(kk, np.float64)
+    psi = torch.empty((kk, sector.dim), dtype=_dtype_of(o.vtype), device="cuda") if want_psi else None
+    rep = LowestReport()
+    st = lib.edx_lanczos_lowest(sector.handle, int(k), ctypes.byref(o), int(verify), _P(ws.data_ptr()),
+                                ws.numel(), e.ctypes.data_as(_P),
+                                _P(psi.data_ptr()) if psi is not None else None, ctypes.byref(rep),
+                                _stream_ptr(stream))
+    _check(st, ok=tuple(allow) + (EDX_OK,))
+    r = {f: getattr(rep, f) for f, _ in LowestReport._fields_}
+    n = r["nfound"]
+    return e[:n], (psi[:n] if psi is not None else None), r, st
+
+
+class Espace:
+    """Owning wrapper of an edx_espace (finite-temperature state list)."""
+
+    def __init__(self, nsec, **kw):
+        o = EspaceOpts()
+        lib.edx_espace_default_opts(ctypes.byref(o))
+        for k, v in kw.items():
+            setattr(o, k, v)
+        self.opts = o
+        h = _P()
+        _check(lib.edx_espace_create(ctypes.byref(o), int(nsec), ctypes.byref(h)))
+        self.handle = h.value
+        self.nsec = int(nsec)
+        self.sectors = None
+        self.vtype = None
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h and lib is not None:
+            lib.edx_espace_destroy(h)
+            self.handle = None
+
+    def diag(self, sectors, ws=None, stream=None, **kw):
+        o = lanczos_opts(**kw)
+        hs = _handles(sectors)
+        need = int(lib.edx_espace_diag_workspace_bytes(self.handle, hs, len(sectors), o.vtype, o.niter))
+        if need == 0:
+            raise ValueError("bad arguments for edx_espace_diag_workspace_bytes")
+        if ws is None or ws.numel() < need:
+            ws = alloc_workspace(need)
+        self.sectors = list(sectors)       # the espace does not own them
+        self.vtype = o.vtype
+        _check(lib.edx_espace_diag(self.handle, hs, len(sectors), ctypes.byref(o), _P(ws.data_ptr()),
+                                   ws.numel(), _stream_ptr(stream)))
+
+    def info(self):
+        n, e0, z = ctypes.c_int32(), ctypes.c_double(), ctypes.c_double()
+        _check(lib.edx_espace_info(self.handle, ctypes.byref(n), ctypes.byref(e0), ctypes.byref(z)))
+        return n.value, e0.value, z.value
+
+    def state(self, i):
+        e, sec, w, p = ctypes.c_double(), ctypes.c_int32(), ctypes.c_double(), _P()
+        _check(lib.edx_espace_state(self.handle, int(i), ctypes.byref(e), ctypes.byref(sec),
+                                    ctypes.byref(w), ctypes.byref(p)))
+        return e.value, sec.value, w.value, p.value
+
+    def sector(self, i):
+        c, k, nx = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        _check(lib.edx_espace_sector(self.handle, int(i), ctypes.byref(c), ctypes.byref(k), ctypes.byref(nx)))
+        return c.value, k.value, nx.value
+
+    def green(self, orb=0, spin=0, ngf=200, lmats=1024, ws=None, stream=None):
+        """Thermal G(i w_n) on the grid of the espace's beta (complex numpy)."""
+        o = GfOpts(int(ngf), int(lmats), self.vtype, 0, float(self.opts.beta))
+        need = int(lib.edx_espace_green_workspace_bytes(self.handle, int(ngf)))
+        if need == 0:
+            raise ValueError("no kept states (run diag first)")
+        if ws is None or ws.numel() < need:
+            ws = alloc_workspace(need)
+        g = np.zeros(2 * lmats, np.float64)
+        _check(lib.edx_espace_green(self.handle, int(orb), int(spin), ctypes.byref(o), _P(ws.data_ptr()),
+                                    ws.numel(), g.ctypes.data_as(_P), _stream_ptr(stream)))
+        return g[0::2] + 1j * g[1::2]
 
 
 def _handles(sectors):
