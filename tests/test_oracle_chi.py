@@ -1,0 +1,93 @@
+"""Oracle pins for the density-type susceptibilities (eq. KLgf with the bosonic
+sign, O diagonal in the occupation basis).
+
+  * the sector form equals a Jordan-Wigner build on the whole Fock space
+    (O from the number operators, the ground state of the sector embedded in
+    the Fock space), for spin and charge operators, and a flipped bosonic sign
+    is caught;
+  * U = 0: the charge susceptibility of one orbital and spin is the bubble of
+    the one-body eigenvectors (occupied -> empty transitions);
+  * the Krylov form equals the exact sum once the Krylov space is exhausted;
+  * chi(i nu) is real and positive-definite in the sense -C(i nu) >= 0 and
+    decreases with nu (a sum of 2 d / (nu^2 + d^2) terms).
+"""
+import numpy as np
+import pytest
+
+from oracle import chi, closed, fock, jw
+from paper_2105_06806_amd import inputs
+
+
+def _jw_chi(model, sec, cu, cd, z):
+    ns = fock.ns_of(model)
+    H, c = jw.fock_hamiltonian(model)
+    n = [c[m].T @ c[m] for m in range(2 * ns)]
+    O = sum(cu[a] * n[a] + cd[a] * n[ns + a] for a in range(model["norb"]))
+    _, _, I = fock.sector_states(ns, *sec)
+    idx = I.astype(np.int64)
+    w0, V0 = np.linalg.eigh(H[np.ix_(idx, idx)])
+    psi = np.zeros(H.shape[0])
+    psi[idx] = V0[:, 0]
+    w, V = np.linalg.eigh(H)
+    amp = V.T @ (O @ psi)
+    return chi.spectral(w, amp ** 2, w0[0], z)
+
+
+@pytest.mark.parametrize("kind", ["spin", "charge"])
+@pytest.mark.parametrize("norb,nbath,sec,orb", [(1, 3, (2, 2), 0), (2, 1, (2, 1), 1)])
+def test_sector_form_equals_jordan_wigner(kind, norb, nbath, sec, orb):
+    m = inputs.make_model(norb, nbath, 2.5, Jh=0.3, seed=81 + norb, symmetric=False)
+    cu = np.zeros(norb)
+    cd = np.zeros(norb)
+    cu[orb], cd[orb] = (0.5, -0.5) if kind == "spin" else (1.0, 1.0)
+    z = 1j * chi.bosonic(5.0, 12)
+    got, _ = chi.chi_exact(m, *sec, cu, cd, z)
+    ref = _jw_chi(m, sec, cu, cd, z)
+    assert np.abs(got - ref).max() < 1e-12
+    assert np.abs(got.imag).max() < 1e-12
+    assert np.all(got.real <= 1e-14) and np.all(np.diff(got.real) >= -1e-14)
+
+
+def test_flipped_bosonic_sign_is_caught(monkeypatch):
+    m = inputs.make_model(1, 3, 2.0, seed=84, symmetric=False)
+    z = 1j * chi.bosonic(4.0, 6)
+    ref = _jw_chi(m, (2, 2), [0.5], [-0.5], z)
+
+    def wrong(poles, weights, e0, zz):
+        d = np.asarray(poles) - e0
+        keep = np.abs(d) > 1e-10
+        d, w = d[keep], np.asarray(weights)[keep]
+        return (w[None, :] * (1 / (zz[:, None] - d) + 1 / (zz[:, None] + d))).sum(axis=1)
+    monkeypatch.setattr(chi, "spectral", wrong)
+    got, _ = chi.chi_exact(m, 2, 2, [0.5], [-0.5], z)
+    assert np.abs(got - ref).max() > 1e-3
+
+
+def test_noninteracting_bubble():
+    """U = 0, one spin: C_{n n}(z) = sum_{k occ, l empty} |phi_k(0) phi_l(0)|^2
+    [1/(z - (e_l - e_k)) - 1/(z + (e_l - e_k))]."""
+    m = inputs.make_model(1, 4, 0.0, seed=85, symmetric=False, eps_imp=0.2)
+    ns = fock.ns_of(m)
+    nup, ndw = 2, 3
+    e, U = np.linalg.eigh(closed.onebody_matrix(m))
+    z = 1j * chi.bosonic(6.0, 10)
+    got, _ = chi.chi_exact(m, nup, ndw, [1.0], [0.0], z)
+    ref = np.zeros(len(z), dtype=complex)
+    for k in range(nup):
+        for l in range(nup, ns):
+            w = (U[0, k] * U[0, l]) ** 2
+            d = e[l] - e[k]
+            ref += w * (1 / (z - d) - 1 / (z + d))
+    assert np.abs(got - ref).max() < 1e-12
+
+
+def test_krylov_exhausted_equals_exact():
+    m = inputs.make_model(2, 1, 2.5, Jh=0.4, seed=86, symmetric=False)
+    sec = (2, 2)
+    H = fock.explicit_hamiltonian(m, *sec)
+    w, V = np.linalg.eigh(H.toarray())
+    z = 1j * chi.bosonic(8.0, 16)
+    cu, cd = [0.5, 0.0], [-0.5, 0.0]
+    ref, _ = chi.chi_exact(m, *sec, cu, cd, z)
+    got, wgt, _ = chi.chi_krylov(m, *sec, V[:, 0], w[0], cu, cd, H.shape[0], z, lambda x: H @ x)
+    assert np.abs(got - ref).max() < 1e-9 * np.abs(ref).max()
