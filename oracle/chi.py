@@ -9,7 +9,9 @@ O is diagonal in the occupation basis and keeps the sector:
 (spin: c_up = 1/2, c_dw = -1/2 on one orbital; charge: 1, 1; a cross-orbital
 function follows from O = A + B as the paper describes).  Terms with
 E_m = E0 contribute 1/z - 1/z = 0 at z != 0 and are dropped (also at z = 0,
-the T = 0 limit).  Bosonic Matsubara grid: nu_n = 2 n pi / beta.
+the T = 0 limit); "E_m = E0" means within the ground-state degeneracy
+threshold gs_threshold = 1e-9 of the input table (times max(1, |E0|)).
+Bosonic Matsubara grid: nu_n = 2 n pi / beta.
 
 ``chi_exact`` sums over every eigenstate of the sector (dense).  ``chi_krylov``
 is the Krylov form: start from O|psi0>, run N plain Lanczos steps in the same
@@ -23,7 +25,7 @@ import numpy as np
 
 from . import fock, spectra
 
-DROP_REL = 1e-10     # |E_m - E0| <= DROP_REL * max(1, |E0|): a zero-energy pole
+DROP_REL = 1e-9      # |E_m - E0| <= DROP_REL * max(1, |E0|): a zero-energy pole
 
 
 def bosonic(beta, lmats):
@@ -68,3 +70,43 @@ def chi_krylov(model, nup, ndw, psi0, e0, coef_up, coef_dw, ngf, z, matvec):
     a, b = spectra.plain_lanczos(matvec, phi, ngf)
     th, U = spectra.tridiag_eigh(a, b)
     return spectral(th, wgt * U[0, :] ** 2, e0, z), wgt, (a, b)
+
+
+def chi_thermal_states(model, states, coef_up, coef_dw, z, beta):
+    """Thermal form: sum_n w_n C_n(z) over a list of (E, sec, psi), C_n the exact
+    per-state function with E_n as reference, w_n normalised over the list."""
+    e = np.array([t[0] for t in states])
+    w = np.exp(-beta * (e - e.min()))
+    w = w / w.sum()
+    out = np.zeros(len(z), dtype=complex)
+    for wn, (en, sec, psi) in zip(w, states):
+        H = fock.explicit_hamiltonian(model, *sec).toarray()
+        wm, V = np.linalg.eigh(H)
+        o = diag_operator(model, sec[0], sec[1], coef_up, coef_dw)
+        amp = V.T @ (o * np.asarray(psi, float))
+        out += wn * spectral(wm, amp ** 2, en, z)
+    return out
+
+
+def chi_double_sum(model, sectors, coef_up, coef_dw, z, beta):
+    """Textbook bosonic Lehmann double sum over every eigenstate of the listed
+    sectors (O keeps the sector):
+      C(z) = (1/Z) sum_{n,m} |<m|O|n>|^2 (e^{-beta E_n} - e^{-beta E_m}) / (z - (E_m - E_n)),
+    pairs with |E_m - E_n| within the zero-pole threshold left out."""
+    spec = []
+    for sec in sectors:
+        H = fock.explicit_hamiltonian(model, *sec).toarray()
+        w, V = np.linalg.eigh(H)
+        o = diag_operator(model, sec[0], sec[1], coef_up, coef_dw)
+        spec.append((w, V.T @ (o[:, None] * V)))
+    e0 = min(w[0] for w, _ in spec)
+    Z = sum(np.exp(-beta * (w - e0)).sum() for w, _ in spec)
+    out = np.zeros(len(z), dtype=complex)
+    for w, M in spec:
+        b = np.exp(-beta * (w - e0))
+        d = w[:, None] - w[None, :]                       # E_m - E_n  [m, n]
+        keep = np.abs(d) > DROP_REL * max(1.0, abs(e0))
+        num = (M ** 2) * (b[None, :] - b[:, None])
+        for k, zz in enumerate(z):
+            out[k] += (num[keep] / (zz - d[keep])).sum()
+    return out / Z

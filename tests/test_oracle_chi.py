@@ -9,7 +9,9 @@ sign, O diagonal in the occupation basis).
     the one-body eigenvectors (occupied -> empty transitions);
   * the Krylov form equals the exact sum once the Krylov space is exhausted;
   * chi(i nu) is real and positive-definite in the sense -C(i nu) >= 0 and
-    decreases with nu (a sum of 2 d / (nu^2 + d^2) terms).
+    decreases with nu (a sum of 2 d / (nu^2 + d^2) terms);
+  * finite temperature: the per-state thermal sum over every eigenstate equals
+    the textbook bosonic double sum.
 """
 import numpy as np
 import pytest
@@ -91,3 +93,15 @@ def test_krylov_exhausted_equals_exact():
     ref, _ = chi.chi_exact(m, *sec, cu, cd, z)
     got, wgt, _ = chi.chi_krylov(m, *sec, V[:, 0], w[0], cu, cd, H.shape[0], z, lambda x: H @ x)
     assert np.abs(got - ref).max() < 1e-9 * np.abs(ref).max()
+
+
+def test_thermal_per_state_equals_double_sum():
+    from oracle import thermal
+    m = inputs.make_model(1, 3, 2.0, seed=87, symmetric=False)
+    secs = thermal.all_sectors(m)
+    beta = 3.0
+    z = 1j * chi.bosonic(beta, 10)
+    cu, cd = [0.5], [-0.5]
+    got = chi.chi_thermal_states(m, thermal.all_states(m), cu, cd, z, beta)
+    ref = chi.chi_double_sum(m, secs, cu, cd, z, beta)
+    assert np.abs(got - ref).max() < 1e-12
