@@ -199,7 +199,8 @@ void edx_lanczos_default_opts(edx_lanczos_opts* o);
 #define EDX_WS_GREEN 1
 
 /* Device workspace bytes for edx_lanczos_ground_state (what = EDX_WS_LANCZOS,
- * n = niter) or edx_green_cf (what = EDX_WS_GREEN, n = ngf). */
+ * n = niter), edx_green_cf (what = EDX_WS_GREEN, n = ngf) or edx_chi
+ * (what = EDX_WS_CHI = 3, n = ngf). */
 size_t edx_workspace_bytes(const edx_sector* s, int32_t what, int32_t vtype,
                            int32_t n);
 
@@ -278,6 +279,41 @@ edx_status edx_green_cf(const edx_sector* gs, const void* psi0, double e0,
                         void* ws, size_t ws_bytes, double* g_host,
                         edx_gf_report* rep, void* stream);
 
+/* Poles and weights of a Krylov spectral function (Sec. 5 "Dynamical
+ * correlation functions": the eigenvalues theta_m of the Lanczos tridiagonal
+ * matrix and the squared first components |a_m|^2 of its eigenvectors).
+ * alpha [m] diagonal, beta [m-1] off-diagonal, theta and weight [m] outputs,
+ * all host; theta ascending.  Implicit symmetric QR with the Wilkinson shift,
+ * O(m^2).  EDX_E_NOCONV if a block does not converge. */
+edx_status edx_tridiag_spectrum(const double* alpha, const double* beta, int32_t m,
+                                double* theta, double* weight);
+
+/* Density-type susceptibility at T = 0 (eq. KLgf with the bosonic sign, Sec. 5
+ * "Dynamical correlation functions"; the paper's spin and charge functions):
+ * O = sum_a (cu[a] n_{a up} + cd[a] n_{a dw}) (host arrays [norb]; S_z of
+ * orbital a: cu[a] = 1/2, cd[a] = -1/2; charge: 1, 1; a cross-orbital function
+ * from O = A + B), diagonal in the occupation basis, so O psi0 stays in the
+ * sector of psi0 (dense, D elements of opts->vtype):
+ *   C(i nu_n) = sum_m |<m|O|psi0>|^2 [1/(i nu_n - (E_m - E0)) - 1/(i nu_n + (E_m - E0))]
+ *             = -sum_m |<m|O|psi0>|^2 2 d_m / (nu_n^2 + d_m^2),  nu_n = 2 n pi / beta,
+ * from ngf plain Lanczos steps started at (O - <O>) psi0, with the poles and
+ * weights of the tridiagonal matrix.  Poles with |d_m| within gs_threshold =
+ * 1e-9 max(1, |E0|) (FP32 vectors: at least 2 * 2^-23 |T|) are dropped: they
+ * give 1/z - 1/z = 0 for z != 0 and the T = 0 limit at z = 0 (subtracting <O>
+ * psi0 only removes such a pole).  chi_host: 2*lmats doubles (re, im). */
+typedef struct {
+  double w;          /* |(O - <O>) psi0|^2                                   */
+  double mean;       /* <psi0|O|psi0>                                        */
+  int32_t n;         /* recurrence length                                     */
+  int32_t dropped;   /* poles dropped as zero-energy                          */
+} edx_chi_report;
+
+#define EDX_WS_CHI 3
+
+edx_status edx_chi(const edx_sector* s, const void* psi0, double e0, const double* cu,
+                   const double* cd, const edx_gf_opts* opts, void* ws, size_t ws_bytes,
+                   double* chi_host, edx_chi_report* rep, void* stream);
+
 /* ---- finite temperature: the eigenstate list (Sec. 5 "Eigenspace class"
  * and the thermal form of "Dynamical correlation functions") ----
  * An edx_espace holds the low-lying states of a fixed set of nsec sectors.
@@ -342,6 +378,16 @@ size_t edx_espace_green_workspace_bytes(const edx_espace* E, int32_t ngf);
 edx_status edx_espace_green(edx_espace* E, int32_t orb, int32_t spin,
                             const edx_gf_opts* opts, void* ws, size_t ws_bytes,
                             double* g_host, void* stream);
+
+/* Thermal susceptibility sum_n w_n C_n over the kept states, C_n the T = 0
+ * form of edx_chi for state n with E_n as reference.  For z != 0 this is the
+ * bosonic Lehmann double sum (pairs with equal energies cancel); at nu = 0 the
+ * zero-energy terms (beta |<m|O|n>|^2 w_n within a degenerate level) are not
+ * included. */
+size_t edx_espace_chi_workspace_bytes(const edx_espace* E, int32_t ngf);
+edx_status edx_espace_chi(edx_espace* E, const double* cu, const double* cd,
+                          const edx_gf_opts* opts, void* ws, size_t ws_bytes,
+                          double* chi_host, void* stream);
 
 /* ---- batched ground states (many sectors, one persistent launch) ----
  * Every job is an independent sector; the ground energy of each follows the

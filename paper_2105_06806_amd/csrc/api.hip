@@ -253,6 +253,7 @@ size_t edx_workspace_bytes(const edx_sector* s, int32_t what, int32_t vtype, int
   if (what == EDX_WS_LANCZOS) return lanczos_workspace_bytes(s, vtype, n, 0);
   if (what == EDX_WS_GREEN) return green_workspace_bytes(s, vtype, n);
   if (what == 2) return lanczos_workspace_bytes(s, vtype, n, 2);   // full re-orthogonalisation
+  if (what == EDX_WS_CHI) return chi_workspace_bytes(s, vtype, n);
   return 0;
 }
 
@@ -286,6 +287,35 @@ edx_status edx_lanczos_lowest(const edx_sector* s, int32_t k, const edx_lanczos_
     return invalid("tol/rtol must be >= 0, one of them > 0");
   return lowest_states_impl(s, k, opts, verify, ws, ws_bytes, e, psi, rep,
                             static_cast<hipStream_t>(stream));
+}
+
+edx_status edx_tridiag_spectrum(const double* alpha, const double* beta, int32_t m,
+                                double* theta, double* weight) {
+  if (m < 1 || !alpha || !theta || !weight || (m > 1 && !beta))
+    return invalid("alpha, beta, theta, weight must be non-NULL and m >= 1");
+  if (!tridiag_spectrum(alpha, beta, m, theta, weight)) {
+    set_error("tridiag_spectrum: QR iteration did not converge");
+    return EDX_E_NOCONV;
+  }
+  return EDX_OK;
+}
+
+edx_status edx_chi(const edx_sector* s, const void* psi0, double e0, const double* cu,
+                   const double* cd, const edx_gf_opts* opts, void* ws, size_t ws_bytes,
+                   double* chi_host, edx_chi_report* rep, void* stream) {
+  EDX_TRY(check_sector(s));
+  if (!psi0 || !cu || !cd || !opts || !ws || !chi_host)
+    return invalid("psi0, cu, cd, opts, ws and chi_host must be non-NULL");
+  if (!valid_vtype(opts->vtype)) return invalid("vtype must be EDX_F64 or EDX_F32");
+  if (opts->ngf > 4096) return invalid("ngf must be <= 4096");
+  DiagCoef c{};
+  for (int a = 0; a < s->model.norb; ++a) {
+    if (!std::isfinite(cu[a]) || !std::isfinite(cd[a])) return invalid("cu/cd must be finite");
+    c.up[a] = cu[a];
+    c.dw[a] = cd[a];
+  }
+  return chi_impl(s, psi0, e0, c, opts, ws, ws_bytes, chi_host, rep,
+                  static_cast<hipStream_t>(stream));
 }
 
 edx_status edx_green_cf(const edx_sector* gs, const void* psi0, double e0, int32_t orb,

@@ -202,6 +202,16 @@ edx_status k_multi_axpy(int vtype, void* w, const void* basis, int64_t ld,
 int multi_blocks(int64_t n);
 
 // ---- green.hip
+// coefficients of a diagonal operator O = sum_a (up[a] n_{a up} + dw[a] n_{a dw})
+struct DiagCoef {
+  double up[kMaxNorb];
+  double dw[kMaxNorb];
+};
+// phi = (O - *mean) psi (mean != nullptr, partial: |phi|^2) or partial sums of
+// <psi|O|psi> (mean == nullptr); nblocks <= kMaxPartials workgroups of 256
+edx_status k_diag_apply(const edx_sector* s, int vtype, const void* psi, void* phi,
+                        const DiagCoef& c, const double* mean, double* partial, int nblocks,
+                        hipStream_t st);
 edx_status k_apply_op(const edx_sector* src, const edx_sector* dst, int vtype,
                       const void* psi, void* phi, int orb, int spin, int create,
                       hipStream_t st);
@@ -234,10 +244,15 @@ size_t green_workspace_bytes(const edx_sector* s, int vtype, int ngf);
 edx_status green_cf_impl(const edx_sector* gs, const void* psi0, double e0, int orb, int spin,
                          const edx_gf_opts* o, void* ws, size_t ws_bytes, double* g_host,
                          edx_gf_report* rep, hipStream_t st);
+size_t chi_workspace_bytes(const edx_sector* s, int vtype, int ngf);
+edx_status chi_impl(const edx_sector* s, const void* psi0, double e0, const DiagCoef& c,
+                    const edx_gf_opts* o, void* ws, size_t ws_bytes, double* chi_host,
+                    edx_chi_report* rep, hipStream_t st);
 // ---- lanczos.cpp (host)
 double tridiag_lowest(const double* a, const double* b, int m, int k);
 void tridiag_vector(const double* a, const double* b, int m, double lam,
                     double* y);
+bool tridiag_spectrum(const double* a, const double* b, int m, double* theta, double* w);
 
 inline int wpad_of(int width) { return width <= 8 ? 8 : (width <= 16 ? 16 : 24); }
 // Column stride of the library's Krylov vectors for a sector with dup rows:

@@ -243,4 +243,45 @@ edx_status edx_espace_green(edx_espace* E, int32_t orb, int32_t spin, const edx_
   return EDX_OK;
 }
 
+size_t edx_espace_chi_workspace_bytes(const edx_espace* E, int32_t ngf) {
+  if (!E || ngf < 1) return 0;
+  size_t need = 0;
+  for (int i = 0; i < E->nsec; ++i)
+    if (E->kept[i] > 0 && E->secs[i])
+      need = std::max(need, chi_workspace_bytes(E->secs[i], E->vtype, ngf));
+  return need;
+}
+
+edx_status edx_espace_chi(edx_espace* E, const double* cu, const double* cd,
+                          const edx_gf_opts* o, void* ws, size_t ws_bytes, double* chi_host,
+                          void* stream) {
+  if (!E || !cu || !cd || !o || !ws || !chi_host)
+    return invalid_e("espace, cu, cd, opts, ws and chi_host must be non-NULL");
+  if (E->list.empty()) return invalid_e("the state list is empty (run edx_espace_diag first)");
+  if (o->vtype != E->vtype) return invalid_e("opts->vtype differs from the stored vectors' type");
+  if (std::fabs(o->beta - E->o.beta) > 1e-12 * E->o.beta)
+    return invalid_e("opts->beta differs from the espace's beta");
+  if (o->ngf < 1 || o->ngf > 4096) return invalid_e("ngf must be in [1, 4096]");
+  const int lm = o->lmats;
+  if (lm < 1) return invalid_e("lmats must be >= 1");
+  std::vector<double> acc(2 * (size_t)lm, 0.0), cn(2 * (size_t)lm);
+  for (int n = 0; n < (int)E->list.size(); ++n) {
+    const auto& t = E->list[n];
+    const edx_sector* s = E->secs[t.sec];
+    DiagCoef c{};
+    for (int a = 0; a < s->model.norb; ++a) {
+      c.up[a] = cu[a];
+      c.dw[a] = cd[a];
+    }
+    const void* psi =
+        static_cast<const char*>(E->buf[t.sec]) + (size_t)t.idx * s->dim * vbytes(E->vtype);
+    EDX_TRY(chi_impl(s, psi, t.e, c, o, ws, ws_bytes, cn.data(), nullptr,
+                     static_cast<hipStream_t>(stream)));
+    const double w = std::exp(-E->o.beta * (t.e - E->e0)) / E->z;
+    for (size_t q = 0; q < acc.size(); ++q) acc[q] += w * cn[q];
+  }
+  std::copy(acc.begin(), acc.end(), chi_host);
+  return EDX_OK;
+}
+
 }  // extern "C"

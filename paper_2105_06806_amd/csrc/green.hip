@@ -54,6 +54,45 @@ __global__ __launch_bounds__(256) void k_apply(const T* __restrict__ psi, T* __r
   }
 }
 
+// phi = (O - mean) psi for O = sum_a (cu[a] n_{a up} + cd[a] n_{a dw}), diagonal
+// in the occupation basis, read from the impurity patterns of the two strings.
+// psi dense (stride dup), phi padded (stride ld, zero padding).  mean == nullptr:
+// only partial sums of <psi|O|psi>; otherwise phi is written and the partial
+// sums are |phi|^2.
+template <typename T>
+__global__ __launch_bounds__(256) void k_diag_op(const T* __restrict__ psi, T* __restrict__ phi,
+                                                 int64_t dup, int64_t ld, int64_t len,
+                                                 const uint8_t* __restrict__ pup,
+                                                 const uint8_t* __restrict__ pdw, int norb,
+                                                 DiagCoef c, const double* __restrict__ mean,
+                                                 double* __restrict__ partial) {
+  __shared__ double red[4];
+  double acc = 0.0;
+  const double mu = mean ? *mean : 0.0;
+  for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < len;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t id = idx / ld;
+    const int64_t iu = idx - id * ld;
+    if (iu >= dup) {
+      if (mean) phi[idx] = T(0);
+      continue;
+    }
+    const uint32_t a = pup[iu], b = pdw[id];
+    double f = 0.0;
+    for (int o = 0; o < norb; ++o) f += c.up[o] * ((a >> o) & 1u) + c.dw[o] * ((b >> o) & 1u);
+    const double x = (double)psi[iu + id * dup];
+    if (mean) {
+      const T t = (T)((f - mu) * x);
+      phi[idx] = t;
+      acc += (double)t * (double)t;
+    } else {
+      acc += f * x * x;
+    }
+  }
+  const double s = block_sum(acc, red);
+  if (threadIdx.x == 0) partial[blockIdx.x] = s;
+}
+
 __global__ void k_cf(const double* __restrict__ ap, const double* __restrict__ bp, int np,
                      double wp, const double* __restrict__ ah, const double* __restrict__ bh,
                      int nh, double wh, double e0, double beta, int lmats,
@@ -104,6 +143,22 @@ edx_status k_apply_op(const edx_sector* src, const edx_sector* dst, int vtype, c
     hipLaunchKernelGGL(k_apply<float>, dim3(grid), dim3(256), 0, st, (const float*)psi,
                        (float*)phi, dst->dup, dst->ld, n, src->dup, tmap, srank, orb, spin, create,
                        src->nup);
+  EDX_HIP(hipGetLastError());
+  return EDX_OK;
+}
+
+edx_status k_diag_apply(const edx_sector* s, int vtype, const void* psi, void* phi,
+                        const DiagCoef& c, const double* mean, double* partial, int nblocks,
+                        hipStream_t st) {
+  const int64_t n = s->vlen;
+  if (vtype == EDX_F64)
+    hipLaunchKernelGGL(k_diag_op<double>, dim3(nblocks), dim3(256), 0, st, (const double*)psi,
+                       (double*)phi, s->dup, s->ld, n, s->up.pat, s->dw.pat, s->model.norb, c,
+                       mean, partial);
+  else
+    hipLaunchKernelGGL(k_diag_op<float>, dim3(nblocks), dim3(256), 0, st, (const float*)psi,
+                       (float*)phi, s->dup, s->ld, n, s->up.pat, s->dw.pat, s->model.norb, c,
+                       mean, partial);
   EDX_HIP(hipGetLastError());
   return EDX_OK;
 }

@@ -146,6 +146,70 @@ void tridiag_vector(const double* a, const double* b, int m, double lam, double*
   }
 }
 
+// Eigenvalues and squared first components of the symmetric tridiagonal
+// matrix (diagonal a[0..m), off-diagonal b[0..m-1)): the poles and weights of
+// a Krylov spectral function.  Implicit symmetric QR with the Wilkinson shift
+// (Golub and Van Loan, symmetric QR step): each sweep chases the bulge of one
+// Givens rotation down the active block; only the first row q of the
+// accumulated rotations Q (T = Q diag(theta) Q^T) is kept, so a sweep costs
+// O(m) and the whole spectrum O(m^2).  Returns false if a block fails to
+// converge in 60 sweeps per eigenvalue.
+bool tridiag_spectrum(const double* a, const double* b, int m, double* theta, double* w) {
+  if (m <= 0) return true;
+  std::vector<double> d(a, a + m), e(m, 0.0), q(m, 0.0);
+  for (int i = 0; i + 1 < m; ++i) e[i] = b[i];
+  q[0] = 1.0;
+  const double eps = std::numeric_limits<double>::epsilon();
+  int h = m - 1;
+  long budget = 60L * m + 60;
+  while (h > 0) {
+    // deflate converged off-diagonals at the bottom
+    if (std::fabs(e[h - 1]) <= eps * (std::fabs(d[h - 1]) + std::fabs(d[h])) ||
+        e[h - 1] == 0.0) {
+      e[h - 1] = 0.0;
+      --h;
+      continue;
+    }
+    // top of the unreduced block ending at h
+    int l = h - 1;
+    while (l > 0 && !(std::fabs(e[l - 1]) <= eps * (std::fabs(d[l - 1]) + std::fabs(d[l])))) --l;
+    if (l > 0) e[l - 1] = 0.0;
+    if (--budget < 0) return false;
+    // Wilkinson shift from the trailing 2x2 of the block
+    const double dl = 0.5 * (d[h - 1] - d[h]);
+    const double eh = e[h - 1];
+    const double den = dl + (dl >= 0.0 ? 1.0 : -1.0) * std::hypot(dl, eh);
+    const double mu = den != 0.0 ? d[h] - eh * eh / den : d[h];
+    double x = d[l] - mu, y = e[l];
+    for (int k = l; k < h; ++k) {
+      const double r = std::hypot(x, y);
+      const double c = r != 0.0 ? x / r : 1.0;
+      const double sn = r != 0.0 ? y / r : 0.0;
+      if (k > l) e[k - 1] = r;                      // the bulge at (k-1, k+1) is gone
+      const double ak = d[k], bk = e[k], ck = d[k + 1];
+      d[k] = c * c * ak + 2.0 * c * sn * bk + sn * sn * ck;
+      d[k + 1] = sn * sn * ak - 2.0 * c * sn * bk + c * c * ck;
+      e[k] = c * sn * (ck - ak) + (c * c - sn * sn) * bk;
+      if (k + 1 < h) {                               // new bulge at (k, k+2)
+        y = sn * e[k + 1];
+        e[k + 1] = c * e[k + 1];
+        x = e[k];
+      }
+      const double qk = q[k], qk1 = q[k + 1];
+      q[k] = c * qk + sn * qk1;
+      q[k + 1] = -sn * qk + c * qk1;
+    }
+  }
+  std::vector<int> ord(m);
+  for (int i = 0; i < m; ++i) ord[i] = i;
+  std::sort(ord.begin(), ord.end(), [&](int x, int y) { return d[x] < d[y]; });
+  for (int i = 0; i < m; ++i) {
+    theta[i] = d[ord[i]];
+    w[i] = q[ord[i]] * q[ord[i]];
+  }
+  return true;
+}
+
 // ---------------------------------------------------------------- workspace
 namespace {
 
@@ -799,6 +863,96 @@ edx_status green_cf_impl(const edx_sector* gs, const void* psi0, double e0, int 
         if (bo) bo[k] = k + 1 < nlen[br] ? hb[br][k + 1] : 0.0;
       }
     }
+  }
+  return EDX_OK;
+}
+
+// ---------------------------------------------------------------- susceptibility
+size_t chi_workspace_bytes(const edx_sector* s, int vtype, int ngf) {
+  return lanczos_ws_layout(s->vlen, vtype, ngf, 0, hv_partial_blocks(s, vtype), false, nullptr,
+                           nullptr) + 512;
+}
+
+edx_status chi_impl(const edx_sector* s, const void* psi0, double e0, const DiagCoef& c,
+                    const edx_gf_opts* o, void* ws, size_t ws_bytes, double* chi_host,
+                    edx_chi_report* rep, hipStream_t st) {
+  const int vtype = o->vtype;
+  const int ngf = o->ngf;
+  if (o->lmats < 1 || o->lmats > kMaxLmats || ngf < 1 || !(o->beta > 0.0)) {
+    set_error("chi: need 1 <= lmats <= 65536, ngf >= 1, beta > 0");
+    return EDX_E_INVALID;
+  }
+  LanczosWs L;
+  char* base = reinterpret_cast<char*>(align_up(reinterpret_cast<uintptr_t>(ws)));
+  const size_t need = lanczos_ws_layout(s->vlen, vtype, ngf, 0, hv_partial_blocks(s, vtype),
+                                        false, base, &L);
+  if (need + (size_t)(base - (char*)ws) > ws_bytes) {
+    set_error("chi: workspace too small (need " + std::to_string(need + 512) + " bytes)");
+    return EDX_E_NOMEM;
+  }
+  const int64_t n = s->vlen;
+  const int nb = elem_blocks(n);
+  // phi_0 = (O - <O>) psi0 in the padded layout
+  EDX_TRY(k_diag_apply(s, vtype, psi0, L.vec, c, nullptr, L.partial, nb, st));
+  EDX_TRY(k_reduce(L.partial, nb, 1, L.coef, st));
+  EDX_TRY(k_diag_apply(s, vtype, psi0, L.vec, c, L.coef, L.partial, nb, st));
+  EDX_TRY(k_beta_finish(L.partial, nb, L.beta, L.scale, st));
+  double h[2] = {0.0, 0.0};
+  EDX_HIP(hipMemcpyAsync(h, L.beta, sizeof(double), hipMemcpyDeviceToHost, st));
+  EDX_HIP(hipMemcpyAsync(h + 1, L.coef, sizeof(double), hipMemcpyDeviceToHost, st));
+  EDX_HIP(hipStreamSynchronize(st));
+  const double wgt = h[0] * h[0];
+  std::fill(chi_host, chi_host + 2 * (size_t)o->lmats, 0.0);
+  int len = 0, dropped = 0;
+  if (h[0] > 0.0) {
+    EDX_HIP(hipMemsetAsync(L.beta, 0, sizeof(double), st));
+    for (int j = 0; j < ngf; ++j)
+      EDX_TRY(lanczos_step(s, vtype, L, j, 0, L.alpha, L.beta, L.scale, nullptr, nullptr, st));
+    std::vector<double> ha(ngf + 1), hb(ngf + 1);
+    EDX_HIP(hipMemcpyAsync(ha.data(), L.alpha, sizeof(double) * ngf, hipMemcpyDeviceToHost, st));
+    EDX_HIP(hipMemcpyAsync(hb.data(), L.beta, sizeof(double) * (ngf + 1), hipMemcpyDeviceToHost,
+                           st));
+    EDX_HIP(hipStreamSynchronize(st));
+    // truncate at the first breakdown (as for the Green's function)
+    double tn = 0.0;
+    len = ngf;
+    for (int j = 0; j < ngf; ++j) {
+      tn = std::max(tn, std::fabs(ha[j]) + hb[j] + hb[j + 1]);
+      if (j + 1 < ngf && !(hb[j + 1] > 1e-12 * tn)) {
+        len = j + 1;
+        break;
+      }
+    }
+    std::vector<double> th(len), wt(len);
+    if (!tridiag_spectrum(ha.data(), hb.data() + 1, len, th.data(), wt.data())) {
+      set_error("chi: tridiagonal QR did not converge");
+      return EDX_E_NOCONV;
+    }
+    double thr = 1e-9 * std::max(1.0, std::fabs(e0));
+    if (vtype == EDX_F32) thr = std::max(thr, 2.0 * 1.1920929e-7 * tn);
+    std::vector<double> dd, ww;
+    for (int k = 0; k < len; ++k) {
+      const double d = th[k] - e0;
+      if (std::fabs(d) <= thr) {
+        ++dropped;
+        continue;
+      }
+      dd.push_back(d);
+      ww.push_back(wgt * wt[k]);
+    }
+    // 1/(i nu - d) - 1/(i nu + d) = -2 d / (nu^2 + d^2): real
+    for (int q = 0; q < o->lmats; ++q) {
+      const double nu = 2.0 * q * M_PI / o->beta;
+      double acc = 0.0;
+      for (size_t k = 0; k < dd.size(); ++k) acc -= 2.0 * ww[k] * dd[k] / (nu * nu + dd[k] * dd[k]);
+      chi_host[2 * q] = acc;
+    }
+  }
+  if (rep) {
+    rep->w = wgt;
+    rep->mean = h[1];
+    rep->n = len;
+    rep->dropped = dropped;
   }
   return EDX_OK;
 }

@@ -70,6 +70,11 @@ class EspaceOpts(ctypes.Structure):
                 ("nstates_step", ctypes.c_int32), ("verify", ctypes.c_int32)]
 
 
+class ChiReport(ctypes.Structure):
+    _fields_ = [("w", ctypes.c_double), ("mean", ctypes.c_double),
+                ("n", ctypes.c_int32), ("dropped", ctypes.c_int32)]
+
+
 class BatchResult(ctypes.Structure):
     _fields_ = [("e0", ctypes.c_double), ("beta_last", ctypes.c_double),
                 ("iters", ctypes.c_int32), ("status", ctypes.c_int32),
@@ -139,6 +144,10 @@ _SIGS = {
     "edx_espace_sector": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]),
     "edx_espace_green_workspace_bytes": (ctypes.c_size_t, [_P, ctypes.c_int32]),
     "edx_espace_green": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(GfOpts), _P, ctypes.c_size_t, _P, _P]),
+    "edx_tridiag_spectrum": (ctypes.c_int, [_P, _P, ctypes.c_int32, _P, _P]),
+    "edx_chi": (ctypes.c_int, [_P, _P, ctypes.c_double, _P, _P, ctypes.POINTER(GfOpts), _P, ctypes.c_size_t, _P, ctypes.POINTER(ChiReport), _P]),
+    "edx_espace_chi_workspace_bytes": (ctypes.c_size_t, [_P, ctypes.c_int32]),
+    "edx_espace_chi": (ctypes.c_int, [_P, _P, _P, ctypes.POINTER(GfOpts), _P, ctypes.c_size_t, _P, _P]),
     "edx_green_cf": (ctypes.c_int, [_P, _P, ctypes.c_double, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(GfOpts), _P, ctypes.c_size_t, _P, ctypes.POINTER(GfReport), _P]),
     "edx_batch_workspace_bytes": (ctypes.c_size_t, [_P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int64]),
     "edx_batch_ground_state": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.POINTER(LanczosOpts), ctypes.POINTER(BatchTiles), _P, ctypes.c_size_t, ctypes.POINTER(BatchResult), ctypes.POINTER(ctypes.c_double), _P]),
@@ -498,6 +507,60 @@ class Espace:
         _check(lib.edx_espace_green(self.handle, int(orb), int(spin), ctypes.byref(o), _P(ws.data_ptr()),
                                     ws.numel(), g.ctypes.data_as(_P), _stream_ptr(stream)))
         return g[0::2] + 1j * g[1::2]
+
+    def chi(self, cu, cd, ngf=200, lmats=256, ws=None, stream=None):
+        """Thermal density-type susceptibility on the bosonic grid of the espace's beta."""
+        norb = int(self.sectors[0].model["norb"])
+        cu, cd = _coefs(norb, cu, cd)
+        o = GfOpts(int(ngf), int(lmats), self.vtype, 0, float(self.opts.beta))
+        need = int(lib.edx_espace_chi_workspace_bytes(self.handle, int(ngf)))
+        if need == 0:
+            raise ValueError("no kept states (run diag first)")
+        if ws is None or ws.numel() < need:
+            ws = alloc_workspace(need)
+        g = np.zeros(2 * lmats, np.float64)
+        _check(lib.edx_espace_chi(self.handle, cu.ctypes.data_as(_P), cd.ctypes.data_as(_P), ctypes.byref(o),
+                                  _P(ws.data_ptr()), ws.numel(), g.ctypes.data_as(_P), _stream_ptr(stream)))
+        return g[0::2] + 1j * g[1::2]
+
+
+def tridiag_spectrum(alpha, beta):
+    """Eigenvalues and squared first components of the tridiagonal matrix."""
+    a = np.ascontiguousarray(alpha, np.float64)
+    b = np.ascontiguousarray(beta, np.float64)
+    m = a.size
+    if b.size != max(m - 1, 0):
+        raise ValueError("beta needs len(alpha) - 1 entries")
+    th = np.zeros(m)
+    w = np.zeros(m)
+    _check(lib.edx_tridiag_spectrum(a.ctypes.data_as(_P), b.ctypes.data_as(_P) if m > 1 else None, m,
+                                    th.ctypes.data_as(_P), w.ctypes.data_as(_P)))
+    return th, w
+
+
+def _coefs(norb, cu, cd):
+    cu = np.ascontiguousarray(cu, np.float64)
+    cd = np.ascontiguousarray(cd, np.float64)
+    if cu.size != norb or cd.size != norb:
+        raise ValueError(f"cu and cd need {norb} coefficients")
+    return cu, cd
+
+
+def chi(sector, psi0, e0, cu, cd, ngf=200, beta=200.0, lmats=1024, ws=None, stream=None):
+    """Density-type susceptibility C(i nu_n) (complex numpy; real by symmetry)
+    and the report dict."""
+    vtype = _vtype_of(psi0)
+    cu, cd = _coefs(int(sector.model["norb"]), cu, cd)
+    o = GfOpts(int(ngf), int(lmats), vtype, 0, float(beta))
+    need = workspace_bytes(sector, 3, vtype, ngf)
+    if ws is None:
+        ws = alloc_workspace(need)
+    g = np.zeros(2 * lmats, np.float64)
+    rep = ChiReport()
+    _check(lib.edx_chi(sector.handle, _P(psi0.data_ptr()), float(e0), cu.ctypes.data_as(_P),
+                       cd.ctypes.data_as(_P), ctypes.byref(o), _P(ws.data_ptr()), ws.numel(),
+                       g.ctypes.data_as(_P), ctypes.byref(rep), _stream_ptr(stream)))
+    return g[0::2] + 1j * g[1::2], {f: getattr(rep, f) for f, _ in ChiReport._fields_}
 
 
 def _handles(sectors):

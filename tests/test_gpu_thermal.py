@@ -225,3 +225,66 @@ def test_espace_rejects(edx):
     E = edx.Espace(2, beta=10.0)
     with pytest.raises(ValueError):
         E.diag([S], niter=50, rtol=1e-8)        # wrong sector count
+
+
+# ---- density-type susceptibilities
+
+CHI_CASES = [
+    ("ns8_spin", inputs.workload("ns8")[0], (4, 4), [0.5], [-0.5]),
+    ("ns8_charge_53", inputs.workload("ns8")[0], (5, 3), [1.0], [1.0]),
+    ("o2_spin_orb1", inputs.make_model(2, 3, 3.0, Jh=0.5, seed=91, symmetric=False), (4, 3),
+     [0.0, 0.5], [0.0, -0.5]),
+    ("o2_mixed", inputs.make_model(2, 3, 3.0, Jh=0.5, seed=92, symmetric=False), (3, 4),
+     [0.5, 0.3], [-0.5, 0.2]),
+    ("o2_kanamori_spin", inputs.make_model(2, 3, 3.0, Jh=0.5, seed=93, symmetric=False, Jx=0.5,
+                                           Jp=0.5), (4, 4), [0.5, 0.5], [-0.5, -0.5]),
+    ("orbital_charge", inputs.make_model(2, 3, 2.5, Jh=0.4, seed=94, symmetric=False),
+     ((2, 2), (1, 3)), [1.0, 0.0], [1.0, 0.0]),
+]
+
+
+@pytest.mark.parametrize("name,m,sec,cu,cd", CHI_CASES, ids=[c[0] for c in CHI_CASES])
+def test_chi_fp64(edx, name, m, sec, cu, cd):
+    from oracle import chi as ochi
+    S = _sector(edx, m, sec)
+    e0, psi, rep, _ = edx.lanczos_ground_state(S, niter=400, tol=1e-14, rtol=1e-11, seed=6,
+                                               allow=(edx.EDX_E_DEGENERATE,))
+    H = fock.explicit_hamiltonian(m, *sec).toarray()
+    w = np.linalg.eigvalsh(H)
+    assert w[1] - w[0] > 1e-6, "pick a case with a unique ground state"
+    beta, lm = 50.0, 64
+    z = 1j * ochi.bosonic(beta, lm)
+    ref, _ = ochi.chi_exact(m, *sec, cu, cd, z)
+    got, r = edx.chi(S, psi, e0, cu, cd, ngf=250, beta=beta, lmats=lm)
+    assert np.abs(got - ref).max() <= 1e-8 * np.abs(ref).max(), r
+    assert np.all(got.imag == 0.0)
+
+
+def test_chi_fp32(edx):
+    from oracle import chi as ochi
+    m, [sec] = inputs.workload("ns8")
+    S = edx.build_sector(m, *sec)
+    e0, psi, rep, _ = edx.lanczos_ground_state(S, vtype="f32", niter=400, tol=1e-9, seed=6,
+                                               allow=(edx.EDX_E_NOCONV,))
+    z = 1j * ochi.bosonic(50.0, 32)
+    ref, _ = ochi.chi_exact(m, *sec, [0.5], [-0.5], z)
+    got, r = edx.chi(S, psi, e0, [0.5], [-0.5], ngf=200, beta=50.0, lmats=32)
+    assert np.abs(got - ref).max() <= 1e-4 * np.abs(ref).max()
+
+
+def test_espace_thermal_chi_whole_fock_space(edx):
+    """Thermal spin and charge susceptibilities over every state of the Fock
+    space (Ns = 4) against the bosonic Lehmann double sum."""
+    from oracle import chi as ochi
+    m = inputs.make_model(1, 3, 2.0, seed=95, symmetric=False)
+    secs = _all_sectors(m)
+    beta = 4.0
+    E = edx.Espace(len(secs), beta=beta, cutoff=0.0, nstates_sector=64, nstates_total=100000)
+    S = [edx.build_sector(m, *s) for s in secs]
+    E.diag(S, niter=200, tol=0.0, rtol=1e-11, seed=1)
+    assert E.info()[0] == 4 ** fock.ns_of(m)
+    z = 1j * ochi.bosonic(beta, 24)
+    for cu, cd in (([0.5], [-0.5]), ([1.0], [1.0])):
+        ref = ochi.chi_double_sum(m, secs, cu, cd, z, beta)
+        got = E.chi(cu, cd, ngf=60, lmats=24)
+        assert np.abs(got - ref).max() <= 1e-8 * np.abs(ref).max(), cu
