@@ -74,6 +74,16 @@ typedef struct {
   double xmu;              /* chemical potential on the impurity levels  */
   double Jx;               /* spin exchange J_X                          */
   double Jp;               /* pair hopping J_P                           */
+  /* Holstein phonon (Sec. "Electron-phonon coupling"):
+   *   H += w0 b+b + sum_{a sigma} g_a n_{a sigma} (b + b+),
+   * one local mode truncated at nph quanta (0 = no phonons, at most 63).
+   * A sector is then the electronic sector times D_ph = nph + 1 phonon
+   * states, index i = i_up + D_up (i_dw + D_dw p) (eq. HephBuild), and every
+   * vector of it is D_ph electronic vectors one after another. */
+  int32_t nph;
+  int32_t pad_;
+  double w0;               /* phonon frequency                           */
+  const double* g;         /* [norb] couplings g_a (NULL when nph = 0)   */
 } edx_model;
 
 typedef struct edx_sector edx_sector;

@@ -57,6 +57,17 @@ static edx_status check_model(const edx_model* m, Model* out) {
   if (!std::isfinite(m->U) || !std::isfinite(m->Ust) || !std::isfinite(m->Jh) ||
       !std::isfinite(m->xmu) || !std::isfinite(m->Jx) || !std::isfinite(m->Jp))
     return invalid("non-finite interaction parameter");
+  if (m->nph < 0 || m->nph > kMaxPh) return invalid("nph must be in [0, 63]");
+  out->nph = m->nph;
+  if (m->nph > 0) {
+    if (!m->g) return invalid("g is NULL with nph > 0");
+    if (!std::isfinite(m->w0)) return invalid("non-finite w0");
+    out->w0 = m->w0;
+    for (int a = 0; a < m->norb; ++a) {
+      if (!std::isfinite(m->g[a])) return invalid("non-finite g");
+      out->g[a] = m->g[a];
+    }
+  }
   return EDX_OK;
 }
 
@@ -179,7 +190,7 @@ edx_status edx_hv(const edx_sector* s, edx_vtype vtype, const void* v, void* w, 
   if (!v || !w) return invalid("v or w is NULL");
   if (ld == 0) ld = s->dup;
   if (ld < s->dup) return invalid("ld must be 0 (dense) or >= D_up");
-  const size_t bytes = (size_t)(ld * s->ddw) * vbytes(vtype);
+  const size_t bytes = (size_t)(ld * s->ddw * s->dph) * vbytes(vtype);
   const char* pv = static_cast<const char*>(v);
   const char* pw = static_cast<const char*>(w);
   if (pv < pw + bytes && pw < pv + bytes) return invalid("v and w overlap");

@@ -459,9 +459,10 @@ int device_cus() {
 int64_t batch_wide_default() { return 2000000; }
 
 // Jobs of the whole-GPU path: D >= wide_min, and every sector with spin
-// exchange or pair hopping (the lanes implement the spin-separable H only).
+// exchange, pair hopping or phonons (the lanes implement the spin-separable
+// electronic H only).
 static bool is_wide(const edx_sector* s, int64_t wide_min) {
-  return s->nd || (wide_min > 0 && s->dim >= wide_min);
+  return s->nd || s->dph > 1 || (wide_min > 0 && s->dim >= wide_min);
 }
 
 edx_status batch_run(const edx_sector* const* secs, int n, const edx_lanczos_opts* o,

@@ -15,6 +15,7 @@ namespace edx {
 
 constexpr int kMaxNs = 24;
 constexpr int kMaxNorb = 3;
+constexpr int kMaxPh = 63;                   // phonon cutoff N_ph (D_ph <= 64)
 constexpr uint32_t kColMask = 0x00FFFFFFu;   // hop entry: bits 0..23 column
 constexpr int kAmpShift = 24;                // bits 24..30 pair, bit 31 sign
 constexpr uint32_t kPadPair = 0x7Fu;         // pair index of padding entries
@@ -56,6 +57,9 @@ struct Model {
   std::vector<double> eps_imp, eps_bath, vhyb;
   double U = 0, Ust = 0, Jh = 0, xmu = 0;
   double Jx = 0, Jp = 0;   // spin exchange, pair hopping (eq. Ham1)
+  int nph = 0;             // phonon cutoff N_ph (0: no phonons)
+  double w0 = 0;           // phonon frequency
+  double g[kMaxNorb] = {0, 0, 0};   // electron-phonon couplings g_a
 };
 
 // Tables of one spin species of a sector, device resident.
@@ -95,7 +99,8 @@ struct edx_sector {
   int64_t dup = 0, ddw = 0, dim = 0;
   bool nd = false;           // spin exchange / pair hopping present (norb >= 2)
   int64_t ld = 0;            // column stride of the library's Krylov vectors
-  int64_t vlen = 0;          // ld * ddw elements per Krylov vector
+  int64_t vlen = 0;          // ld * ddw * dph elements per Krylov vector
+  int dph = 1;               // phonon states N_ph + 1 (1: no phonons); slowest index
   int device = 0;
   edx::SpinTables up, dw;
   // Signed amplitudes indexed by (hop entry >> 24); identical for both spins.

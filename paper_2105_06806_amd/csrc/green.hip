@@ -23,8 +23,8 @@ namespace {
 
 template <typename T>
 __global__ __launch_bounds__(256) void k_apply(const T* __restrict__ psi, T* __restrict__ phi,
-                                               int64_t tdup, int64_t tld, int64_t tlen,
-                                               int64_t sdup,
+                                               int64_t tdup, int64_t tld, int64_t tddw,
+                                               int64_t tlen, int64_t sdup, int64_t sddw,
                                                const uint32_t* __restrict__ tmap,
                                                const int32_t* __restrict__ srank, int orb,
                                                int spin, int create, int nup) {
@@ -32,12 +32,14 @@ __global__ __launch_bounds__(256) void k_apply(const T* __restrict__ psi, T* __r
   const uint32_t below = bit - 1u;
   for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < tlen;
        idx += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t id = idx / tld;
-    const int64_t iu = idx - id * tld;
+    const int64_t col = idx / tld;          // column over all phonon slices
+    const int64_t iu = idx - col * tld;
     if (iu >= tdup) {
       phi[idx] = T(0);
       continue;
     }
+    const int64_t p = col / tddw;           // phonon index (0 without phonons)
+    const int64_t id = col - p * tddw;
     const uint32_t t = tmap[spin == 0 ? iu : id];
     const bool has = (t & bit) != 0u;
     T val = T(0);
@@ -46,7 +48,7 @@ __global__ __launch_bounds__(256) void k_apply(const T* __restrict__ psi, T* __r
       const int64_t r = srank[s];
       int par = __popc(s & below) & 1;
       if (spin == 1) par ^= (nup & 1);
-      const int64_t src = spin == 0 ? r + id * sdup : iu + r * sdup;
+      const int64_t src = spin == 0 ? r + (id + p * sddw) * sdup : iu + (r + p * sddw) * sdup;
       const T x = psi[src];
       val = par ? -x : x;
     }
@@ -61,8 +63,8 @@ __global__ __launch_bounds__(256) void k_apply(const T* __restrict__ psi, T* __r
 // sums are |phi|^2.
 template <typename T>
 __global__ __launch_bounds__(256) void k_diag_op(const T* __restrict__ psi, T* __restrict__ phi,
-                                                 int64_t dup, int64_t ld, int64_t len,
-                                                 const uint8_t* __restrict__ pup,
+                                                 int64_t dup, int64_t ld, int64_t ddw,
+                                                 int64_t len, const uint8_t* __restrict__ pup,
                                                  const uint8_t* __restrict__ pdw, int norb,
                                                  DiagCoef c, const double* __restrict__ mean,
                                                  double* __restrict__ partial) {
@@ -77,7 +79,7 @@ __global__ __launch_bounds__(256) void k_diag_op(const T* __restrict__ psi, T* _
       if (mean) phi[idx] = T(0);
       continue;
     }
-    const uint32_t a = pup[iu], b = pdw[id];
+    const uint32_t a = pup[iu], b = pdw[id % ddw];   // phonon slices repeat the columns
     double f = 0.0;
     for (int o = 0; o < norb; ++o) f += c.up[o] * ((a >> o) & 1u) + c.dw[o] * ((b >> o) & 1u);
     const double x = (double)psi[iu + id * dup];
@@ -137,12 +139,12 @@ edx_status k_apply_op(const edx_sector* src, const edx_sector* dst, int vtype, c
   const int32_t* srank = spin == 0 ? src->up.rank : src->dw.rank;
   if (vtype == EDX_F64)
     hipLaunchKernelGGL(k_apply<double>, dim3(grid), dim3(256), 0, st, (const double*)psi,
-                       (double*)phi, dst->dup, dst->ld, n, src->dup, tmap, srank, orb, spin, create,
-                       src->nup);
+                       (double*)phi, dst->dup, dst->ld, dst->ddw, n, src->dup, src->ddw, tmap,
+                       srank, orb, spin, create, src->nup);
   else
     hipLaunchKernelGGL(k_apply<float>, dim3(grid), dim3(256), 0, st, (const float*)psi,
-                       (float*)phi, dst->dup, dst->ld, n, src->dup, tmap, srank, orb, spin, create,
-                       src->nup);
+                       (float*)phi, dst->dup, dst->ld, dst->ddw, n, src->dup, src->ddw, tmap,
+                       srank, orb, spin, create, src->nup);
   EDX_HIP(hipGetLastError());
   return EDX_OK;
 }
@@ -153,11 +155,11 @@ edx_status k_diag_apply(const edx_sector* s, int vtype, const void* psi, void* p
   const int64_t n = s->vlen;
   if (vtype == EDX_F64)
     hipLaunchKernelGGL(k_diag_op<double>, dim3(nblocks), dim3(256), 0, st, (const double*)psi,
-                       (double*)phi, s->dup, s->ld, n, s->up.pat, s->dw.pat, s->model.norb, c,
+                       (double*)phi, s->dup, s->ld, s->ddw, n, s->up.pat, s->dw.pat, s->model.norb, c,
                        mean, partial);
   else
     hipLaunchKernelGGL(k_diag_op<float>, dim3(nblocks), dim3(256), 0, st, (const float*)psi,
-                       (float*)phi, s->dup, s->ld, n, s->up.pat, s->dw.pat, s->model.norb, c,
+                       (float*)phi, s->dup, s->ld, s->ddw, n, s->up.pat, s->dw.pat, s->model.norb, c,
                        mean, partial);
   EDX_HIP(hipGetLastError());
   return EDX_OK;

@@ -726,9 +726,16 @@ HvPlan hv_plan(const edx_sector* s, int vtype) {
 
 // partial sums of <v, Hv>: the last spin-separable pass's blocks, then the
 // H_nd pass's
+// partial sums of one electronic pass (one phonon slice)
+static int hv_el_partial_blocks(const edx_sector* s, const HvPlan& p) {
+  return p.col_blocks + (p.mode == 2 ? 0 : nd_blocks(s));
+}
+
+constexpr int kPhBlocks = 1024;   // workgroups of the phonon pass
+
 int hv_partial_blocks(const edx_sector* s, int vtype) {
   const HvPlan p = hv_plan(s, vtype);
-  return p.col_blocks + (p.mode == 2 ? 0 : nd_blocks(s));
+  return s->dph * hv_el_partial_blocks(s, p) + (s->dph > 1 ? kPhBlocks : 0);
 }
 
 namespace {
@@ -875,9 +882,54 @@ edx_status launch_t(const edx_sector* s, const T* v, T* w, int64_t ld, const dou
 
 }  // namespace
 
-edx_status hv_launch(const edx_sector* s, int vtype, const void* v, void* w, int64_t ld,
-                     const double* vscale, double* partial, hipStream_t st,
-                     const HvPlan* plan) {
+namespace {
+
+// Holstein terms (Sec. "Electron-phonon coupling", eq. HephBuild), added to the
+// electronic product of every phonon slice p:
+//   w_p += vs (w0 p v_p + G(i) (sqrt(p) v_{p-1} + sqrt(p+1) v_{p+1})),
+//   G(i) = sum_a g_a (n_{a up} + n_{a dw}) from the two impurity patterns.
+// Streams v three times (slices p-1, p, p+1) and w once each way; partial sums
+// of <v, added terms> complete the Lanczos alpha of the electronic passes.
+template <typename T>
+__global__ __launch_bounds__(256) void k_hv_ph(const T* __restrict__ v, T* __restrict__ w,
+                                               int64_t dup, int64_t ld, int64_t ddw, int dph,
+                                               const uint8_t* __restrict__ pup,
+                                               const uint8_t* __restrict__ pdw, int norb,
+                                               double g0, double g1, double g2, double w0,
+                                               const double* __restrict__ vscale,
+                                               double* __restrict__ partial) {
+  __shared__ double red[4];
+  const double vs = vscale ? *vscale : 1.0;
+  const int64_t slice = ld * ddw;
+  const int64_t total = slice * dph;
+  double acc = 0.0;
+  for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < total;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t p = idx / slice;
+    const int64_t r = idx - p * slice;
+    const int64_t id = r / ld;
+    const int64_t iu = r - id * ld;
+    if (iu >= dup) continue;
+    const uint32_t pu = pup[iu], pd = pdw[id];
+    double gv = g0 * (double)((pu & 1u) + (pd & 1u));
+    if (norb > 1) gv += g1 * (double)(((pu >> 1) & 1u) + ((pd >> 1) & 1u));
+    if (norb > 2) gv += g2 * (double)(((pu >> 2) & 1u) + ((pd >> 2) & 1u));
+    const double x = (double)v[idx];
+    double res = w0 * (double)p * x;
+    if (p > 0) res += gv * sqrt((double)p) * (double)v[idx - slice];
+    if (p + 1 < dph) res += gv * sqrt((double)(p + 1)) * (double)v[idx + slice];
+    res *= vs;
+    w[idx] = (T)((double)w[idx] + res);
+    acc += x * vs * res;
+  }
+  const double sum = block_sum(acc, red);
+  if (partial && threadIdx.x == 0) partial[blockIdx.x] = sum;
+}
+
+// the electronic product on one slice (column stride ld, D_dw columns)
+edx_status hv_launch_el(const edx_sector* s, int vtype, const void* v, void* w, int64_t ld,
+                        const double* vscale, double* partial, hipStream_t st,
+                        const HvPlan* plan) {
   HvPlan p = plan ? *plan : hv_plan(s, vtype);
   if (ld < s->dup) {
     set_error("hv: leading dimension below D_up");
@@ -910,6 +962,39 @@ edx_status hv_launch(const edx_sector* s, int vtype, const void* v, void* w, int
     hipLaunchKernelGGL(k_hv_nd<float>, dim3(nb), dim3(256), patlds, st, na,
                        static_cast<const float*>(v), static_cast<float*>(w), vscale, pnd);
   }
+  EDX_HIP(hipGetLastError());
+  return EDX_OK;
+}
+
+}  // namespace
+
+edx_status hv_launch(const edx_sector* s, int vtype, const void* v, void* w, int64_t ld,
+                     const double* vscale, double* partial, hipStream_t st,
+                     const HvPlan* plan) {
+  if (s->dph <= 1) return hv_launch_el(s, vtype, v, w, ld, vscale, partial, st, plan);
+  if (ld < s->dup) {
+    set_error("hv: leading dimension below D_up");
+    return EDX_E_INVALID;
+  }
+  const HvPlan p = plan ? *plan : hv_plan(s, vtype);
+  const int eb = hv_el_partial_blocks(s, p);
+  const size_t sb = (size_t)(ld * s->ddw) * vbytes(vtype);
+  for (int q = 0; q < s->dph; ++q)
+    EDX_TRY(hv_launch_el(s, vtype, static_cast<const char*>(v) + q * sb,
+                         static_cast<char*>(w) + q * sb, ld, vscale,
+                         partial ? partial + (size_t)q * eb : nullptr, st, &p));
+  double* pph = partial ? partial + (size_t)s->dph * eb : nullptr;
+  const Model& m = s->model;
+  if (vtype == EDX_F64)
+    hipLaunchKernelGGL(k_hv_ph<double>, dim3(kPhBlocks), dim3(256), 0, st,
+                       static_cast<const double*>(v), static_cast<double*>(w), s->dup, ld,
+                       s->ddw, s->dph, s->up.pat, s->dw.pat, m.norb, m.g[0], m.g[1], m.g[2],
+                       m.w0, vscale, pph);
+  else
+    hipLaunchKernelGGL(k_hv_ph<float>, dim3(kPhBlocks), dim3(256), 0, st,
+                       static_cast<const float*>(v), static_cast<float*>(w), s->dup, ld,
+                       s->ddw, s->dph, s->up.pat, s->dw.pat, m.norb, m.g[0], m.g[1], m.g[2],
+                       m.w0, vscale, pph);
   EDX_HIP(hipGetLastError());
   return EDX_OK;
 }

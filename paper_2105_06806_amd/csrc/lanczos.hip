@@ -357,7 +357,7 @@ edx_status lanczos_ground_state_impl(const edx_sector* s, const edx_lanczos_opts
   }
   const int64_t n = s->vlen;
   // start vector u_0 and scale_0 = 1/|u_0|
-  EDX_TRY(k_start_vector(vtype, L.vec, s->dup, s->ld, s->ddw, o->seed, L.partial, st));
+  EDX_TRY(k_start_vector(vtype, L.vec, s->dup, s->ld, s->ddw * s->dph, o->seed, L.partial, st));
   EDX_TRY(k_beta_finish(L.partial, elem_blocks(n), L.beta, L.scale, st));
   EDX_HIP(hipMemsetAsync(L.beta, 0, sizeof(double), st));   // beta_0 couples nothing
 
@@ -432,7 +432,7 @@ edx_status lanczos_ground_state_impl(const edx_sector* s, const edx_lanczos_opts
       // replay: identical start vector and recurrence, psi += y_j v_j
       EDX_HIP(hipMemcpyAsync(L.y, y.data(), sizeof(double) * m, hipMemcpyHostToDevice, st));
       EDX_HIP(hipMemsetAsync(acc, 0, (size_t)n * vbytes(vtype), st));
-      EDX_TRY(k_start_vector(vtype, L.vec, s->dup, s->ld, s->ddw, o->seed, L.partial, st));
+      EDX_TRY(k_start_vector(vtype, L.vec, s->dup, s->ld, s->ddw * s->dph, o->seed, L.partial, st));
       EDX_TRY(k_beta_finish(L.partial, elem_blocks(n), L.beta2, L.scale2, st));
       EDX_HIP(hipMemsetAsync(L.beta2, 0, sizeof(double), st));
       for (int j = 0; j < m; ++j)
@@ -443,7 +443,7 @@ edx_status lanczos_ground_state_impl(const edx_sector* s, const edx_lanczos_opts
     EDX_TRY(k_norm2(vtype, acc, n, L.partial, st));
     EDX_TRY(k_beta_finish(L.partial, elem_blocks(n), L.coef, L.coef + 1, st));
     if (L.psi)
-      EDX_TRY(k_unpad_scale(vtype, acc, s->ld, s->dup, s->ddw, L.coef + 1, psi0, st));
+      EDX_TRY(k_unpad_scale(vtype, acc, s->ld, s->dup, s->ddw * s->dph, L.coef + 1, psi0, st));
     else
       EDX_TRY(k_scale_copy(vtype, psi0, L.coef + 1, psi0, n, st));
     EDX_HIP(hipStreamSynchronize(st));
@@ -560,7 +560,7 @@ edx_status lowest_states_impl(const edx_sector* s, int k, const edx_lanczos_opts
                              st));
       if (nl == 0) EDX_TRY(k_norm2(vtype, L.vec, n, L.partial, st));
     } else {
-      EDX_TRY(k_start_vector(vtype, L.vec, s->dup, s->ld, s->ddw,
+      EDX_TRY(k_start_vector(vtype, L.vec, s->dup, s->ld, s->ddw * s->dph,
                              o->seed + 0x9E3779B97F4A7C15ull * (uint64_t)runs, L.partial, st));
     }
     if (nl > 0) EDX_TRY(project_out(vtype, L.vec, X, L, nl, n, st));
@@ -685,7 +685,7 @@ edx_status lowest_states_impl(const edx_sector* s, int k, const edx_lanczos_opts
     EDX_HIP(hipMemcpyAsync(L.coef + 2, &one, sizeof(double), hipMemcpyHostToDevice, st));
     for (int i = 0; i < nf; ++i) {
       char* dst = reinterpret_cast<char*>(psi_out) + (size_t)i * s->dim * vbytes(vtype);
-      EDX_TRY(k_unpad_scale(vtype, slot(order[i]), s->ld, s->dup, s->ddw, L.coef + 2, dst, st));
+      EDX_TRY(k_unpad_scale(vtype, slot(order[i]), s->ld, s->dup, s->ddw * s->dph, L.coef + 2, dst, st));
     }
   }
   EDX_HIP(hipStreamSynchronize(st));
@@ -715,15 +715,18 @@ size_t green_workspace_bytes(const edx_sector* s, int vtype, int ngf) {
     for (int i = 1; i <= k; ++i) r = r * (nn - k + i) / i;
     return r;
   };
-  // Krylov vectors of a neighbour sector use its padded column stride
+  // Krylov vectors of a neighbour sector use its padded column stride (times
+  // the phonon copies)
   const int64_t cu = comb(ns, s->nup), cd = comb(ns, s->ndw);
   for (int d : {-1, 1}) {
-    dmax = std::max(dmax, vec_ld(comb(ns, s->nup + d)) * cd);
-    dmax = std::max(dmax, vec_ld(cu) * comb(ns, s->ndw + d));
+    dmax = std::max(dmax, vec_ld(comb(ns, s->nup + d)) * cd * s->dph);
+    dmax = std::max(dmax, vec_ld(cu) * comb(ns, s->ndw + d) * s->dph);
   }
-  // hv partial blocks of a neighbour sector: bounded by its column count
+  // hv partial blocks of a neighbour sector: bounded by its column count per
+  // phonon slice, plus the phonon pass
   const int64_t ddw_max = std::max({comb(ns, s->ndw - 1), comb(ns, s->ndw), comb(ns, s->ndw + 1)});
-  const int hvb = (int)std::max<int64_t>(kMaxPartials, ddw_max + 8 + kNdMaxBlocks);
+  const int hvb = (int)std::max<int64_t>(kMaxPartials,
+                                         s->dph * (ddw_max + 8 + kNdMaxBlocks) + 1024);
   return lanczos_ws_layout(dmax, vtype, ngf, 0, hvb, false, nullptr, nullptr) +
          sizeof(double) * (2 * kMaxLmats + 4 * (ngf + 1)) + 512;
 }

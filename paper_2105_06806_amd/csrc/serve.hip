@@ -352,6 +352,10 @@ edx_status edx_server_submit(edx_server* S, const edx_model* model, int32_t nup,
     set_error("server: non-finite interaction parameter");
     return EDX_E_INVALID;
   }
+  if (model->nph != 0) {
+    set_error("server: models with phonons are not served (use the direct entry points)");
+    return EDX_E_UNSUPPORTED;
+  }
   R->nup = nup;
   R->ndw = ndw;
   R->footprint = estimate_footprint(S->opts, m, nup, ndw);

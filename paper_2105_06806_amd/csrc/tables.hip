@@ -425,9 +425,10 @@ edx_status build_sector_impl(const Model& m, int nup, int ndw, hipStream_t st,
   }
   S->dup = S->up.D;
   S->ddw = S->dw.D;
-  S->dim = S->dup * S->ddw;
+  S->dph = m.nph + 1;
+  S->dim = S->dup * S->ddw * S->dph;
   S->ld = vec_ld(S->dup);
-  S->vlen = S->ld * S->ddw;
+  S->vlen = S->ld * S->ddw * S->dph;
   S->nd = m.norb >= 2 && (m.Jx != 0.0 || m.Jp != 0.0);
   if (S->nd) EDX_TRY(build_nd_terms(S.get(), m, binom, st));
 

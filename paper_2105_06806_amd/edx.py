@@ -35,7 +35,9 @@ class _Model(ctypes.Structure):
                 ("vhyb", ctypes.POINTER(ctypes.c_double)),
                 ("U", ctypes.c_double), ("Ust", ctypes.c_double),
                 ("Jh", ctypes.c_double), ("xmu", ctypes.c_double),
-                ("Jx", ctypes.c_double), ("Jp", ctypes.c_double)]
+                ("Jx", ctypes.c_double), ("Jp", ctypes.c_double),
+                ("nph", ctypes.c_int32), ("pad_", ctypes.c_int32),
+                ("w0", ctypes.c_double), ("g", ctypes.POINTER(ctypes.c_double))]
 
 
 class HvPlan(ctypes.Structure):
@@ -226,6 +228,7 @@ class Sector:
         dup, ddw, dim = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
         _check(lib.edx_sector_dims(handle, ctypes.byref(dup), ctypes.byref(ddw), ctypes.byref(dim)))
         self.dup, self.ddw, self.dim = dup.value, ddw.value, dim.value
+        self.dph = self.dim // (self.dup * self.ddw)   # phonon copies (1: none)
         ld = ctypes.c_int64()
         _check(lib.edx_sector_ld(handle, ctypes.byref(ld)))
         self.ld = ld.value   # column stride of the library's own Krylov vectors
@@ -268,7 +271,9 @@ def _model_struct(m):
 
     s = _Model(int(m["norb"]), int(m["nbath"]), arr(m["eps_imp"]), arr(m["eps_bath"]),
                arr(m["vhyb"]), float(m["U"]), float(m["Ust"]), float(m["Jh"]), float(m["xmu"]),
-               float(m.get("Jx", 0.0)), float(m.get("Jp", 0.0)))
+               float(m.get("Jx", 0.0)), float(m.get("Jp", 0.0)), int(m.get("nph", 0)), 0,
+               float(m.get("w0", 0.0)),
+               arr(m["g"]) if int(m.get("nph", 0)) > 0 else None)
     return s, keep
 
 
@@ -299,9 +304,9 @@ def build_sector_orbital(model, nup, ndw, stream=None):
 def _vec_len(sector, v, w, ld):
     if v.dtype != w.dtype:
         raise TypeError("v and w must have the same dtype")
-    n = (ld or sector.dup) * sector.ddw
+    n = (ld or sector.dup) * sector.ddw * sector.dph
     if v.numel() != n or w.numel() != n or not v.is_contiguous() or not w.is_contiguous():
-        raise ValueError(f"v and w must be contiguous with ld * D_dw = {n} elements")
+        raise ValueError(f"v and w must be contiguous with ld * D_dw * D_ph = {n} elements")
 
 
 def hv(sector, v, w, stream=None, ld=0):
@@ -317,15 +322,16 @@ def hv(sector, v, w, stream=None, ld=0):
 def pad(sector, x, ld=None):
     """Dense vector (D elements) -> column stride ld (default sector.ld), zero padding."""
     ld = sector.ld if ld is None else ld
-    out = x.new_zeros(ld * sector.ddw)
-    out.view(sector.ddw, ld)[:, :sector.dup] = x.view(sector.ddw, sector.dup)
+    nc = sector.ddw * sector.dph
+    out = x.new_zeros(ld * nc)
+    out.view(nc, ld)[:, :sector.dup] = x.view(nc, sector.dup)
     return out
 
 
 def unpad(sector, x, ld=None):
     """Column stride ld (default sector.ld) -> dense vector of D elements (a copy)."""
     ld = sector.ld if ld is None else ld
-    return x.view(sector.ddw, ld)[:, :sector.dup].reshape(-1).clone()
+    return x.view(sector.ddw * sector.dph, ld)[:, :sector.dup].reshape(-1).clone()
 
 
 def _plan_dict(p):

@@ -56,11 +56,13 @@ def _plain_bath(rng, nbath, elo, ehi, vlo, vhi):
 
 
 def make_model(norb, nbath, U, Ust=None, Jh=0.0, eps_imp=None, xmu=0.0,
-               seed=0, symmetric=True, elo=-1.0, ehi=1.0, vlo=0.2, vhi=0.6, Jx=0.0, Jp=0.0):
+               seed=0, symmetric=True, elo=-1.0, ehi=1.0, vlo=0.2, vhi=0.6, Jx=0.0, Jp=0.0,
+               nph=0, w0=0.0, g=None):
     """Draw one bath realisation.  ``eps_imp`` defaults to the half-filling
     Hartree shift -(U/2 + (norb-1)(2U'-J)/2), which is -U/2 for norb=1.
     ``Jx``, ``Jp``: spin-exchange and pair-hopping couplings (0: density-density
-    interaction only)."""
+    interaction only).  ``nph``, ``w0``, ``g``: Holstein phonon cutoff, frequency
+    and per-orbital couplings (nph = 0: no phonons)."""
     rng = np.random.default_rng(seed)
     if Ust is None:
         Ust = U - 2.0 * Jh
@@ -77,6 +79,8 @@ def make_model(norb, nbath, U, Ust=None, Jh=0.0, eps_imp=None, xmu=0.0,
         "eps_bath": eb, "vhyb": vb,
         "U": float(U), "Ust": float(Ust), "Jh": float(Jh),
         "Jx": float(Jx), "Jp": float(Jp),
+        "nph": int(nph), "w0": float(w0),
+        "g": np.zeros(norb) if g is None else np.broadcast_to(np.asarray(g, float), (norb,)).copy(),
     }
 
 
