@@ -24,6 +24,11 @@ Also in the JSON line (one pass of every hot-path row, each on its workload):
                  persistent launch vs the same solves one after another
   serve          Poisson streams of ground state + G requests at several rates:
                  p50/p99 latency and solves/s vs one-at-a-time plain solves
+  hv_kanamori    H.v with spin exchange and pair hopping
+  orbital        orbital-resolved sector: H.v and ground state
+  lowest_thermal several low-lying states; eigenstate list, thermal G and chi
+  eph            H.v with a Holstein phonon mode
+  shard          per-GPU pieces of the column-distributed product at p = 8
 """
 from __future__ import annotations
 
@@ -178,6 +183,143 @@ def bench_hv_kanamori(edx, torch, a):
                            f"J=Jx=Jp={m0['Jh']} (kanamori) vs Jx=Jp=0")
         out[name] = row
     return out
+
+
+def _hv_rate(edx, torch, S, a, dt=None, reps=None):
+    """Mean FP32 H.v time on the padded layout with the autotuned plan."""
+    dt = dt or torch.float32
+    gen = torch.Generator(device="cuda").manual_seed(4)
+    v = edx.pad(S, torch.rand(S.dim, dtype=dt, device="cuda", generator=gen) * 2 - 1)
+    w = torch.empty_like(v)
+    plan, _ = edx.autotune_hv(S, v, w, reps=a.tune_reps, ld=S.ld)
+    ms, _ = time_hv(edx, torch, S, v, w, reps or max(10, a.steps // 2), a.warmup, ld=S.ld)
+    us = float(ms.mean()) * 1e3
+    gbs = S.dim * 2 * v.element_size() / (us * 1e-6) / 1e9
+    del v, w
+    torch.cuda.empty_cache()
+    return {"us": round(us, 1), "gbs": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4),
+            "plan": plan}
+
+
+def bench_orbital(edx, torch, a):
+    """Orbital-resolved sector: Norb=2, Nbath=7 (Ns=16), per-orbital counts
+    (4,4)/(4,4), D = 70^4; FP32 H.v and an FP64 ground state, beside the
+    total-N 8/8 sector of the same model it is part of."""
+    from paper_2105_06806_amd import inputs
+    m, [sec] = inputs.workload("ns16o2")
+    S = edx.build_sector_orbital(m, (4, 4), (4, 4))
+    r = {"workload": f"Norb=2 Nbath=7 (Ns=16) orbital sector (4,4)/(4,4), D={S.dim}",
+         "hv_f32": _hv_rate(edx, torch, S, a)}
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e0, _, rep, _ = edx.lanczos_ground_state(S, want_psi=False, niter=512, tol=1e-12, seed=3,
+                                             allow=(edx.EDX_E_DEGENERATE, edx.EDX_E_NOCONV))
+    r["gs_f64_s"] = round(time.perf_counter() - t0, 3)
+    r["gs_iters"] = rep["iters"]
+    return r
+
+
+def bench_lowest_and_thermal(edx, torch, a):
+    """Several low-lying states and finite temperature: the 8 lowest states of
+    the Ns=12 6/6 sector (FP64, locking + check run), and the eigenstate list
+    plus thermal G and spin susceptibility over every sector of an Ns=8 model
+    (beta=10, cutoff 1e-6, 3 annealing calls)."""
+    from paper_2105_06806_amd import inputs
+    out = {}
+    m, [sec] = inputs.workload("ns12")
+    S = edx.build_sector(m, *sec)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e, _, rep, st = edx.lanczos_lowest(S, 8, want_psi=False, niter=400, tol=0.0, rtol=1e-10,
+                                       seed=5, allow=(edx.EDX_E_NOCONV,))
+    out["lowest8_ns12"] = {"s": round(time.perf_counter() - t0, 3), "runs": rep["runs"],
+                           "iters": rep["iters"], "verified": rep["verified"],
+                           "gaps": [round(float(x - e[0]), 6) for x in e]}
+    m8, _ = inputs.workload("ns8")
+    secs = [(x, y) for x in range(9) for y in range(9)]
+    Ss = [edx.build_sector(m8, *q) for q in secs]
+    E = edx.Espace(len(secs), beta=10.0, cutoff=1e-6, nstates_sector=2, nstates_total=2000,
+                   nstates_step=4)
+    t0 = time.perf_counter()
+    for _ in range(3):
+        E.diag(Ss, niter=300, tol=0.0, rtol=1e-10, seed=1)
+    t1 = time.perf_counter()
+    G = E.green(0, 0, ngf=100, lmats=512)
+    t2 = time.perf_counter()
+    C = E.chi([0.5], [-0.5], ngf=100, lmats=64)
+    t3 = time.perf_counter()
+    n, e0, z = E.info()
+    out["thermal_ns8"] = {"workload": "Ns=8 model, all 81 sectors, beta=10, cutoff 1e-6",
+                          "diag3_s": round(t1 - t0, 3), "states_kept": n,
+                          "green_s": round(t2 - t1, 3), "chi_s": round(t3 - t2, 3),
+                          "chi_static": round(float(C[0].real), 6)}
+    return out
+
+
+def bench_eph(edx, torch, a):
+    """Holstein phonon (N_ph = 4, D_ph = 5) on the Ns=14 7/7 sector: FP32 H.v
+    (D = 3432^2 x 5 = 58.9M) against the purely electronic product of the same
+    sector (the phonon pass is the difference)."""
+    from paper_2105_06806_amd import inputs
+    m0 = inputs.make_model(1, 13, 2.0, seed=inputs.SEED_BASE["ns16"] + 14)
+    m = dict(m0, nph=4, w0=0.5, g=np.array([0.4]))
+    Se = edx.build_sector(m0, 7, 7)
+    Sp = edx.build_sector(m, 7, 7)
+    el = _hv_rate(edx, torch, Se, a)
+    ph = _hv_rate(edx, torch, Sp, a)
+    return {"workload": f"Ns=14 7/7 with a Holstein mode N_ph=4: D={Sp.dim} (electronic {Se.dim})",
+            "hv_f32": ph, "electronic_hv_f32": el,
+            "phonon_pass_share": round(1 - 5 * el["us"] / ph["us"], 4)}
+
+
+def bench_shard(edx, torch, a, p=8):
+    """The per-GPU work of the column-distributed product (Sec. 3.2) at the
+    Ns=16 8/8 shapes for p = 8 GPUs, measured on this GPU: the spin-up pass +
+    H_d on a D_up x D_dw/p block, the spin-down pass on a D_dw x D_up/p block of
+    the transposed vector, and the local transposes of one share (the all-to-all
+    packing); the xGMI transfer is a model (7 links x 153 GB/s, each peer over
+    its own link), not a measurement."""
+    from paper_2105_06806_amd import inputs
+    m, [sec] = inputs.workload("ns16")
+    S = edx.build_sector(m, *sec)
+    ld, ldt = S.ld, (S.ddw + 31) // 32 * 32
+    gen = torch.Generator(device="cuda").manual_seed(6)
+    v = edx.pad(S, torch.rand(S.dim, dtype=torch.float32, device="cuda", generator=gen) * 2 - 1)
+    w = torch.empty_like(v)
+    vt = torch.zeros(ldt * S.dup, dtype=torch.float32, device="cuda")
+    wt = torch.empty_like(vt)
+    cb = (S.ddw + p - 1) // p
+    edx.transpose(v, S.dup, S.ddw, ld, vt, ldt)
+    share = torch.zeros(cb * S.dup, dtype=torch.float32, device="cuda")
+
+    def timed(fn, reps=20):
+        for _ in range(3):
+            fn()
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+              for _ in range(reps)]
+        for x, y in ev:
+            x.record()
+            fn()
+            y.record()
+        torch.cuda.synchronize()
+        return float(np.mean([x.elapsed_time(y) for x, y in ev])) * 1e3
+
+    t_up = timed(lambda: edx.hv_block(S, 0, v, w, ld, 0, cb))
+    t_dw = timed(lambda: edx.hv_block(S, 1, vt, wt, ldt, 0, cb))
+    t_tr = timed(lambda: edx.transpose(v, S.dup, cb, ld, share, cb))
+    share_bytes = S.dup * cb * 4
+    t_link = share_bytes / p / 153e9 * 1e6        # one peer message per link
+    t_whole = _hv_rate(edx, torch, S, a, reps=10)["us"]
+    del v, w, vt, wt, share
+    torch.cuda.empty_cache()
+    comp = t_up + t_dw + 2 * t_tr
+    return {"workload": f"Ns=16 8/8 FP32 split over p={p}: blocks {S.dup}x{cb} and {S.ddw}x{cb}",
+            "up_pass_us": round(t_up, 1), "down_pass_us": round(t_dw, 1),
+            "local_transpose_us": round(t_tr, 1), "per_gpu_compute_us": round(comp, 1),
+            "xgmi_model_us_per_transpose": round(t_link, 1),
+            "per_gpu_total_model_us": round(comp + 2 * t_link, 1),
+            "one_gpu_whole_hv_us": t_whole,
+            "model_speedup_vs_one_gpu": round(t_whole / (comp + 2 * t_link), 2)}
 
 
 def cpu_baseline(m, sec, elem_bytes, budget_s=15.0, max_procs=16):
@@ -456,6 +598,10 @@ def main():
     if not a.quick:
         for name, fn in (("hv_ns16o2", lambda: bench_hv_o2(edx, torch, a)),
                          ("hv_kanamori", lambda: bench_hv_kanamori(edx, torch, a)),
+                         ("orbital", lambda: bench_orbital(edx, torch, a)),
+                         ("lowest_thermal", lambda: bench_lowest_and_thermal(edx, torch, a)),
+                         ("eph", lambda: bench_eph(edx, torch, a)),
+                         ("shard", lambda: bench_shard(edx, torch, a)),
                          ("ns12", lambda: bench_ns12(edx)), ("ns15o3", lambda: bench_ns15o3(edx)),
                          ("batch", lambda: bench_batch(edx, torch)),
                          ("serve", lambda: bench_serve(edx, torch, a.full))):

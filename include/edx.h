@@ -225,6 +225,27 @@ edx_status edx_lanczos_ground_state(const edx_sector* s,
                                     size_t ws_bytes, double* e0, void* psi0,
                                     edx_lanczos_report* rep, void* stream);
 
+/* ---- the per-GPU pieces of the column-distributed product (Sec. 3.2:
+ * columns of V split over processes, two transposes per product), callable on
+ * one GPU so that a sharded product can be composed and its per-GPU work
+ * measured at the real block shapes.
+ * part 0: w[:, c0:c1] = H_d o V[:, c0:c1] + H_up V[:, c0:c1] for the column
+ *         block [c0, c1) of V (D_up x D_dw, column stride ld >= D_up);
+ * part 1: w[:, c0:c1] = H_dw VT[:, c0:c1] for the column block [c0, c1) of the
+ *         transposed vector VT (D_dw x D_up, column stride ld >= D_dw), i.e. the
+ *         spin-down hops made local by the transpose (no diagonal).
+ * Output columns are overwritten, their padding rows written as zero; other
+ * columns are untouched.  With phonons, apply per phonon slice.
+ * EDX_E_INVALID for a bad part, range or ld. */
+edx_status edx_hv_block(const edx_sector* s, edx_vtype vtype, int32_t part, const void* v,
+                        void* w, int64_t ld, int64_t c0, int64_t c1, void* stream);
+
+/* dst (cols x rows, column stride ldd >= cols) = src^T, or dst += src^T when
+ * add = 1; src is rows x cols with column stride lds >= rows (device, vtype
+ * elements).  The local part of the all-to-all transpose of Sec. 3.2. */
+edx_status edx_transpose(edx_vtype vtype, const void* src, int64_t rows, int64_t cols,
+                         int64_t lds, void* dst, int64_t ldd, int32_t add, void* stream);
+
 /* ---- several low-lying states (Sec. 5 "Eigenspace class": lanc_nstates_*)
  * The k lowest eigenpairs of one sector by Lanczos with full
  * re-orthogonalisation and locking: each run starts from a random vector

@@ -197,6 +197,36 @@ edx_status edx_hv(const edx_sector* s, edx_vtype vtype, const void* v, void* w, 
   return hv_launch(s, vtype, v, w, ld, nullptr, nullptr, static_cast<hipStream_t>(stream));
 }
 
+edx_status edx_hv_block(const edx_sector* s, edx_vtype vtype, int32_t part, const void* v,
+                        void* w, int64_t ld, int64_t c0, int64_t c1, void* stream) {
+  EDX_TRY(check_sector(s));
+  if (!valid_vtype(vtype)) return invalid("vtype must be EDX_F64 or EDX_F32");
+  if (!v || !w) return invalid("v or w is NULL");
+  if (part != 0 && part != 1) return invalid("part must be 0 or 1");
+  if (s->nd) {
+    set_error("hv_block: spin exchange / pair hopping couple both spins (no column-local form)");
+    return EDX_E_UNSUPPORTED;
+  }
+  const int64_t rows = part == 0 ? s->dup : s->ddw;
+  const int64_t cols = part == 0 ? s->ddw : s->dup;
+  if (ld < rows) return invalid("ld below the column length");
+  if (c0 < 0 || c1 > cols || c0 >= c1) return invalid("column range outside [0, ncols)");
+  const size_t bytes = (size_t)(ld * cols) * vbytes(vtype);
+  const char* pv = static_cast<const char*>(v);
+  const char* pw = static_cast<const char*>(w);
+  if (pv < pw + bytes && pw < pv + bytes) return invalid("v and w overlap");
+  return hv_block_launch(s, vtype, part, v, w, ld, c0, c1, static_cast<hipStream_t>(stream));
+}
+
+edx_status edx_transpose(edx_vtype vtype, const void* src, int64_t rows, int64_t cols,
+                         int64_t lds, void* dst, int64_t ldd, int32_t add, void* stream) {
+  if (!valid_vtype(vtype)) return invalid("vtype must be EDX_F64 or EDX_F32");
+  if (!src || !dst) return invalid("src or dst is NULL");
+  if (rows < 0 || cols < 0 || lds < rows || ldd < cols) return invalid("bad shape or stride");
+  if (add != 0 && add != 1) return invalid("add must be 0 or 1");
+  return k_transpose(vtype, src, rows, cols, lds, dst, ldd, add, static_cast<hipStream_t>(stream));
+}
+
 edx_status edx_hv_get_plan(const edx_sector* s, edx_vtype vtype, edx_hv_plan* plan) {
   if (!s || !plan) return invalid("sector or plan is NULL");
   if (!valid_vtype(vtype)) return invalid("vtype must be EDX_F64 or EDX_F32");

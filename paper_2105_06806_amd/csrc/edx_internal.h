@@ -107,6 +107,7 @@ struct edx_sector {
   double* amp64 = nullptr;   // [256] device
   float* amp32 = nullptr;    // [256] device
   // W[p_up * 8 + p_dw]: density-density energy of two impurity patterns.
+  double* zeros = nullptr;   // max(D_up, D_dw) + 64 zero doubles (block passes)
   double* w64 = nullptr;     // [64] device
   float* w32 = nullptr;      // [64] device
   int32_t* binom = nullptr;  // [25*25] device binomial table
@@ -126,6 +127,18 @@ struct edx_sector {
   double* nd_amp64 = nullptr;
   float* nd_amp32 = nullptr;
   int nd_nt = 0;               // number of terms in the table
+  // with phonons: per phonon slice p a term table of the same form for the
+  // fused pass (the H_nd terms plus (0, -+D_dw, G(pu, pd) sqrt(p or p+1)):
+  // the neighbouring slices are D_dw columns away) and W + w0 p
+  int32_t* ph_off = nullptr;   // [dph][P*P + 1], relative to the slice's first term
+  int32_t* ph_du = nullptr;
+  int32_t* ph_dd = nullptr;
+  double* ph_amp64 = nullptr;
+  float* ph_amp32 = nullptr;
+  std::vector<int> ph_start;   // host: first term of slice p, [dph + 1]
+  int ph_nt_max = 0;           // largest per-slice term count
+  double* wph64 = nullptr;     // [dph][64]
+  float* wph32 = nullptr;
   // lazily built neighbour sectors for the Green's function:
   // [spin][0] = N_s + 1 (particle), [spin][1] = N_s - 1 (hole); for an
   // orbital-resolved sector per orbital: [spin][orb][branch]
@@ -163,6 +176,11 @@ edx_status hv_launch(const edx_sector* s, int vtype, const void* v, void* w, int
 edx_status hv_autotune(edx_sector* s, int vtype, const void* v, void* w, int64_t ld, int reps,
                        hipStream_t st, HvPlan* best, double* best_us);
 int hv_partial_blocks(const edx_sector* s, int vtype);
+// per-GPU pieces of the column-distributed product (see edx_hv_block)
+edx_status hv_block_launch(const edx_sector* s, int vtype, int part, const void* v, void* w,
+                           int64_t ld, int64_t c0, int64_t c1, hipStream_t st);
+edx_status k_transpose(int vtype, const void* src, int64_t rows, int64_t cols, int64_t lds,
+                       void* dst, int64_t ldd, int add, hipStream_t st);
 
 // ---- krylov.hip
 int elem_blocks(int64_t n);

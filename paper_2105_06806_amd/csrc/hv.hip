@@ -188,7 +188,8 @@ template <typename T, int WUP>
 __global__ __launch_bounds__(1024) void k_hv_col(HvArgs<T> a, const T* __restrict__ v,
                                                  T* __restrict__ w,
                                                  const double* __restrict__ vscale,
-                                                 double* __restrict__ partial, int ncol) {
+                                                 double* __restrict__ partial, int ncol,
+                                                 int accumulate) {
   constexpr int RPT = 2;   // rows per thread per iteration
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T* amp = reinterpret_cast<T*>(smem_raw);
@@ -231,7 +232,7 @@ __global__ __launch_bounds__(1024) void k_hv_col(HvArgs<T> a, const T* __restric
       pu[r] = a.pup[rows[r]] * 8;
 #pragma unroll
       for (int c = 0; c < kColMax; ++c)
-        wold[r][c] = c < nc ? w[rows[r] + jc[c] * ld] : T(0);
+        wold[r][c] = (c < nc && accumulate) ? w[rows[r] + jc[c] * ld] : T(0);
     }
 #pragma unroll
     for (int r = 0; r < RPT; ++r) {
@@ -307,6 +308,25 @@ struct NdTab {
   const T* amp;
   int P, nt;
 };
+
+// terms of the fused pass's staged table: H_nd, or with phonons the largest
+// per-slice table (H_nd + phonon terms)
+inline int nd_lds_terms(const edx_sector* s) {
+  return s->dph > 1 ? s->ph_nt_max : (s->nd ? s->nd_nt : 0);
+}
+
+template <typename T>
+const T* ph_amp(const edx_sector* s);
+template <>
+const double* ph_amp<double>(const edx_sector* s) { return s->ph_amp64; }
+template <>
+const float* ph_amp<float>(const edx_sector* s) { return s->ph_amp32; }
+template <typename T>
+const T* wph(const edx_sector* s);
+template <>
+const double* wph<double>(const edx_sector* s) { return s->wph64; }
+template <>
+const float* wph<float>(const edx_sector* s) { return s->wph32; }
 
 template <typename T>
 const T* nd_amp(const edx_sector* s);
@@ -658,7 +678,8 @@ HvPlan hv_default_plan(const edx_sector* s, int vtype) {
   // table row is then reused over more columns), as far as LDS allows and
   // keeping a block per CU.
   const size_t colb = (size_t)s->dup * sz;
-  const size_t ndl = s->nd ? 16 + nd_tab_lds(1 << s->model.norb, s->nd_nt, sz) : 0;
+  const int ndt = nd_lds_terms(s);
+  const size_t ndl = ndt > 0 ? 16 + nd_tab_lds(1 << s->model.norb, ndt, sz) : 0;
   int c = (int)std::max<size_t>(1, (kColLdsBytes - ndl) / colb);
   c = std::min(c, colb >= 48 * 1024 ? 3 : 2);
   while (c > 1 && (s->ddw + c - 1) / c < 256) --c;
@@ -708,8 +729,8 @@ edx_status hv_validate(const edx_sector* s, int vtype, HvPlan* p) {
     set_error("hv plan: row_rows = 128 (two rows per lane) needs an even D_up");
     return EDX_E_UNSUPPORTED;
   }
-  const size_t ndl = (s->nd && p->mode == 2)
-                         ? 16 + nd_tab_lds(1 << s->model.norb, s->nd_nt, sz) : 0;
+  const size_t ndl = (nd_lds_terms(s) > 0 && p->mode == 2)
+                         ? 16 + nd_tab_lds(1 << s->model.norb, nd_lds_terms(s), sz) : 0;
   if (smem_header() + (size_t)p->col_cols * s->dup * sz + ndl > 160 * 1024) {
     set_error("hv plan: columns do not fit in LDS");
     return EDX_E_UNSUPPORTED;
@@ -731,11 +752,13 @@ static int hv_el_partial_blocks(const edx_sector* s, const HvPlan& p) {
   return p.col_blocks + (p.mode == 2 ? 0 : nd_blocks(s));
 }
 
-constexpr int kPhBlocks = 1024;   // workgroups of the phonon pass
+// workgroups of the phonon pass: groups of 8 columns per slice
+static int ph_blocks(const edx_sector* s) { return (int)((s->ddw + 7) / 8) * s->dph; }
 
 int hv_partial_blocks(const edx_sector* s, int vtype) {
   const HvPlan p = hv_plan(s, vtype);
-  return s->dph * hv_el_partial_blocks(s, p) + (s->dph > 1 ? kPhBlocks : 0);
+  // the fused plan applies the phonon terms itself (per-slice term tables)
+  return s->dph * hv_el_partial_blocks(s, p) + (s->dph > 1 && p.mode != 2 ? ph_blocks(s) : 0);
 }
 
 namespace {
@@ -791,7 +814,7 @@ edx_status launch_col_w(const HvArgs<T>& a, bool fused, int nblk, int nthr, size
     EDX_HIP(hipFuncSetAttribute((const void*)k_hv_col<T, WUP>,
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     hipLaunchKernelGGL((k_hv_col<T, WUP>), dim3(nblk), dim3(nthr), lds, st, a, v, w, vscale,
-                       partial, ncol);
+                       partial, ncol, 1);
     EDX_HIP(hipGetLastError());
     return EDX_OK;
   }
@@ -825,8 +848,8 @@ edx_status launch_row_r(const HvArgs<T>& a, int64_t grid, hipStream_t st, const 
 
 template <typename T>
 edx_status launch_t(const edx_sector* s, const T* v, T* w, int64_t ld, const double* vscale,
-                    double* partial, hipStream_t st, const HvPlan& p) {
-  const HvArgs<T> a = make_args<T>(s, ld);
+                    double* partial, hipStream_t st, const HvPlan& p, int slice) {
+  HvArgs<T> a = make_args<T>(s, ld);
   const size_t hdr = smem_header();
   if (p.mode == 0) {
     const size_t lds = hdr + (size_t)s->dim * sizeof(T);
@@ -841,7 +864,15 @@ edx_status launch_t(const edx_sector* s, const T* v, T* w, int64_t ld, const dou
   // the fused pass also applies spin exchange / pair hopping from a staged table
   NdTab<T> nd{nullptr, nullptr, nullptr, nullptr, 1 << s->model.norb, 0};
   size_t ndl = 0;
-  if (s->nd && p.mode == 2) {
+  if (p.mode == 2 && s->dph > 1 && slice >= 0) {
+    // phonon slice: W + w0 p and the slice's term table (H_nd + phonon terms)
+    const int P = 1 << s->model.norb;
+    const int t0 = s->ph_start[slice], nt = s->ph_start[slice + 1] - t0;
+    nd = NdTab<T>{s->ph_off + (size_t)slice * (P * P + 1), s->ph_du + t0, s->ph_dd + t0,
+                  ph_amp<T>(s) + t0, P, nt};
+    a.W = wph<T>(s) + (size_t)slice * 64;
+    if (nt > 0) ndl = 16 + nd_tab_lds(nd.P, nd.nt, sizeof(T));
+  } else if (s->nd && p.mode == 2) {
     nd = NdTab<T>{s->nd_off, s->nd_du, s->nd_dd, nd_amp<T>(s), 1 << s->model.norb, s->nd_nt};
     ndl = 16 + nd_tab_lds(nd.P, nd.nt, sizeof(T));
   }
@@ -890,6 +921,10 @@ namespace {
 //   G(i) = sum_a g_a (n_{a up} + n_{a dw}) from the two impurity patterns.
 // Streams v three times (slices p-1, p, p+1) and w once each way; partial sums
 // of <v, added terms> complete the Lanczos alpha of the electronic passes.
+// Grid: x = groups of kPhCols columns of one slice, y = phonon slice; a block
+// walks its columns row by row (coalesced, no index division).
+constexpr int kPhCols = 8;
+
 template <typename T>
 __global__ __launch_bounds__(256) void k_hv_ph(const T* __restrict__ v, T* __restrict__ w,
                                                int64_t dup, int64_t ld, int64_t ddw, int dph,
@@ -901,35 +936,39 @@ __global__ __launch_bounds__(256) void k_hv_ph(const T* __restrict__ v, T* __res
   __shared__ double red[4];
   const double vs = vscale ? *vscale : 1.0;
   const int64_t slice = ld * ddw;
-  const int64_t total = slice * dph;
+  const int p = blockIdx.y;
+  const double wp = w0 * (double)p;
+  const double sp = sqrt((double)p), sp1 = sqrt((double)(p + 1));
+  const bool lo = p > 0, hi = p + 1 < dph;
+  const int64_t j0 = (int64_t)blockIdx.x * kPhCols;
+  const int64_t j1 = j0 + kPhCols < ddw ? j0 + kPhCols : ddw;
   double acc = 0.0;
-  for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < total;
-       idx += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t p = idx / slice;
-    const int64_t r = idx - p * slice;
-    const int64_t id = r / ld;
-    const int64_t iu = r - id * ld;
-    if (iu >= dup) continue;
-    const uint32_t pu = pup[iu], pd = pdw[id];
-    double gv = g0 * (double)((pu & 1u) + (pd & 1u));
-    if (norb > 1) gv += g1 * (double)(((pu >> 1) & 1u) + ((pd >> 1) & 1u));
-    if (norb > 2) gv += g2 * (double)(((pu >> 2) & 1u) + ((pd >> 2) & 1u));
-    const double x = (double)v[idx];
-    double res = w0 * (double)p * x;
-    if (p > 0) res += gv * sqrt((double)p) * (double)v[idx - slice];
-    if (p + 1 < dph) res += gv * sqrt((double)(p + 1)) * (double)v[idx + slice];
-    res *= vs;
-    w[idx] = (T)((double)w[idx] + res);
-    acc += x * vs * res;
+  for (int64_t id = j0; id < j1; ++id) {
+    const uint32_t pd = pdw[id];
+    const int64_t base = (int64_t)p * slice + id * ld;
+    for (int64_t iu = threadIdx.x; iu < dup; iu += blockDim.x) {
+      const uint32_t pu = pup[iu];
+      double gv = g0 * (double)((pu & 1u) + (pd & 1u));
+      if (norb > 1) gv += g1 * (double)(((pu >> 1) & 1u) + ((pd >> 1) & 1u));
+      if (norb > 2) gv += g2 * (double)(((pu >> 2) & 1u) + ((pd >> 2) & 1u));
+      const int64_t idx = base + iu;
+      const double x = (double)v[idx];
+      double res = wp * x;
+      if (lo) res += gv * sp * (double)v[idx - slice];
+      if (hi) res += gv * sp1 * (double)v[idx + slice];
+      res *= vs;
+      w[idx] = (T)((double)w[idx] + res);
+      acc += x * vs * res;
+    }
   }
   const double sum = block_sum(acc, red);
-  if (partial && threadIdx.x == 0) partial[blockIdx.x] = sum;
+  if (partial && threadIdx.x == 0) partial[(int64_t)blockIdx.y * gridDim.x + blockIdx.x] = sum;
 }
 
 // the electronic product on one slice (column stride ld, D_dw columns)
 edx_status hv_launch_el(const edx_sector* s, int vtype, const void* v, void* w, int64_t ld,
                         const double* vscale, double* partial, hipStream_t st,
-                        const HvPlan* plan) {
+                        const HvPlan* plan, int slice) {
   HvPlan p = plan ? *plan : hv_plan(s, vtype);
   if (ld < s->dup) {
     set_error("hv: leading dimension below D_up");
@@ -942,10 +981,10 @@ edx_status hv_launch_el(const edx_sector* s, int vtype, const void* v, void* w, 
     p.row_rows = 64;
   if (vtype == EDX_F64)
     EDX_TRY(launch_t<double>(s, static_cast<const double*>(v), static_cast<double*>(w), ld,
-                             vscale, partial, st, p));
+                             vscale, partial, st, p, slice));
   else
     EDX_TRY(launch_t<float>(s, static_cast<const float*>(v), static_cast<float*>(w), ld, vscale,
-                            partial, st, p));
+                            partial, st, p, slice));
   if (!s->nd || p.mode == 2) return EDX_OK;
   const int nb = nd_blocks(s);
   double* pnd = partial ? partial + p.col_blocks : nullptr;
@@ -971,7 +1010,7 @@ edx_status hv_launch_el(const edx_sector* s, int vtype, const void* v, void* w, 
 edx_status hv_launch(const edx_sector* s, int vtype, const void* v, void* w, int64_t ld,
                      const double* vscale, double* partial, hipStream_t st,
                      const HvPlan* plan) {
-  if (s->dph <= 1) return hv_launch_el(s, vtype, v, w, ld, vscale, partial, st, plan);
+  if (s->dph <= 1) return hv_launch_el(s, vtype, v, w, ld, vscale, partial, st, plan, -1);
   if (ld < s->dup) {
     set_error("hv: leading dimension below D_up");
     return EDX_E_INVALID;
@@ -979,22 +1018,152 @@ edx_status hv_launch(const edx_sector* s, int vtype, const void* v, void* w, int
   const HvPlan p = plan ? *plan : hv_plan(s, vtype);
   const int eb = hv_el_partial_blocks(s, p);
   const size_t sb = (size_t)(ld * s->ddw) * vbytes(vtype);
+  // fused plan: each slice's pass applies its phonon terms (term table); the
+  // other plans add them in a separate pass
+  const bool fused = p.mode == 2;
   for (int q = 0; q < s->dph; ++q)
     EDX_TRY(hv_launch_el(s, vtype, static_cast<const char*>(v) + q * sb,
                          static_cast<char*>(w) + q * sb, ld, vscale,
-                         partial ? partial + (size_t)q * eb : nullptr, st, &p));
+                         partial ? partial + (size_t)q * eb : nullptr, st, &p, fused ? q : -1));
+  if (fused) return EDX_OK;
   double* pph = partial ? partial + (size_t)s->dph * eb : nullptr;
   const Model& m = s->model;
+  const dim3 grid((unsigned)((s->ddw + kPhCols - 1) / kPhCols), (unsigned)s->dph);
   if (vtype == EDX_F64)
-    hipLaunchKernelGGL(k_hv_ph<double>, dim3(kPhBlocks), dim3(256), 0, st,
+    hipLaunchKernelGGL(k_hv_ph<double>, grid, dim3(256), 0, st,
                        static_cast<const double*>(v), static_cast<double*>(w), s->dup, ld,
                        s->ddw, s->dph, s->up.pat, s->dw.pat, m.norb, m.g[0], m.g[1], m.g[2],
                        m.w0, vscale, pph);
   else
-    hipLaunchKernelGGL(k_hv_ph<float>, dim3(kPhBlocks), dim3(256), 0, st,
+    hipLaunchKernelGGL(k_hv_ph<float>, grid, dim3(256), 0, st,
                        static_cast<const float*>(v), static_cast<float*>(w), s->dup, ld,
                        s->ddw, s->dph, s->up.pat, s->dw.pat, m.norb, m.g[0], m.g[1], m.g[2],
                        m.w0, vscale, pph);
+  EDX_HIP(hipGetLastError());
+  return EDX_OK;
+}
+
+// ---------------------------------------------------------------- distributed pieces
+// The per-GPU work of the column-distributed product (Sec. 3.2, two transposes
+// per product), run on one GPU: part 0 is the local pass on a column block of V
+// (spin-up hops inside the columns plus H_d), part 1 the pass on a column block
+// of the transposed vector V^T (D_dw x D_up, spin-down hops inside its columns,
+// no diagonal).  Both are the column pass of the two-pass plan on a shifted
+// view: for part 1 the roles of the two spins swap and the diagonal tables are
+// replaced by zeros.  Output columns are overwritten.
+namespace {
+
+template <typename T>
+edx_status block_t(const edx_sector* s, int part, const T* v, T* w, int64_t ld, int64_t c0,
+                   int64_t c1, hipStream_t st) {
+  HvArgs<T> a = make_args<T>(s, ld);
+  const T* zt = reinterpret_cast<const T*>(s->zeros);
+  if (part == 0) {
+    a.ddw = c1 - c0;
+    a.edw += c0;
+    a.pdw += c0;
+  } else {
+    a.dup = s->ddw;
+    a.ddw = c1 - c0;
+    a.hup = s->dw.hop;
+    a.sup = s->dw.wpad;
+    a.hdw = s->up.hop;
+    a.sdw = s->up.wpad;
+    a.eup = zt;
+    a.edw = zt;
+    a.pup = s->dw.pat;
+    a.pdw = s->up.pat + c0;
+    a.W = zt;
+  }
+  const int64_t len = a.dup;
+  // several columns per workgroup only while that still leaves >= 4
+  // workgroups per CU (narrow blocks of a p-way split)
+  int C = 1;
+  for (int c = 3; c >= 2; --c)
+    if (smem_header() + (size_t)c * len * sizeof(T) <= 150 * 1024 && a.ddw / c >= 1024) {
+      C = c;
+      break;
+    }
+  const size_t lds = smem_header() + (size_t)C * len * sizeof(T);
+  if (lds > 160 * 1024) {
+    set_error("hv_block: column does not fit in LDS");
+    return EDX_E_UNSUPPORTED;
+  }
+  const int nthr = C == 3 ? 1024 : 512;
+  const int nblk = (int)((a.ddw + C - 1) / C);
+  const T* vb = v + c0 * ld;
+  T* wb = w + c0 * ld;
+  auto go = [&](auto kern) -> edx_status {
+    EDX_HIP(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)lds));
+    hipLaunchKernelGGL(kern, dim3(nblk), dim3(nthr), lds, st, a, vb, wb, nullptr, nullptr, C, 0);
+    EDX_HIP(hipGetLastError());
+    return EDX_OK;
+  };
+  switch (a.sup) {
+    case 8: return go(k_hv_col<T, 8>);
+    case 16: return go(k_hv_col<T, 16>);
+    default: return go(k_hv_col<T, 24>);
+  }
+}
+
+// dst (cols x rows, stride ldd) = src^T (+ dst if add); src is rows x cols with
+// stride lds.  64 x 64 tiles through LDS (padded rows: no bank conflicts), so
+// both the reads and the writes are coalesced.
+template <typename T>
+__global__ __launch_bounds__(256) void k_transpose_t(const T* __restrict__ src, int64_t rows,
+                                                     int64_t cols, int64_t lds,
+                                                     T* __restrict__ dst, int64_t ldd, int add,
+                                                     int64_t tiles_r) {
+  __shared__ T tile[64][65];
+  const int64_t tr = blockIdx.x % tiles_r;
+  const int64_t tc = blockIdx.x / tiles_r;
+  const int tx = threadIdx.x & 63;
+  const int ty = threadIdx.x >> 6;   // 0..3
+  const int64_t r0 = tr * 64, c0 = tc * 64;
+  for (int k = ty; k < 64; k += 4) {
+    const int64_t r = r0 + tx, c = c0 + k;
+    if (r < rows && c < cols) tile[k][tx] = src[r + c * lds];
+  }
+  __syncthreads();
+  for (int k = ty; k < 64; k += 4) {
+    const int64_t c = c0 + tx, r = r0 + k;   // dst element (c, r)
+    if (r < rows && c < cols) {
+      const T x = tile[tx][k];
+      T* d = dst + c + r * ldd;
+      *d = add ? (T)(*d + x) : x;
+    }
+  }
+}
+
+}  // namespace
+
+edx_status hv_block_launch(const edx_sector* s, int vtype, int part, const void* v, void* w,
+                           int64_t ld, int64_t c0, int64_t c1, hipStream_t st) {
+  if (vtype == EDX_F64)
+    return block_t<double>(s, part, static_cast<const double*>(v), static_cast<double*>(w), ld,
+                           c0, c1, st);
+  return block_t<float>(s, part, static_cast<const float*>(v), static_cast<float*>(w), ld, c0,
+                        c1, st);
+}
+
+edx_status k_transpose(int vtype, const void* src, int64_t rows, int64_t cols, int64_t lds,
+                       void* dst, int64_t ldd, int add, hipStream_t st) {
+  const int64_t tr = (rows + 63) / 64, tcn = (cols + 63) / 64;
+  const int64_t nb = tr * tcn;
+  if (nb > 0x7FFFFFFF) {
+    set_error("transpose: too many tiles");
+    return EDX_E_UNSUPPORTED;
+  }
+  if (nb == 0) return EDX_OK;
+  if (vtype == EDX_F64)
+    hipLaunchKernelGGL(k_transpose_t<double>, dim3((unsigned)nb), dim3(256), 0, st,
+                       static_cast<const double*>(src), rows, cols, lds,
+                       static_cast<double*>(dst), ldd, add, tr);
+  else
+    hipLaunchKernelGGL(k_transpose_t<float>, dim3((unsigned)nb), dim3(256), 0, st,
+                       static_cast<const float*>(src), rows, cols, lds, static_cast<float*>(dst),
+                       ldd, add, tr);
   EDX_HIP(hipGetLastError());
   return EDX_OK;
 }

@@ -723,10 +723,10 @@ size_t green_workspace_bytes(const edx_sector* s, int vtype, int ngf) {
     dmax = std::max(dmax, vec_ld(cu) * comb(ns, s->ndw + d) * s->dph);
   }
   // hv partial blocks of a neighbour sector: bounded by its column count per
-  // phonon slice, plus the phonon pass
+  // phonon slice, plus the phonon pass (8 columns per workgroup and slice)
   const int64_t ddw_max = std::max({comb(ns, s->ndw - 1), comb(ns, s->ndw), comb(ns, s->ndw + 1)});
-  const int hvb = (int)std::max<int64_t>(kMaxPartials,
-                                         s->dph * (ddw_max + 8 + kNdMaxBlocks) + 1024);
+  const int hvb = (int)std::max<int64_t>(
+      kMaxPartials, s->dph * (ddw_max + 8 + kNdMaxBlocks + (s->dph > 1 ? ddw_max / 8 + 1 : 0)));
   return lanczos_ws_layout(dmax, vtype, ngf, 0, hvb, false, nullptr, nullptr) +
          sizeof(double) * (2 * kMaxLmats + 4 * (ngf + 1)) + 512;
 }

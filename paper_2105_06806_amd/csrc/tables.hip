@@ -19,6 +19,7 @@
 //    per string and the impurity pattern p = s & (2^norb - 1); the cross-spin
 //    terms come from W[p_up][p_dw].
 #include <algorithm>
+#include <cmath>
 #include <cstring>
 
 #include "edx_internal.h"
@@ -275,6 +276,7 @@ void destroy_sector(edx_sector* s) {
   dfree(s, s->amp64);
   dfree(s, s->amp32);
   dfree(s, s->w64);
+  dfree(s, s->zeros);
   dfree(s, s->w32);
   dfree(s, s->binom);
   dfree(s, s->corder);
@@ -283,6 +285,13 @@ void destroy_sector(edx_sector* s) {
   dfree(s, s->nd_dd);
   dfree(s, s->nd_amp64);
   dfree(s, s->nd_amp32);
+  dfree(s, s->ph_off);
+  dfree(s, s->ph_du);
+  dfree(s, s->ph_dd);
+  dfree(s, s->ph_amp64);
+  dfree(s, s->ph_amp32);
+  dfree(s, s->wph64);
+  dfree(s, s->wph32);
   delete s;
 }
 
@@ -308,11 +317,17 @@ int low_rank(uint32_t pat, const std::vector<int32_t>& binom) {
 int below(uint32_t s, int m) { return __builtin_popcount(s & ((1u << m) - 1u)) & 1; }
 }  // namespace
 
-edx_status build_nd_terms(edx_sector* S, const Model& m, const std::vector<int32_t>& binom,
-                          hipStream_t st) {
+// H_nd terms per impurity pattern pair (host): off[key]..off[key+1] index the
+// (du, dd, amp) of key = pu * P + pd
+static void nd_terms_host(const Model& m, const std::vector<int32_t>& binom,
+                          std::vector<int32_t>& off, std::vector<int32_t>& du,
+                          std::vector<int32_t>& dd, std::vector<double>& amp) {
   const int P = 1 << m.norb;
-  std::vector<int32_t> off(P * P + 1, 0), du, dd;
-  std::vector<double> amp;
+  off.assign(P * P + 1, 0);
+  du.clear();
+  dd.clear();
+  amp.clear();
+  if (!(m.norb >= 2 && (m.Jx != 0.0 || m.Jp != 0.0))) return;
   for (int pu = 0; pu < P; ++pu)
     for (int pd = 0; pd < P; ++pd) {
       for (int p = 0; p < m.norb; ++p)
@@ -335,6 +350,13 @@ edx_status build_nd_terms(edx_sector* S, const Model& m, const std::vector<int32
         }
       off[pu * P + pd + 1] = (int32_t)du.size();
     }
+}
+
+edx_status build_nd_terms(edx_sector* S, const Model& m, const std::vector<int32_t>& binom,
+                          hipStream_t st) {
+  std::vector<int32_t> off, du, dd;
+  std::vector<double> amp;
+  nd_terms_host(m, binom, off, du, dd, amp);
   S->nd_nt = (int)du.size();
   const size_t nt = std::max<size_t>(1, du.size());
   du.resize(nt, 0);
@@ -357,6 +379,84 @@ edx_status build_nd_terms(edx_sector* S, const Model& m, const std::vector<int32
   return EDX_OK;
 }
 
+// Per phonon slice p (Sec. "Electron-phonon coupling", eq. HephBuild): the
+// coupling G(pu, pd) = sum_a g_a (n_{a up} + n_{a dw}) times sqrt(p) reaches
+// slice p - 1 and times sqrt(p + 1) slice p + 1, both at the same electronic
+// element, i.e. D_dw columns back or ahead in the vector; merged per pattern
+// pair with the H_nd terms so that the fused pass applies both.  W_p = W + w0 p.
+static edx_status build_ph_terms(edx_sector* S, const Model& m,
+                                 const std::vector<int32_t>& binom, const double* W,
+                                 hipStream_t st) {
+  const int P = 1 << m.norb, K = P * P, dph = S->dph;
+  std::vector<int32_t> noff, ndu, ndd;
+  std::vector<double> namp;
+  nd_terms_host(m, binom, noff, ndu, ndd, namp);
+  std::vector<int32_t> off((size_t)dph * (K + 1), 0), du, dd;
+  std::vector<double> amp;
+  S->ph_start.assign(dph + 1, 0);
+  S->ph_nt_max = 0;
+  for (int p = 0; p < dph; ++p) {
+    const int start = (int)du.size();
+    S->ph_start[p] = start;
+    for (int key = 0; key < K; ++key) {
+      const int pu = key / P, pd = key % P;
+      for (int t = noff[key]; t < noff[key + 1]; ++t) {
+        du.push_back(ndu[t]);
+        dd.push_back(ndd[t]);
+        amp.push_back(namp[t]);
+      }
+      double G = 0.0;
+      for (int a = 0; a < m.norb; ++a) G += m.g[a] * (((pu >> a) & 1) + ((pd >> a) & 1));
+      if (G != 0.0) {
+        if (p > 0) {
+          du.push_back(0);
+          dd.push_back((int32_t)-S->ddw);
+          amp.push_back(G * std::sqrt((double)p));
+        }
+        if (p + 1 < dph) {
+          du.push_back(0);
+          dd.push_back((int32_t)S->ddw);
+          amp.push_back(G * std::sqrt((double)(p + 1)));
+        }
+      }
+      off[(size_t)p * (K + 1) + key + 1] = (int32_t)du.size() - start;
+    }
+    S->ph_nt_max = std::max(S->ph_nt_max, (int)du.size() - start);
+  }
+  S->ph_start[dph] = (int)du.size();
+  const size_t nt = std::max<size_t>(1, du.size());
+  du.resize(nt, 0);
+  dd.resize(nt, 0);
+  amp.resize(nt, 0.0);
+  std::vector<float> ampf(amp.begin(), amp.end());
+  std::vector<double> wp((size_t)dph * 64);
+  std::vector<float> wpf((size_t)dph * 64);
+  for (int p = 0; p < dph; ++p)
+    for (int k = 0; k < 64; ++k) {
+      wp[(size_t)p * 64 + k] = W[k] + m.w0 * p;
+      wpf[(size_t)p * 64 + k] = (float)wp[(size_t)p * 64 + k];
+    }
+  EDX_TRY(dalloc(S, &S->ph_off, off.size() * sizeof(int32_t)));
+  EDX_TRY(dalloc(S, &S->ph_du, nt * sizeof(int32_t)));
+  EDX_TRY(dalloc(S, &S->ph_dd, nt * sizeof(int32_t)));
+  EDX_TRY(dalloc(S, &S->ph_amp64, nt * sizeof(double)));
+  EDX_TRY(dalloc(S, &S->ph_amp32, nt * sizeof(float)));
+  EDX_TRY(dalloc(S, &S->wph64, wp.size() * sizeof(double)));
+  EDX_TRY(dalloc(S, &S->wph32, wpf.size() * sizeof(float)));
+  EDX_HIP(hipMemcpyAsync(S->ph_off, off.data(), off.size() * sizeof(int32_t),
+                         hipMemcpyHostToDevice, st));
+  EDX_HIP(hipMemcpyAsync(S->ph_du, du.data(), nt * sizeof(int32_t), hipMemcpyHostToDevice, st));
+  EDX_HIP(hipMemcpyAsync(S->ph_dd, dd.data(), nt * sizeof(int32_t), hipMemcpyHostToDevice, st));
+  EDX_HIP(hipMemcpyAsync(S->ph_amp64, amp.data(), nt * sizeof(double), hipMemcpyHostToDevice, st));
+  EDX_HIP(hipMemcpyAsync(S->ph_amp32, ampf.data(), nt * sizeof(float), hipMemcpyHostToDevice, st));
+  EDX_HIP(hipMemcpyAsync(S->wph64, wp.data(), wp.size() * sizeof(double), hipMemcpyHostToDevice,
+                         st));
+  EDX_HIP(hipMemcpyAsync(S->wph32, wpf.data(), wpf.size() * sizeof(float), hipMemcpyHostToDevice,
+                         st));
+  EDX_HIP(hipStreamSynchronize(st));   // host vectors go out of scope
+  return EDX_OK;
+}
+
 size_t sector_table_bytes(int ns, int nup, int ndw) {
   auto comb = [](int n, int k) -> int64_t {
     if (k < 0 || k > n) return 0;
@@ -373,6 +473,7 @@ size_t sector_table_bytes(int ns, int nup, int ndw) {
   b += (kMaxNs + 1) * (kMaxNs + 1) * 4 + 256 * 12 + 64 * 12 + 16 + 8 * kMaxNs + 8 * a;
   b += (size_t)comb(ns, ndw) * 4 + a;   // column order
   b += 6 * a + 65 * 4 + 64 * 12 * (4 + 4 + 8 + 4);   // H_nd term table
+  b += 8 * ((size_t)std::max(comb(ns, nup), comb(ns, ndw)) + 64) + a;   // zero block
   return b;
 }
 
@@ -478,6 +579,12 @@ edx_status build_sector_impl(const Model& m, int nup, int ndw, hipStream_t st,
   EDX_HIP(hipMemcpyAsync(S->amp32, ampf, sizeof(ampf), hipMemcpyHostToDevice, st));
   EDX_HIP(hipMemcpyAsync(S->w64, W, sizeof(W), hipMemcpyHostToDevice, st));
   EDX_HIP(hipMemcpyAsync(S->w32, Wf, sizeof(Wf), hipMemcpyHostToDevice, st));
+  if (S->dph > 1) EDX_TRY(build_ph_terms(S.get(), m, binom, W, st));
+  {
+    const size_t zb = sizeof(double) * ((size_t)std::max(S->dup, S->ddw) + 64);
+    EDX_TRY(dalloc(S.get(), &S->zeros, zb));
+    EDX_HIP(hipMemsetAsync(S->zeros, 0, zb, st));
+  }
   EDX_HIP(hipStreamSynchronize(st));
   dfree(S.get(), d_elev);
   *out = S.release();

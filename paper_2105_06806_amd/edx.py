@@ -146,6 +146,8 @@ _SIGS = {
     "edx_espace_sector": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]),
     "edx_espace_green_workspace_bytes": (ctypes.c_size_t, [_P, ctypes.c_int32]),
     "edx_espace_green": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(GfOpts), _P, ctypes.c_size_t, _P, _P]),
+    "edx_hv_block": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int32, _P, _P, ctypes.c_int64, ctypes.c_int64, ctypes.c_int64, _P]),
+    "edx_transpose": (ctypes.c_int, [ctypes.c_int, _P, ctypes.c_int64, ctypes.c_int64, ctypes.c_int64, _P, ctypes.c_int64, ctypes.c_int32, _P]),
     "edx_tridiag_spectrum": (ctypes.c_int, [_P, _P, ctypes.c_int32, _P, _P]),
     "edx_chi": (ctypes.c_int, [_P, _P, ctypes.c_double, _P, _P, ctypes.POINTER(GfOpts), _P, ctypes.c_size_t, _P, ctypes.POINTER(ChiReport), _P]),
     "edx_espace_chi_workspace_bytes": (ctypes.c_size_t, [_P, ctypes.c_int32]),
@@ -317,6 +319,29 @@ def hv(sector, v, w, stream=None, ld=0):
     _check(lib.edx_hv(sector.handle, _vtype_of(v), _P(v.data_ptr()), _P(w.data_ptr()), int(ld),
                       _stream_ptr(stream)))
     return w
+
+
+def hv_block(sector, part, v, w, ld, c0, c1, stream=None):
+    """One GPU's piece of the column-distributed product (see edx_hv_block)."""
+    if v.dtype != w.dtype:
+        raise TypeError("v and w must have the same dtype")
+    cols = sector.ddw if part == 0 else sector.dup
+    if v.numel() < ld * cols or w.numel() < ld * cols:
+        raise ValueError(f"v and w need ld * {cols} elements")
+    _check(lib.edx_hv_block(sector.handle, _vtype_of(v), int(part), _P(v.data_ptr()), _P(w.data_ptr()),
+                            int(ld), int(c0), int(c1), _stream_ptr(stream)))
+    return w
+
+
+def transpose(src, rows, cols, lds, dst, ldd, add=False, stream=None):
+    """dst (cols x rows, stride ldd) = src^T (+ dst), device tensors."""
+    if src.dtype != dst.dtype:
+        raise TypeError("src and dst must have the same dtype")
+    if src.numel() < lds * cols or dst.numel() < ldd * rows:
+        raise ValueError("tensor smaller than its shape and stride")
+    _check(lib.edx_transpose(_vtype_of(src), _P(src.data_ptr()), int(rows), int(cols), int(lds),
+                             _P(dst.data_ptr()), int(ldd), int(bool(add)), _stream_ptr(stream)))
+    return dst
 
 
 def pad(sector, x, ld=None):
