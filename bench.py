@@ -59,6 +59,10 @@ def parse():
     ap.add_argument("--quick", action="store_true", help="headline H.v only")
     ap.add_argument("--full", action="store_true", help="full-size serving sweep")
     ap.add_argument("--tune-reps", type=int, default=3)
+    ap.add_argument("--only", default=None,
+                    help="comma-separated sections (hv_ns16o2, hv_kanamori, orbital, lowest_thermal, "
+                         "eph, shard, ns12, ns15o3, batch, serve): run just these, no headline "
+                         "(profiling runs)")
     ap.add_argument("--plan", default=None,
                     help="mode,col_cols,col_threads,row_rows,row_cols[,col_order] of the FP32 "
                          "headline instead of autotuning (profiling runs)")
@@ -520,6 +524,23 @@ def main():
     from paper_2105_06806_amd import edx, inputs
 
     log(f"device: {torch.cuda.get_device_properties(0).name}")
+    sections = {"hv_ns16o2": lambda: bench_hv_o2(edx, torch, a),
+                "hv_kanamori": lambda: bench_hv_kanamori(edx, torch, a),
+                "orbital": lambda: bench_orbital(edx, torch, a),
+                "lowest_thermal": lambda: bench_lowest_and_thermal(edx, torch, a),
+                "eph": lambda: bench_eph(edx, torch, a),
+                "shard": lambda: bench_shard(edx, torch, a),
+                "ns12": lambda: bench_ns12(edx), "ns15o3": lambda: bench_ns15o3(edx),
+                "batch": lambda: bench_batch(edx, torch),
+                "serve": lambda: bench_serve(edx, torch, a.full)}
+    if a.only:
+        out = {}
+        for name in a.only.split(","):
+            log(f"{name} ...")
+            out[name] = sections[name]()
+            log(f"{name}: {out[name]}")
+        print(json.dumps(out), flush=True)
+        return
     m, [sec] = inputs.workload("ns16")
     S = edx.build_sector(m, *sec)
     D = S.dim
@@ -596,15 +617,7 @@ def main():
             "median_us": round(r32["ms_median"] * 1e3, 1)},
     }
     if not a.quick:
-        for name, fn in (("hv_ns16o2", lambda: bench_hv_o2(edx, torch, a)),
-                         ("hv_kanamori", lambda: bench_hv_kanamori(edx, torch, a)),
-                         ("orbital", lambda: bench_orbital(edx, torch, a)),
-                         ("lowest_thermal", lambda: bench_lowest_and_thermal(edx, torch, a)),
-                         ("eph", lambda: bench_eph(edx, torch, a)),
-                         ("shard", lambda: bench_shard(edx, torch, a)),
-                         ("ns12", lambda: bench_ns12(edx)), ("ns15o3", lambda: bench_ns15o3(edx)),
-                         ("batch", lambda: bench_batch(edx, torch)),
-                         ("serve", lambda: bench_serve(edx, torch, a.full))):
+        for name, fn in sections.items():
             t0 = time.perf_counter()
             log(f"{name} ...")
             try:
