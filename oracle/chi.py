@@ -18,6 +18,16 @@ is the Krylov form: start from O|psi0>, run N plain Lanczos steps in the same
 sector, and use the eigenpairs (theta_m, first components u_m) of the
 tridiagonal matrix:
   C(z) = |O psi0|^2 sum_m u_m^2 [1/(z - (theta_m - E0)) - 1/(z + (theta_m - E0))].
+
+The paper also names excitonic and pair susceptibilities.  Here:
+  * excitonic (orbitals a != b): O = sum_sigma (c+_{a sigma} c_{b sigma} +
+    c+_{b sigma} c_{a sigma}), Hermitian and within the sector, so the same
+    form as above;
+  * pair (orbital a): O = c_{a dw} c_{a up}, which leaves the sector: with the
+    bosonic sign of eq. KLgf,
+      C(z) = <O 1/(z - (H - E0)) O+> - <O+ 1/(z + (H - E0)) O>
+           = sum_m |<m|O+|0>|^2 / (z - (E_m - E0))        (m in N_up+1, N_dw+1)
+             - sum_m |<m|O|0>|^2 / (z + (E_m - E0))       (m in N_up-1, N_dw-1).
 """
 from __future__ import annotations
 
@@ -110,3 +120,80 @@ def chi_double_sum(model, sectors, coef_up, coef_dw, z, beta):
         for k, zz in enumerate(z):
             out[k] += (num[keep] / (zz - d[keep])).sum()
     return out / Z
+
+
+def _apply_ops(model, nup, ndw, psi, ops, tgt):
+    """phi = (product of ops, rightmost first) psi into sector tgt (full-string
+    signs); ops as (mode, creator?) left to right."""
+    ns = fock.ns_of(model)
+    up, dw, I = fock.sector_states(ns, nup, ndw, model)
+    tup, tdw, _ = fock.sector_states(ns, tgt[0], tgt[1], model)
+    phi = np.zeros(len(tup) * len(tdw))
+    if phi.size == 0:
+        return phi
+    valid, Inew, sgn = fock.apply_product(I, ops)
+    j = np.nonzero(valid)[0]
+    idx = fock._index_of(tup, tdw, ns, Inew[j])
+    np.add.at(phi, idx, sgn[j] * np.asarray(psi, float)[j])
+    return phi
+
+
+def exciton_apply(model, nup, ndw, psi, a, b):
+    """O psi for O = sum_sigma (c+_a c_b + c+_b c_a) on both spins."""
+    ns = fock.ns_of(model)
+    out = np.zeros(np.asarray(psi).size)
+    for sg in (0, 1):
+        ma, mb = a + sg * ns, b + sg * ns
+        for (x, y) in ((ma, mb), (mb, ma)):
+            out += _apply_ops(model, nup, ndw, psi, [(x, True), (y, False)], (nup, ndw))
+    return out
+
+
+def chi_exciton_exact(model, nup, ndw, a, b, z):
+    H = fock.explicit_hamiltonian(model, nup, ndw).toarray()
+    w, V = np.linalg.eigh(H)
+    amp = V.T @ exciton_apply(model, nup, ndw, V[:, 0], a, b)
+    return spectral(w, amp ** 2, w[0], z), w[0]
+
+
+def _shift(spec, d, a):
+    if np.ndim(spec) == 0:
+        return int(spec) + d
+    t = list(spec)
+    t[a] += d
+    return tuple(t)
+
+
+def _valid(model, spec):
+    if np.ndim(spec) == 0:
+        return 0 <= spec <= fock.ns_of(model)
+    return all(0 <= x <= model["nbath"] + 1 for x in spec)
+
+
+def pair_apply(model, nup, ndw, psi, a, create):
+    """O+ psi = c+_{a up} c+_{a dw} psi (create) or O psi = c_{a dw} c_{a up} psi;
+    returns (target sector, phi) or (target, empty) when it does not exist."""
+    ns = fock.ns_of(model)
+    d = 1 if create else -1
+    tgt = (_shift(nup, d, a), _shift(ndw, d, a))
+    if not (_valid(model, tgt[0]) and _valid(model, tgt[1])):
+        return tgt, np.zeros(0)
+    ops = [(a, True), (a + ns, True)] if create else [(a + ns, False), (a, False)]
+    return tgt, _apply_ops(model, nup, ndw, psi, ops, tgt)
+
+
+def chi_pair_exact(model, nup, ndw, a, z):
+    """Pair susceptibility at T = 0 from the dense spectra of the three sectors."""
+    H = fock.explicit_hamiltonian(model, nup, ndw).toarray()
+    w0, V0 = np.linalg.eigh(H)
+    E0, psi = w0[0], V0[:, 0]
+    out = np.zeros(len(z), dtype=complex)
+    for create, sgn in ((True, -1.0), (False, +1.0)):
+        tgt, phi = pair_apply(model, nup, ndw, psi, a, create)
+        if phi.size == 0:
+            continue
+        wt, Vt = np.linalg.eigh(fock.explicit_hamiltonian(model, *tgt).toarray())
+        amp2 = (Vt.T @ phi) ** 2
+        term = (amp2[None, :] / (np.asarray(z)[:, None] + sgn * (wt[None, :] - E0))).sum(axis=1)
+        out += term if create else -term
+    return out, E0

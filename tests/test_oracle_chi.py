@@ -11,7 +11,10 @@ sign, O diagonal in the occupation basis).
   * chi(i nu) is real and positive-definite in the sense -C(i nu) >= 0 and
     decreases with nu (a sum of 2 d / (nu^2 + d^2) terms);
   * finite temperature: the per-state thermal sum over every eigenstate equals
-    the textbook bosonic double sum.
+    the textbook bosonic double sum;
+  * excitonic and pair functions against Jordan-Wigner builds on the whole
+    Fock space and against U = 0 closed forms (particle-hole and
+    particle-particle bubbles of the one-body eigenvectors).
 """
 import numpy as np
 import pytest
@@ -104,4 +107,73 @@ def test_thermal_per_state_equals_double_sum():
     cu, cd = [0.5], [-0.5]
     got = chi.chi_thermal_states(m, thermal.all_states(m), cu, cd, z, beta)
     ref = chi.chi_double_sum(m, secs, cu, cd, z, beta)
+    assert np.abs(got - ref).max() < 1e-12
+
+
+def _jw_general(model, sec, O, z, bosonic_pair=False):
+    """sum over every Fock eigenstate m of the sector ground state |0> embedded
+    in the Fock space: |<m|O+|0>|^2/(z - d) - |<m|O|0>|^2/(z + d) (pair), or the
+    Hermitian form with O."""
+    ns = fock.ns_of(model)
+    H, c = jw.fock_hamiltonian(model)
+    _, _, I = fock.sector_states(ns, *sec)
+    idx = I.astype(np.int64)
+    w0, V0 = np.linalg.eigh(H[np.ix_(idx, idx)])
+    psi = np.zeros(H.shape[0])
+    psi[idx] = V0[:, 0]
+    w, V = np.linalg.eigh(H)
+    if not bosonic_pair:
+        amp = V.T @ (O @ psi)
+        return chi.spectral(w, amp ** 2, w0[0], z)
+    ap = (V.T @ (O.T @ psi)) ** 2
+    ah = (V.T @ (O @ psi)) ** 2
+    d = w - w0[0]
+    zz = np.asarray(z)[:, None]
+    kp, kh = ap > 1e-28, ah > 1e-28                  # states the operator reaches
+    return (ap[kp][None, :] / (zz - d[kp][None, :])).sum(axis=1) - \
+        (ah[kh][None, :] / (zz + d[kh][None, :])).sum(axis=1)
+
+
+@pytest.mark.parametrize("sec", [(2, 1), (2, 2), (1, 3)])
+def test_exciton_and_pair_equal_jordan_wigner(sec):
+    m = inputs.make_model(2, 1, 2.5, Jh=0.4, seed=88, symmetric=False)
+    ns = fock.ns_of(m)
+    z = 1j * chi.bosonic(5.0, 10)
+    _, c = jw.fock_hamiltonian(m)
+    cd = [x.T for x in c]
+    Oe = sum(cd[0 + s * ns] @ c[1 + s * ns] + cd[1 + s * ns] @ c[0 + s * ns] for s in (0, 1))
+    got, _ = chi.chi_exciton_exact(m, *sec, 0, 1, z)
+    assert np.abs(got - _jw_general(m, sec, Oe, z)).max() < 1e-12
+    for a in (0, 1):
+        Op = c[a + ns] @ c[a]                        # c_{a dw} c_{a up}
+        got, _ = chi.chi_pair_exact(m, *sec, a, z)
+        ref = _jw_general(m, sec, Op, z, bosonic_pair=True)
+        assert np.abs(got - ref).max() < 1e-12, a
+
+
+def test_pair_and_exciton_noninteracting_bubbles():
+    m = inputs.make_model(2, 2, 0.0, Jh=0.0, Ust=0.0, seed=89, symmetric=False, eps_imp=0.15)
+    ns = fock.ns_of(m)
+    nup, ndw = 3, 2
+    e, U = np.linalg.eigh(closed.onebody_matrix(m))
+    z = 1j * chi.bosonic(6.0, 8)
+    # pair of orbital 0: add up in l >= nup and down in k >= ndw, or remove from occupied
+    ref = np.zeros(len(z), dtype=complex)
+    for l in range(nup, ns):
+        for k in range(ndw, ns):
+            ref += (U[0, l] * U[0, k]) ** 2 / (z - (e[l] + e[k]))
+    for l in range(nup):
+        for k in range(ndw):
+            ref -= (U[0, l] * U[0, k]) ** 2 / (z + (-e[l] - e[k]))
+    got, _ = chi.chi_pair_exact(m, nup, ndw, 0, z)
+    assert np.abs(got - ref).max() < 1e-12
+    # exciton 0-1: particle-hole pairs of each spin
+    ref = np.zeros(len(z), dtype=complex)
+    for n in (nup, ndw):
+        for k in range(n):
+            for l in range(n, ns):
+                amp = U[0, l] * U[1, k] + U[1, l] * U[0, k]
+                d = e[l] - e[k]
+                ref += amp ** 2 * (1 / (z - d) - 1 / (z + d))
+    got, _ = chi.chi_exciton_exact(m, nup, ndw, 0, 1, z)
     assert np.abs(got - ref).max() < 1e-12
