@@ -209,8 +209,9 @@ void edx_lanczos_default_opts(edx_lanczos_opts* o);
 #define EDX_WS_GREEN 1
 
 /* Device workspace bytes for edx_lanczos_ground_state (what = EDX_WS_LANCZOS,
- * n = niter), edx_green_cf (what = EDX_WS_GREEN, n = ngf) or edx_chi
- * (what = EDX_WS_CHI = 3, n = ngf). */
+ * n = niter), edx_green_cf (what = EDX_WS_GREEN, n = ngf), edx_chi and
+ * edx_chi_exciton (what = EDX_WS_CHI = 3, n = ngf) or edx_chi_pair
+ * (what = EDX_WS_PAIR = 4, n = ngf). */
 size_t edx_workspace_bytes(const edx_sector* s, int32_t what, int32_t vtype,
                            int32_t n);
 
@@ -344,6 +345,29 @@ typedef struct {
 edx_status edx_chi(const edx_sector* s, const void* psi0, double e0, const double* cu,
                    const double* cd, const edx_gf_opts* opts, void* ws, size_t ws_bytes,
                    double* chi_host, edx_chi_report* rep, void* stream);
+
+/* Excitonic susceptibility at T = 0 (the same form as edx_chi): O = sum_sigma
+ * (c+_{a sigma} c_{b sigma} + c+_{b sigma} c_{a sigma}) for impurity orbitals
+ * a != b, which keeps the sector.  Total-N sectors without phonons (it moves
+ * electrons between orbitals, so an orbital-resolved sector is refused with
+ * EDX_E_UNSUPPORTED).  Workspace as for edx_chi (EDX_WS_CHI). */
+edx_status edx_chi_exciton(const edx_sector* s, const void* psi0, double e0, int32_t a,
+                           int32_t b, const edx_gf_opts* opts, void* ws, size_t ws_bytes,
+                           double* chi_host, edx_chi_report* rep, void* stream);
+
+/* Pair susceptibility at T = 0 (eq. KLgf with the bosonic sign), O =
+ * c_{a dw} c_{a up} of impurity orbital a:
+ *   C(i nu_n) = <O 1/(z - (H - E0)) O+> - <O+ 1/(z + (H - E0)) O>,  z = i 2 n pi / beta,
+ * from ngf plain Lanczos steps in each of the sectors (N_up + 1, N_dw + 1) and
+ * (N_up - 1, N_dw - 1) (orbital-resolved: orbital a's two counts +-1), built on
+ * first use and kept with `gs`, and the two continued fractions (the second
+ * with a minus sign).  rep: wp = |O+ psi0|^2, wh = |O psi0|^2 and the lengths.
+ * Sectors with phonons -> EDX_E_UNSUPPORTED.  Workspace: edx_workspace_bytes
+ * with what = EDX_WS_PAIR. */
+#define EDX_WS_PAIR 4
+edx_status edx_chi_pair(const edx_sector* gs, const void* psi0, double e0, int32_t a,
+                        const edx_gf_opts* opts, void* ws, size_t ws_bytes, double* chi_host,
+                        edx_gf_report* rep, void* stream);
 
 /* ---- finite temperature: the eigenstate list (Sec. 5 "Eigenspace class"
  * and the thermal form of "Dynamical correlation functions") ----

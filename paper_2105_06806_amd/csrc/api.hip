@@ -295,6 +295,7 @@ size_t edx_workspace_bytes(const edx_sector* s, int32_t what, int32_t vtype, int
   if (what == EDX_WS_GREEN) return green_workspace_bytes(s, vtype, n);
   if (what == 2) return lanczos_workspace_bytes(s, vtype, n, 2);   // full re-orthogonalisation
   if (what == EDX_WS_CHI) return chi_workspace_bytes(s, vtype, n);
+  if (what == EDX_WS_PAIR) return pair_workspace_bytes(s, vtype, n);
   return 0;
 }
 
@@ -357,6 +358,40 @@ edx_status edx_chi(const edx_sector* s, const void* psi0, double e0, const doubl
   }
   return chi_impl(s, psi0, e0, c, opts, ws, ws_bytes, chi_host, rep,
                   static_cast<hipStream_t>(stream));
+}
+
+edx_status edx_chi_exciton(const edx_sector* s, const void* psi0, double e0, int32_t a,
+                           int32_t b, const edx_gf_opts* opts, void* ws, size_t ws_bytes,
+                           double* chi_host, edx_chi_report* rep, void* stream) {
+  EDX_TRY(check_sector(s));
+  if (!psi0 || !opts || !ws || !chi_host) return invalid("psi0, opts, ws and chi_host must be non-NULL");
+  if (!valid_vtype(opts->vtype)) return invalid("vtype must be EDX_F64 or EDX_F32");
+  if (opts->ngf > 4096) return invalid("ngf must be <= 4096");
+  if (a < 0 || b < 0 || a >= s->model.norb || b >= s->model.norb || a == b)
+    return invalid("a and b must be two different orbitals");
+  if (s->orb || s->dph > 1) {
+    set_error("chi_exciton: needs a total-N sector without phonons");
+    return EDX_E_UNSUPPORTED;
+  }
+  DiagCoef c{};
+  return chi_impl(s, psi0, e0, c, opts, ws, ws_bytes, chi_host, rep,
+                  static_cast<hipStream_t>(stream), 1, std::min(a, b), std::max(a, b));
+}
+
+edx_status edx_chi_pair(const edx_sector* gs, const void* psi0, double e0, int32_t a,
+                        const edx_gf_opts* opts, void* ws, size_t ws_bytes, double* chi_host,
+                        edx_gf_report* rep, void* stream) {
+  EDX_TRY(check_sector(gs));
+  if (!psi0 || !opts || !ws || !chi_host) return invalid("psi0, opts, ws and chi_host must be non-NULL");
+  if (!valid_vtype(opts->vtype)) return invalid("vtype must be EDX_F64 or EDX_F32");
+  if (opts->ngf > 4096) return invalid("ngf must be <= 4096");
+  if (a < 0 || a >= gs->model.norb) return invalid("orbital out of range");
+  if (gs->dph > 1) {
+    set_error("chi_pair: sectors with phonons are not supported");
+    return EDX_E_UNSUPPORTED;
+  }
+  return pair_impl(gs, psi0, e0, a, opts, ws, ws_bytes, chi_host, rep,
+                   static_cast<hipStream_t>(stream));
 }
 
 edx_status edx_green_cf(const edx_sector* gs, const void* psi0, double e0, int32_t orb,

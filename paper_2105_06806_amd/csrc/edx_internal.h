@@ -145,6 +145,8 @@ struct edx_sector {
   std::mutex nb_mu;
   edx_sector* nb[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
   edx_sector* nb_orb[2][edx::kMaxNorb][2] = {};
+  // sectors of the pair operators: [orbital (0 for a total-N sector)][+2 / -2]
+  edx_sector* nb_pair[edx::kMaxNorb][2] = {};
   bool orb = false;          // orbital-resolved sector (per-orbital counts)
 };
 
@@ -241,7 +243,14 @@ edx_status k_apply_op(const edx_sector* src, const edx_sector* dst, int vtype,
 edx_status k_green_cf(const double* ap, const double* bp, int np, double wp,
                       const double* ah, const double* bh, int nh, double wh,
                       double e0, double beta, int lmats, double* g,
-                      hipStream_t st);
+                      hipStream_t st, int bosonic = 0);
+// phi = (O_exc - *mean) psi (or partials of <psi|O_exc|psi> when mean == nullptr),
+// O_exc = sum_sigma (c+_a c_b + c+_b c_a), impurity levels a < b, same sector
+edx_status k_exc_apply(const edx_sector* s, int vtype, const void* psi, void* phi, int a,
+                       int b, const double* mean, double* partial, int nblocks, hipStream_t st);
+// phi (sector dst) = c+_{a up} c+_{a dw} psi (create) or c_{a dw} c_{a up} psi
+edx_status k_pair_apply(const edx_sector* src, const edx_sector* dst, int vtype, const void* psi,
+                        void* phi, int a, int create, hipStream_t st);
 
 // ---- batch.hip
 edx_status batch_run(const edx_sector* const* secs, int n, const edx_lanczos_opts* o,
@@ -268,9 +277,14 @@ edx_status green_cf_impl(const edx_sector* gs, const void* psi0, double e0, int 
                          const edx_gf_opts* o, void* ws, size_t ws_bytes, double* g_host,
                          edx_gf_report* rep, hipStream_t st);
 size_t chi_workspace_bytes(const edx_sector* s, int vtype, int ngf);
+// op 0: diagonal density operator c; op 1: excitonic operator of levels a < b
 edx_status chi_impl(const edx_sector* s, const void* psi0, double e0, const DiagCoef& c,
                     const edx_gf_opts* o, void* ws, size_t ws_bytes, double* chi_host,
-                    edx_chi_report* rep, hipStream_t st);
+                    edx_chi_report* rep, hipStream_t st, int op = 0, int a = 0, int b = 1);
+size_t pair_workspace_bytes(const edx_sector* s, int vtype, int ngf);
+edx_status pair_impl(const edx_sector* gs, const void* psi0, double e0, int a,
+                     const edx_gf_opts* o, void* ws, size_t ws_bytes, double* chi_host,
+                     edx_gf_report* rep, hipStream_t st);
 // ---- lanczos.cpp (host)
 double tridiag_lowest(const double* a, const double* b, int m, int k);
 void tridiag_vector(const double* a, const double* b, int m, double lam,

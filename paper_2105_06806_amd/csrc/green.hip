@@ -95,13 +95,102 @@ __global__ __launch_bounds__(256) void k_diag_op(const T* __restrict__ psi, T* _
   if (threadIdx.x == 0) partial[blockIdx.x] = s;
 }
 
+// Excitonic operator O = sum_sigma (c+_a c_b + c+_b c_a) (impurity levels a < b,
+// same spin): each output string t with exactly one of bits a, b set receives
+// psi of t with that electron moved, signed by the occupied levels strictly
+// between a and b (unchanged by the move).  Both spins; psi dense, phi padded
+// (zero padding); mean == nullptr: only partial sums of <psi|O|psi>; otherwise
+// phi = (O - mean) psi and partial sums of |phi|^2.
+template <typename T>
+__global__ __launch_bounds__(256) void k_exc_op(const T* __restrict__ psi, T* __restrict__ phi,
+                                                int64_t dup, int64_t ld, int64_t len,
+                                                const uint32_t* __restrict__ umap,
+                                                const int32_t* __restrict__ urank,
+                                                const uint32_t* __restrict__ dmap,
+                                                const int32_t* __restrict__ drank, int a, int b,
+                                                const double* __restrict__ mean,
+                                                double* __restrict__ partial) {
+  __shared__ double red[4];
+  const uint32_t mab = (1u << a) | (1u << b);
+  const uint32_t between = ((1u << b) - 1u) & ~((2u << a) - 1u);
+  const double mu = mean ? *mean : 0.0;
+  double acc = 0.0;
+  for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < len;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t id = idx / ld;
+    const int64_t iu = idx - id * ld;
+    if (iu >= dup) {
+      if (mean) phi[idx] = T(0);
+      continue;
+    }
+    double val = 0.0;
+    const uint32_t tu = umap[iu], td = dmap[id];
+    if (__popc(tu & mab) == 1) {
+      const double x = (double)psi[urank[tu ^ mab] + id * dup];
+      val += (__popc(tu & between) & 1) ? -x : x;
+    }
+    if (__popc(td & mab) == 1) {
+      const double x = (double)psi[iu + (int64_t)drank[td ^ mab] * dup];
+      val += (__popc(td & between) & 1) ? -x : x;
+    }
+    const double x0 = (double)psi[iu + id * dup];
+    if (mean) {
+      const T t = (T)(val - mu * x0);
+      phi[idx] = t;
+      acc += (double)t * (double)t;
+    } else {
+      acc += x0 * val;
+    }
+  }
+  const double s = block_sum(acc, red);
+  if (threadIdx.x == 0) partial[blockIdx.x] = s;
+}
+
+// Pair operators of impurity level a: create = c+_{a up} c+_{a dw} (the spin-down
+// creator acts first), else c_{a dw} c_{a up} (the spin-up annihilator first).
+// Gather form from the target sector: the source strings are the target's
+// with bit a toggled in both spins; the full-string sign counts the occupied
+// levels below a of each spin and, for the spin-down operator, every spin-up
+// electron present when it acts.
+template <typename T>
+__global__ __launch_bounds__(256) void k_pair(const T* __restrict__ psi, T* __restrict__ phi,
+                                              int64_t tdup, int64_t tld, int64_t tlen,
+                                              int64_t sdup, const uint32_t* __restrict__ tumap,
+                                              const uint32_t* __restrict__ tdmap,
+                                              const int32_t* __restrict__ surank,
+                                              const int32_t* __restrict__ sdrank, int a,
+                                              int create, int nup_src) {
+  const uint32_t bit = 1u << a, below = bit - 1u;
+  for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < tlen;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t id = idx / tld;
+    const int64_t iu = idx - id * tld;
+    if (iu >= tdup) {
+      phi[idx] = T(0);
+      continue;
+    }
+    const uint32_t tu = tumap[iu], td = tdmap[id];
+    const bool want = create != 0;
+    T val = T(0);
+    if (((tu & bit) != 0u) == want && ((td & bit) != 0u) == want) {
+      const uint32_t su = tu ^ bit, sd = td ^ bit;
+      const int nup_dw_op = create ? nup_src : nup_src - 1;   // spin-up count when c_dw acts
+      const int par = (__popc(tu & below) + __popc(td & below) + nup_dw_op) & 1;
+      const T x = psi[surank[su] + (int64_t)sdrank[sd] * sdup];
+      val = par ? -x : x;
+    }
+    phi[idx] = val;
+  }
+}
+
 __global__ void k_cf(const double* __restrict__ ap, const double* __restrict__ bp, int np,
                      double wp, const double* __restrict__ ah, const double* __restrict__ bh,
                      int nh, double wh, double e0, double beta, int lmats,
-                     double* __restrict__ g) {
+                     double* __restrict__ g, int bosonic) {
   const int n = blockIdx.x * blockDim.x + threadIdx.x;
   if (n >= lmats) return;
-  const double wn = (2.0 * n + 1.0) * M_PI / beta;
+  // fermionic (2n+1) pi / beta, or bosonic 2n pi / beta
+  const double wn = (2.0 * n + (bosonic ? 0.0 : 1.0)) * M_PI / beta;
   double gr = 0.0, gi = 0.0;
   for (int br = 0; br < 2; ++br) {
     const double* a = br == 0 ? ap : ah;
@@ -165,12 +254,44 @@ edx_status k_diag_apply(const edx_sector* s, int vtype, const void* psi, void* p
   return EDX_OK;
 }
 
+edx_status k_exc_apply(const edx_sector* s, int vtype, const void* psi, void* phi, int a,
+                       int b, const double* mean, double* partial, int nblocks, hipStream_t st) {
+  const int64_t n = s->vlen;
+  if (vtype == EDX_F64)
+    hipLaunchKernelGGL(k_exc_op<double>, dim3(nblocks), dim3(256), 0, st, (const double*)psi,
+                       (double*)phi, s->dup, s->ld, n, s->up.map, s->up.rank, s->dw.map,
+                       s->dw.rank, a, b, mean, partial);
+  else
+    hipLaunchKernelGGL(k_exc_op<float>, dim3(nblocks), dim3(256), 0, st, (const float*)psi,
+                       (float*)phi, s->dup, s->ld, n, s->up.map, s->up.rank, s->dw.map,
+                       s->dw.rank, a, b, mean, partial);
+  EDX_HIP(hipGetLastError());
+  return EDX_OK;
+}
+
+edx_status k_pair_apply(const edx_sector* src, const edx_sector* dst, int vtype, const void* psi,
+                        void* phi, int a, int create, hipStream_t st) {
+  const int64_t n = dst->vlen;
+  const int64_t b = (n + 255) / 256;
+  const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(b, 8192));
+  if (vtype == EDX_F64)
+    hipLaunchKernelGGL(k_pair<double>, dim3(grid), dim3(256), 0, st, (const double*)psi,
+                       (double*)phi, dst->dup, dst->ld, n, src->dup, dst->up.map, dst->dw.map,
+                       src->up.rank, src->dw.rank, a, create, src->nup);
+  else
+    hipLaunchKernelGGL(k_pair<float>, dim3(grid), dim3(256), 0, st, (const float*)psi,
+                       (float*)phi, dst->dup, dst->ld, n, src->dup, dst->up.map, dst->dw.map,
+                       src->up.rank, src->dw.rank, a, create, src->nup);
+  EDX_HIP(hipGetLastError());
+  return EDX_OK;
+}
+
 edx_status k_green_cf(const double* ap, const double* bp, int np, double wp, const double* ah,
                       const double* bh, int nh, double wh, double e0, double beta, int lmats,
-                      double* g, hipStream_t st) {
+                      double* g, hipStream_t st, int bosonic) {
   const int grid = (lmats + 255) / 256;
   hipLaunchKernelGGL(k_cf, dim3(grid), dim3(256), 0, st, ap, bp, np, wp, ah, bh, nh, wh, e0,
-                     beta, lmats, g);
+                     beta, lmats, g, bosonic);
   EDX_HIP(hipGetLastError());
   return EDX_OK;
 }

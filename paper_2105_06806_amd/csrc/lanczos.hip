@@ -876,9 +876,24 @@ size_t chi_workspace_bytes(const edx_sector* s, int vtype, int ngf) {
                            nullptr) + 512;
 }
 
+// O psi0 - <O> psi0 for a Hermitian operator that keeps the sector: op 0 the
+// diagonal density operator c, op 1 the excitonic operator of levels (a, b)
+static edx_status chi_start(const edx_sector* s, int vtype, const void* psi0, int op,
+                            const DiagCoef& c, int a, int b, void* phi, double* partial,
+                            double* mean, int nb, hipStream_t st) {
+  if (op == 0) {
+    EDX_TRY(k_diag_apply(s, vtype, psi0, phi, c, nullptr, partial, nb, st));
+    EDX_TRY(k_reduce(partial, nb, 1, mean, st));
+    return k_diag_apply(s, vtype, psi0, phi, c, mean, partial, nb, st);
+  }
+  EDX_TRY(k_exc_apply(s, vtype, psi0, phi, a, b, nullptr, partial, nb, st));
+  EDX_TRY(k_reduce(partial, nb, 1, mean, st));
+  return k_exc_apply(s, vtype, psi0, phi, a, b, mean, partial, nb, st);
+}
+
 edx_status chi_impl(const edx_sector* s, const void* psi0, double e0, const DiagCoef& c,
                     const edx_gf_opts* o, void* ws, size_t ws_bytes, double* chi_host,
-                    edx_chi_report* rep, hipStream_t st) {
+                    edx_chi_report* rep, hipStream_t st, int op, int a, int b) {
   const int vtype = o->vtype;
   const int ngf = o->ngf;
   if (o->lmats < 1 || o->lmats > kMaxLmats || ngf < 1 || !(o->beta > 0.0)) {
@@ -896,9 +911,7 @@ edx_status chi_impl(const edx_sector* s, const void* psi0, double e0, const Diag
   const int64_t n = s->vlen;
   const int nb = elem_blocks(n);
   // phi_0 = (O - <O>) psi0 in the padded layout
-  EDX_TRY(k_diag_apply(s, vtype, psi0, L.vec, c, nullptr, L.partial, nb, st));
-  EDX_TRY(k_reduce(L.partial, nb, 1, L.coef, st));
-  EDX_TRY(k_diag_apply(s, vtype, psi0, L.vec, c, L.coef, L.partial, nb, st));
+  EDX_TRY(chi_start(s, vtype, psi0, op, c, a, b, L.vec, L.partial, L.coef, nb, st));
   EDX_TRY(k_beta_finish(L.partial, nb, L.beta, L.scale, st));
   double h[2] = {0.0, 0.0};
   EDX_HIP(hipMemcpyAsync(h, L.beta, sizeof(double), hipMemcpyDeviceToHost, st));
@@ -956,6 +969,143 @@ edx_status chi_impl(const edx_sector* s, const void* psi0, double e0, const Diag
     rep->mean = h[1];
     rep->n = len;
     rep->dropped = dropped;
+  }
+  return EDX_OK;
+}
+
+// ---------------------------------------------------------------- pair susceptibility
+// Sectors reached by the pair operators of orbital a: (N_up + 1, N_dw + 1) for
+// c+_{a up} c+_{a dw} (k = 0) and (N_up - 1, N_dw - 1) for c_{a dw} c_{a up}
+// (k = 1); in an orbital-resolved sector only orbital a's two counts change.
+static edx_status ensure_pair_neighbours(const edx_sector* gs, int a, hipStream_t st) {
+  edx_sector* g = const_cast<edx_sector*>(gs);
+  std::lock_guard<std::mutex> lk(g->nb_mu);
+  edx_sector** slot = g->nb_pair[g->orb ? a : 0];
+  const Allocator* alloc = gs->alloc.alloc ? &gs->alloc : nullptr;
+  for (int k = 0; k < 2; ++k) {
+    if (slot[k]) continue;
+    const int d = k == 0 ? 1 : -1;
+    edx_sector* t = nullptr;
+    if (gs->orb) {
+      int cu[kMaxNorb], cd[kMaxNorb];
+      for (int q = 0; q < kMaxNorb; ++q) {
+        cu[q] = gs->up.counts[q];
+        cd[q] = gs->dw.counts[q];
+      }
+      cu[a] += d;
+      cd[a] += d;
+      const int top = gs->model.nbath + 1;
+      if (cu[a] < 0 || cd[a] < 0 || cu[a] > top || cd[a] > top) continue;
+      EDX_TRY(build_sector_impl(gs->model, gs->nup + d, gs->ndw + d, st, &t, alloc, cu, cd));
+    } else {
+      const int nu = gs->nup + d, nd = gs->ndw + d;
+      if (nu < 0 || nd < 0 || nu > gs->model.ns || nd > gs->model.ns) continue;
+      EDX_TRY(build_sector_impl(gs->model, nu, nd, st, &t, alloc));
+    }
+    slot[k] = t;
+  }
+  return EDX_OK;
+}
+
+size_t pair_workspace_bytes(const edx_sector* s, int vtype, int ngf) {
+  auto comb = [](int nn, int k) -> int64_t {
+    if (k < 0 || k > nn) return 0;
+    int64_t r = 1;
+    for (int i = 1; i <= k; ++i) r = r * (nn - k + i) / i;
+    return r;
+  };
+  const int ns = s->model.ns;
+  int64_t dmax = 1, ddw_max = 1;
+  for (int d : {-1, 1}) {
+    dmax = std::max(dmax, vec_ld(comb(ns, s->nup + d)) * comb(ns, s->ndw + d));
+    ddw_max = std::max(ddw_max, comb(ns, s->ndw + d));
+  }
+  const int hvb = (int)std::max<int64_t>(kMaxPartials, ddw_max + 8 + kNdMaxBlocks);
+  return lanczos_ws_layout(dmax, vtype, ngf, 0, hvb, false, nullptr, nullptr) +
+         sizeof(double) * (2 * kMaxLmats + 4 * (ngf + 1)) + 512;
+}
+
+edx_status pair_impl(const edx_sector* gs, const void* psi0, double e0, int a,
+                     const edx_gf_opts* o, void* ws, size_t ws_bytes, double* chi_host,
+                     edx_gf_report* rep, hipStream_t st) {
+  const int vtype = o->vtype;
+  const int ngf = o->ngf;
+  if (o->lmats < 1 || o->lmats > kMaxLmats || ngf < 1 || !(o->beta > 0.0)) {
+    set_error("chi_pair: need 1 <= lmats <= 65536, ngf >= 1, beta > 0");
+    return EDX_E_INVALID;
+  }
+  const size_t need = pair_workspace_bytes(gs, vtype, ngf);
+  if (need > ws_bytes) {
+    set_error("chi_pair: workspace too small (need " + std::to_string(need) + " bytes)");
+    return EDX_E_NOMEM;
+  }
+  EDX_TRY(ensure_pair_neighbours(gs, a, st));
+  edx_sector* const* nbs = gs->nb_pair[gs->orb ? a : 0];
+  char* base = reinterpret_cast<char*>(align_up(reinterpret_cast<uintptr_t>(ws)));
+  double w[2] = {0.0, 0.0};
+  int nlen[2] = {0, 0};
+  std::vector<double> ha[2], hb[2];
+  for (int br = 0; br < 2; ++br) {
+    const edx_sector* t = nbs[br];
+    if (!t) continue;
+    LanczosWs L;
+    lanczos_ws_layout(t->vlen, vtype, ngf, 0, hv_partial_blocks(t, vtype), false, base, &L);
+    EDX_TRY(k_pair_apply(gs, t, vtype, psi0, L.vec, a, br == 0 ? 1 : 0, st));
+    EDX_TRY(k_norm2(vtype, L.vec, t->vlen, L.partial, st));
+    EDX_TRY(k_beta_finish(L.partial, elem_blocks(t->vlen), L.beta, L.scale, st));
+    double nrm = 0.0;
+    EDX_HIP(hipMemcpyAsync(&nrm, L.beta, sizeof(double), hipMemcpyDeviceToHost, st));
+    EDX_HIP(hipStreamSynchronize(st));
+    w[br] = nrm * nrm;
+    if (!(nrm > 0.0)) continue;
+    EDX_HIP(hipMemsetAsync(L.beta, 0, sizeof(double), st));
+    for (int j = 0; j < ngf; ++j)
+      EDX_TRY(lanczos_step(t, vtype, L, j, 0, L.alpha, L.beta, L.scale, nullptr, nullptr, st));
+    ha[br].resize(ngf + 1);
+    hb[br].resize(ngf + 1);
+    EDX_HIP(hipMemcpyAsync(ha[br].data(), L.alpha, sizeof(double) * ngf, hipMemcpyDeviceToHost, st));
+    EDX_HIP(hipMemcpyAsync(hb[br].data(), L.beta, sizeof(double) * (ngf + 1), hipMemcpyDeviceToHost,
+                           st));
+    EDX_HIP(hipStreamSynchronize(st));
+    double tn = 0.0;
+    int len = ngf;
+    for (int j = 0; j < ngf; ++j) {
+      tn = std::max(tn, std::fabs(ha[br][j]) + hb[br][j] + hb[br][j + 1]);
+      if (j + 1 < ngf && !(hb[br][j + 1] > 1e-12 * tn)) {
+        len = j + 1;
+        break;
+      }
+    }
+    nlen[br] = len;
+  }
+  size_t off = 0;
+  for (int br = 0; br < 2; ++br) {
+    const edx_sector* t = nbs[br];
+    off = std::max(off, lanczos_ws_layout(t ? t->vlen : 1, vtype, ngf, 0,
+                                          t ? hv_partial_blocks(t, vtype) : 1, false, nullptr,
+                                          nullptr));
+  }
+  double* gdev = reinterpret_cast<double*>(base + off);
+  double* cdev = gdev + 2 * kMaxLmats;
+  std::vector<double> coeff(4 * (ngf + 1), 0.0);
+  for (int br = 0; br < 2; ++br) {
+    if (nlen[br] == 0) continue;
+    std::copy(ha[br].begin(), ha[br].begin() + nlen[br], coeff.begin() + (2 * br) * (ngf + 1));
+    std::copy(hb[br].begin() + 1, hb[br].begin() + 1 + nlen[br],
+              coeff.begin() + (2 * br + 1) * (ngf + 1));
+  }
+  EDX_HIP(hipMemcpyAsync(cdev, coeff.data(), sizeof(double) * coeff.size(), hipMemcpyHostToDevice,
+                         st));
+  // bosonic: the hole branch enters with a minus sign, nu_n = 2 n pi / beta
+  EDX_TRY(k_green_cf(cdev, cdev + (ngf + 1), nlen[0], w[0], cdev + 2 * (ngf + 1),
+                     cdev + 3 * (ngf + 1), nlen[1], -w[1], e0, o->beta, o->lmats, gdev, st, 1));
+  EDX_HIP(hipMemcpyAsync(chi_host, gdev, sizeof(double) * 2 * o->lmats, hipMemcpyDeviceToHost, st));
+  EDX_HIP(hipStreamSynchronize(st));
+  if (rep) {
+    rep->wp = w[0];
+    rep->wh = w[1];
+    rep->np = nlen[0];
+    rep->nh = nlen[1];
   }
   return EDX_OK;
 }

@@ -269,6 +269,8 @@ void destroy_sector(edx_sector* s) {
     for (int k = 0; k < 2; ++k) {
       destroy_sector(s->nb[sp][k]);
       for (int a = 0; a < kMaxNorb; ++a) destroy_sector(s->nb_orb[sp][a][k]);
+      destroy_sector(s->nb_pair[sp][k]);
+      if (sp == 0) destroy_sector(s->nb_pair[2][k]);
     }
   const bool shared = (s->dw.map == s->up.map);
   free_spin(s, s->up);

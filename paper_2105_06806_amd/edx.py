@@ -150,6 +150,8 @@ _SIGS = {
     "edx_transpose": (ctypes.c_int, [ctypes.c_int, _P, ctypes.c_int64, ctypes.c_int64, ctypes.c_int64, _P, ctypes.c_int64, ctypes.c_int32, _P]),
     "edx_tridiag_spectrum": (ctypes.c_int, [_P, _P, ctypes.c_int32, _P, _P]),
     "edx_chi": (ctypes.c_int, [_P, _P, ctypes.c_double, _P, _P, ctypes.POINTER(GfOpts), _P, ctypes.c_size_t, _P, ctypes.POINTER(ChiReport), _P]),
+    "edx_chi_exciton": (ctypes.c_int, [_P, _P, ctypes.c_double, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(GfOpts), _P, ctypes.c_size_t, _P, ctypes.POINTER(ChiReport), _P]),
+    "edx_chi_pair": (ctypes.c_int, [_P, _P, ctypes.c_double, ctypes.c_int32, ctypes.POINTER(GfOpts), _P, ctypes.c_size_t, _P, ctypes.POINTER(GfReport), _P]),
     "edx_espace_chi_workspace_bytes": (ctypes.c_size_t, [_P, ctypes.c_int32]),
     "edx_espace_chi": (ctypes.c_int, [_P, _P, _P, ctypes.POINTER(GfOpts), _P, ctypes.c_size_t, _P, _P]),
     "edx_green_cf": (ctypes.c_int, [_P, _P, ctypes.c_double, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(GfOpts), _P, ctypes.c_size_t, _P, ctypes.POINTER(GfReport), _P]),
@@ -592,6 +594,34 @@ def chi(sector, psi0, e0, cu, cd, ngf=200, beta=200.0, lmats=1024, ws=None, stre
                        cd.ctypes.data_as(_P), ctypes.byref(o), _P(ws.data_ptr()), ws.numel(),
                        g.ctypes.data_as(_P), ctypes.byref(rep), _stream_ptr(stream)))
     return g[0::2] + 1j * g[1::2], {f: getattr(rep, f) for f, _ in ChiReport._fields_}
+
+
+def chi_exciton(sector, psi0, e0, a, b, ngf=200, beta=200.0, lmats=1024, ws=None, stream=None):
+    """Excitonic susceptibility of orbitals a != b (complex numpy) and report."""
+    vtype = _vtype_of(psi0)
+    o = GfOpts(int(ngf), int(lmats), vtype, 0, float(beta))
+    if ws is None:
+        ws = alloc_workspace(workspace_bytes(sector, 3, vtype, ngf))
+    g = np.zeros(2 * lmats, np.float64)
+    rep = ChiReport()
+    _check(lib.edx_chi_exciton(sector.handle, _P(psi0.data_ptr()), float(e0), int(a), int(b),
+                               ctypes.byref(o), _P(ws.data_ptr()), ws.numel(), g.ctypes.data_as(_P),
+                               ctypes.byref(rep), _stream_ptr(stream)))
+    return g[0::2] + 1j * g[1::2], {f: getattr(rep, f) for f, _ in ChiReport._fields_}
+
+
+def chi_pair(sector, psi0, e0, a, ngf=200, beta=200.0, lmats=1024, ws=None, stream=None):
+    """Pair susceptibility of orbital a (complex numpy) and report."""
+    vtype = _vtype_of(psi0)
+    o = GfOpts(int(ngf), int(lmats), vtype, 0, float(beta))
+    if ws is None:
+        ws = alloc_workspace(workspace_bytes(sector, 4, vtype, ngf))
+    g = np.zeros(2 * lmats, np.float64)
+    rep = GfReport()
+    _check(lib.edx_chi_pair(sector.handle, _P(psi0.data_ptr()), float(e0), int(a), ctypes.byref(o),
+                            _P(ws.data_ptr()), ws.numel(), g.ctypes.data_as(_P), ctypes.byref(rep),
+                            _stream_ptr(stream)))
+    return g[0::2] + 1j * g[1::2], {"wp": rep.wp, "wh": rep.wh, "np": rep.np, "nh": rep.nh}
 
 
 def _handles(sectors):

@@ -288,3 +288,66 @@ def test_espace_thermal_chi_whole_fock_space(edx):
         ref = ochi.chi_double_sum(m, secs, cu, cd, z, beta)
         got = E.chi(cu, cd, ngf=60, lmats=24)
         assert np.abs(got - ref).max() <= 1e-8 * np.abs(ref).max(), cu
+
+
+EXC_CASES = [
+    ("o2", inputs.make_model(2, 3, 3.0, Jh=0.5, seed=96, symmetric=False), (4, 3), 0, 1),
+    ("o3_02", inputs.make_model(3, 1, 2.5, Jh=0.4, seed=97, symmetric=False), (3, 3), 0, 2),
+    ("o2_kanamori", inputs.make_model(2, 2, 3.0, Jh=0.5, seed=98, symmetric=False, Jx=0.5, Jp=0.5),
+     (3, 3), 1, 0),
+]
+
+
+@pytest.mark.parametrize("name,m,sec,a,b", EXC_CASES, ids=[c[0] for c in EXC_CASES])
+def test_chi_exciton_fp64(edx, name, m, sec, a, b):
+    from oracle import chi as ochi
+    w = np.linalg.eigvalsh(fock.explicit_hamiltonian(m, *sec).toarray())
+    assert w[1] - w[0] > 1e-6
+    S = edx.build_sector(m, *sec)
+    e0, psi, _, _ = edx.lanczos_ground_state(S, niter=400, tol=1e-14, rtol=1e-11, seed=6,
+                                             allow=(edx.EDX_E_DEGENERATE,))
+    z = 1j * ochi.bosonic(50.0, 48)
+    ref, _ = ochi.chi_exciton_exact(m, *sec, a, b, z)
+    got, r = edx.chi_exciton(S, psi, e0, a, b, ngf=250, beta=50.0, lmats=48)
+    assert np.abs(got - ref).max() <= 1e-8 * np.abs(ref).max(), r
+
+
+PAIR_CASES = [
+    ("ns8", inputs.workload("ns8")[0], (4, 4), 0),
+    ("o2_orb1", inputs.make_model(2, 2, 3.0, Jh=0.5, seed=99, symmetric=False), (3, 2), 1),
+    ("o2_kanamori", inputs.make_model(2, 2, 3.0, Jh=0.5, seed=98, symmetric=False, Jx=0.5, Jp=0.5),
+     (3, 3), 0),
+    ("orbital", inputs.make_model(2, 3, 2.5, Jh=0.4, seed=94, symmetric=False), ((2, 2), (1, 3)), 0),
+    ("empty_branch", inputs.make_model(1, 3, 2.0, seed=100, symmetric=False), (4, 1), 0),
+]
+
+
+@pytest.mark.parametrize("name,m,sec,a", PAIR_CASES, ids=[c[0] for c in PAIR_CASES])
+def test_chi_pair_fp64(edx, name, m, sec, a):
+    from oracle import chi as ochi
+    w = np.linalg.eigvalsh(fock.explicit_hamiltonian(m, *sec).toarray())
+    assert w[1] - w[0] > 1e-6
+    S = _sector(edx, m, sec)
+    e0, psi, _, _ = edx.lanczos_ground_state(S, niter=400, tol=1e-14, rtol=1e-11, seed=7,
+                                             allow=(edx.EDX_E_DEGENERATE,))
+    z = 1j * ochi.bosonic(50.0, 48)
+    ref, _ = ochi.chi_pair_exact(m, *sec, a, z)
+    got, r = edx.chi_pair(S, psi, e0, a, ngf=250, beta=50.0, lmats=48)
+    assert np.abs(got - ref).max() <= 1e-8 * np.abs(ref).max(), r
+
+
+def test_chi_exciton_pair_reject(edx):
+    m = inputs.make_model(2, 3, 2.5, Jh=0.4, seed=94, symmetric=False)
+    S = edx.build_sector_orbital(m, (2, 2), (1, 3))
+    e0, psi, _, _ = edx.lanczos_ground_state(S, niter=200, tol=1e-12, seed=1,
+                                             allow=(edx.EDX_E_DEGENERATE,))
+    with pytest.raises(edx.EdxError) as e:
+        edx.chi_exciton(S, psi, e0, 0, 1, ngf=20, beta=10.0, lmats=8)
+    assert e.value.status == edx.EDX_E_UNSUPPORTED
+    S2 = edx.build_sector(m, 4, 3)
+    e0, psi, _, _ = edx.lanczos_ground_state(S2, niter=200, tol=1e-12, seed=1,
+                                             allow=(edx.EDX_E_DEGENERATE,))
+    with pytest.raises(edx.EdxError):
+        edx.chi_exciton(S2, psi, e0, 1, 1, ngf=20, beta=10.0, lmats=8)
+    with pytest.raises(edx.EdxError):
+        edx.chi_pair(S2, psi, e0, 2, ngf=20, beta=10.0, lmats=8)
