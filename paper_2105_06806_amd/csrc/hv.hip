@@ -31,6 +31,7 @@
 // gathers are what bounds these kernels (load bandwidth between L2 and the
 // CUs), so the Krylov vectors of the library use such an ld.
 #include <algorithm>
+#include <cmath>
 #include <type_traits>
 #include <vector>
 
@@ -312,7 +313,8 @@ struct NdTab {
 // terms of the fused pass's staged table: H_nd, or with phonons the largest
 // per-slice table (H_nd + phonon terms)
 inline int nd_lds_terms(const edx_sector* s) {
-  return s->dph > 1 ? s->ph_nt_max : (s->nd ? s->nd_nt : 0);
+  if (!s->nd) return 0;   // phonons alone use the direct path, no table
+  return s->dph > 1 ? s->ph_nt_max : s->nd_nt;
 }
 
 template <typename T>
@@ -328,6 +330,22 @@ const double* wph<double>(const edx_sector* s) { return s->wph64; }
 template <>
 const float* wph<float>(const edx_sector* s) { return s->wph32; }
 
+// Holstein terms of one phonon slice p for the fused pass (Sec. "Electron-phonon
+// coupling"): (g(pu) + g(pd)) (sp v_{p-1} + sp1 v_{p+1}) at the element itself,
+// the neighbouring slices `slice` elements away; g(pattern) = sum_a g_a n_a.
+template <typename T>
+struct PhArgs {
+  int64_t slice;   // elements per phonon slice (ld * D_dw)
+  T sp, sp1;       // sqrt(p), sqrt(p + 1)
+  T g0, g1, g2;    // couplings g_a
+  int lo, hi;      // slice p - 1 / p + 1 exists
+};
+
+template <typename T>
+__device__ __forceinline__ T gpat(const PhArgs<T>& ph, int pat) {
+  return ((pat & 1) ? ph.g0 : T(0)) + ((pat & 2) ? ph.g1 : T(0)) + ((pat & 4) ? ph.g2 : T(0));
+}
+
 template <typename T>
 const T* nd_amp(const edx_sector* s);
 template <>
@@ -342,13 +360,13 @@ inline size_t nd_tab_lds(int P, int nt, size_t tsz) {
   return al16((size_t)(P * P + 1) * 4) + al16((size_t)nt * 8) + al16((size_t)nt * tsz);
 }
 
-template <typename T, int WUP, int WDW, int NC, bool ND>
+template <typename T, int WUP, int WDW, int NC, bool ND, bool PH>
 __global__ __launch_bounds__(1024) void k_hv_fused(HvArgs<T> a, const T* __restrict__ v,
                                                    T* __restrict__ w,
                                                    const double* __restrict__ vscale,
                                                    double* __restrict__ partial, int order,
                                                    const int32_t* __restrict__ corder,
-                                                   NdTab<T> nd) {
+                                                   NdTab<T> nd, PhArgs<T> ph) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T* amp = reinterpret_cast<T*>(smem_raw);
   T* Wt = amp + kAmpTable;
@@ -402,11 +420,13 @@ __global__ __launch_bounds__(1024) void k_hv_fused(HvArgs<T> a, const T* __restr
   T gamp[NC][WDW];         // their amplitudes times the vector scale
   T ed[NC];
   int pd[NC];
+  T gd[NC];   // phonon coupling of the spin-down pattern (PH)
 #pragma unroll
   for (int c = 0; c < NC; ++c) {
     const int64_t j = jc[c];
     ed[c] = a.edw[j];
     pd[c] = a.pdw[j];
+    gd[c] = PH ? gpat(ph, pd[c]) : T(0);
 #pragma unroll
     for (int k = 0; k < WDW; ++k) {
       const uint32_t f = a.hdw[j * WDW + k];
@@ -435,6 +455,19 @@ __global__ __launch_bounds__(1024) void k_hv_fused(HvArgs<T> a, const T* __restr
       for (int c = 0; c < NC; ++c)
 #pragma unroll
         for (int k = 0; k < WDW; ++k) g[c][k] = gcol[c][k][iu32];
+      // phonon neighbours: the same element one slice back / ahead, issued
+      // with the gathers so that their latency overlaps
+      T pv[NC], pn[NC];
+#pragma unroll
+      for (int c = 0; c < NC; ++c) {
+        pv[c] = T(0);
+        pn[c] = T(0);
+        if constexpr (PH) {
+          const int64_t e0 = iu + jc[c] * ld;
+          if (ph.lo) pv[c] = v[e0 - ph.slice];
+          if (ph.hi) pn[c] = v[e0 + ph.slice];
+        }
+      }
       T acc[NC];
 #pragma unroll
       for (int c = 0; c < NC; ++c) acc[c] = T(0);
@@ -452,6 +485,7 @@ __global__ __launch_bounds__(1024) void k_hv_fused(HvArgs<T> a, const T* __restr
 #pragma unroll
         for (int k = 0; k < WDW; ++k) s2 += gamp[c][k] * g[c][k];
         T res = acc[c] + (eu + ed[c] + Wt[pu + pd[c]]) * x + s2;
+        if constexpr (PH) res += (gpat(ph, patu) + gd[c]) * (ph.sp * pv[c] + ph.sp1 * pn[c]) * sc;
         if constexpr (ND) {
           // spin exchange / pair hopping: sources near (iu, jc[c])
           const int key = patu * nd.P + pd[c];
@@ -769,16 +803,18 @@ struct FusedOrder {
   int order;
   const int32_t* corder;
   NdTab<T> nd;   // nd.nt = 0: no spin exchange / pair hopping in this pass
+  bool ph = false;   // phonon slice without H_nd: the direct phonon terms
+  PhArgs<T> pa{};
 };
 
-template <typename T, int WUP, int WDW, int NC, bool ND>
+template <typename T, int WUP, int WDW, int NC, bool ND, bool PH>
 edx_status launch_fused_n(const HvArgs<T>& a, int nblk, int nthr, size_t lds, hipStream_t st,
                           const T* v, T* w, const double* vscale, double* partial,
                           FusedOrder<T> fo, const NdTab<T>& nd) {
-  const void* kern = (const void*)k_hv_fused<T, WUP, WDW, NC, ND>;
+  const void* kern = (const void*)k_hv_fused<T, WUP, WDW, NC, ND, PH>;
   EDX_HIP(hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-  hipLaunchKernelGGL((k_hv_fused<T, WUP, WDW, NC, ND>), dim3(nblk), dim3(nthr), lds, st, a, v,
-                     w, vscale, partial, fo.order, fo.corder, nd);
+  hipLaunchKernelGGL((k_hv_fused<T, WUP, WDW, NC, ND, PH>), dim3(nblk), dim3(nthr), lds, st, a,
+                     v, w, vscale, partial, fo.order, fo.corder, nd, fo.pa);
   EDX_HIP(hipGetLastError());
   return EDX_OK;
 }
@@ -788,10 +824,13 @@ edx_status launch_fused_k(const HvArgs<T>& a, int nblk, int nthr, size_t lds, hi
                           const T* v, T* w, const double* vscale, double* partial,
                           FusedOrder<T> fo) {
   if (fo.nd.nt > 0)
-    return launch_fused_n<T, WUP, WDW, NC, true>(a, nblk, nthr, lds, st, v, w, vscale, partial,
-                                                 fo, fo.nd);
-  return launch_fused_n<T, WUP, WDW, NC, false>(a, nblk, nthr, lds, st, v, w, vscale, partial,
-                                                fo, fo.nd);
+    return launch_fused_n<T, WUP, WDW, NC, true, false>(a, nblk, nthr, lds, st, v, w, vscale,
+                                                        partial, fo, fo.nd);
+  if (fo.ph)
+    return launch_fused_n<T, WUP, WDW, NC, false, true>(a, nblk, nthr, lds, st, v, w, vscale,
+                                                        partial, fo, fo.nd);
+  return launch_fused_n<T, WUP, WDW, NC, false, false>(a, nblk, nthr, lds, st, v, w, vscale,
+                                                       partial, fo, fo.nd);
 }
 
 template <typename T, int WUP, int WDW>
@@ -864,8 +903,23 @@ edx_status launch_t(const edx_sector* s, const T* v, T* w, int64_t ld, const dou
   // the fused pass also applies spin exchange / pair hopping from a staged table
   NdTab<T> nd{nullptr, nullptr, nullptr, nullptr, 1 << s->model.norb, 0};
   size_t ndl = 0;
-  if (p.mode == 2 && s->dph > 1 && slice >= 0) {
-    // phonon slice: W + w0 p and the slice's term table (H_nd + phonon terms)
+  bool use_ph = false;
+  PhArgs<T> pa{};
+  if (p.mode == 2 && s->dph > 1 && slice >= 0 && !s->nd) {
+    // phonon slice: W + w0 p, and the coupling to the neighbouring slices
+    // read directly next to the gathers
+    a.W = wph<T>(s) + (size_t)slice * 64;
+    use_ph = true;
+    pa.slice = ld * s->ddw;
+    pa.sp = (T)std::sqrt((double)slice);
+    pa.sp1 = (T)std::sqrt((double)(slice + 1));
+    pa.g0 = (T)s->model.g[0];
+    pa.g1 = (T)s->model.g[1];
+    pa.g2 = (T)s->model.g[2];
+    pa.lo = slice > 0;
+    pa.hi = slice + 1 < s->dph;
+  } else if (p.mode == 2 && s->dph > 1 && slice >= 0) {
+    // phonon slice with H_nd: W + w0 p and the slice's merged term table
     const int P = 1 << s->model.norb;
     const int t0 = s->ph_start[slice], nt = s->ph_start[slice + 1] - t0;
     nd = NdTab<T>{s->ph_off + (size_t)slice * (P * P + 1), s->ph_du + t0, s->ph_dd + t0,
@@ -903,7 +957,9 @@ edx_status launch_t(const edx_sector* s, const T* v, T* w, int64_t ld, const dou
       return EDX_E_INVALID;
   }
   const bool fused = p.mode == 2;
-  const FusedOrder<T> fo{s->corder ? p.col_order : std::min(p.col_order, 1), s->corder, nd};
+  FusedOrder<T> fo{s->corder ? p.col_order : std::min(p.col_order, 1), s->corder, nd};
+  fo.ph = use_ph;
+  fo.pa = pa;
   switch (a.sup) {
     case 8: return launch_col_w<T, 8>(a, fused, nblk, nthr, lds, st, v, w, vscale, partial, p.col_cols, fo);
     case 16: return launch_col_w<T, 16>(a, fused, nblk, nthr, lds, st, v, w, vscale, partial, p.col_cols, fo);
