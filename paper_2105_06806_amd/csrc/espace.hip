@@ -11,8 +11,10 @@
 // them: one device block per sector, states one after another, so the kept
 // states of a sector are always its lowest ones and need no copy.
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "edx_internal.h"
@@ -36,9 +38,78 @@ struct edx_espace {
 namespace edx {
 namespace {
 
+// sectors solved concurrently by edx_espace_diag (one stream and host thread
+// each): small sectors are bound by launch and synchronisation latency, which
+// the other streams' work hides
+constexpr int kEspaceStreams = 3;
+
 edx_status invalid_e(const std::string& msg) {
   set_error(msg);
   return EDX_E_INVALID;
+}
+
+// Runs fn(n, stream, workspace part, t) for every kept state n on up to
+// kEspaceStreams host threads and streams, state n on thread n % T (a fixed
+// assignment, so per-thread sums are reproducible).  ws holds T parts of
+// `part` bytes; the caller's stream is thread 0's.
+template <class F>
+edx_status for_kept_states(const edx_espace* E, void* ws, size_t ws_bytes, size_t part,
+                           hipStream_t st, int* nthr_out, F fn) {
+  const int ns = (int)E->list.size();
+  const int T = (int)std::min<size_t>({(size_t)kEspaceStreams, (size_t)ns,
+                                       part ? ws_bytes / part : 1});
+  if (T < 1) {
+    set_error("espace: workspace too small (need " + std::to_string(part) + " bytes)");
+    return EDX_E_NOMEM;
+  }
+  *nthr_out = T;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || hipStreamSynchronize(st) != hipSuccess) {
+    set_error("espace: device query failed");
+    return EDX_E_DEVICE;
+  }
+  std::vector<hipStream_t> sts(T, st);
+  for (int t = 1; t < T; ++t)
+    if (hipStreamCreateWithFlags(&sts[t], hipStreamNonBlocking) != hipSuccess) {
+      for (int q = 1; q < t; ++q) (void)hipStreamDestroy(sts[q]);
+      set_error("espace: stream set-up failed");
+      return EDX_E_DEVICE;
+    }
+  std::vector<edx_status> tst(T, EDX_OK);
+  std::vector<std::string> terr(T);
+  std::atomic<bool> stop{false};
+  auto worker = [&](int t) {
+    if (t > 0 && hipSetDevice(dev) != hipSuccess) {
+      tst[t] = EDX_E_DEVICE;
+      terr[t] = "espace: hipSetDevice failed in a helper thread";
+      stop.store(true);
+      return;
+    }
+    char* wsp = static_cast<char*>(ws) + (size_t)t * part;
+    for (int n = t; n < ns && !stop.load(); n += T) {
+      const edx_status rc = fn(n, sts[t], wsp, t);
+      if (rc != EDX_OK) {
+        tst[t] = rc;
+        terr[t] = edx_last_error();
+        stop.store(true);
+        break;
+      }
+    }
+  };
+  std::vector<std::thread> th;
+  for (int t = 1; t < T; ++t) th.emplace_back(worker, t);
+  worker(0);
+  for (auto& x : th) x.join();
+  for (int t = 1; t < T; ++t) {
+    (void)hipStreamSynchronize(sts[t]);
+    (void)hipStreamDestroy(sts[t]);
+  }
+  for (int t = 0; t < T; ++t)
+    if (tst[t] != EDX_OK) {
+      set_error(terr[t]);
+      return tst[t];
+    }
+  return EDX_OK;
 }
 
 void release(edx_espace* E) {
@@ -107,7 +178,7 @@ size_t edx_espace_diag_workspace_bytes(const edx_espace* E, edx_sector* const* s
     if (!secs[i]) return 0;
     need = std::max(need, lowest_workspace_bytes(secs[i], vtype, niter, E->next[i]));
   }
-  return need;
+  return align_up(need) * (size_t)std::min(kEspaceStreams, (int)nsec);
 }
 
 edx_status edx_espace_diag(edx_espace* E, edx_sector* const* secs, int32_t nsec,
@@ -124,27 +195,103 @@ edx_status edx_espace_diag(edx_espace* E, edx_sector* const* secs, int32_t nsec,
   release(E);
   E->vtype = o->vtype;
   E->secs.assign(secs, secs + nsec);
-  std::vector<edx_espace::State> all;
+  // one workspace part per stream
+  size_t part = 0;
+  for (int i = 0; i < nsec; ++i)
+    part = std::max(part, align_up(lowest_workspace_bytes(secs[i], o->vtype, o->niter,
+                                                          E->next[i])));
+  const int nthr = (int)std::min<size_t>({(size_t)kEspaceStreams, (size_t)nsec,
+                                          part ? ws_bytes / part : 1});
+  if (nthr < 1) {
+    set_error("espace: workspace too small (need " + std::to_string(part) + " bytes)");
+    return EDX_E_NOMEM;
+  }
+  std::vector<int> kreq(nsec);
   for (int i = 0; i < nsec; ++i) {
     const edx_sector* s = secs[i];
-    const int k = (int)std::min<int64_t>(E->next[i], s->dim);
+    kreq[i] = (int)std::min<int64_t>(E->next[i], s->dim);
     void* p = nullptr;
-    if (hipMalloc(&p, (size_t)k * s->dim * vbytes(o->vtype)) != hipSuccess) {
+    if (hipMalloc(&p, (size_t)kreq[i] * s->dim * vbytes(o->vtype)) != hipSuccess) {
       (void)hipGetLastError();
       release(E);
       set_error("espace: out of device memory for the state vectors");
       return EDX_E_NOMEM;
     }
     E->buf[i] = p;
-    std::vector<double> e(k);
-    edx_lowest_report r{};
-    const edx_status rc = lowest_states_impl(s, k, o, E->o.verify, ws, ws_bytes, e.data(), p, &r, st);
-    if (rc != EDX_OK) {
-      release(E);
-      return rc;
+  }
+  // largest sectors first, pulled by the workers from a shared counter
+  std::vector<int> order(nsec);
+  for (int i = 0; i < nsec; ++i) order[i] = i;
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int x, int y) { return secs[x]->dim > secs[y]->dim; });
+  std::vector<std::vector<double>> ev(nsec);
+  std::vector<int> found(nsec, 0);
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || hipStreamSynchronize(st) != hipSuccess) {
+    release(E);
+    set_error("espace: device query failed");
+    return EDX_E_DEVICE;
+  }
+  std::vector<hipStream_t> sts(nthr, st);
+  edx_status fail = EDX_OK;
+  for (int t = 1; t < nthr; ++t)
+    if (hipStreamCreateWithFlags(&sts[t], hipStreamNonBlocking) != hipSuccess) {
+      sts[t] = st;
+      fail = EDX_E_DEVICE;
     }
-    E->computed[i] = r.nfound;
-    for (int j = 0; j < r.nfound; ++j) all.push_back({e[j], i, j});
+  std::atomic<int> next{0};
+  std::vector<edx_status> tst(nthr, EDX_OK);
+  std::vector<std::string> terr(nthr);
+  auto worker = [&](int t) {
+    if (t > 0 && hipSetDevice(dev) != hipSuccess) {
+      tst[t] = EDX_E_DEVICE;
+      terr[t] = "espace: hipSetDevice failed in a helper thread";
+      next.store(nsec);
+      return;
+    }
+    char* wsp = static_cast<char*>(ws) + (size_t)t * part;
+    for (;;) {
+      const int q = next.fetch_add(1);
+      if (q >= nsec) break;
+      const int i = order[q];
+      ev[i].assign(kreq[i], 0.0);
+      edx_lowest_report r{};
+      const edx_status rc = lowest_states_impl(secs[i], kreq[i], o, E->o.verify, wsp, part,
+                                               ev[i].data(), E->buf[i], &r, sts[t]);
+      if (rc != EDX_OK) {
+        tst[t] = rc;
+        terr[t] = edx_last_error();
+        next.store(nsec);
+        break;
+      }
+      found[i] = r.nfound;
+    }
+  };
+  if (fail == EDX_OK) {
+    std::vector<std::thread> th;
+    for (int t = 1; t < nthr; ++t) th.emplace_back(worker, t);
+    worker(0);
+    for (auto& x : th) x.join();
+  }
+  for (int t = 1; t < nthr; ++t)
+    if (sts[t] != st) {
+      (void)hipStreamSynchronize(sts[t]);
+      (void)hipStreamDestroy(sts[t]);
+    }
+  for (int t = 0; t < nthr && fail == EDX_OK; ++t)
+    if (tst[t] != EDX_OK) {
+      fail = tst[t];
+      set_error(terr[t]);
+    }
+  if (fail != EDX_OK) {
+    release(E);
+    if (fail == EDX_E_DEVICE && edx_last_error()[0] == 0) set_error("espace: stream set-up failed");
+    return fail;
+  }
+  std::vector<edx_espace::State> all;
+  for (int i = 0; i < nsec; ++i) {
+    E->computed[i] = found[i];
+    for (int j = 0; j < found[i]; ++j) all.push_back({ev[i][j], i, j});
   }
   std::stable_sort(all.begin(), all.end(), [](const edx_espace::State& a, const edx_espace::State& b) {
     if (a.e != b.e) return a.e < b.e;
@@ -213,7 +360,7 @@ size_t edx_espace_green_workspace_bytes(const edx_espace* E, int32_t ngf) {
   for (int i = 0; i < E->nsec; ++i)
     if (E->kept[i] > 0 && E->secs[i])
       need = std::max(need, green_workspace_bytes(E->secs[i], E->vtype, ngf));
-  return need;
+  return align_up(need) * (size_t)std::max(1, std::min(kEspaceStreams, (int)E->list.size()));
 }
 
 edx_status edx_espace_green(edx_espace* E, int32_t orb, int32_t spin, const edx_gf_opts* o,
@@ -227,19 +374,31 @@ edx_status edx_espace_green(edx_espace* E, int32_t orb, int32_t spin, const edx_
   if (o->ngf < 1 || o->ngf > 4096) return invalid_e("ngf must be in [1, 4096]");
   const int lm = o->lmats;
   if (lm < 1) return invalid_e("lmats must be >= 1");
-  std::vector<double> acc(2 * (size_t)lm, 0.0), gn(2 * (size_t)lm);
-  for (int n = 0; n < (int)E->list.size(); ++n) {
+  for (const auto& t : E->list)
+    if (orb < 0 || orb >= E->secs[t.sec]->model.norb) return invalid_e("orb out of range");
+  size_t part = 0;
+  for (int i = 0; i < E->nsec; ++i)
+    if (E->kept[i] > 0) part = std::max(part, align_up(green_workspace_bytes(E->secs[i], E->vtype, o->ngf)));
+  // per-thread sums (state n on thread n % T), added in thread order
+  std::vector<std::vector<double>> acc(kEspaceStreams, std::vector<double>(2 * (size_t)lm, 0.0));
+  std::vector<std::vector<double>> gn(kEspaceStreams, std::vector<double>(2 * (size_t)lm));
+  int T = 1;
+  EDX_TRY(for_kept_states(E, ws, ws_bytes, part, static_cast<hipStream_t>(stream), &T,
+                          [&](int n, hipStream_t st, void* wsp, int th) -> edx_status {
     const auto& t = E->list[n];
     const edx_sector* s = E->secs[t.sec];
-    if (orb < 0 || orb >= s->model.norb) return invalid_e("orb out of range");
     const void* psi =
         static_cast<const char*>(E->buf[t.sec]) + (size_t)t.idx * s->dim * vbytes(E->vtype);
-    EDX_TRY(green_cf_impl(s, psi, t.e, orb, spin, o, ws, ws_bytes, gn.data(), nullptr,
-                          static_cast<hipStream_t>(stream)));
+    EDX_TRY(green_cf_impl(s, psi, t.e, orb, spin, o, wsp, part, gn[th].data(), nullptr, st));
     const double w = std::exp(-E->o.beta * (t.e - E->e0)) / E->z;
-    for (size_t q = 0; q < acc.size(); ++q) acc[q] += w * gn[q];
+    for (size_t q = 0; q < acc[th].size(); ++q) acc[th][q] += w * gn[th][q];
+    return EDX_OK;
+  }));
+  for (size_t q = 0; q < 2 * (size_t)lm; ++q) {
+    double x = 0.0;
+    for (int th = 0; th < T; ++th) x += acc[th][q];
+    g_host[q] = x;
   }
-  std::copy(acc.begin(), acc.end(), g_host);
   return EDX_OK;
 }
 
@@ -249,7 +408,7 @@ size_t edx_espace_chi_workspace_bytes(const edx_espace* E, int32_t ngf) {
   for (int i = 0; i < E->nsec; ++i)
     if (E->kept[i] > 0 && E->secs[i])
       need = std::max(need, chi_workspace_bytes(E->secs[i], E->vtype, ngf));
-  return need;
+  return align_up(need) * (size_t)std::max(1, std::min(kEspaceStreams, (int)E->list.size()));
 }
 
 edx_status edx_espace_chi(edx_espace* E, const double* cu, const double* cd,
@@ -264,8 +423,14 @@ edx_status edx_espace_chi(edx_espace* E, const double* cu, const double* cd,
   if (o->ngf < 1 || o->ngf > 4096) return invalid_e("ngf must be in [1, 4096]");
   const int lm = o->lmats;
   if (lm < 1) return invalid_e("lmats must be >= 1");
-  std::vector<double> acc(2 * (size_t)lm, 0.0), cn(2 * (size_t)lm);
-  for (int n = 0; n < (int)E->list.size(); ++n) {
+  size_t part = 0;
+  for (int i = 0; i < E->nsec; ++i)
+    if (E->kept[i] > 0) part = std::max(part, align_up(chi_workspace_bytes(E->secs[i], E->vtype, o->ngf)));
+  std::vector<std::vector<double>> acc(kEspaceStreams, std::vector<double>(2 * (size_t)lm, 0.0));
+  std::vector<std::vector<double>> cn(kEspaceStreams, std::vector<double>(2 * (size_t)lm));
+  int T = 1;
+  EDX_TRY(for_kept_states(E, ws, ws_bytes, part, static_cast<hipStream_t>(stream), &T,
+                          [&](int n, hipStream_t st, void* wsp, int th) -> edx_status {
     const auto& t = E->list[n];
     const edx_sector* s = E->secs[t.sec];
     DiagCoef c{};
@@ -275,12 +440,16 @@ edx_status edx_espace_chi(edx_espace* E, const double* cu, const double* cd,
     }
     const void* psi =
         static_cast<const char*>(E->buf[t.sec]) + (size_t)t.idx * s->dim * vbytes(E->vtype);
-    EDX_TRY(chi_impl(s, psi, t.e, c, o, ws, ws_bytes, cn.data(), nullptr,
-                     static_cast<hipStream_t>(stream)));
+    EDX_TRY(chi_impl(s, psi, t.e, c, o, wsp, part, cn[th].data(), nullptr, st));
     const double w = std::exp(-E->o.beta * (t.e - E->e0)) / E->z;
-    for (size_t q = 0; q < acc.size(); ++q) acc[q] += w * cn[q];
+    for (size_t q = 0; q < acc[th].size(); ++q) acc[th][q] += w * cn[th][q];
+    return EDX_OK;
+  }));
+  for (size_t q = 0; q < 2 * (size_t)lm; ++q) {
+    double x = 0.0;
+    for (int th = 0; th < T; ++th) x += acc[th][q];
+    chi_host[q] = x;
   }
-  std::copy(acc.begin(), acc.end(), chi_host);
   return EDX_OK;
 }
 
