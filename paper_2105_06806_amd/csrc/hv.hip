@@ -498,7 +498,9 @@ __global__ __launch_bounds__(1024) void k_hv_fused(HvArgs<T> a, const T* __restr
           res += sn * sc;
         }
         if (ALL || c < nc) {
-          w[iu + jc[c] * ld] = res;
+          // streaming store: w is not read again in this pass, so it should
+          // not displace the neighbour columns the gathers reuse from L2
+          __builtin_nontemporal_store(res, &w[iu + jc[c] * ld]);
           dot += (double)x * (double)res;
         }
       }
