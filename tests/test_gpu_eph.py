@@ -171,3 +171,20 @@ def test_eph_rejects(edx):
     with pytest.raises(edx.EdxError) as e:
         edx.build_sector(m, 2, 2)
     assert e.value.status == edx.EDX_E_INVALID
+
+
+def test_eph_chi_spin(edx):
+    """Spin susceptibility of an electron-phonon ground state: O acts on the
+    electrons of every phonon slice; against the dense spectrum of eq. HephBuild."""
+    from oracle import chi as ochi
+    m, sec = GS_CASES[0][1], GS_CASES[0][2]
+    H = eph.explicit_hamiltonian(m, *sec).toarray()
+    w, V = np.linalg.eigh(H)
+    o = np.tile(ochi.diag_operator(m, *sec, [0.5], [-0.5]), m["nph"] + 1)
+    z = 1j * ochi.bosonic(40.0, 32)
+    ref = ochi.spectral(w, (V.T @ (o * V[:, 0])) ** 2, w[0], z)
+    S = edx.build_sector(m, *sec)
+    e0, psi, _, _ = edx.lanczos_ground_state(S, niter=400, tol=1e-14, rtol=1e-11, seed=3,
+                                             allow=(edx.EDX_E_DEGENERATE,))
+    got, _ = edx.chi(S, psi, e0, [0.5], [-0.5], ngf=300, beta=40.0, lmats=32)
+    assert np.abs(got - ref).max() <= 1e-8 * np.abs(ref).max()

@@ -648,3 +648,22 @@ def test_orbital_rejects(edx):
     with pytest.raises(edx.EdxError) as e:
         edx.build_sector_orbital(mk, (2, 1), (1, 2))
     assert e.value.status == edx.EDX_E_UNSUPPORTED
+
+
+def test_batch_orbital_and_phonon_sectors(edx):
+    """Orbital-resolved sectors run through the persistent lanes (their tables
+    have the same form); phonon sectors go through the whole-GPU path.  Every
+    ground energy equals the dense spectrum of the sector."""
+    from oracle import eph
+    mo = inputs.make_model(2, 3, 2.5, Jh=0.4, seed=131, symmetric=False)
+    mp = inputs.make_model(1, 5, 2.0, seed=132, symmetric=False, nph=3, w0=0.6, g=0.35)
+    jobs = [(mo, ((2, 2), (1, 3)), "orb"), (mo, ((1, 2), (2, 2)), "orb"), (mo, ((2, 1), (1, 1)), "orb"),
+            (mp, (3, 3), "ph"), (mp, (3, 2), "ph")]
+    secs = [edx.build_sector_orbital(m, *sec) if kind == "orb" else edx.build_sector(m, *sec)
+            for m, sec, kind in jobs]
+    res, _ = edx.batch_ground_state(secs, niter=512, tol=1e-13, check_every=4, seed=3)
+    for (m, sec, kind), r in zip(jobs, res):
+        assert r["status"] == 0, (sec, r)
+        H = (eph.explicit_hamiltonian(m, *sec) if kind == "ph" else fock.explicit_hamiltonian(m, *sec))
+        E0 = np.linalg.eigvalsh(H.toarray())[0]
+        assert abs(r["e0"] - E0) <= 1e-9 * abs(E0), (sec, r["e0"], E0)
