@@ -59,6 +59,12 @@ def parse():
     ap.add_argument("--quick", action="store_true", help="headline H.v only")
     ap.add_argument("--full", action="store_true", help="full-size serving sweep")
     ap.add_argument("--tune-reps", type=int, default=3)
+    ap.add_argument("--serve-n", type=int, default=None,
+                    help="requests per rate of the serving sweep (default 120, 1000 with --full)")
+    ap.add_argument("--serve-ns-hi", type=int, default=None,
+                    help="largest Ns of the serving requests (default 14, 16 with --full)")
+    ap.add_argument("--serve-rates", default=None,
+                    help="comma-separated multiples of the plain capacity for the serving sweep")
     ap.add_argument("--only", default=None,
                     help="comma-separated sections (hv_ns16o2, hv_kanamori, orbital, lowest_thermal, "
                          "eph, shard, ns12, ns15o3, batch, serve): run just these, no headline "
@@ -468,10 +474,10 @@ def bench_batch(edx, torch):
             "wide_min_dim": tiles["wide_min_dim"]}
 
 
-def bench_serve(edx, torch, full):
+def bench_serve(edx, torch, full, nreq=None, ns_hi=None, rates=None):
     from paper_2105_06806_amd import inputs
-    ns_hi = 16 if full else 14
-    nreq = 1000 if full else 120
+    ns_hi = ns_hi or (16 if full else 14)
+    nreq = nreq or (1000 if full else 120)
     kw = dict(niter=512, tol=1e-9, seed=5, check_every=4)
     gkw = dict(ngf=100, lmats=512, beta=200.0)
     reqs = inputs.serve_requests(nreq, ns_lo=10, ns_hi=ns_hi)
@@ -490,7 +496,8 @@ def bench_serve(edx, torch, full):
            "plain_solves_per_s": round(cap, 2), "plain_p50_s": round(float(np.median(lat_plain)), 4),
            "rates": []}
     srv = edx.Server(hbm_budget=64 << 30, max_slots=8, vtype="f32", **gkw, **kw)
-    for fac in ((0.5, 1.0, 1.5, 2.0) if not full else (0.25, 0.5, 0.75, 0.9, 1.0, 1.25, 2.0)):
+    facs = rates or ((0.5, 1.0, 1.5, 2.0) if not full else (0.25, 0.5, 0.75, 0.9, 1.0, 1.25, 2.0))
+    for fac in facs:
         rate = fac * cap
         arr = inputs.poisson_arrivals(nreq, rate, seed=int(fac * 1000))
         t_begin = edx.Server.clock()
@@ -532,7 +539,9 @@ def main():
                 "shard": lambda: bench_shard(edx, torch, a),
                 "ns12": lambda: bench_ns12(edx), "ns15o3": lambda: bench_ns15o3(edx),
                 "batch": lambda: bench_batch(edx, torch),
-                "serve": lambda: bench_serve(edx, torch, a.full)}
+                "serve": lambda: bench_serve(
+                    edx, torch, a.full, a.serve_n, a.serve_ns_hi,
+                    tuple(float(x) for x in a.serve_rates.split(",")) if a.serve_rates else None)}
     if a.only:
         out = {}
         for name in a.only.split(","):
