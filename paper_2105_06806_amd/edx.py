@@ -308,6 +308,8 @@ def build_sector_orbital(model, nup, ndw, stream=None):
 def _vec_len(sector, v, w, ld):
     if v.dtype != w.dtype:
         raise TypeError("v and w must have the same dtype")
+    if not (v.is_cuda and w.is_cuda):
+        raise ValueError("v and w must be CUDA tensors")
     n = (ld or sector.dup) * sector.ddw * sector.dph
     if v.numel() != n or w.numel() != n or not v.is_contiguous() or not w.is_contiguous():
         raise ValueError(f"v and w must be contiguous with ld * D_dw * D_ph = {n} elements")
@@ -328,6 +330,8 @@ def hv_block(sector, part, v, w, ld, c0, c1, stream=None):
     if v.dtype != w.dtype:
         raise TypeError("v and w must have the same dtype")
     cols = sector.ddw if part == 0 else sector.dup
+    if not (v.is_cuda and w.is_cuda and v.is_contiguous() and w.is_contiguous()):
+        raise ValueError("v and w must be contiguous CUDA tensors")
     if v.numel() < ld * cols or w.numel() < ld * cols:
         raise ValueError(f"v and w need ld * {cols} elements")
     _check(lib.edx_hv_block(sector.handle, _vtype_of(v), int(part), _P(v.data_ptr()), _P(w.data_ptr()),
@@ -339,6 +343,8 @@ def transpose(src, rows, cols, lds, dst, ldd, add=False, stream=None):
     """dst (cols x rows, stride ldd) = src^T (+ dst), device tensors."""
     if src.dtype != dst.dtype:
         raise TypeError("src and dst must have the same dtype")
+    if not (src.is_cuda and dst.is_cuda and src.is_contiguous() and dst.is_contiguous()):
+        raise ValueError("src and dst must be contiguous CUDA tensors")
     if src.numel() < lds * cols or dst.numel() < ldd * rows:
         raise ValueError("tensor smaller than its shape and stride")
     _check(lib.edx_transpose(_vtype_of(src), _P(src.data_ptr()), int(rows), int(cols), int(lds),
@@ -432,7 +438,7 @@ def lanczos_ground_state(sector, want_psi=True, ws=None, stream=None, allow=(EDX
 def green_cf(sector, psi0, e0, orb=0, spin=0, ngf=200, beta=200.0, lmats=4096, ws=None, stream=None,
              coeffs=False):
     """Impurity G(i w_n) as a complex numpy array, plus the report dict."""
-    vtype = _vtype_of(psi0)
+    vtype = _check_state(sector, psi0)
     o = GfOpts(int(ngf), int(lmats), vtype, 0, float(beta))
     need = workspace_bytes(sector, WS_GREEN, vtype, ngf)
     if ws is None:
@@ -557,6 +563,14 @@ class Espace:
         return g[0::2] + 1j * g[1::2]
 
 
+def _check_state(sector, psi0):
+    """A state vector handed to the library: dense, contiguous, on the GPU,
+    D elements (the library cannot see the tensor's size)."""
+    if not psi0.is_cuda or not psi0.is_contiguous() or psi0.numel() != sector.dim:
+        raise ValueError(f"psi0 must be a contiguous CUDA tensor of D = {sector.dim} elements")
+    return _vtype_of(psi0)
+
+
 def tridiag_spectrum(alpha, beta):
     """Eigenvalues and squared first components of the tridiagonal matrix."""
     a = np.ascontiguousarray(alpha, np.float64)
@@ -582,7 +596,7 @@ def _coefs(norb, cu, cd):
 def chi(sector, psi0, e0, cu, cd, ngf=200, beta=200.0, lmats=1024, ws=None, stream=None):
     """Density-type susceptibility C(i nu_n) (complex numpy; real by symmetry)
     and the report dict."""
-    vtype = _vtype_of(psi0)
+    vtype = _check_state(sector, psi0)
     cu, cd = _coefs(int(sector.model["norb"]), cu, cd)
     o = GfOpts(int(ngf), int(lmats), vtype, 0, float(beta))
     need = workspace_bytes(sector, 3, vtype, ngf)
@@ -598,7 +612,7 @@ def chi(sector, psi0, e0, cu, cd, ngf=200, beta=200.0, lmats=1024, ws=None, stre
 
 def chi_exciton(sector, psi0, e0, a, b, ngf=200, beta=200.0, lmats=1024, ws=None, stream=None):
     """Excitonic susceptibility of orbitals a != b (complex numpy) and report."""
-    vtype = _vtype_of(psi0)
+    vtype = _check_state(sector, psi0)
     o = GfOpts(int(ngf), int(lmats), vtype, 0, float(beta))
     if ws is None:
         ws = alloc_workspace(workspace_bytes(sector, 3, vtype, ngf))
@@ -612,7 +626,7 @@ def chi_exciton(sector, psi0, e0, a, b, ngf=200, beta=200.0, lmats=1024, ws=None
 
 def chi_pair(sector, psi0, e0, a, ngf=200, beta=200.0, lmats=1024, ws=None, stream=None):
     """Pair susceptibility of orbital a (complex numpy) and report."""
-    vtype = _vtype_of(psi0)
+    vtype = _check_state(sector, psi0)
     o = GfOpts(int(ngf), int(lmats), vtype, 0, float(beta))
     if ws is None:
         ws = alloc_workspace(workspace_bytes(sector, 4, vtype, ngf))
