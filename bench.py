@@ -412,7 +412,7 @@ def bench_ns15o3(edx):
     import torch
     out = {"workload": "Norb=3 Nbath=4 Ns=15 7/7 D=41409225, U=3 J=0.5; G = G_up + G_dw of orbital 0 "
                        "(the ground level is spin-swap degenerate), 1024 Matsubara, beta=200"}
-    runs = [("f64", 0), ("f32", 0), ("f32", 1), ("f32", 2)]
+    runs = [("f64", 0), ("f32", 0), ("f32", 1), ("f32", 2), ("f32", 3)]
     for vt, ro in runs:
         torch.cuda.synchronize()
         t0 = time.perf_counter()

@@ -184,7 +184,10 @@ edx_status edx_autotune_hv(edx_sector* s, edx_vtype vtype, const void* v, void* 
 typedef struct {
   int32_t niter;        /* max steps, default 512 (lanc_niter)              */
   int32_t vtype;        /* edx_vtype of the Krylov vectors and psi0         */
-  int32_t reorth;       /* 0 none (plain, as the paper), 1 local, 2 full    */
+  int32_t reorth;       /* 0 none (plain, as the paper), 1 local, 2 full,
+                           3 none with the basis kept: psi0 from the stored
+                           vectors instead of a replay of the recurrence
+                           (niter + 1 vectors of workspace)                  */
   int32_t check_every;  /* host stop-rule check period in steps (>= 1)      */
   double tol;           /* stop if |E_j - E_{j-1}| <= tol * max(1, |E_j|)   */
   double rtol;          /* and (if > 0) beta_{j+1}|y_j| <= rtol * max(1,|E|) */
@@ -207,9 +210,10 @@ void edx_lanczos_default_opts(edx_lanczos_opts* o);
 
 #define EDX_WS_LANCZOS 0
 #define EDX_WS_GREEN 1
+#define EDX_WS_LANCZOS_BASIS 2
 
 /* Device workspace bytes for edx_lanczos_ground_state (what = EDX_WS_LANCZOS,
- * n = niter), edx_green_cf (what = EDX_WS_GREEN, n = ngf), edx_chi and
+ * n = niter; what = EDX_WS_LANCZOS_BASIS = 2 for reorth 2 or 3), edx_green_cf (what = EDX_WS_GREEN, n = ngf), edx_chi and
  * edx_chi_exciton (what = EDX_WS_CHI = 3, n = ngf) or edx_chi_pair
  * (what = EDX_WS_PAIR = 4, n = ngf). */
 size_t edx_workspace_bytes(const edx_sector* s, int32_t what, int32_t vtype,

@@ -306,7 +306,7 @@ edx_status edx_lanczos_ground_state(const edx_sector* s, const edx_lanczos_opts*
   if (!opts || !e0 || !ws) return invalid("opts, e0 and ws must be non-NULL");
   if (!valid_vtype(opts->vtype)) return invalid("vtype must be EDX_F64 or EDX_F32");
   if (opts->niter < 1 || opts->niter > 4096) return invalid("niter must be in [1, 4096]");
-  if (opts->reorth < 0 || opts->reorth > 2) return invalid("reorth must be 0, 1 or 2");
+  if (opts->reorth < 0 || opts->reorth > 3) return invalid("reorth must be 0, 1, 2 or 3");
   if (!(opts->tol >= 0.0) || !(opts->rtol >= 0.0)) return invalid("tol/rtol must be >= 0");
   return lanczos_ground_state_impl(s, opts, ws, ws_bytes, e0, psi0, rep,
                                    static_cast<hipStream_t>(stream));

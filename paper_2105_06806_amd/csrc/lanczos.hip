@@ -238,7 +238,7 @@ constexpr int kMaxLmats = 65536;
 size_t lanczos_ws_layout(int64_t vlen, int vtype, int niter, int reorth, int hv_blocks,
                          bool psi_acc, char* base, LanczosWs* L) {
   const size_t vs = align_up((size_t)vlen * vbytes(vtype));
-  const int nvec = reorth == 2 ? niter + 1 : 3;
+  const int nvec = reorth >= 2 ? niter + 1 : 3;   // 2 and 3 keep the basis
   const int slots = reorth == 2 ? std::max(niter + 1, 2) : 2;
   const int pcap = std::max(kMaxPartials, hv_blocks);
   size_t off = 0;
@@ -275,7 +275,7 @@ struct StepBufs {
 
 StepBufs bufs_for(const LanczosWs& L, int j, int reorth) {
   StepBufs b;
-  if (reorth == 2) {
+  if (reorth >= 2) {
     b.cur = L.vec + (size_t)j * L.vstride;
     b.prev = j > 0 ? L.vec + (size_t)(j - 1) * L.vstride : nullptr;
     b.w = L.vec + (size_t)(j + 1) * L.vstride;
@@ -418,7 +418,9 @@ edx_status lanczos_ground_state_impl(const edx_sector* s, const edx_lanczos_opts
     // psi0 is accumulated in the layout of the Krylov vectors, then written
     // densely (D elements) into the caller's buffer
     void* acc = L.psi ? (void*)L.psi : psi0;
-    if (reorth == 2) {
+    if (reorth >= 2) {
+      // psi0 from the stored basis (full re-orthogonalisation, or plain with
+      // the basis kept)
       std::vector<double> hs(m);
       EDX_HIP(hipMemcpyAsync(hs.data(), L.scale, sizeof(double) * m, hipMemcpyDeviceToHost, st));
       EDX_HIP(hipStreamSynchronize(st));

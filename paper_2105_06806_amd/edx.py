@@ -420,7 +420,7 @@ def alloc_workspace(nbytes, device="cuda"):
 def lanczos_ground_state(sector, want_psi=True, ws=None, stream=None, allow=(EDX_OK,), **kw):
     """Returns (e0, psi0 tensor or None, report dict, status)."""
     o = lanczos_opts(**kw)
-    what = WS_LANCZOS_FULL if o.reorth == 2 else WS_LANCZOS
+    what = WS_LANCZOS_FULL if o.reorth >= 2 else WS_LANCZOS
     need = workspace_bytes(sector, what, o.vtype, o.niter)
     if ws is None:
         ws = alloc_workspace(need)

@@ -667,3 +667,17 @@ def test_batch_orbital_and_phonon_sectors(edx):
         H = (eph.explicit_hamiltonian(m, *sec) if kind == "ph" else fock.explicit_hamiltonian(m, *sec))
         E0 = np.linalg.eigvalsh(H.toarray())[0]
         assert abs(r["e0"] - E0) <= 1e-9 * abs(E0), (sec, r["e0"], E0)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_lanczos_kept_basis_equals_replay(edx, dtype):
+    """reorth = 3 (plain recurrence, basis kept, psi0 without a replay) gives the
+    energy and vector of the replayed plain recurrence."""
+    m, [sec] = inputs.workload("ns12")
+    S = edx.build_sector(m, *sec)
+    kw = dict(vtype=dtype, niter=400, tol=1e-12 if dtype == "f64" else 1e-8, seed=13)
+    e0, p0, r0, _ = edx.lanczos_ground_state(S, reorth=0, **kw)
+    e3, p3, r3, _ = edx.lanczos_ground_state(S, reorth=3, **kw)
+    assert r0["iters"] == r3["iters"] and e0 == e3
+    tol = 1e-12 if dtype == "f64" else 1e-5
+    assert float((p0.double() - p3.double()).abs().max()) < tol
