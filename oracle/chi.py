@@ -197,3 +197,63 @@ def chi_pair_exact(model, nup, ndw, a, z):
         term = (amp2[None, :] / (np.asarray(z)[:, None] + sgn * (wt[None, :] - E0))).sum(axis=1)
         out += term if create else -term
     return out, E0
+
+
+def exciton_state(model, sec, psi, e, a, b, z):
+    """T = 0 excitonic function of one eigenstate (energy e) of sector sec."""
+    H = fock.explicit_hamiltonian(model, *sec).toarray()
+    w, V = np.linalg.eigh(H)
+    amp = V.T @ exciton_apply(model, sec[0], sec[1], psi, a, b)
+    return spectral(w, amp ** 2, e, z)
+
+
+def pair_state(model, sec, psi, e, a, z):
+    """Pair function of one eigenstate (energy e): both branches, no pole dropped."""
+    out = np.zeros(len(z), dtype=complex)
+    for create, sgn in ((True, -1.0), (False, +1.0)):
+        tgt, phi = pair_apply(model, sec[0], sec[1], psi, a, create)
+        if phi.size == 0:
+            continue
+        wt, Vt = np.linalg.eigh(fock.explicit_hamiltonian(model, *tgt).toarray())
+        amp2 = (Vt.T @ phi) ** 2
+        term = (amp2[None, :] / (np.asarray(z)[:, None] + sgn * (wt[None, :] - e))).sum(axis=1)
+        out += term if create else -term
+    return out
+
+
+def thermal_states_sum(states, beta, per_state):
+    """sum_n w_n C_n over (E, sec, psi) with w_n normalised over the list;
+    per_state(sec, psi, e) gives C_n."""
+    e = np.array([t[0] for t in states])
+    w = np.exp(-beta * (e - e.min()))
+    w = w / w.sum()
+    return sum(wn * per_state(sec, psi, en) for wn, (en, sec, psi) in zip(w, states))
+
+
+def pair_double_sum(model, sectors, a, z, beta):
+    """Bosonic Lehmann double sum of the pair operator O = c_{a dw} c_{a up} over
+    every eigenstate of a set of sectors closed under O and O+:
+      C(z) = (1/Z) sum_{n,m} |<m|O+|n>|^2 (e^{-beta E_n} - e^{-beta E_m}) / (z - (E_m - E_n))."""
+    spec = {}
+    for sec in sectors:
+        H = fock.explicit_hamiltonian(model, *sec).toarray()
+        spec[sec] = np.linalg.eigh(H)
+    e0 = min(w[0] for w, _ in spec.values())
+    Z = sum(np.exp(-beta * (w - e0)).sum() for w, _ in spec.values())
+    out = np.zeros(len(z), dtype=complex)
+    for sec, (wn, Vn) in spec.items():
+        tgt = (sec[0] + 1, sec[1] + 1)
+        if tgt not in spec:
+            continue
+        wm, Vm = spec[tgt]
+        M = np.zeros((len(wm), len(wn)))
+        for k in range(len(wn)):
+            t2, phi = pair_apply(model, sec[0], sec[1], Vn[:, k], a, True)
+            M[:, k] = Vm.T @ phi
+        bn = np.exp(-beta * (wn - e0))
+        bm = np.exp(-beta * (wm - e0))
+        num = (M ** 2) * (bn[None, :] - bm[:, None])
+        d = wm[:, None] - wn[None, :]
+        for q, zz in enumerate(z):
+            out[q] += (num / (zz - d)).sum()
+    return out / Z

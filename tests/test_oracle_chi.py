@@ -177,3 +177,43 @@ def test_pair_and_exciton_noninteracting_bubbles():
                 ref += amp ** 2 * (1 / (z - d) - 1 / (z + d))
     got, _ = chi.chi_exciton_exact(m, nup, ndw, 0, 1, z)
     assert np.abs(got - ref).max() < 1e-12
+
+
+def test_thermal_pair_per_state_equals_double_sum():
+    """Pair function at finite temperature: the per-state sum over every
+    eigenstate of the Fock space equals the bosonic double sum (z != 0)."""
+    from oracle import thermal
+    m = inputs.make_model(1, 2, 2.0, seed=90, symmetric=False)
+    secs = thermal.all_sectors(m)
+    beta = 2.5
+    z = 1j * chi.bosonic(beta, 8)[1:]
+    got = chi.thermal_states_sum(thermal.all_states(m), beta,
+                                 lambda sec, psi, e: chi.pair_state(m, sec, psi, e, 0, z))
+    ref = chi.pair_double_sum(m, secs, 0, z, beta)
+    assert np.abs(got - ref).max() < 1e-12
+
+
+def test_thermal_exciton_per_state_equals_double_sum():
+    from oracle import thermal
+    m = inputs.make_model(2, 1, 2.0, Jh=0.3, seed=91, symmetric=False)
+    beta = 2.0
+    z = 1j * chi.bosonic(beta, 8)[1:]
+    states = thermal.all_states(m)
+    got = chi.thermal_states_sum(states, beta,
+                                 lambda sec, psi, e: chi.exciton_state(m, sec, psi, e, 0, 1, z))
+    # double sum with the Hermitian exciton operator, sector by sector
+    e0 = min(s[0] for s in states)
+    Z = sum(np.exp(-beta * (s[0] - e0)) for s in states)
+    ref = np.zeros(len(z), dtype=complex)
+    for sec in thermal.all_sectors(m):
+        H = fock.explicit_hamiltonian(m, *sec).toarray()
+        w, V = np.linalg.eigh(H)
+        M = np.column_stack([V.T @ chi.exciton_apply(m, sec[0], sec[1], V[:, k], 0, 1)
+                             for k in range(len(w))])
+        b = np.exp(-beta * (w - e0))
+        d = w[:, None] - w[None, :]
+        keep = np.abs(d) > 1e-9
+        num = M ** 2 * (b[None, :] - b[:, None])
+        for q, zz in enumerate(z):
+            ref[q] += (num[keep] / (zz - d[keep])).sum()
+    assert np.abs(got - ref / Z).max() < 1e-12
