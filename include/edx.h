@@ -448,6 +448,17 @@ edx_status edx_espace_chi(edx_espace* E, const double* cu, const double* cd,
                           const edx_gf_opts* opts, void* ws, size_t ws_bytes,
                           double* chi_host, void* stream);
 
+/* Thermal excitonic and pair susceptibilities, sum_n w_n C_n over the kept
+ * states with the T = 0 forms of edx_chi_exciton / edx_chi_pair and E_n as the
+ * reference; the same sector restrictions apply to every kept state's sector.
+ * Workspaces: edx_espace_chi_workspace_bytes (exciton) and
+ * edx_espace_pair_workspace_bytes (pair). */
+size_t edx_espace_pair_workspace_bytes(const edx_espace* E, int32_t ngf);
+edx_status edx_espace_chi_exciton(edx_espace* E, int32_t a, int32_t b, const edx_gf_opts* opts,
+                                  void* ws, size_t ws_bytes, double* chi_host, void* stream);
+edx_status edx_espace_chi_pair(edx_espace* E, int32_t a, const edx_gf_opts* opts, void* ws,
+                               size_t ws_bytes, double* chi_host, void* stream);
+
 /* ---- batched ground states (many sectors, one persistent launch) ----
  * Every job is an independent sector; the ground energy of each follows the
  * plain recurrence of edx_lanczos_ground_state (psi0 is not formed).  The

@@ -453,4 +453,77 @@ edx_status edx_espace_chi(edx_espace* E, const double* cu, const double* cd,
   return EDX_OK;
 }
 
+size_t edx_espace_pair_workspace_bytes(const edx_espace* E, int32_t ngf) {
+  if (!E || ngf < 1) return 0;
+  size_t need = 0;
+  for (int i = 0; i < E->nsec; ++i)
+    if (E->kept[i] > 0 && E->secs[i])
+      need = std::max(need, pair_workspace_bytes(E->secs[i], E->vtype, ngf));
+  return align_up(need) * (size_t)std::max(1, std::min(kEspaceStreams, (int)E->list.size()));
+}
+
+// thermal sum of a per-state function: kind 0 exciton (a, b), 1 pair (a)
+static edx_status espace_op_sum(edx_espace* E, int kind, int a, int b, const edx_gf_opts* o,
+                                void* ws, size_t ws_bytes, double* out, void* stream) {
+  if (!E || !o || !ws || !out) return invalid_e("espace, opts, ws and output must be non-NULL");
+  if (E->list.empty()) return invalid_e("the state list is empty (run edx_espace_diag first)");
+  if (o->vtype != E->vtype) return invalid_e("opts->vtype differs from the stored vectors' type");
+  if (std::fabs(o->beta - E->o.beta) > 1e-12 * E->o.beta)
+    return invalid_e("opts->beta differs from the espace's beta");
+  if (o->ngf < 1 || o->ngf > 4096) return invalid_e("ngf must be in [1, 4096]");
+  const int lm = o->lmats;
+  if (lm < 1) return invalid_e("lmats must be >= 1");
+  size_t part = 0;
+  for (const auto& t : E->list) {
+    const edx_sector* s = E->secs[t.sec];
+    const int norb = s->model.norb;
+    if (kind == 0 && (a < 0 || b < 0 || a >= norb || b >= norb || a == b))
+      return invalid_e("a and b must be two different orbitals");
+    if (kind == 1 && (a < 0 || a >= norb)) return invalid_e("orbital out of range");
+    if (s->dph > 1 || (kind == 0 && s->orb)) {
+      set_error("espace: this susceptibility needs sectors without phonons (and total-N for the "
+                "excitonic one)");
+      return EDX_E_UNSUPPORTED;
+    }
+    part = std::max(part, align_up(kind == 0 ? chi_workspace_bytes(s, E->vtype, o->ngf)
+                                             : pair_workspace_bytes(s, E->vtype, o->ngf)));
+  }
+  std::vector<std::vector<double>> acc(kEspaceStreams, std::vector<double>(2 * (size_t)lm, 0.0));
+  std::vector<std::vector<double>> cn(kEspaceStreams, std::vector<double>(2 * (size_t)lm));
+  int T = 1;
+  EDX_TRY(for_kept_states(E, ws, ws_bytes, part, static_cast<hipStream_t>(stream), &T,
+                          [&](int n, hipStream_t st, void* wsp, int th) -> edx_status {
+    const auto& t = E->list[n];
+    const edx_sector* s = E->secs[t.sec];
+    const void* psi =
+        static_cast<const char*>(E->buf[t.sec]) + (size_t)t.idx * s->dim * vbytes(E->vtype);
+    if (kind == 0) {
+      DiagCoef c{};
+      EDX_TRY(chi_impl(s, psi, t.e, c, o, wsp, part, cn[th].data(), nullptr, st, 1,
+                       std::min(a, b), std::max(a, b)));
+    } else {
+      EDX_TRY(pair_impl(s, psi, t.e, a, o, wsp, part, cn[th].data(), nullptr, st));
+    }
+    const double w = std::exp(-E->o.beta * (t.e - E->e0)) / E->z;
+    for (size_t q = 0; q < acc[th].size(); ++q) acc[th][q] += w * cn[th][q];
+    return EDX_OK;
+  }));
+  for (size_t q = 0; q < 2 * (size_t)lm; ++q) {
+    double x = 0.0;
+    for (int th = 0; th < T; ++th) x += acc[th][q];
+    out[q] = x;
+  }
+  return EDX_OK;
+}
+
+edx_status edx_espace_chi_exciton(edx_espace* E, int32_t a, int32_t b, const edx_gf_opts* o,
+                                  void* ws, size_t ws_bytes, double* chi_host, void* stream) {
+  return espace_op_sum(E, 0, a, b, o, ws, ws_bytes, chi_host, stream);
+}
+
+edx_status edx_espace_chi_pair(edx_espace* E, int32_t a, const edx_gf_opts* o, void* ws,
+                               size_t ws_bytes, double* chi_host, void* stream) {
+  return espace_op_sum(E, 1, a, 0, o, ws, ws_bytes, chi_host, stream);
+}
+
 }  // extern "C"

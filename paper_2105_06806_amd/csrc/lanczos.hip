@@ -470,9 +470,10 @@ edx_status lanczos_ground_state_impl(const edx_sector* s, const edx_lanczos_opts
 }
 
 // ---------------------------------------------------------------- low-lying states
-// Workspace: the Lanczos basis of one run (full re-orthogonalisation) and k + 1
-// vectors after it: k locked eigenvectors (orthonormal, padded layout) and one
-// staging slot for a Ritz vector that is not locked yet.
+// Workspace: the Lanczos basis of one run (full re-orthogonalisation) and k + 2
+// vectors after it: k locked eigenvectors (orthonormal, padded layout), one
+// staging slot for a Ritz vector that is not locked yet and one for H x when a
+// candidate's residual is checked.
 namespace {
 
 size_t lowest_ws_layout(int64_t vlen, int vtype, int niter, int k, int hvb, char* base,
@@ -480,7 +481,8 @@ size_t lowest_ws_layout(int64_t vlen, int vtype, int niter, int k, int hvb, char
   const int nit = std::max(niter, k + 1);   // scalar arrays and dot slots cover k
   const size_t off = lanczos_ws_layout(vlen, vtype, nit, 2, hvb, false, base, L);
   if (locked) *locked = base ? base + off : nullptr;
-  return off + align_up((size_t)vlen * vbytes(vtype)) * (size_t)(k + 1);
+  // k locked vectors, a staging slot and a residual slot
+  return off + align_up((size_t)vlen * vbytes(vtype)) * (size_t)(k + 2);
 }
 
 // w -= sum_k <x_k, w> x_k over nl orthonormal x_k, twice; L.partial then holds
@@ -545,6 +547,7 @@ edx_status lowest_states_impl(const edx_sector* s, int k, const edx_lanczos_opts
   int runs = 0, iters = 0;
   double resid_max = 0.0;
   const int max_runs = 4 * k + 8;
+  int stall = 0;                    // consecutive runs that locked nothing
   auto slot = [&](int i) { return X + (size_t)i * vs; };
 
   while (runs < max_runs) {
@@ -589,9 +592,19 @@ edx_status lowest_states_impl(const edx_sector* s, int k, const edx_lanczos_opts
       EDX_HIP(hipMemcpyAsync(hb.data(), L.beta, sizeof(double) * (upto + 1),
                              hipMemcpyDeviceToHost, st));
       EDX_HIP(hipStreamSynchronize(st));
-      for (int j = done; j < upto; ++j) tnorm = std::max(tnorm, std::fabs(ha[j]) + hb[j] + hb[j + 1]);
-      const int mm = upto;
-      const bool bd = !(hb[mm] > 1e-12 * tnorm) || mm >= s->dim - nl;
+      // the first breakdown ends the run: its Krylov space is invariant (every
+      // Ritz pair exact) and the vectors after it would come from rounding noise
+      int mm = upto;
+      bool bd = false;
+      for (int j = done; j < upto; ++j) {
+        tnorm = std::max(tnorm, std::fabs(ha[j]) + hb[j] + hb[j + 1]);
+        if (!(hb[j + 1] > 1e-12 * tnorm)) {
+          mm = j + 1;
+          bd = true;
+          break;
+        }
+      }
+      bd = bd || mm >= s->dim - nl;
       const double floor32 = vtype == EDX_F32 ? 2.0 * 1.1920929e-7 * tnorm : 0.0;
       const int w = std::min(want, mm);
       theta.assign(w, 0.0);
@@ -650,8 +663,27 @@ edx_status lowest_states_impl(const edx_sector* s, int k, const edx_lanczos_opts
       double nrm = 0.0;
       EDX_HIP(hipMemcpyAsync(&nrm, L.coef, sizeof(double), hipMemcpyDeviceToHost, st));
       EDX_HIP(hipStreamSynchronize(st));
-      if (!(nrm > 0.5)) break;   // not independent of the locked states: leave it
+      if (!(nrm > 0.5)) continue;   // not independent of the locked states: leave it
       EDX_TRY(k_scale_copy(vtype, dst, L.coef + 1, dst, n, st));
+      // the candidate's true residual |H x - theta x|: a Krylov space run past an
+      // exhausted invariant subspace (degenerate spectrum) can produce Ritz
+      // pairs whose estimate is small but whose vectors are not eigenvectors
+      {
+        char* tmp = slot(k + 1);
+        EDX_TRY(hv_launch(s, vtype, dst, tmp, s->ld, nullptr, nullptr, st));
+        const double sc[2] = {1.0, theta[i]};
+        EDX_HIP(hipMemcpyAsync(L.y, sc, sizeof(sc), hipMemcpyHostToDevice, st));
+        EDX_TRY(k_update(vtype, tmp, dst, L.y, nullptr, nullptr, L.y + 1, L.y + 1, n, nullptr,
+                         nullptr, L.partial, st));
+        EDX_TRY(k_beta_finish(L.partial, elem_blocks(n), L.alpha2, L.scale2, st));
+        double rn = 0.0;
+        EDX_HIP(hipMemcpyAsync(&rn, L.alpha2, sizeof(double), hipMemcpyDeviceToHost, st));
+        EDX_HIP(hipStreamSynchronize(st));
+        const double thr = std::max(100.0 * rtol * std::max(1.0, std::fabs(theta[i])),
+                                    (vtype == EDX_F32 ? 1e-5 : 1e-9) * std::max(1.0, tnorm));
+        if (!(rn <= thr)) continue;
+        res[i] = std::max(res[i], rn);
+      }
       if (checking) {
         // replaces the highest locked state
         const int hi = (int)(std::max_element(E.begin(), E.end()) - E.begin());
@@ -666,10 +698,13 @@ edx_status lowest_states_impl(const edx_sector* s, int k, const edx_lanczos_opts
       if (checking) break;
     }
     if (verified && checking) break;
-    // restart from the wanted Ritz vectors that did not converge
+    // a run that locked nothing restarts from a fresh random vector; many in a
+    // row end the search
+    stall = locked_now == 0 ? stall + 1 : 0;
     from_staging = false;
+    if (stall >= 8) break;
     const int wl = (int)ys.size();
-    if (locked_now < wl && (int)E.size() < s->dim) {
+    if (locked_now > 0 && locked_now < wl && (int)E.size() < s->dim) {
       std::vector<std::vector<double>> rest(ys.begin() + locked_now, ys.end());
       const int free_slot = std::min((int)E.size(), k);
       EDX_TRY(ritz_combination(vtype, L, m, hs, rest, std::vector<double>(rest.size(), 1.0),

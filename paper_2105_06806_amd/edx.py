@@ -152,6 +152,9 @@ _SIGS = {
     "edx_chi": (ctypes.c_int, [_P, _P, ctypes.c_double, _P, _P, ctypes.POINTER(GfOpts), _P, ctypes.c_size_t, _P, ctypes.POINTER(ChiReport), _P]),
     "edx_chi_exciton": (ctypes.c_int, [_P, _P, ctypes.c_double, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(GfOpts), _P, ctypes.c_size_t, _P, ctypes.POINTER(ChiReport), _P]),
     "edx_chi_pair": (ctypes.c_int, [_P, _P, ctypes.c_double, ctypes.c_int32, ctypes.POINTER(GfOpts), _P, ctypes.c_size_t, _P, ctypes.POINTER(GfReport), _P]),
+    "edx_espace_pair_workspace_bytes": (ctypes.c_size_t, [_P, ctypes.c_int32]),
+    "edx_espace_chi_exciton": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(GfOpts), _P, ctypes.c_size_t, _P, _P]),
+    "edx_espace_chi_pair": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.POINTER(GfOpts), _P, ctypes.c_size_t, _P, _P]),
     "edx_espace_chi_workspace_bytes": (ctypes.c_size_t, [_P, ctypes.c_int32]),
     "edx_espace_chi": (ctypes.c_int, [_P, _P, _P, ctypes.POINTER(GfOpts), _P, ctypes.c_size_t, _P, _P]),
     "edx_green_cf": (ctypes.c_int, [_P, _P, ctypes.c_double, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(GfOpts), _P, ctypes.c_size_t, _P, ctypes.POINTER(GfReport), _P]),
@@ -560,6 +563,32 @@ class Espace:
         g = np.zeros(2 * lmats, np.float64)
         _check(lib.edx_espace_chi(self.handle, cu.ctypes.data_as(_P), cd.ctypes.data_as(_P), ctypes.byref(o),
                                   _P(ws.data_ptr()), ws.numel(), g.ctypes.data_as(_P), _stream_ptr(stream)))
+        return g[0::2] + 1j * g[1::2]
+
+    def chi_exciton(self, a, b, ngf=200, lmats=256, ws=None, stream=None):
+        """Thermal excitonic susceptibility of orbitals a != b (bosonic grid)."""
+        o = GfOpts(int(ngf), int(lmats), self.vtype, 0, float(self.opts.beta))
+        need = int(lib.edx_espace_chi_workspace_bytes(self.handle, int(ngf)))
+        if need == 0:
+            raise ValueError("no kept states (run diag first)")
+        if ws is None or ws.numel() < need:
+            ws = alloc_workspace(need)
+        g = np.zeros(2 * lmats, np.float64)
+        _check(lib.edx_espace_chi_exciton(self.handle, int(a), int(b), ctypes.byref(o), _P(ws.data_ptr()),
+                                          ws.numel(), g.ctypes.data_as(_P), _stream_ptr(stream)))
+        return g[0::2] + 1j * g[1::2]
+
+    def chi_pair(self, a, ngf=200, lmats=256, ws=None, stream=None):
+        """Thermal pair susceptibility of orbital a (bosonic grid)."""
+        o = GfOpts(int(ngf), int(lmats), self.vtype, 0, float(self.opts.beta))
+        need = int(lib.edx_espace_pair_workspace_bytes(self.handle, int(ngf)))
+        if need == 0:
+            raise ValueError("no kept states (run diag first)")
+        if ws is None or ws.numel() < need:
+            ws = alloc_workspace(need)
+        g = np.zeros(2 * lmats, np.float64)
+        _check(lib.edx_espace_chi_pair(self.handle, int(a), ctypes.byref(o), _P(ws.data_ptr()),
+                                       ws.numel(), g.ctypes.data_as(_P), _stream_ptr(stream)))
         return g[0::2] + 1j * g[1::2]
 
 

@@ -42,6 +42,9 @@ LOW_CASES = [
      (4, 4), 6),
     ("orbital", inputs.make_model(2, 3, 2.5, Jh=0.4, seed=73, symmetric=False), ((2, 2), (1, 3)), 5),
     ("tiny_all", inputs.make_model(1, 5, 2.0, seed=74), (1, 0), 10),     # k > D = 6
+    # every state of a sector with 27 distinct levels among 36: one Krylov space
+    # is exhausted long before the sector, and the copies come from later runs
+    ("degenerate_all", inputs.make_model(2, 1, 2.0, Jh=0.3, seed=141, symmetric=False), (2, 2), 36),
 ]
 
 
@@ -351,3 +354,29 @@ def test_chi_exciton_pair_reject(edx):
         edx.chi_exciton(S2, psi, e0, 1, 1, ngf=20, beta=10.0, lmats=8)
     with pytest.raises(edx.EdxError):
         edx.chi_pair(S2, psi, e0, 2, ngf=20, beta=10.0, lmats=8)
+
+
+def test_espace_thermal_exciton_and_pair(edx):
+    """Thermal excitonic (two orbitals) and pair functions over every state of
+    small Fock spaces against the oracle's per-state sums (z != 0, where they
+    equal the bosonic double sums)."""
+    from oracle import chi as ochi
+    beta = 3.0
+    for m, kind in ((inputs.make_model(2, 1, 2.0, Jh=0.3, seed=141, symmetric=False), "exciton"),
+                    (inputs.make_model(1, 2, 2.0, seed=142, symmetric=False), "pair")):
+        secs = _all_sectors(m)
+        E = edx.Espace(len(secs), beta=beta, cutoff=0.0, nstates_sector=64, nstates_total=100000)
+        S = [edx.build_sector(m, *s) for s in secs]
+        E.diag(S, niter=200, tol=0.0, rtol=1e-11, seed=1)
+        assert E.info()[0] == 4 ** fock.ns_of(m)
+        z = 1j * ochi.bosonic(beta, 12)
+        states = thermal.all_states(m)
+        if kind == "exciton":
+            ref = ochi.thermal_states_sum(states, beta,
+                                          lambda sec, psi, e: ochi.exciton_state(m, sec, psi, e, 0, 1, z))
+            got = E.chi_exciton(0, 1, ngf=80, lmats=12)
+        else:
+            ref = ochi.thermal_states_sum(states, beta,
+                                          lambda sec, psi, e: ochi.pair_state(m, sec, psi, e, 0, z))
+            got = E.chi_pair(0, ngf=80, lmats=12)
+        assert np.abs(got[1:] - ref[1:]).max() <= 1e-8 * np.abs(ref[1:]).max(), kind
