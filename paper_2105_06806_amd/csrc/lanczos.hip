@@ -557,7 +557,10 @@ edx_status lowest_states_impl(const edx_sector* s, int k, const edx_lanczos_opts
       verified = true;
       break;
     }
-    const int want = checking ? 1 : k - nl;
+    // states aimed at in this run: all that remain when the run may be long,
+    // fewer when niter bounds it (a short Krylov space converges only its
+    // lowest few Ritz pairs; the restart then keeps their vectors)
+    const int want = checking ? 1 : std::min(k - nl, std::max(1, niter / 16));
     char* stage = slot(nl);         // first free slot (slot k while checking)
     // start vector, orthogonal to the locked states
     if (from_staging) {
@@ -642,6 +645,7 @@ edx_status lowest_states_impl(const edx_sector* s, int k, const edx_lanczos_opts
 
     // lock the converged leading pairs (or, while checking, test the lowest)
     int locked_now = 0;
+    std::vector<char> took(ys.size(), 0);
     for (int i = 0; i < nconv; ++i) {
       if (checking) {
         const double emax = *std::max_element(E.begin(), E.end());
@@ -695,17 +699,24 @@ edx_status lowest_states_impl(const edx_sector* s, int k, const edx_lanczos_opts
       }
       resid_max = std::max(resid_max, res[i]);
       ++locked_now;
+      took[i] = 1;
       if (checking) break;
     }
     if (verified && checking) break;
-    // a run that locked nothing restarts from a fresh random vector; many in a
-    // row end the search
+    // a run that locked nothing continues from its wanted Ritz vectors if it
+    // reached niter (the restart), else from a fresh random vector; many runs
+    // in a row without progress end the search
     stall = locked_now == 0 ? stall + 1 : 0;
     from_staging = false;
-    if (stall >= 8) break;
+    const bool hit_niter = m >= niter;
+    if (stall >= 16) break;
     const int wl = (int)ys.size();
-    if (locked_now > 0 && locked_now < wl && (int)E.size() < s->dim) {
-      std::vector<std::vector<double>> rest(ys.begin() + locked_now, ys.end());
+    if ((locked_now > 0 || hit_niter) && locked_now < wl && (int)E.size() < s->dim) {
+      // the lowest wanted Ritz vector not locked: a restarted single-vector
+      // Lanczos keeps converging it (a sum of several would dilute it)
+      std::vector<std::vector<double>> rest;
+      for (int i = 0; i < wl && rest.empty(); ++i)
+        if (!took[i]) rest.push_back(ys[i]);
       const int free_slot = std::min((int)E.size(), k);
       EDX_TRY(ritz_combination(vtype, L, m, hs, rest, std::vector<double>(rest.size(), 1.0),
                                slot(free_slot), n, st));
