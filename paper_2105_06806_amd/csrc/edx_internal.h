@@ -225,6 +225,10 @@ edx_status k_multi_axpy(int vtype, void* w, const void* basis, int64_t ld,
                         int m, const double* coef, int64_t n, double* partial,
                         hipStream_t st);
 int multi_blocks(int64_t n);
+// thick restart: basis_c <- sum_{j<m} C[j*l + c] basis_j for c < l, in place
+constexpr int kMaxKeep = 32;
+edx_status k_basis_rotate(int vtype, void* basis, int64_t ld, int m, int l, const double* C,
+                          int64_t n, hipStream_t st);
 
 // ---- green.hip
 // coefficients of a diagonal operator O = sum_a (up[a] n_{a up} + dw[a] n_{a dw})

@@ -218,6 +218,31 @@ __global__ __launch_bounds__(kThreads) void k_multi_axpy_kernel(T* __restrict__ 
   if (partial && threadIdx.x == 0) partial[blockIdx.x] = s;
 }
 
+// In-place change of basis for a thick restart: basis_c <- sum_{j<m} C[j][c] basis_j
+// for c < l (C row-major, m x l, l <= kMaxKeep).  Each thread owns its
+// elements and reads all m of them before it writes, so the overwrite is safe.
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_basis_rotate_kernel(T* __restrict__ basis,
+                                                                  int64_t ld, int m, int l,
+                                                                  const double* __restrict__ C,
+                                                                  int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)kThreads + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * kThreads) {
+    double acc[kMaxKeep];
+#pragma unroll
+    for (int c = 0; c < kMaxKeep; ++c) acc[c] = 0.0;
+    for (int j = 0; j < m; ++j) {
+      const double x = (double)basis[(int64_t)j * ld + i];
+#pragma unroll
+      for (int c = 0; c < kMaxKeep; ++c)
+        if (c < l) acc[c] += C[(int64_t)j * l + c] * x;
+    }
+#pragma unroll
+    for (int c = 0; c < kMaxKeep; ++c)
+      if (c < l) basis[(int64_t)c * ld + i] = (T)acc[c];
+  }
+}
+
 // coef[k] *= scale[k]^2: <v_k, w> v_k = s_k^2 <u_k, w> u_k for unnormalised u_k
 __global__ void k_coef_scale2_kernel(double* __restrict__ coef, const double* __restrict__ scale,
                                      int m) {
@@ -402,6 +427,23 @@ edx_status k_multi_dot(int vtype, const void* basis, int64_t ld, int m, const vo
   else
     hipLaunchKernelGGL(k_multi_dot_kernel<float>, dim3(g), dim3(kThreads), 0, st,
                        (const float*)basis, ld, m, (const float*)w, n, partial, kMaxPartials);
+  EDX_HIP(hipGetLastError());
+  return EDX_OK;
+}
+
+edx_status k_basis_rotate(int vtype, void* basis, int64_t ld, int m, int l, const double* C,
+                          int64_t n, hipStream_t st) {
+  if (l < 1 || l > kMaxKeep || m < l) {
+    set_error("basis_rotate: need 1 <= l <= " + std::to_string(kMaxKeep) + " and l <= m");
+    return EDX_E_INVALID;
+  }
+  const int g = elem_blocks(n);
+  if (vtype == EDX_F64)
+    hipLaunchKernelGGL(k_basis_rotate_kernel<double>, dim3(g), dim3(kThreads), 0, st,
+                       (double*)basis, ld, m, l, C, n);
+  else
+    hipLaunchKernelGGL(k_basis_rotate_kernel<float>, dim3(g), dim3(kThreads), 0, st,
+                       (float*)basis, ld, m, l, C, n);
   EDX_HIP(hipGetLastError());
   return EDX_OK;
 }

@@ -485,6 +485,65 @@ size_t lowest_ws_layout(int64_t vlen, int vtype, int niter, int k, int hvb, char
   return off + align_up((size_t)vlen * vbytes(vtype)) * (size_t)(k + 2);
 }
 
+// Thick restart.  Keeping l orthonormal Ritz vectors x = V Y of a run that hit
+// niter gives H x = x G + v_m s^T with G = Y^T T Y (l x l) and s = beta_m Y[m-1, :];
+// with v_m appended the projected matrix is the arrow [[G, s], [s^T, .]].
+// Householder reflections on the first l indices, taken from the last row up,
+// bring it back to tridiagonal form without moving v_m, so the recurrence
+// continues from step l as a plain Lanczos run would.  A is (l+1) x (l+1),
+// row-major; on return a[0..l) is the diagonal, b[1..l] the couplings (b[i]
+// between i-1 and i, b[l] between l-1 and v_m), all >= 0, and Q (l x l,
+// row-major) the change of basis of the kept vectors.
+void arrow_to_tridiag(std::vector<double> A, int l, double* a, double* b,
+                      std::vector<double>& Q) {
+  const int n = l + 1;
+  Q.assign((size_t)l * l, 0.0);
+  for (int i = 0; i < l; ++i) Q[(size_t)i * l + i] = 1.0;
+  auto at = [&](int i, int j) -> double& { return A[(size_t)i * n + j]; };
+  std::vector<double> u(n);
+  for (int r = l; r >= 2; --r) {
+    // reflect x = A[r, 0..r) onto a multiple of e_{r-1}
+    double low = 0.0, nrm = 0.0;
+    for (int k = 0; k < r; ++k) {
+      nrm += at(r, k) * at(r, k);
+      if (k < r - 1) low += at(r, k) * at(r, k);
+    }
+    if (low == 0.0) continue;
+    nrm = std::sqrt(nrm);
+    const double al = at(r, r - 1) >= 0.0 ? -nrm : nrm;
+    double un = 0.0;
+    for (int k = 0; k < r; ++k) {
+      u[k] = at(r, k) - (k == r - 1 ? al : 0.0);
+      un += u[k] * u[k];
+    }
+    un = std::sqrt(un);
+    for (int k = 0; k < r; ++k) u[k] /= un;
+    for (int c = 0; c < n; ++c) {            // A <- P A
+      double t = 0.0;
+      for (int k = 0; k < r; ++k) t += u[k] * at(k, c);
+      for (int k = 0; k < r; ++k) at(k, c) -= 2.0 * u[k] * t;
+    }
+    for (int i = 0; i < n; ++i) {            // A <- A P
+      double t = 0.0;
+      for (int k = 0; k < r; ++k) t += at(i, k) * u[k];
+      for (int k = 0; k < r; ++k) at(i, k) -= 2.0 * t * u[k];
+    }
+    for (int i = 0; i < l; ++i) {            // Q <- Q P
+      double t = 0.0;
+      for (int k = 0; k < r; ++k) t += Q[(size_t)i * l + k] * u[k];
+      for (int k = 0; k < r; ++k) Q[(size_t)i * l + k] -= 2.0 * t * u[k];
+    }
+  }
+  for (int i = 0; i < l; ++i) a[i] = at(i, i);
+  for (int i = 1; i <= l; ++i) b[i] = at(i, i - 1);
+  // signs: flip kept vectors so every coupling is >= 0 (v_m keeps its sign)
+  std::vector<double> d(n, 1.0);
+  for (int i = l; i >= 1; --i) d[i - 1] = b[i] * d[i] < 0.0 ? -1.0 : 1.0;
+  for (int i = 1; i <= l; ++i) b[i] = std::fabs(b[i]);
+  for (int i = 0; i < l; ++i)
+    for (int c = 0; c < l; ++c) Q[(size_t)i * l + c] *= d[c];
+}
+
 // w -= sum_k <x_k, w> x_k over nl orthonormal x_k, twice; L.partial then holds
 // the partial sums of |w|^2 (multi_blocks(n) of them)
 edx_status project_out(int vtype, void* w, const char* X, const LanczosWs& L, int nl, int64_t n,
@@ -510,6 +569,85 @@ edx_status ritz_combination(int vtype, const LanczosWs& L, int m, const std::vec
   EDX_TRY(k_multi_axpy(vtype, out, L.vec, (int64_t)(L.vstride / vbytes(vtype)), m, L.coef, n,
                        nullptr, st));
   EDX_HIP(hipStreamSynchronize(st));   // coef is a host temporary
+  return EDX_OK;
+}
+
+constexpr int kMaxRestarts = 64;   // thick restarts per run
+
+// Thick restart of a run whose basis holds mm vectors: the lowest lk Ritz
+// vectors become basis vectors 0..lk-1, v_mm becomes vector lk, and alpha,
+// beta, scale (device) and ha, hb (host) describe the tridiagonal of the new
+// basis (arrow_to_tridiag), so the next step is j = lk.
+edx_status thick_restart(const edx_sector* s, int vtype, const LanczosWs& L, int mm, int lk,
+                         std::vector<double>& ha, std::vector<double>& hb, hipStream_t st) {
+  const int64_t n = s->vlen;
+  const int64_t ldv = (int64_t)(L.vstride / vbytes(vtype));
+  // Ritz coefficient vectors, orthonormalised (a cluster of Ritz values can
+  // give nearly parallel inverse-iteration vectors)
+  std::vector<std::vector<double>> Y(lk, std::vector<double>(mm));
+  for (int i = 0; i < lk; ++i) {
+    const double th = tridiag_lowest(ha.data(), hb.data() + 1, mm, i);
+    tridiag_vector(ha.data(), hb.data() + 1, mm, th, Y[i].data());
+    for (int q = 0; q < i; ++q) {
+      double d = 0.0;
+      for (int j = 0; j < mm; ++j) d += Y[q][j] * Y[i][j];
+      for (int j = 0; j < mm; ++j) Y[i][j] -= d * Y[q][j];
+    }
+    double nn = 0.0;
+    for (int j = 0; j < mm; ++j) nn += Y[i][j] * Y[i][j];
+    nn = std::sqrt(nn);
+    for (int j = 0; j < mm; ++j) Y[i][j] /= nn;
+  }
+  // arrow matrix: G = Y^T T Y and s = beta_mm Y[mm-1, :]
+  std::vector<double> A((size_t)(lk + 1) * (lk + 1), 0.0), TY(mm);
+  for (int c = 0; c < lk; ++c) {
+    const std::vector<double>& y = Y[c];
+    for (int j = 0; j < mm; ++j) {
+      double t = ha[j] * y[j];
+      if (j > 0) t += hb[j] * y[j - 1];
+      if (j + 1 < mm) t += hb[j + 1] * y[j + 1];
+      TY[j] = t;
+    }
+    for (int r = 0; r < lk; ++r) {
+      double g = 0.0;
+      for (int j = 0; j < mm; ++j) g += Y[r][j] * TY[j];
+      A[(size_t)r * (lk + 1) + c] = g;
+    }
+    A[(size_t)lk * (lk + 1) + c] = A[(size_t)c * (lk + 1) + lk] = hb[mm] * y[mm - 1];
+  }
+  for (int r = 0; r < lk; ++r)        // symmetrise the rounding
+    for (int c = 0; c < r; ++c) {
+      const double g = 0.5 * (A[(size_t)r * (lk + 1) + c] + A[(size_t)c * (lk + 1) + r]);
+      A[(size_t)r * (lk + 1) + c] = A[(size_t)c * (lk + 1) + r] = g;
+    }
+  std::vector<double> na(lk), nb(lk + 1), Q;
+  arrow_to_tridiag(A, lk, na.data(), nb.data(), Q);
+  // C[j][c] = scale_j sum_i Y_i[j] Q[i][c]: the stored u_j are unnormalised
+  std::vector<double> hs(mm + 1);
+  EDX_HIP(hipMemcpyAsync(hs.data(), L.scale, sizeof(double) * (mm + 1), hipMemcpyDeviceToHost,
+                         st));
+  EDX_HIP(hipStreamSynchronize(st));
+  std::vector<double> C((size_t)mm * lk, 0.0);
+  for (int j = 0; j < mm; ++j)
+    for (int c = 0; c < lk; ++c) {
+      double t = 0.0;
+      for (int i = 0; i < lk; ++i) t += Y[i][j] * Q[(size_t)i * lk + c];
+      C[(size_t)j * lk + c] = hs[j] * t;
+    }
+  EDX_HIP(hipMemcpyAsync(L.partial, C.data(), sizeof(double) * C.size(), hipMemcpyHostToDevice,
+                         st));
+  EDX_TRY(k_basis_rotate(vtype, L.vec, ldv, mm, lk, L.partial, n, st));
+  EDX_HIP(hipMemcpyAsync(L.vec + (size_t)lk * L.vstride, L.vec + (size_t)mm * L.vstride,
+                         (size_t)n * vbytes(vtype), hipMemcpyDeviceToDevice, st));
+  std::vector<double> sc(lk + 1, 1.0), be(lk + 1, 0.0);
+  sc[lk] = hs[mm];
+  for (int i = 1; i <= lk; ++i) be[i] = nb[i];
+  EDX_HIP(hipMemcpyAsync(L.scale, sc.data(), sizeof(double) * (lk + 1), hipMemcpyHostToDevice, st));
+  EDX_HIP(hipMemcpyAsync(L.alpha, na.data(), sizeof(double) * lk, hipMemcpyHostToDevice, st));
+  EDX_HIP(hipMemcpyAsync(L.beta, be.data(), sizeof(double) * (lk + 1), hipMemcpyHostToDevice, st));
+  EDX_HIP(hipStreamSynchronize(st));   // the sources are host temporaries
+  for (int i = 0; i < lk; ++i) ha[i] = na[i];
+  for (int i = 0; i <= lk; ++i) hb[i] = be[i];
   return EDX_OK;
 }
 
@@ -560,7 +698,7 @@ edx_status lowest_states_impl(const edx_sector* s, int k, const edx_lanczos_opts
     // states aimed at in this run: all that remain when the run may be long,
     // fewer when niter bounds it (a short Krylov space converges only its
     // lowest few Ritz pairs; the restart then keeps their vectors)
-    const int want = checking ? 1 : std::min(k - nl, std::max(1, niter / 16));
+    const int want = checking ? 1 : std::min(k - nl, std::max(1, niter / 4));
     char* stage = slot(nl);         // first free slot (slot k while checking)
     // start vector, orthogonal to the locked states
     if (from_staging) {
@@ -577,7 +715,7 @@ edx_status lowest_states_impl(const edx_sector* s, int k, const edx_lanczos_opts
     ++runs;
 
     // Lanczos run with full re-orthogonalisation and deflation
-    int m = 0, done = 0;
+    int m = 0, done = 0, done_run = 0, restarts = 0;
     double tnorm = 0.0;
     std::vector<double> theta;
     std::vector<std::vector<double>> ys;
@@ -623,10 +761,25 @@ edx_status lowest_states_impl(const edx_sector* s, int k, const edx_lanczos_opts
         lead = lead && ok;
         if (lead) ++nconv;
       }
-      if (nconv == want || bd || upto == niter) m = mm;
+      if (nconv == want || bd) {
+        m = mm;
+      } else if (upto == niter) {
+        // the basis is full: thick restart with the lowest lk Ritz vectors
+        const int lk = std::min({std::max(want + 4, niter / 3), niter / 2, kMaxKeep, mm - 1});
+        if (restarts >= kMaxRestarts || lk < 1) {
+          m = mm;
+        } else {
+          ++restarts;
+          iters += mm - done_run;
+          EDX_TRY(thick_restart(s, vtype, L, mm, lk, ha, hb, st));
+          done_run = lk;
+          done = lk;
+          continue;
+        }
+      }
       done = upto;
     }
-    iters += m;
+    iters += m - done_run;
     // orthonormalise the Ritz coefficient vectors (modified Gram-Schmidt):
     // a tight cluster of Ritz values can give nearly parallel inverse-iteration vectors
     for (size_t i = 0; i < ys.size(); ++i) {

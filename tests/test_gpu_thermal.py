@@ -107,6 +107,35 @@ def test_lowest_states_larger_sector(edx):
     assert np.abs(H @ X - X * e[None, :]).max() <= 1e-7 * _hscale(m)
 
 
+@pytest.mark.parametrize("niter", [60, 32])
+def test_lowest_states_thick_restart(edx, niter):
+    """A basis far smaller than the iterations needed: the run restarts from
+    its lowest Ritz vectors (thick restart) and still converges all 8 states.
+    Ns = 10 (D = 63,504) against ARPACK on the explicit matrix."""
+    m = inputs.make_model(1, 9, 2.0, seed=75, symmetric=False)
+    sec = (5, 5)
+    H = fock.explicit_hamiltonian(m, *sec)
+    ref = np.sort(spla.eigsh(H, k=8, which="SA", tol=1e-13)[0])
+    S = edx.build_sector(m, *sec)
+    e, psi, rep, _ = edx.lanczos_lowest(S, 8, niter=niter, tol=0.0, rtol=1e-10, seed=9)
+    assert rep["nfound"] == 8 and rep["verified"] == 1
+    assert rep["iters"] > niter * rep["runs"]          # restarts happened
+    assert np.abs(e - ref).max() <= 1e-10 * np.abs(ref).max()
+    X = psi.cpu().numpy().T
+    assert np.abs(X.T @ X - np.eye(8)).max() < 1e-10
+    assert np.abs(H @ X - X * e[None, :]).max() <= 1e-7 * _hscale(m)
+
+
+def test_lowest_states_thick_restart_fp32(edx):
+    m, [sec] = inputs.workload("ns8")
+    w = np.linalg.eigvalsh(fock.explicit_hamiltonian(m, *sec).toarray())
+    S = edx.build_sector(m, *sec)
+    e, _, rep, _ = edx.lanczos_lowest(S, 6, vtype="f32", want_psi=False, niter=24, tol=0.0,
+                                      rtol=1e-6, seed=3)
+    assert rep["nfound"] == 6
+    assert np.abs(e - w[:6]).max() <= 1e-5 * np.abs(w[:6]).max()
+
+
 def test_lowest_rejects(edx):
     m, [sec] = inputs.workload("ns8")
     S = edx.build_sector(m, *sec)
