@@ -611,7 +611,7 @@ def main():
         "roofline": {"bound": "hbm", "achieved": round(r32["gbs"], 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(r32["gbs"] / HBM_PEAK_GBS, 4),
                      "traffic": traffic if single else None,
-                     "kernel": "k_hv_fused<float,8,8,3,false,false>" if single else "k_hv_row + k_hv_col",
+                     "kernel": "k_hv_fused<float,8,8,3,false,false,true>" if single else "k_hv_row + k_hv_col",
                      "traffic_source": tstate},
         # the three views of the headline: algorithmic bytes / time, counter
         # (MALL/HBM-side) bytes / time, each against 8 TB/s and a plain copy

@@ -53,6 +53,7 @@ struct HvArgs {
   const uint8_t* __restrict__ pdw;
   const T* __restrict__ amp;   // [256]
   const T* __restrict__ W;     // [64]
+  const uint8_t* __restrict__ hrow;   // compact spin-up rows (fused pass) or nullptr
 };
 
 template <typename T>
@@ -61,12 +62,14 @@ HvArgs<T> make_args(const edx_sector* s, int64_t ld);
 template <>
 HvArgs<double> make_args<double>(const edx_sector* s, int64_t ld) {
   return HvArgs<double>{s->dup, s->ddw, ld, s->up.hop, s->dw.hop, s->up.wpad, s->dw.wpad,
-                        s->up.e64, s->dw.e64, s->up.pat, s->dw.pat, s->amp64, s->w64};
+                        s->up.e64, s->dw.e64, s->up.pat, s->dw.pat, s->amp64, s->w64,
+                        s->hrow};
 }
 template <>
 HvArgs<float> make_args<float>(const edx_sector* s, int64_t ld) {
   return HvArgs<float>{s->dup, s->ddw, ld, s->up.hop, s->dw.hop, s->up.wpad, s->dw.wpad,
-                       s->up.e32, s->dw.e32, s->up.pat, s->dw.pat, s->amp32, s->w32};
+                       s->up.e32, s->dw.e32, s->up.pat, s->dw.pat, s->amp32, s->w32,
+                       s->hrow};
 }
 
 // ---------------------------------------------------------------- small
@@ -144,33 +147,34 @@ __device__ __forceinline__ void stage_cols(T* __restrict__ vs, const T* __restri
 }
 
 // nc (<= NC) arbitrary columns jc[0..nc) of a vector with column stride ld
-// into a dense LDS image (column c at c * dup).
+// into an interleaved LDS image: element r of column c at r * NC + c, so one
+// spin-up hop reads the NC values it needs from adjacent words.
 template <typename T, int NC>
-__device__ __forceinline__ void stage_list(T* __restrict__ vs, const T* __restrict__ v,
-                                           const int64_t (&jc)[NC], int nc, int64_t dup,
-                                           int64_t ld, T sc) {
-  const int64_t n = (int64_t)nc * dup;
-  auto at = [&](int64_t i) {
-    int64_t base = jc[0] * ld;
-    int64_t off = i;
-#pragma unroll
-    for (int c = 1; c < NC; ++c)
-      if (i >= c * dup) {
-        base = jc[c] * ld;
-        off = i - c * dup;
-      }
-    return v[base + off];
-  };
+__device__ __forceinline__ void stage_interleaved(T* __restrict__ vs, const T* __restrict__ v,
+                                                  const int64_t (&jc)[NC], int nc, int64_t dup,
+                                                  int64_t ld, T sc) {
   const int bd = blockDim.x;
-  int64_t i = threadIdx.x;
-  for (; i + 7 * bd < n; i += 8 * bd) {
-    T x[8];
+  constexpr int U = NC >= 3 ? 4 : 8 / NC;   // rows per thread per pass: 8..12 loads in flight
+  const T* src[NC];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) x[u] = at(i + u * bd);
+  for (int c = 0; c < NC; ++c) src[c] = v + jc[c] * ld;
+  for (int64_t r0 = threadIdx.x; r0 < dup; r0 += (int64_t)U * bd) {
+    T x[NC][U];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) vs[i + u * bd] = x[u] * sc;
+    for (int c = 0; c < NC; ++c)
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int64_t r = r0 + (int64_t)u * bd;
+        x[c][u] = (c < nc && r < dup) ? src[c][r] : T(0);
+      }
+#pragma unroll
+    for (int c = 0; c < NC; ++c)
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int64_t r = r0 + (int64_t)u * bd;
+        if (c < nc && r < dup) vs[r * NC + c] = x[c][u] * sc;
+      }
   }
-  for (; i < n; i += bd) vs[i] = at(i) * sc;
 }
 
 template <int W>
@@ -360,18 +364,51 @@ inline size_t nd_tab_lds(int P, int nt, size_t tsz) {
   return al16((size_t)(P * P + 1) * 4) + al16((size_t)nt * 8) + al16((size_t)nt * tsz);
 }
 
-template <typename T, int WUP, int WDW, int NC, bool ND, bool PH>
+// BUF: the spin-down gathers are buffer loads (resource over v, vbytes bytes):
+// each neighbour column's byte offset sits in a scalar register and every
+// gather of a row shares one 32-bit lane offset, where a global load needs a
+// 64-bit address per lane and gather.  Requires vbytes < 2^32.
+template <typename T>
+__device__ __forceinline__ T buf_load(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+  if constexpr (sizeof(T) == 4) {
+    return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, (int)voff, (int)soff, 0));
+  } else {
+    typedef unsigned int u2 __attribute__((ext_vector_type(2)));
+    const u2 x = __builtin_amdgcn_raw_buffer_load_b64(r, (int)voff, (int)soff, 0);
+    return __longlong_as_double((long long)(((unsigned long long)x.y << 32) | x.x));
+  }
+}
+
+// streaming (non-temporal) buffer store
+template <typename T>
+__device__ __forceinline__ void buf_store_nt(__amdgpu_buffer_rsrc_t r, uint32_t voff,
+                                             uint32_t soff, T x) {
+  if constexpr (sizeof(T) == 4) {
+    __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(x), r, (int)voff, (int)soff, 2);
+  } else {
+    typedef unsigned int u2 __attribute__((ext_vector_type(2)));
+    const unsigned long long b = (unsigned long long)__double_as_longlong(x);
+    u2 y;
+    y.x = (unsigned)b;
+    y.y = (unsigned)(b >> 32);
+    __builtin_amdgcn_raw_buffer_store_b64(y, r, (int)voff, (int)soff, 2);
+  }
+}
+
+template <typename T, int WUP, int WDW, int NC, bool ND, bool PH, bool BUF>
 __global__ __launch_bounds__(1024) void k_hv_fused(HvArgs<T> a, const T* __restrict__ v,
                                                    T* __restrict__ w,
                                                    const double* __restrict__ vscale,
                                                    double* __restrict__ partial, int order,
                                                    const int32_t* __restrict__ corder,
-                                                   NdTab<T> nd, PhArgs<T> ph) {
+                                                   NdTab<T> nd, PhArgs<T> ph, uint32_t vbytes) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  T* amp = reinterpret_cast<T*>(smem_raw);
+  // LDS: the staged columns first (at offset 0, so a spin-up hop's address is
+  // a single multiply), then the amplitude and W tables and the reduction slots
+  T* vs = reinterpret_cast<T*>(smem_raw);
+  T* amp = reinterpret_cast<T*>(smem_raw + al16((size_t)NC * a.dup * sizeof(T)));
   T* Wt = amp + kAmpTable;
   double* red = reinterpret_cast<double*>(Wt + 64);
-  T* vs = reinterpret_cast<T*>(red + 16);
   const int64_t dup = a.dup, ld = a.ld;
   // with ND the spin-exchange / pair-hopping table follows the columns:
   // offsets, (row shift, column shift) pairs, amplitudes
@@ -379,8 +416,7 @@ __global__ __launch_bounds__(1024) void k_hv_fused(HvArgs<T> a, const T* __restr
   int2* n_dud = nullptr;
   T* n_amp = nullptr;
   if (ND) {
-    unsigned char* q = reinterpret_cast<unsigned char*>(vs + NC * dup);
-    q = reinterpret_cast<unsigned char*>(al16(reinterpret_cast<uintptr_t>(q)));
+    unsigned char* q = reinterpret_cast<unsigned char*>(red + 16);
     n_off = reinterpret_cast<int*>(q);
     n_dud = reinterpret_cast<int2*>(q + al16((size_t)(nd.P * nd.P + 1) * 4));
     n_amp = reinterpret_cast<T*>(reinterpret_cast<unsigned char*>(n_dud) +
@@ -415,8 +451,9 @@ __global__ __launch_bounds__(1024) void k_hv_fused(HvArgs<T> a, const T* __restr
   const T sc = vscale ? (T)(*vscale) : T(1);
   for (int i = threadIdx.x; i < kAmpTable; i += blockDim.x) amp[i] = a.amp[i];
   for (int i = threadIdx.x; i < 64; i += blockDim.x) Wt[i] = a.W[i];
-  stage_list<T, NC>(vs, v, jc, nc, dup, ld, sc);
+  stage_interleaved<T, NC>(vs, v, jc, nc, dup, ld, sc);
   gptr<T> gcol[NC][WDW];   // neighbour columns (block-uniform)
+  uint32_t goff[NC][WDW];  // BUF: their byte offsets from v
   T gamp[NC][WDW];         // their amplitudes times the vector scale
   T ed[NC];
   int pd[NC];
@@ -430,9 +467,31 @@ __global__ __launch_bounds__(1024) void k_hv_fused(HvArgs<T> a, const T* __restr
 #pragma unroll
     for (int k = 0; k < WDW; ++k) {
       const uint32_t f = a.hdw[j * WDW + k];
-      gcol[c][k] = uniform(v + (int64_t)(f & kColMask) * ld);
+      if constexpr (BUF)
+        goff[c][k] = __builtin_amdgcn_readfirstlane(
+            (uint32_t)((uint64_t)(f & kColMask) * (uint64_t)ld * sizeof(T)));
+      else
+        gcol[c][k] = uniform(v + (int64_t)(f & kColMask) * ld);
       gamp[c][k] = uniform(a.amp[f >> kAmpShift] * sc);
     }
+  }
+  // BUF: buffer resources over v, w and the row tables; every row offset is
+  // 32-bit and the store offsets of the NC output columns are block-uniform
+  constexpr int HW = 3 * WUP / 4;   // 32-bit words of a compact spin-up row
+  __amdgpu_buffer_rsrc_t vres, wres, hres, eres, pres;
+  uint32_t woff[NC];
+  if constexpr (BUF) {
+    vres = __builtin_amdgcn_make_buffer_rsrc(const_cast<T*>(v), 0, (int)vbytes, 0x00020000);
+    wres = __builtin_amdgcn_make_buffer_rsrc(w, 0, (int)vbytes, 0x00020000);
+    hres = __builtin_amdgcn_make_buffer_rsrc(const_cast<uint8_t*>(a.hrow), 0,
+                                             (int)(dup * HW * 4), 0x00020000);
+    eres = __builtin_amdgcn_make_buffer_rsrc(const_cast<T*>(a.eup), 0, (int)(dup * sizeof(T)),
+                                             0x00020000);
+    pres = __builtin_amdgcn_make_buffer_rsrc(const_cast<uint8_t*>(a.pup), 0, (int)dup,
+                                             0x00020000);
+#pragma unroll
+    for (int c = 0; c < NC; ++c)
+      woff[c] = __builtin_amdgcn_readfirstlane((uint32_t)((uint64_t)jc[c] * ld * sizeof(T)));
   }
   __syncthreads();
   double dot = 0.0;
@@ -441,20 +500,57 @@ __global__ __launch_bounds__(1024) void k_hv_fused(HvArgs<T> a, const T* __restr
   // gathers of a row in flight together
   auto rows = [&](auto all_tag) {
     constexpr bool ALL = decltype(all_tag)::value;
-    for (int64_t iu = threadIdx.x; iu < dup; iu += blockDim.x) {
+    // (BUF: a 32-bit row index; D_up < 2^24 always)
+    using RowT = std::conditional_t<BUF, uint32_t, int64_t>;
+    for (RowT iu = threadIdx.x; iu < (RowT)dup; iu += blockDim.x) {
       // the row's own tables first: loads complete in issue order, so the
       // spin-up part can start before the gathers have arrived
-      uint32_t e[WUP];
-      load_row<WUP>(a.hup, iu, e);
-      const T eu = a.eup[iu];
-      const int patu = a.pup[iu];
-      const int pu = patu * 8;
       const uint32_t iu32 = (uint32_t)iu;
+      const uint32_t voff = iu32 * (uint32_t)sizeof(T);
+      // hop k: column col[k] (bits 0..23 of e[k]), amplitude index ai[k]
+      uint32_t e[WUP];
+      uint32_t col[WUP], ai[WUP];
+      T eu;
+      int patu;
+      if constexpr (BUF) {
+        // compact row: 16-bit columns, then 8-bit amplitude indices
+        uint32_t r[HW];
+#pragma unroll
+        for (int q = 0; q < HW / 2; ++q) {
+          typedef unsigned int u2 __attribute__((ext_vector_type(2)));
+          const u2 x = __builtin_amdgcn_raw_buffer_load_b64(hres, (int)(iu32 * HW * 4 + q * 8),
+                                                            0, 0);
+          r[2 * q] = x.x;
+          r[2 * q + 1] = x.y;
+        }
+        eu = buf_load<T>(eres, voff, 0);
+        patu = __builtin_amdgcn_raw_buffer_load_b8(pres, (int)iu32, 0, 0);
+#pragma unroll
+        for (int k = 0; k < WUP; ++k) {
+          col[k] = (r[k >> 1] >> (16 * (k & 1))) & 0xFFFFu;
+          ai[k] = (r[WUP / 2 + (k >> 2)] >> (8 * (k & 3))) & 0xFFu;
+        }
+      } else {
+        load_row<WUP>(a.hup, iu, e);
+        eu = a.eup[iu];
+        patu = a.pup[iu];
+#pragma unroll
+        for (int k = 0; k < WUP; ++k) {
+          col[k] = e[k] & kColMask;
+          ai[k] = e[k] >> kAmpShift;
+        }
+      }
+      const int pu = patu * 8;
       T g[NC][WDW];
 #pragma unroll
       for (int c = 0; c < NC; ++c)
 #pragma unroll
-        for (int k = 0; k < WDW; ++k) g[c][k] = gcol[c][k][iu32];
+        for (int k = 0; k < WDW; ++k) {
+          if constexpr (BUF)
+            g[c][k] = buf_load<T>(vres, voff, goff[c][k]);
+          else
+            g[c][k] = gcol[c][k][iu32];
+        }
       // phonon neighbours: the same element one slice back / ahead, issued
       // with the gathers so that their latency overlaps
       T pv[NC], pn[NC];
@@ -473,14 +569,14 @@ __global__ __launch_bounds__(1024) void k_hv_fused(HvArgs<T> a, const T* __restr
       for (int c = 0; c < NC; ++c) acc[c] = T(0);
 #pragma unroll
       for (int k = 0; k < WUP; ++k) {
-        const T am = amp[e[k] >> kAmpShift];
-        const int64_t col = e[k] & kColMask;
+        const T ak = amp[ai[k]];
+        const T* src = vs + __umul24(col[k], (uint32_t)NC);
 #pragma unroll
-        for (int c = 0; c < NC; ++c) acc[c] += am * vs[c * dup + col];
+        for (int c = 0; c < NC; ++c) acc[c] += ak * src[c];
       }
 #pragma unroll
       for (int c = 0; c < NC; ++c) {
-        const T x = vs[c * dup + iu];
+        const T x = vs[iu32 * (uint32_t)NC + c];
         T s2 = T(0);
 #pragma unroll
         for (int k = 0; k < WDW; ++k) s2 += gamp[c][k] * g[c][k];
@@ -500,7 +596,10 @@ __global__ __launch_bounds__(1024) void k_hv_fused(HvArgs<T> a, const T* __restr
         if (ALL || c < nc) {
           // streaming store: w is not read again in this pass, so it should
           // not displace the neighbour columns the gathers reuse from L2
-          __builtin_nontemporal_store(res, &w[iu + jc[c] * ld]);
+          if constexpr (BUF)
+            buf_store_nt<T>(wres, voff, woff[c], res);
+          else
+            __builtin_nontemporal_store(res, &w[iu + jc[c] * ld]);
           dot += (double)x * (double)res;
         }
       }
@@ -767,7 +866,7 @@ edx_status hv_validate(const edx_sector* s, int vtype, HvPlan* p) {
   }
   const size_t ndl = (nd_lds_terms(s) > 0 && p->mode == 2)
                          ? 16 + nd_tab_lds(1 << s->model.norb, nd_lds_terms(s), sz) : 0;
-  if (smem_header() + (size_t)p->col_cols * s->dup * sz + ndl > 160 * 1024) {
+  if (smem_header() + (size_t)p->col_cols * s->dup * sz + 16 + ndl > 160 * 1024) {
     set_error("hv plan: columns do not fit in LDS");
     return EDX_E_UNSUPPORTED;
   }
@@ -809,14 +908,14 @@ struct FusedOrder {
   PhArgs<T> pa{};
 };
 
-template <typename T, int WUP, int WDW, int NC, bool ND, bool PH>
+template <typename T, int WUP, int WDW, int NC, bool ND, bool PH, bool BUF = false>
 edx_status launch_fused_n(const HvArgs<T>& a, int nblk, int nthr, size_t lds, hipStream_t st,
                           const T* v, T* w, const double* vscale, double* partial,
-                          FusedOrder<T> fo, const NdTab<T>& nd) {
-  const void* kern = (const void*)k_hv_fused<T, WUP, WDW, NC, ND, PH>;
+                          FusedOrder<T> fo, const NdTab<T>& nd, uint32_t vbytes = 0) {
+  const void* kern = (const void*)k_hv_fused<T, WUP, WDW, NC, ND, PH, BUF>;
   EDX_HIP(hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-  hipLaunchKernelGGL((k_hv_fused<T, WUP, WDW, NC, ND, PH>), dim3(nblk), dim3(nthr), lds, st, a,
-                     v, w, vscale, partial, fo.order, fo.corder, nd, fo.pa);
+  hipLaunchKernelGGL((k_hv_fused<T, WUP, WDW, NC, ND, PH, BUF>), dim3(nblk), dim3(nthr), lds, st,
+                     a, v, w, vscale, partial, fo.order, fo.corder, nd, fo.pa, vbytes);
   EDX_HIP(hipGetLastError());
   return EDX_OK;
 }
@@ -831,6 +930,13 @@ edx_status launch_fused_k(const HvArgs<T>& a, int nblk, int nthr, size_t lds, hi
   if (fo.ph)
     return launch_fused_n<T, WUP, WDW, NC, false, true>(a, nblk, nthr, lds, st, v, w, vscale,
                                                         partial, fo, fo.nd);
+  // the electronic pass of a whole vector: buffer-load gathers when every
+  // byte offset into v fits in 32 bits
+  const uint64_t vb = (uint64_t)a.ld * (uint64_t)a.ddw * sizeof(T);
+  if (vb <= 0xFFFFFFFFull && a.hrow)
+    return launch_fused_n<T, WUP, WDW, NC, false, false, true>(a, nblk, nthr, lds, st, v, w,
+                                                               vscale, partial, fo, fo.nd,
+                                                               (uint32_t)vb);
   return launch_fused_n<T, WUP, WDW, NC, false, false>(a, nblk, nthr, lds, st, v, w, vscale,
                                                        partial, fo, fo.nd);
 }
@@ -932,7 +1038,7 @@ edx_status launch_t(const edx_sector* s, const T* v, T* w, int64_t ld, const dou
     nd = NdTab<T>{s->nd_off, s->nd_du, s->nd_dd, nd_amp<T>(s), 1 << s->model.norb, s->nd_nt};
     ndl = 16 + nd_tab_lds(nd.P, nd.nt, sizeof(T));
   }
-  const size_t lds = hdr + (size_t)p.col_cols * s->dup * sizeof(T) + ndl;
+  const size_t lds = hdr + (size_t)p.col_cols * s->dup * sizeof(T) + 16 + ndl;
   const int nthr = p.col_threads;
   if (lds > 160 * 1024) {
     set_error("hv: column does not fit in LDS (D_up too large)");

@@ -161,6 +161,22 @@ __global__ void k_diag(const uint32_t* __restrict__ map, int64_t D, int norb,
   }
 }
 
+// Compact spin-up hop rows for the fused pass (D_up < 2^16): per row the wpad
+// columns as 16-bit words, then the wpad amplitude indices (entry >> 24) as bytes.
+__global__ void k_hrow(const uint32_t* __restrict__ hop, int wpad, int64_t D,
+                       uint8_t* __restrict__ out) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < D;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    uint16_t* c = reinterpret_cast<uint16_t*>(out + i * 3 * wpad);
+    uint8_t* x = out + i * 3 * wpad + 2 * wpad;
+    for (int k = 0; k < wpad; ++k) {
+      const uint32_t f = hop[i * wpad + k];
+      c[k] = (uint16_t)(f & 0xFFFFu);
+      x[k] = (uint8_t)(f >> kAmpShift);
+    }
+  }
+}
+
 template <typename P>
 edx_status dalloc(edx_sector* S, P** p, size_t bytes) {
   bytes = std::max<size_t>(bytes, 1);
@@ -277,6 +293,7 @@ void destroy_sector(edx_sector* s) {
   if (!shared) free_spin(s, s->dw);
   dfree(s, s->amp64);
   dfree(s, s->amp32);
+  dfree(s, s->hrow);
   dfree(s, s->w64);
   dfree(s, s->zeros);
   dfree(s, s->w32);
@@ -476,6 +493,7 @@ size_t sector_table_bytes(int ns, int nup, int ndw) {
   b += (size_t)comb(ns, ndw) * 4 + a;   // column order
   b += 6 * a + 65 * 4 + 64 * 12 * (4 + 4 + 8 + 4);   // H_nd term table
   b += 8 * ((size_t)std::max(comb(ns, nup), comb(ns, ndw)) + 64) + a;   // zero block
+  b += (size_t)comb(ns, nup) * 3 * 24 + a;   // compact spin-up rows
   return b;
 }
 
@@ -581,6 +599,15 @@ edx_status build_sector_impl(const Model& m, int nup, int ndw, hipStream_t st,
   EDX_HIP(hipMemcpyAsync(S->amp32, ampf, sizeof(ampf), hipMemcpyHostToDevice, st));
   EDX_HIP(hipMemcpyAsync(S->w64, W, sizeof(W), hipMemcpyHostToDevice, st));
   EDX_HIP(hipMemcpyAsync(S->w32, Wf, sizeof(Wf), hipMemcpyHostToDevice, st));
+  if (S->dup < 65536) {
+    // compact spin-up rows of the fused pass
+    const int64_t D = S->dup;
+    const int wp = S->up.wpad;
+    EDX_TRY(dalloc(S.get(), &S->hrow, (size_t)D * 3 * wp));
+    hipLaunchKernelGGL(k_hrow, dim3((unsigned)std::min<int64_t>((D + 255) / 256, 4096)), dim3(256),
+                       0, st, S->up.hop, wp, D, S->hrow);
+    EDX_HIP(hipGetLastError());
+  }
   if (S->dph > 1) EDX_TRY(build_ph_terms(S.get(), m, binom, W, st));
   {
     const size_t zb = sizeof(double) * ((size_t)std::max(S->dup, S->ddw) + 64);
