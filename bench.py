@@ -231,7 +231,8 @@ def bench_orbital(edx, torch, a):
 
 def bench_lowest_and_thermal(edx, torch, a):
     """Several low-lying states and finite temperature: the 8 lowest states of
-    the Ns=12 6/6 sector (FP64, locking + check run), and the eigenstate list
+    the Ns=12 6/6 sector (FP64, locking + check run; basis of 400 vectors, and of
+    50 with thick restarts), and the eigenstate list
     plus thermal G and spin susceptibility over every sector of an Ns=8 model
     (beta=10, cutoff 1e-6, 3 annealing calls)."""
     from paper_2105_06806_amd import inputs
@@ -245,6 +246,16 @@ def bench_lowest_and_thermal(edx, torch, a):
     out["lowest8_ns12"] = {"s": round(time.perf_counter() - t0, 3), "runs": rep["runs"],
                            "iters": rep["iters"], "verified": rep["verified"],
                            "gaps": [round(float(x - e[0]), 6) for x in e]}
+    # the same 8 states from a 50-vector basis (thick restarts)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e50, _, rep, st = edx.lanczos_lowest(S, 8, want_psi=False, niter=50, tol=0.0, rtol=1e-10,
+                                         seed=5, allow=(edx.EDX_E_NOCONV,))
+    out["lowest8_ns12_niter50"] = {"s": round(time.perf_counter() - t0, 3), "runs": rep["runs"],
+                                   "iters": rep["iters"], "verified": rep["verified"],
+                                   "nfound": rep["nfound"],
+                                   "max_dev_vs_niter400": float(np.abs(e50 - e).max())
+                                   if len(e50) == len(e) else None}
     m8, _ = inputs.workload("ns8")
     secs = [(x, y) for x in range(9) for y in range(9)]
     Ss = [edx.build_sector(m8, *q) for q in secs]

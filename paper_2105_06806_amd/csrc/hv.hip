@@ -146,35 +146,91 @@ __device__ __forceinline__ void stage_cols(T* __restrict__ vs, const T* __restri
   for (; i < n; i += bd) vs[i] = at(i) * sc;
 }
 
+// BUF: the spin-down gathers are buffer loads (resource over v, vbytes bytes):
+// each neighbour column's byte offset sits in a scalar register and every
+// gather of a row shares one 32-bit lane offset, where a global load needs a
+// 64-bit address per lane and gather.  Requires vbytes < 2^32.
+template <typename T>
+__device__ __forceinline__ T buf_load(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+  if constexpr (sizeof(T) == 4) {
+    return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, (int)voff, (int)soff, 0));
+  } else {
+    typedef unsigned int u2 __attribute__((ext_vector_type(2)));
+    const u2 x = __builtin_amdgcn_raw_buffer_load_b64(r, (int)voff, (int)soff, 0);
+    return __longlong_as_double((long long)(((unsigned long long)x.y << 32) | x.x));
+  }
+}
+
+// streaming (non-temporal) buffer store
+template <typename T>
+__device__ __forceinline__ void buf_store_nt(__amdgpu_buffer_rsrc_t r, uint32_t voff,
+                                             uint32_t soff, T x) {
+  if constexpr (sizeof(T) == 4) {
+    __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(x), r, (int)voff, (int)soff, 2);
+  } else {
+    typedef unsigned int u2 __attribute__((ext_vector_type(2)));
+    const unsigned long long b = (unsigned long long)__double_as_longlong(x);
+    u2 y;
+    y.x = (unsigned)b;
+    y.y = (unsigned)(b >> 32);
+    __builtin_amdgcn_raw_buffer_store_b64(y, r, (int)voff, (int)soff, 2);
+  }
+}
+
 // nc (<= NC) arbitrary columns jc[0..nc) of a vector with column stride ld
 // into an interleaved LDS image: element r of column c at r * NC + c, so one
-// spin-up hop reads the NC values it needs from adjacent words.
-template <typename T, int NC>
-__device__ __forceinline__ void stage_interleaved(T* __restrict__ vs, const T* __restrict__ v,
-                                                  const int64_t (&jc)[NC], int nc, int64_t dup,
-                                                  int64_t ld, T sc) {
+// spin-up hop reads the NC values it needs from adjacent words.  In passes of
+// U rows per thread: stage_issue puts every load of a pass in flight (one
+// memory latency per pass; for Ns = 16 FP32 and NC = 3 one pass covers the
+// columns), stage_put scales and stores them, so the block-uniform set-up can
+// run between the two.
+template <typename T, int NC, int U>
+struct StageBuf {
+  T x[NC][U];
+};
+
+template <typename T, int NC, int U>
+__device__ __forceinline__ void stage_issue(StageBuf<T, NC, U>& b, const T* __restrict__ v,
+                                            const int64_t (&jc)[NC], int nc, int64_t dup,
+                                            int64_t ld, int64_t r0) {
   const int bd = blockDim.x;
-  constexpr int U = NC >= 3 ? 4 : 8 / NC;   // rows per thread per pass: 8..12 loads in flight
-  const T* src[NC];
 #pragma unroll
-  for (int c = 0; c < NC; ++c) src[c] = v + jc[c] * ld;
-  for (int64_t r0 = threadIdx.x; r0 < dup; r0 += (int64_t)U * bd) {
-    T x[NC][U];
+  for (int c = 0; c < NC; ++c)
 #pragma unroll
-    for (int c = 0; c < NC; ++c)
+    for (int u = 0; u < U; ++u) {
+      const int64_t r = r0 + (int64_t)u * bd;
+      b.x[c][u] = (c < nc && r < dup) ? v[jc[c] * ld + r] : T(0);
+    }
+}
+
+// the same through a buffer resource over v: one 32-bit lane offset per row,
+// the column offsets (coff, bytes) block-uniform
+template <typename T, int NC, int U>
+__device__ __forceinline__ void stage_issue_buf(StageBuf<T, NC, U>& b, __amdgpu_buffer_rsrc_t r,
+                                                const uint32_t (&coff)[NC], int nc, uint32_t dup,
+                                                uint32_t r0) {
+  const uint32_t bd = blockDim.x;
 #pragma unroll
-      for (int u = 0; u < U; ++u) {
-        const int64_t r = r0 + (int64_t)u * bd;
-        x[c][u] = (c < nc && r < dup) ? src[c][r] : T(0);
-      }
+  for (int c = 0; c < NC; ++c)
 #pragma unroll
-    for (int c = 0; c < NC; ++c)
+    for (int u = 0; u < U; ++u) {
+      const uint32_t row = r0 + (uint32_t)u * bd;
+      b.x[c][u] = (c < nc && row < dup) ? buf_load<T>(r, row * (uint32_t)sizeof(T), coff[c])
+                                        : T(0);
+    }
+}
+
+template <typename T, int NC, int U>
+__device__ __forceinline__ void stage_put(T* __restrict__ vs, const StageBuf<T, NC, U>& b, int nc,
+                                          int64_t dup, int64_t r0, T sc) {
+  const int bd = blockDim.x;
 #pragma unroll
-      for (int u = 0; u < U; ++u) {
-        const int64_t r = r0 + (int64_t)u * bd;
-        if (c < nc && r < dup) vs[r * NC + c] = x[c][u] * sc;
-      }
-  }
+  for (int c = 0; c < NC; ++c)
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t r = r0 + (int64_t)u * bd;
+      if (c < nc && r < dup) vs[r * NC + c] = b.x[c][u] * sc;
+    }
 }
 
 template <int W>
@@ -364,37 +420,6 @@ inline size_t nd_tab_lds(int P, int nt, size_t tsz) {
   return al16((size_t)(P * P + 1) * 4) + al16((size_t)nt * 8) + al16((size_t)nt * tsz);
 }
 
-// BUF: the spin-down gathers are buffer loads (resource over v, vbytes bytes):
-// each neighbour column's byte offset sits in a scalar register and every
-// gather of a row shares one 32-bit lane offset, where a global load needs a
-// 64-bit address per lane and gather.  Requires vbytes < 2^32.
-template <typename T>
-__device__ __forceinline__ T buf_load(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
-  if constexpr (sizeof(T) == 4) {
-    return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, (int)voff, (int)soff, 0));
-  } else {
-    typedef unsigned int u2 __attribute__((ext_vector_type(2)));
-    const u2 x = __builtin_amdgcn_raw_buffer_load_b64(r, (int)voff, (int)soff, 0);
-    return __longlong_as_double((long long)(((unsigned long long)x.y << 32) | x.x));
-  }
-}
-
-// streaming (non-temporal) buffer store
-template <typename T>
-__device__ __forceinline__ void buf_store_nt(__amdgpu_buffer_rsrc_t r, uint32_t voff,
-                                             uint32_t soff, T x) {
-  if constexpr (sizeof(T) == 4) {
-    __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(x), r, (int)voff, (int)soff, 2);
-  } else {
-    typedef unsigned int u2 __attribute__((ext_vector_type(2)));
-    const unsigned long long b = (unsigned long long)__double_as_longlong(x);
-    u2 y;
-    y.x = (unsigned)b;
-    y.y = (unsigned)(b >> 32);
-    __builtin_amdgcn_raw_buffer_store_b64(y, r, (int)voff, (int)soff, 2);
-  }
-}
-
 template <typename T, int WUP, int WDW, int NC, bool ND, bool PH, bool BUF>
 __global__ __launch_bounds__(1024) void k_hv_fused(HvArgs<T> a, const T* __restrict__ v,
                                                    T* __restrict__ w,
@@ -449,9 +474,26 @@ __global__ __launch_bounds__(1024) void k_hv_fused(HvArgs<T> a, const T* __restr
     jc[c] = order == 2 ? (int64_t)__builtin_amdgcn_readfirstlane(corder[jj]) : jj;
   }
   const T sc = vscale ? (T)(*vscale) : T(1);
+  // first staging pass in flight while the tables and the block-uniform
+  // neighbour set-up are loaded
+  // rows per thread per staging pass (BUF: 40 FP32 / 20 FP64 loads in flight;
+  // otherwise as many as leave the larger ND / PH bodies without spills)
+  constexpr int SU = BUF ? std::max(1, (sizeof(T) == 4 ? 40 : 20) / NC)
+                         : (NC >= 3 ? 4 : 8 / NC);
+  StageBuf<T, NC, SU> sb;
+  __amdgpu_buffer_rsrc_t vres;
+  uint32_t coff[NC];   // BUF: byte offsets of the block's columns
+  if constexpr (BUF) {
+    vres = __builtin_amdgcn_make_buffer_rsrc(const_cast<T*>(v), 0, (int)vbytes, 0x00020000);
+#pragma unroll
+    for (int c = 0; c < NC; ++c)
+      coff[c] = __builtin_amdgcn_readfirstlane((uint32_t)((uint64_t)jc[c] * ld * sizeof(T)));
+    stage_issue_buf(sb, vres, coff, nc, (uint32_t)dup, threadIdx.x);
+  } else {
+    stage_issue(sb, v, jc, nc, dup, ld, (int64_t)threadIdx.x);
+  }
   for (int i = threadIdx.x; i < kAmpTable; i += blockDim.x) amp[i] = a.amp[i];
   for (int i = threadIdx.x; i < 64; i += blockDim.x) Wt[i] = a.W[i];
-  stage_interleaved<T, NC>(vs, v, jc, nc, dup, ld, sc);
   gptr<T> gcol[NC][WDW];   // neighbour columns (block-uniform)
   uint32_t goff[NC][WDW];  // BUF: their byte offsets from v
   T gamp[NC][WDW];         // their amplitudes times the vector scale
@@ -475,13 +517,21 @@ __global__ __launch_bounds__(1024) void k_hv_fused(HvArgs<T> a, const T* __restr
       gamp[c][k] = uniform(a.amp[f >> kAmpShift] * sc);
     }
   }
+  stage_put(vs, sb, nc, dup, (int64_t)threadIdx.x, sc);
+  for (int64_t r0 = threadIdx.x + (int64_t)SU * blockDim.x; r0 < dup;
+       r0 += (int64_t)SU * blockDim.x) {
+    if constexpr (BUF)
+      stage_issue_buf(sb, vres, coff, nc, (uint32_t)dup, (uint32_t)r0);
+    else
+      stage_issue(sb, v, jc, nc, dup, ld, r0);
+    stage_put(vs, sb, nc, dup, r0, sc);
+  }
   // BUF: buffer resources over v, w and the row tables; every row offset is
   // 32-bit and the store offsets of the NC output columns are block-uniform
   constexpr int HW = 3 * WUP / 4;   // 32-bit words of a compact spin-up row
-  __amdgpu_buffer_rsrc_t vres, wres, hres, eres, pres;
+  __amdgpu_buffer_rsrc_t wres, hres, eres, pres;
   uint32_t woff[NC];
   if constexpr (BUF) {
-    vres = __builtin_amdgcn_make_buffer_rsrc(const_cast<T*>(v), 0, (int)vbytes, 0x00020000);
     wres = __builtin_amdgcn_make_buffer_rsrc(w, 0, (int)vbytes, 0x00020000);
     hres = __builtin_amdgcn_make_buffer_rsrc(const_cast<uint8_t*>(a.hrow), 0,
                                              (int)(dup * HW * 4), 0x00020000);
@@ -490,8 +540,7 @@ __global__ __launch_bounds__(1024) void k_hv_fused(HvArgs<T> a, const T* __restr
     pres = __builtin_amdgcn_make_buffer_rsrc(const_cast<uint8_t*>(a.pup), 0, (int)dup,
                                              0x00020000);
 #pragma unroll
-    for (int c = 0; c < NC; ++c)
-      woff[c] = __builtin_amdgcn_readfirstlane((uint32_t)((uint64_t)jc[c] * ld * sizeof(T)));
+    for (int c = 0; c < NC; ++c) woff[c] = coff[c];
   }
   __syncthreads();
   double dot = 0.0;
