@@ -485,6 +485,28 @@ size_t lowest_ws_layout(int64_t vlen, int vtype, int niter, int k, int hvb, char
   return off + align_up((size_t)vlen * vbytes(vtype)) * (size_t)(k + 2);
 }
 
+// y -= sum_q <Y_q, y> Y_q over orthonormal Y_q (two passes), then normalise;
+// false if y lies (to 1e-8 of its norm) in their span or is not finite
+bool orthonormalise_against(const std::vector<std::vector<double>>& Y, std::vector<double>& y) {
+  const size_t m = y.size();
+  double n0 = 0.0;
+  for (double x : y) n0 += x * x;
+  n0 = std::sqrt(n0);
+  if (!(n0 > 0.0) || !std::isfinite(n0)) return false;
+  for (int pass = 0; pass < 2; ++pass)
+    for (const std::vector<double>& q : Y) {
+      double d = 0.0;
+      for (size_t j = 0; j < m; ++j) d += q[j] * y[j];
+      for (size_t j = 0; j < m; ++j) y[j] -= d * q[j];
+    }
+  double nn = 0.0;
+  for (double x : y) nn += x * x;
+  nn = std::sqrt(nn);
+  if (!(nn > 1e-8 * n0)) return false;
+  for (double& x : y) x /= nn;
+  return true;
+}
+
 // Thick restart.  Keeping l orthonormal Ritz vectors x = V Y of a run that hit
 // niter gives H x = x G + v_m s^T with G = Y^T T Y (l x l) and s = beta_m Y[m-1, :];
 // with v_m appended the projected matrix is the arrow [[G, s], [s^T, .]].
@@ -578,26 +600,24 @@ constexpr int kMaxRestarts = 64;   // thick restarts per run
 // vectors become basis vectors 0..lk-1, v_mm becomes vector lk, and alpha,
 // beta, scale (device) and ha, hb (host) describe the tridiagonal of the new
 // basis (arrow_to_tridiag), so the next step is j = lk.
-edx_status thick_restart(const edx_sector* s, int vtype, const LanczosWs& L, int mm, int lk,
+edx_status thick_restart(const edx_sector* s, int vtype, const LanczosWs& L, int mm, int& lk,
                          std::vector<double>& ha, std::vector<double>& hb, hipStream_t st) {
   const int64_t n = s->vlen;
   const int64_t ldv = (int64_t)(L.vstride / vbytes(vtype));
-  // Ritz coefficient vectors, orthonormalised (a cluster of Ritz values can
-  // give nearly parallel inverse-iteration vectors)
-  std::vector<std::vector<double>> Y(lk, std::vector<double>(mm));
+  // Ritz coefficient vectors, orthonormalised.  Equal or clustered Ritz values
+  // (a tridiagonal that has split into blocks) give parallel inverse-iteration
+  // vectors: such a vector adds no direction and is dropped, so lk may shrink
+  // (lk = 0: no restart possible)
+  std::vector<std::vector<double>> Y;
   for (int i = 0; i < lk; ++i) {
+    std::vector<double> y(mm);
     const double th = tridiag_lowest(ha.data(), hb.data() + 1, mm, i);
-    tridiag_vector(ha.data(), hb.data() + 1, mm, th, Y[i].data());
-    for (int q = 0; q < i; ++q) {
-      double d = 0.0;
-      for (int j = 0; j < mm; ++j) d += Y[q][j] * Y[i][j];
-      for (int j = 0; j < mm; ++j) Y[i][j] -= d * Y[q][j];
-    }
-    double nn = 0.0;
-    for (int j = 0; j < mm; ++j) nn += Y[i][j] * Y[i][j];
-    nn = std::sqrt(nn);
-    for (int j = 0; j < mm; ++j) Y[i][j] /= nn;
+    tridiag_vector(ha.data(), hb.data() + 1, mm, th, y.data());
+    if (!orthonormalise_against(Y, y)) continue;
+    Y.push_back(std::move(y));
   }
+  lk = (int)Y.size();
+  if (lk == 0) return EDX_OK;
   // arrow matrix: G = Y^T T Y and s = beta_mm Y[mm-1, :]
   std::vector<double> A((size_t)(lk + 1) * (lk + 1), 0.0), TY(mm);
   for (int c = 0; c < lk; ++c) {
@@ -622,6 +642,11 @@ edx_status thick_restart(const edx_sector* s, int vtype, const LanczosWs& L, int
     }
   std::vector<double> na(lk), nb(lk + 1), Q;
   arrow_to_tridiag(A, lk, na.data(), nb.data(), Q);
+  for (int i = 0; i < lk; ++i)
+    if (!std::isfinite(na[i]) || !std::isfinite(nb[i + 1])) {
+      lk = 0;   // leave the basis as it is
+      return EDX_OK;
+    }
   // C[j][c] = scale_j sum_i Y_i[j] Q[i][c]: the stored u_j are unnormalised
   std::vector<double> hs(mm + 1);
   EDX_HIP(hipMemcpyAsync(hs.data(), L.scale, sizeof(double) * (mm + 1), hipMemcpyDeviceToHost,
@@ -711,6 +736,19 @@ edx_status lowest_states_impl(const edx_sector* s, int k, const edx_lanczos_opts
     }
     if (nl > 0) EDX_TRY(project_out(vtype, L.vec, X, L, nl, n, st));
     EDX_TRY(k_beta_finish(L.partial, elem_blocks(n), L.beta, L.scale, st));
+    if (from_staging) {
+      // a staged (unit) Ritz vector that lies in the locked span leaves almost
+      // nothing after the projection: start from a random vector instead
+      double b0 = 0.0;
+      EDX_HIP(hipMemcpyAsync(&b0, L.beta, sizeof(double), hipMemcpyDeviceToHost, st));
+      EDX_HIP(hipStreamSynchronize(st));
+      if (!(b0 > 1e-6)) {
+        EDX_TRY(k_start_vector(vtype, L.vec, s->dup, s->ld, s->ddw * s->dph,
+                               o->seed + 0x9E3779B97F4A7C15ull * (uint64_t)runs, L.partial, st));
+        if (nl > 0) EDX_TRY(project_out(vtype, L.vec, X, L, nl, n, st));
+        EDX_TRY(k_beta_finish(L.partial, elem_blocks(n), L.beta, L.scale, st));
+      }
+    }
     EDX_HIP(hipMemsetAsync(L.beta, 0, sizeof(double), st));
     ++runs;
 
@@ -765,13 +803,16 @@ edx_status lowest_states_impl(const edx_sector* s, int k, const edx_lanczos_opts
         m = mm;
       } else if (upto == niter) {
         // the basis is full: thick restart with the lowest lk Ritz vectors
-        const int lk = std::min({std::max(want + 4, niter / 3), niter / 2, kMaxKeep, mm - 1});
-        if (restarts >= kMaxRestarts || lk < 1) {
-          m = mm;
+        int lk = std::min({std::max(want + 4, niter / 3), niter / 2, kMaxKeep, mm - 1});
+        if (restarts < kMaxRestarts && lk >= 1)
+          EDX_TRY(thick_restart(s, vtype, L, mm, lk, ha, hb, st));
+        else
+          lk = 0;
+        if (lk < 1) {
+          m = mm;   // no restart: the run ends here
         } else {
           ++restarts;
           iters += mm - done_run;
-          EDX_TRY(thick_restart(s, vtype, L, mm, lk, ha, hb, st));
           done_run = lk;
           done = lk;
           continue;
@@ -780,18 +821,19 @@ edx_status lowest_states_impl(const edx_sector* s, int k, const edx_lanczos_opts
       done = upto;
     }
     iters += m - done_run;
-    // orthonormalise the Ritz coefficient vectors (modified Gram-Schmidt):
-    // a tight cluster of Ritz values can give nearly parallel inverse-iteration vectors
-    for (size_t i = 0; i < ys.size(); ++i) {
-      for (size_t q = 0; q < i; ++q) {
-        double d = 0.0;
-        for (int j = 0; j < m; ++j) d += ys[q][j] * ys[i][j];
-        for (int j = 0; j < m; ++j) ys[i][j] -= d * ys[q][j];
+    // orthonormalise the Ritz coefficient vectors: a tight cluster of Ritz
+    // values can give nearly parallel inverse-iteration vectors; one that adds
+    // no direction is not locked (a later run finds that state)
+    std::vector<char> usable(ys.size(), 1);
+    {
+      std::vector<std::vector<double>> done_y;
+      for (size_t i = 0; i < ys.size(); ++i) {
+        ys[i].resize(m);
+        if (orthonormalise_against(done_y, ys[i]))
+          done_y.push_back(ys[i]);
+        else
+          usable[i] = 0;
       }
-      double nn = 0.0;
-      for (int j = 0; j < m; ++j) nn += ys[i][j] * ys[i][j];
-      nn = std::sqrt(nn);
-      for (int j = 0; j < m; ++j) ys[i][j] /= nn;
     }
     EDX_HIP(hipMemcpyAsync(hs.data(), L.scale, sizeof(double) * m, hipMemcpyDeviceToHost, st));
     EDX_HIP(hipStreamSynchronize(st));
@@ -800,6 +842,7 @@ edx_status lowest_states_impl(const edx_sector* s, int k, const edx_lanczos_opts
     int locked_now = 0;
     std::vector<char> took(ys.size(), 0);
     for (int i = 0; i < nconv; ++i) {
+      if (!usable[i]) continue;
       if (checking) {
         const double emax = *std::max_element(E.begin(), E.end());
         const double delta = std::max(10.0 * rtol * std::max(1.0, std::fabs(emax)), 1e-12) +
@@ -869,11 +912,13 @@ edx_status lowest_states_impl(const edx_sector* s, int k, const edx_lanczos_opts
       // Lanczos keeps converging it (a sum of several would dilute it)
       std::vector<std::vector<double>> rest;
       for (int i = 0; i < wl && rest.empty(); ++i)
-        if (!took[i]) rest.push_back(ys[i]);
-      const int free_slot = std::min((int)E.size(), k);
-      EDX_TRY(ritz_combination(vtype, L, m, hs, rest, std::vector<double>(rest.size(), 1.0),
-                               slot(free_slot), n, st));
-      from_staging = true;
+        if (!took[i] && usable[i]) rest.push_back(ys[i]);
+      if (!rest.empty()) {
+        const int free_slot = std::min((int)E.size(), k);
+        EDX_TRY(ritz_combination(vtype, L, m, hs, rest, std::vector<double>(rest.size(), 1.0),
+                                 slot(free_slot), n, st));
+        from_staging = true;
+      }
     }
   }
   const int nf = (int)E.size();

@@ -131,11 +131,14 @@ def test_eph_decoupled_equals_electronic(edx):
     assert abs(e_el - e_ph) <= 1e-11 * abs(e_el)
 
 
-def test_eph_lowest_states(edx):
-    m, sec = GS_CASES[1][1], GS_CASES[1][2]
+@pytest.mark.parametrize("niter", [400, 16])
+@pytest.mark.parametrize("name,m,sec", GS_CASES, ids=[c[0] for c in GS_CASES])
+def test_eph_lowest_states(edx, name, m, sec, niter):
+    """5 lowest states of eq. HephBuild; niter 16 runs through thick restarts."""
     w = np.linalg.eigvalsh(eph.explicit_hamiltonian(m, *sec).toarray())
-    S = edx.build_sector(m, *sec)
-    e, psi, rep, _ = edx.lanczos_lowest(S, 5, niter=400, tol=0.0, rtol=1e-11, seed=2)
+    S = _build(edx, m, sec)
+    e, psi, rep, _ = edx.lanczos_lowest(S, 5, niter=niter, tol=0.0, rtol=1e-11, seed=2)
+    assert rep["nfound"] == 5 and rep["verified"] == 1
     assert np.abs(e - w[:5]).max() <= 1e-10 * np.abs(w[:5]).max()
 
 
