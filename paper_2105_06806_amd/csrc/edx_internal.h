@@ -108,9 +108,11 @@ struct edx_sector {
   float* amp32 = nullptr;    // [256] device
   // W[p_up * 8 + p_dw]: density-density energy of two impurity patterns.
   double* zeros = nullptr;   // max(D_up, D_dw) + 64 zero doubles (block passes)
-  // spin-up hop rows in 3 * wpad bytes for the fused pass (built when
-  // D_up < 2^16): wpad 16-bit columns, then wpad 8-bit amplitude indices
+  // hop rows in 3 * wpad bytes for the fused pass (spin up) and the column
+  // pass on the transposed vector (spin down), built when D < 2^16: wpad
+  // 16-bit columns, then wpad 8-bit amplitude indices
   uint8_t* hrow = nullptr;
+  uint8_t* hrow_dw = nullptr;
   double* w64 = nullptr;     // [64] device
   float* w32 = nullptr;      // [64] device
   int32_t* binom = nullptr;  // [25*25] device binomial table

@@ -1261,6 +1261,92 @@ edx_status hv_launch(const edx_sector* s, int vtype, const void* v, void* w, int
   return EDX_OK;
 }
 
+// Column pass of the distributed pieces on a column block (edx_hv_block):
+// w = (H_d + H_up) V over NC columns per workgroup, overwriting.  The fused
+// pass's row machinery without the spin-down gathers: interleaved LDS columns
+// at offset 0, compact hop rows, buffer loads and streaming buffer stores
+// (every byte offset into the block below 2^32, D < 2^16).
+template <typename T, int WUP, int NC>
+__global__ __launch_bounds__(1024) void k_hv_colx(HvArgs<T> a, const T* __restrict__ v,
+                                                  T* __restrict__ w, uint32_t vbytes) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T* vs = reinterpret_cast<T*>(smem_raw);
+  T* amp = reinterpret_cast<T*>(smem_raw + al16((size_t)NC * a.dup * sizeof(T)));
+  T* Wt = amp + kAmpTable;
+  const uint32_t dup = (uint32_t)a.dup;
+  const int64_t ld = a.ld;
+  const int64_t j0 = (int64_t)blockIdx.x * NC;
+  const int nc = (int)std::min<int64_t>(NC, a.ddw - j0);
+  constexpr int HW = 3 * WUP / 4;
+  const __amdgpu_buffer_rsrc_t vres =
+      __builtin_amdgcn_make_buffer_rsrc(const_cast<T*>(v), 0, (int)vbytes, 0x00020000);
+  const __amdgpu_buffer_rsrc_t wres = __builtin_amdgcn_make_buffer_rsrc(w, 0, (int)vbytes,
+                                                                        0x00020000);
+  const __amdgpu_buffer_rsrc_t hres = __builtin_amdgcn_make_buffer_rsrc(
+      const_cast<uint8_t*>(a.hrow), 0, (int)(dup * HW * 4), 0x00020000);
+  const __amdgpu_buffer_rsrc_t eres = __builtin_amdgcn_make_buffer_rsrc(
+      const_cast<T*>(a.eup), 0, (int)(dup * sizeof(T)), 0x00020000);
+  const __amdgpu_buffer_rsrc_t pres = __builtin_amdgcn_make_buffer_rsrc(
+      const_cast<uint8_t*>(a.pup), 0, (int)dup, 0x00020000);
+  uint32_t coff[NC];
+  T ed[NC];
+  int pd[NC];
+#pragma unroll
+  for (int c = 0; c < NC; ++c) {
+    const int64_t j = std::min<int64_t>(j0 + c, a.ddw - 1);   // clamped copies past the end
+    coff[c] = __builtin_amdgcn_readfirstlane((uint32_t)((uint64_t)j * ld * sizeof(T)));
+    ed[c] = a.edw[j];
+    pd[c] = a.pdw[j];
+  }
+  constexpr int SU = std::max(1, (sizeof(T) == 4 ? 40 : 20) / NC);
+  StageBuf<T, NC, SU> sb;
+  stage_issue_buf(sb, vres, coff, nc, dup, threadIdx.x);
+  for (int i = threadIdx.x; i < kAmpTable; i += blockDim.x) amp[i] = a.amp[i];
+  for (int i = threadIdx.x; i < 64; i += blockDim.x) Wt[i] = a.W[i];
+  stage_put(vs, sb, nc, (int64_t)dup, (int64_t)threadIdx.x, T(1));
+  for (uint32_t r0 = threadIdx.x + SU * blockDim.x; r0 < dup; r0 += SU * blockDim.x) {
+    stage_issue_buf(sb, vres, coff, nc, dup, r0);
+    stage_put(vs, sb, nc, (int64_t)dup, (int64_t)r0, T(1));
+  }
+  __syncthreads();
+  for (uint32_t iu = threadIdx.x; iu < dup; iu += blockDim.x) {
+    const uint32_t voff = iu * (uint32_t)sizeof(T);
+    uint32_t r[HW];
+#pragma unroll
+    for (int q = 0; q < HW / 2; ++q) {
+      typedef unsigned int u2 __attribute__((ext_vector_type(2)));
+      const u2 x = __builtin_amdgcn_raw_buffer_load_b64(hres, (int)(iu * HW * 4 + q * 8), 0, 0);
+      r[2 * q] = x.x;
+      r[2 * q + 1] = x.y;
+    }
+    const T eu = buf_load<T>(eres, voff, 0);
+    const int pu = (int)__builtin_amdgcn_raw_buffer_load_b8(pres, (int)iu, 0, 0) * 8;
+    T acc[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) acc[c] = T(0);
+#pragma unroll
+    for (int k = 0; k < WUP; ++k) {
+      const uint32_t col = (r[k >> 1] >> (16 * (k & 1))) & 0xFFFFu;
+      const uint32_t ai = (r[WUP / 2 + (k >> 2)] >> (8 * (k & 3))) & 0xFFu;
+      const T am = amp[ai];
+      const T* src = vs + __umul24(col, (uint32_t)NC);
+#pragma unroll
+      for (int c = 0; c < NC; ++c) acc[c] += am * src[c];
+    }
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      if (c >= nc) break;
+      const T x = vs[iu * (uint32_t)NC + c];
+      buf_store_nt<T>(wres, voff, coff[c], acc[c] + (eu + ed[c] + Wt[pu + pd[c]]) * x);
+    }
+  }
+  // padding rows of the output are defined as zero
+  for (int64_t i = (int64_t)dup + threadIdx.x; i < ld; i += blockDim.x)
+#pragma unroll
+    for (int c = 0; c < NC; ++c)
+      if (c < nc) w[i + (j0 + c) * ld] = T(0);
+}
+
 // ---------------------------------------------------------------- distributed pieces
 // The per-GPU work of the column-distributed product (Sec. 3.2, two transposes
 // per product), run on one GPU: part 0 is the local pass on a column block of V
@@ -1311,6 +1397,33 @@ edx_status block_t(const edx_sector* s, int part, const T* v, T* w, int64_t ld, 
   const int nblk = (int)((a.ddw + C - 1) / C);
   const T* vb = v + c0 * ld;
   T* wb = w + c0 * ld;
+  // compact-row pass when the block's byte offsets fit in 32 bits
+  const uint8_t* hr = part == 0 ? s->hrow : s->hrow_dw;
+  const uint64_t bytes = (uint64_t)a.ddw * (uint64_t)ld * sizeof(T);
+  if (hr && bytes <= 0xFFFFFFFFull) {
+    a.hrow = hr;
+    const size_t ldsx = smem_header() + 16 + (size_t)C * len * sizeof(T);
+    auto gox = [&](auto kern) -> edx_status {
+      EDX_HIP(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  (int)ldsx));
+      hipLaunchKernelGGL(kern, dim3(nblk), dim3(nthr), ldsx, st, a, vb, wb, (uint32_t)bytes);
+      EDX_HIP(hipGetLastError());
+      return EDX_OK;
+    };
+    auto byc = [&](auto w8) -> edx_status {
+      constexpr int W = decltype(w8)::value;
+      switch (C) {
+        case 1: return gox(k_hv_colx<T, W, 1>);
+        case 2: return gox(k_hv_colx<T, W, 2>);
+        default: return gox(k_hv_colx<T, W, 3>);
+      }
+    };
+    switch (a.sup) {
+      case 8: return byc(std::integral_constant<int, 8>{});
+      case 16: return byc(std::integral_constant<int, 16>{});
+      default: return byc(std::integral_constant<int, 24>{});
+    }
+  }
   auto go = [&](auto kern) -> edx_status {
     EDX_HIP(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
                                 (int)lds));

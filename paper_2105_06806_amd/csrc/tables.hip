@@ -294,6 +294,7 @@ void destroy_sector(edx_sector* s) {
   dfree(s, s->amp64);
   dfree(s, s->amp32);
   dfree(s, s->hrow);
+  dfree(s, s->hrow_dw);
   dfree(s, s->w64);
   dfree(s, s->zeros);
   dfree(s, s->w32);
@@ -493,7 +494,7 @@ size_t sector_table_bytes(int ns, int nup, int ndw) {
   b += (size_t)comb(ns, ndw) * 4 + a;   // column order
   b += 6 * a + 65 * 4 + 64 * 12 * (4 + 4 + 8 + 4);   // H_nd term table
   b += 8 * ((size_t)std::max(comb(ns, nup), comb(ns, ndw)) + 64) + a;   // zero block
-  b += (size_t)comb(ns, nup) * 3 * 24 + a;   // compact spin-up rows
+  b += ((size_t)comb(ns, nup) + (size_t)comb(ns, ndw)) * 3 * 24 + 2 * a;   // compact hop rows
   return b;
 }
 
@@ -599,13 +600,15 @@ edx_status build_sector_impl(const Model& m, int nup, int ndw, hipStream_t st,
   EDX_HIP(hipMemcpyAsync(S->amp32, ampf, sizeof(ampf), hipMemcpyHostToDevice, st));
   EDX_HIP(hipMemcpyAsync(S->w64, W, sizeof(W), hipMemcpyHostToDevice, st));
   EDX_HIP(hipMemcpyAsync(S->w32, Wf, sizeof(Wf), hipMemcpyHostToDevice, st));
-  if (S->dup < 65536) {
-    // compact spin-up rows of the fused pass
-    const int64_t D = S->dup;
-    const int wp = S->up.wpad;
-    EDX_TRY(dalloc(S.get(), &S->hrow, (size_t)D * 3 * wp));
-    hipLaunchKernelGGL(k_hrow, dim3((unsigned)std::min<int64_t>((D + 255) / 256, 4096)), dim3(256),
-                       0, st, S->up.hop, wp, D, S->hrow);
+  // compact hop rows: spin up for the fused pass, spin down for the column
+  // pass on the transposed vector
+  for (int spin = 0; spin < 2; ++spin) {
+    const SpinTables& T = spin == 0 ? S->up : S->dw;
+    uint8_t** dst = spin == 0 ? &S->hrow : &S->hrow_dw;
+    if (T.D >= 65536) continue;
+    EDX_TRY(dalloc(S.get(), dst, (size_t)T.D * 3 * T.wpad));
+    hipLaunchKernelGGL(k_hrow, dim3((unsigned)std::min<int64_t>((T.D + 255) / 256, 4096)),
+                       dim3(256), 0, st, T.hop, T.wpad, T.D, *dst);
     EDX_HIP(hipGetLastError());
   }
   if (S->dph > 1) EDX_TRY(build_ph_terms(S.get(), m, binom, W, st));
