@@ -94,6 +94,10 @@ HV_CASES = [
     ("orb3", inputs.make_model(3, 3, 3.0, Jh=0.5, seed=28, symmetric=False),
      ((2, 1, 3), (2, 2, 2))),
     ("orb2_edge", inputs.make_model(2, 4, 2.0, seed=29, symmetric=False), ((0, 5), (5, 1))),
+    # hop rows wider than 16 (24-entry table rows): 17 bath levels on one
+    # impurity level; two impurity levels on 9 shared bath levels, 2 electrons
+    ("wide24", inputs.make_model(1, 17, 2.0, seed=30, symmetric=False), (1, 2)),
+    ("o2_wide24", inputs.make_model(2, 9, 2.5, Jh=0.4, seed=31, symmetric=False), (2, 2)),
 ]
 
 PLANS = [
@@ -130,6 +134,8 @@ def test_hv_every_plan(edx, name, m, sec, dtype):
     import torch
     H = fock.explicit_hamiltonian(m, *sec)
     S = _build(edx, m, sec)
+    if name.endswith("wide24"):
+        assert S.hop_nnz(0)[1] > 16, "case must have spin-up hop rows wider than 16"
     x = inputs.random_vector(S.dim, seed=99)
     ref = H @ x
     tdt = torch.float64 if dtype == "f64" else torch.float32

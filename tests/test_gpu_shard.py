@@ -53,6 +53,8 @@ CASES = [
     ("ns11", inputs.make_model(1, 10, 2.5, seed=122, symmetric=False), (5, 6), [4, 7]),
     ("orbital", inputs.make_model(2, 3, 2.5, Jh=0.4, seed=123, symmetric=False), ((2, 2), (1, 3)),
      [2, 3]),
+    # 24-entry hop rows (spin up: one electron next to 17 bath levels)
+    ("wide24", inputs.make_model(1, 17, 2.0, seed=124, symmetric=False), (1, 2), [2, 5]),
 ]
 
 
