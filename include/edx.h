@@ -258,8 +258,11 @@ edx_status edx_transpose(edx_vtype vtype, const void* src, int64_t rows, int64_t
  * every new Krylov vector orthogonal to them and to the run's own basis
  * (classical Gram-Schmidt twice), and locks the lowest Ritz pairs whose
  * residual beta_m |y_{m-1}| <= rtol max(1, |theta|) (tol when rtol = 0; FP32
- * floor as for the ground state).  A run that reaches niter restarts from
- * its unconverged wanted Ritz vectors.  A run from one start vector sees one
+ * floor as for the ground state).  A run aims at min(k - locked, niter/4)
+ * states; when its basis reaches niter first it is thick-restarted in place
+ * (the lowest l <= 32 Ritz vectors kept, the arrow matrix they give brought
+ * back to tridiagonal form, at most 64 restarts a run), so niter bounds the
+ * basis memory, not the number of steps.  A run from one start vector sees one
  * vector per degenerate eigenspace; the locking finds the other copies in
  * later runs, and with verify = 1 a last run checks that the lowest state
  * orthogonal to all k locked ones lies at or above the k-th energy (a lower
