@@ -166,11 +166,13 @@ def _oracle_list(m, secs, beta, cutoff, ntotal):
     return [(look[(t[1], t[2])][0], secs[t[1]], look[(t[1], t[2])][3]) for t in sel], states
 
 
-def test_espace_whole_fock_space_thermal_g(edx):
+@pytest.mark.parametrize("niter", [200, 8])
+def test_espace_whole_fock_space_thermal_g(edx, niter):
     """Norb = 1, Nbath = 3 (Ns = 4), every sector, cutoff 0: after the
     annealing has asked every sector for all its states the list is the whole
     spectrum, and the thermal G equals the Lehmann double sum over the Fock
-    space."""
+    space.  niter = 8 is shorter than the largest sectors (D = 36), so their
+    solves go through thick restarts."""
     m = inputs.make_model(1, 3, 2.0, seed=76, symmetric=False)
     secs = _all_sectors(m)
     beta = 3.0
@@ -178,7 +180,7 @@ def test_espace_whole_fock_space_thermal_g(edx):
                    nstates_step=16)
     S = [edx.build_sector(m, *s) for s in secs]
     for _ in range(4):
-        E.diag(S, niter=200, tol=0.0, rtol=1e-11, seed=1)
+        E.diag(S, niter=niter, tol=0.0, rtol=1e-11, seed=1)
     n, e0, z = E.info()
     assert n == 4 ** fock.ns_of(m)
     _, states = _oracle_list(m, secs, beta, 0.0, 10 ** 6)
