@@ -50,7 +50,7 @@ def hop_pairs(model):
 
 
 def spin_strings_listing(nbit, n):
-    """The build_sector listing (Sec. 5, "Sector construction"): loop over every
+    """The build_sector listing (Sec. 6, "Sector construction"): loop over every
     integer 0..2**nbit-1 and append those whose popcount equals n."""
     out = []
     for i in range(2 ** nbit):
@@ -320,6 +320,9 @@ def spin_hop_csr(model, n, spin):
             cols.append(j)
             sgns.append(sg[j])
             amps.append(np.full(j.size, V))
+    if not rows:                       # no bath levels: no hopping at all
+        rows = cols = sgns = [np.zeros(0, dtype=np.int64)]
+        amps = [np.zeros(0)]
     rows = np.concatenate(rows)
     cols = np.concatenate(cols)
     sgns = np.concatenate(sgns)
