@@ -5,8 +5,8 @@
  * density-density interaction (eq. Ham1), in one sector of fixed (N_up, N_dw)
  * (Sec. 2.2), the storage-free product w = H v with the decomposition
  * H = H_d + H_up (x) 1 + 1 (x) H_dw (eq. Hdecomp, eq. Hbuild), the Lanczos ground
- * state (Sec. 5 "Diagonalization") and the impurity Green's function by the
- * Krylov continued fraction (Sec. 5 "Dynamical correlation functions").
+ * state (Sec. 6 "Diagonalization") and the impurity Green's function by the
+ * Krylov continued fraction (Sec. 6 "Dynamical correlation functions").
  *
  * Conventions (every index is 0-based; the paper's are 1-based):
  *   - level k of spin s: impurity orbital a at level a, bath level (a, nu) at
@@ -14,7 +14,7 @@
  *     occupation of level k.  All spin-up modes precede all spin-down modes in
  *     the fermionic order (Sec. 2.3).
  *   - the strings of one spin in a sector are the Ns-bit integers with the
- *     right popcount in ascending order (the build_sector listing of Sec. 5
+ *     right popcount in ascending order (the build_sector listing of Sec. 6
  *     "Sector construction"); map_s[i] is the i-th one.
  *   - sector index i = i_up + i_dw * D_up: a vector is the D_up x D_dw
  *     column-major matrix of eq. Vmatrix, spin-up fastest, dense, no padding.
@@ -89,7 +89,7 @@ typedef struct {
 typedef struct edx_sector edx_sector;
 typedef struct edx_server edx_server;
 
-/* Build the tables of sector (nup, ndw) on the current device (Sec. 5 "Sector
+/* Build the tables of sector (nup, ndw) on the current device (Sec. 6 "Sector
  * construction", eq. nud_dimension): per spin the ascending string map, its
  * inverse over all 2^Ns integers, the hopping lists with fermionic signs
  * (Sec. 2.3) and the diagonal tables (eq. Hbuild).  Runs kernels on `stream`
@@ -143,6 +143,14 @@ edx_status edx_sector_get_tables(const edx_sector* s, int32_t spin,
                                  double* hop_amp, double* diag_e,
                                  uint8_t* diag_p);
 
+/* Host copy of one spin's inverse map over all 2^Ns integers (Sec. 6
+ * "Sector construction": the position of a string in the ascending listing,
+ * found there by binary search; here tabulated from the colex rank, or for an
+ * orbital-resolved sector from the mixed-radix index of Sec. 2.2):
+ * rank[s] = i when map[i] == s, -1 for strings outside the sector's spin
+ * species.  rank must hold 2^Ns int32 values. */
+edx_status edx_sector_get_rank(const edx_sector* s, int32_t spin, int32_t* rank);
+
 /* w = H v for the sector (Sec. 3 MVP, eq. Hbuild; storage-free, Sec. 2.4).
  * v and w are device arrays of `vtype` holding the D_up x D_dw matrix V of
  * eq. Vmatrix column by column with column stride `ld` (0 = dense, D_up;
@@ -194,14 +202,26 @@ typedef struct {
                         /* with FP32 vectors both thresholds are floored at
                            2 * 2^-23 * |T| (the energy resolution of FP32)    */
   uint64_t seed;        /* SplitMix64 seed of the start vector              */
+  int32_t degen_check;  /* ground-state degeneracy check (default 1): after
+                           psi0 is formed, a second Lanczos run kept
+                           orthogonal to psi0 finds the lowest level of the
+                           complement; a level within gs_threshold =
+                           1e-9 max(1, |E0|) of E0 (FP32 vectors: at least
+                           2 * 2^-23 |T|) makes the ground level degenerate.
+                           Runs only when psi0 is requested.               */
+  int32_t pad_;
 } edx_lanczos_opts;
 
 typedef struct {
   int32_t iters;        /* Lanczos steps taken                              */
   int32_t converged;    /* 1 if the stop rule was met                       */
   int32_t breakdown;    /* 1 if beta fell below 1e-12 * |T|                 */
-  int32_t degenerate;   /* 1 if E1 - E0 < 1e-9                             */
-  double e0, e1;        /* lowest two Ritz values                           */
+  int32_t degenerate;   /* 1 if the ground level is degenerate (see
+                           degen_check; without the check: a second Ritz
+                           value of the run within 1e-9 of E0)             */
+  double e0, e1;        /* E0 and the next level: with the check the lowest
+                           level orthogonal to psi0 (a second copy of E0
+                           when degenerate), else the second Ritz value    */
   double beta_last;     /* last beta                                        */
   double resid;         /* beta_{m} |y_{m-1}|                               */
 } edx_lanczos_report;
@@ -219,12 +239,19 @@ void edx_lanczos_default_opts(edx_lanczos_opts* o);
 size_t edx_workspace_bytes(const edx_sector* s, int32_t what, int32_t vtype,
                            int32_t n);
 
-/* Lowest eigenpair of the sector by Lanczos (Sec. 5 "Diagonalization"):
+/* Lowest eigenpair of the sector by Lanczos (Sec. 6 "Diagonalization"):
  * alpha_j = <v_j, H v_j>, w = H v_j - alpha_j v_j - beta_j v_{j-1},
  * beta_{j+1} = |w|, v_{j+1} = w / beta_{j+1}; scalars and dots in FP64.
  * psi0 (nullable, D elements of opts->vtype) receives the normalised ground
- * vector from a second replay of the same recurrence.  Returns EDX_OK,
- * EDX_E_NOCONV (e0 is the best estimate) or EDX_E_DEGENERATE (flag). */
+ * vector from a second replay of the same recurrence.  A run from one start
+ * vector sees one vector of a degenerate level; with psi0 requested and
+ * opts->degen_check set, a further run deflated against psi0 tests the
+ * ground level against the degeneracy threshold gs_threshold (Appendix A,
+ * 1e-9), and rep->e1 receives its lowest level.  Returns EDX_OK,
+ * EDX_E_NOCONV (e0 is the best estimate) or EDX_E_DEGENERATE (e0 and psi0
+ * are valid; psi0 is one vector of the degenerate level, and quantities that
+ * must average over the level, such as G, go through the eigenstate list,
+ * edx_espace_*). */
 edx_status edx_lanczos_ground_state(const edx_sector* s,
                                     const edx_lanczos_opts* opts, void* ws,
                                     size_t ws_bytes, double* e0, void* psi0,
@@ -251,7 +278,7 @@ edx_status edx_hv_block(const edx_sector* s, edx_vtype vtype, int32_t part, cons
 edx_status edx_transpose(edx_vtype vtype, const void* src, int64_t rows, int64_t cols,
                          int64_t lds, void* dst, int64_t ldd, int32_t add, void* stream);
 
-/* ---- several low-lying states (Sec. 5 "Eigenspace class": lanc_nstates_*)
+/* ---- several low-lying states (Sec. 6 "Eigenspace class": lanc_nstates_*)
  * The k lowest eigenpairs of one sector by Lanczos with full
  * re-orthogonalisation and locking: each run starts from a random vector
  * (SplitMix64, seed + run) orthogonal to the states locked so far, keeps
@@ -318,7 +345,7 @@ edx_status edx_green_cf(const edx_sector* gs, const void* psi0, double e0,
                         void* ws, size_t ws_bytes, double* g_host,
                         edx_gf_report* rep, void* stream);
 
-/* Poles and weights of a Krylov spectral function (Sec. 5 "Dynamical
+/* Poles and weights of a Krylov spectral function (Sec. 6 "Dynamical
  * correlation functions": the eigenvalues theta_m of the Lanczos tridiagonal
  * matrix and the squared first components |a_m|^2 of its eigenvectors).
  * alpha [m] diagonal, beta [m-1] off-diagonal, theta and weight [m] outputs,
@@ -327,7 +354,7 @@ edx_status edx_green_cf(const edx_sector* gs, const void* psi0, double e0,
 edx_status edx_tridiag_spectrum(const double* alpha, const double* beta, int32_t m,
                                 double* theta, double* weight);
 
-/* Density-type susceptibility at T = 0 (eq. KLgf with the bosonic sign, Sec. 5
+/* Density-type susceptibility at T = 0 (eq. KLgf with the bosonic sign, Sec. 6
  * "Dynamical correlation functions"; the paper's spin and charge functions):
  * O = sum_a (cu[a] n_{a up} + cd[a] n_{a dw}) (host arrays [norb]; S_z of
  * orbital a: cu[a] = 1/2, cd[a] = -1/2; charge: 1, 1; a cross-orbital function
@@ -376,7 +403,7 @@ edx_status edx_chi_pair(const edx_sector* gs, const void* psi0, double e0, int32
                         const edx_gf_opts* opts, void* ws, size_t ws_bytes, double* chi_host,
                         edx_gf_report* rep, void* stream);
 
-/* ---- finite temperature: the eigenstate list (Sec. 5 "Eigenspace class"
+/* ---- finite temperature: the eigenstate list (Sec. 6 "Eigenspace class"
  * and the thermal form of "Dynamical correlation functions") ----
  * An edx_espace holds the low-lying states of a fixed set of nsec sectors.
  * edx_espace_diag asks sector i for its next_i lowest states
@@ -466,7 +493,7 @@ edx_status edx_espace_chi_pair(edx_espace* E, int32_t a, const edx_gf_opts* opts
  * Every job is an independent sector; the ground energy of each follows the
  * plain recurrence of edx_lanczos_ground_state (psi0 is not formed).  The
  * paper's counterpart is its parallelism over independent impurity problems
- * (Sec. 5 "Main", inequivalent sites).  Jobs with D >= wide_min_dim fill the
+ * (Sec. 6 "Main", inequivalent sites).  Jobs with D >= wide_min_dim fill the
  * GPU by themselves: they run first, one after another, through the kernels
  * and host stop rule of edx_lanczos_ground_state (tol and rtol).  The others
  * share one cooperative launch: lanes of `lane_wgs` workgroups on one XCD

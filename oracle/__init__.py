@@ -8,7 +8,7 @@ helpers); only the seeded input dictionaries come from a common generator,
 which holds none of the method's arithmetic.
 
 Modules
-  fock      -- sector basis (the build_sector listing, Sec. 5 "Sector
+  fock      -- sector basis (the build_sector listing, Sec. 6 "Sector
                construction"), fermionic signs (Sec. 2.3), the explicit sector
                Hamiltonian built on full 2Ns-bit strings (eq. Ham1), sampled rows
                of H.v for sectors too large to store.
@@ -18,7 +18,7 @@ Modules
   jw        -- Jordan-Wigner Fock-space operators for tiny systems: an
                independent construction of H used to pin ``fock``.
   spectra   -- eigen-solvers: dense eigh, Lanczos with full re-orthogonalisation,
-               ARPACK cross-check, the plain three-term recurrence (Sec. 5
+               ARPACK cross-check, the plain three-term recurrence (Sec. 6
                "Diagonalization") and the tridiagonal eigenproblem.
   green     -- impurity Green's function: exact Lehmann sum (eq. KLgf) and the
                Krylov approximation in spectral form.

@@ -1,6 +1,6 @@
 """Density-type susceptibilities (test infrastructure, FP64).
 
-Sec. 5 "Dynamical correlation functions" (eq. KLgf) with a bosonic operator:
+Sec. 6 "Dynamical correlation functions" (eq. KLgf) with a bosonic operator:
 the time ordering carries the minus sign, so for a Hermitian O
   C_O(z) = <O 1/(z - (H - E0)) O> - <O 1/(z + (H - E0)) O>
          = sum_m |<m|O|0>|^2 [1/(z - (E_m - E0)) - 1/(z + (E_m - E0))].

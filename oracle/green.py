@@ -7,7 +7,7 @@ terms enter with +, energies are measured from the ground energy E0:
 
 ``lehmann_exact`` is that definition summed over every eigenstate of the
 (N_up +- 1) sectors (dense diagonalisation, tiny sectors only).
-``krylov_gf`` is the Krylov approximation of Sec. 5 "Dynamical correlation
+``krylov_gf`` is the Krylov approximation of Sec. 6 "Dynamical correlation
 functions": start from O+|psi0>/|O+|psi0>|, run N plain Lanczos steps, and use
 the eigenpairs (theta_m, first components u_m) of the tridiagonal matrix as
 poles and weights:

@@ -1,8 +1,8 @@
 """Eigen-solvers of the oracle (test infrastructure, FP64).
 
 * ``dense_lowest``: LAPACK ``eigh`` of the dense sector matrix (the paper uses
-  LAPACK for small sectors, Sec. 5 "Diagonalization").
-* ``lanczos_full_reorth``: Lanczos (Sec. 5 "Diagonalization") with full
+  LAPACK for small sectors, Sec. 6 "Diagonalization").
+* ``lanczos_full_reorth``: Lanczos (Sec. 6 "Diagonalization") with full
   re-orthogonalisation against the stored basis, so that it converges to the
   exact lowest eigenvalue with no ghost copies; returns the eigenvector too.
 * ``arpack_lowest``: SciPy ``eigsh`` (ARPACK), an independent cross-check.

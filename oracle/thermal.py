@@ -1,6 +1,6 @@
 """Several low-lying states and finite temperature (test infrastructure, FP64).
 
-Sec. 5 "Eigenspace class": the solver keeps an ordered list of eigenstates
+Sec. 6 "Eigenspace class": the solver keeps an ordered list of eigenstates
 (energy, vector, quantum numbers).  At T = 0 only ground states enter; at
 T > 0 each sector contributes its lanc_nstates_sector lowest states, the list
 holds at most lanc_nstates_total of them, and it is truncated to the states
@@ -12,7 +12,7 @@ of whose computed states survived asks for nstates_step more next time, any
 other sector is cut back to the number it kept (at least one, so that a
 sector whose ground state later moves into the window is still seen).
 
-Sec. 5 "Dynamical correlation functions" (thermal form): with the kept
+Sec. 6 "Dynamical correlation functions" (thermal form): with the kept
 states |n>, weights w_n = exp(-beta (E_n - E_0)) / Z, Z = sum of the kept
 factors,
   G(z) = sum_n w_n G_n(z),
@@ -56,7 +56,7 @@ def boltzmann(energies, beta, e0=None):
 
 
 def espace_select(entries, beta, cutoff, ntotal):
-    """Truncation of the eigenstate list (Sec. 5 "Eigenspace class").
+    """Truncation of the eigenstate list (Sec. 6 "Eigenspace class").
 
     entries: list of (E, sector_index, state_index).  Sorted by energy (ties:
     sector, then state index); the states with exp(-beta (E - E0)) >= cutoff

@@ -183,6 +183,16 @@ edx_status edx_sector_get_tables(const edx_sector* s, int32_t spin, uint32_t* ma
   return EDX_OK;
 }
 
+edx_status edx_sector_get_rank(const edx_sector* s, int32_t spin, int32_t* rank) {
+  EDX_TRY(check_sector(s));
+  if (spin != 0 && spin != 1) return invalid("spin must be 0 or 1");
+  if (!rank) return invalid("rank is NULL");
+  const SpinTables& T = spin == 0 ? s->up : s->dw;
+  const size_t total = size_t(1) << s->model.ns;
+  EDX_HIP(hipMemcpy(rank, T.rank, total * sizeof(int32_t), hipMemcpyDeviceToHost));
+  return EDX_OK;
+}
+
 edx_status edx_hv(const edx_sector* s, edx_vtype vtype, const void* v, void* w, int64_t ld,
                   void* stream) {
   EDX_TRY(check_sector(s));
@@ -287,6 +297,8 @@ void edx_lanczos_default_opts(edx_lanczos_opts* o) {
   o->tol = 1e-12;
   o->rtol = 0.0;
   o->seed = 1234567;
+  o->degen_check = 1;
+  o->pad_ = 0;
 }
 
 size_t edx_workspace_bytes(const edx_sector* s, int32_t what, int32_t vtype, int32_t n) {

@@ -7,7 +7,7 @@
 // so that every workgroup is resident.  Workgroups are grouped into lanes of L workgroups
 // that sit on one XCD (workgroup b runs on XCD b % 8), so a lane shares one L2.
 // A lane pulls the next job from a device queue (jobs sorted by decreasing
-// dimension), runs the whole Lanczos recurrence of Sec. 5 "Diagonalization" for
+// dimension), runs the whole Lanczos recurrence of Sec. 6 "Diagonalization" for
 // it, writes E0 and takes the next job; lanes synchronise internally with a
 // counter barrier (bounded spin: a stuck lane reports an error instead of
 // hanging).  Inside a lane a step is the same sequence as the plain path:
@@ -26,7 +26,7 @@
 #include <thread>
 #include <vector>
 
-#include "common.cuh"
+#include "common.h"
 #include "edx_internal.h"
 
 namespace edx {

@@ -1,5 +1,5 @@
-// Eigenstate list for finite temperature (Sec. 5 "Eigenspace class") and the
-// thermal Green's function (Sec. 5 "Dynamical correlation functions", the
+// Eigenstate list for finite temperature (Sec. 6 "Eigenspace class") and the
+// thermal Green's function (Sec. 6 "Dynamical correlation functions", the
 // Boltzmann-weighted sum over states).
 //
 // Host-side bookkeeping around two device paths that already exist: the k

@@ -1,4 +1,4 @@
-// Green's-function kernels (Sec. 5 "Dynamical correlation functions").
+// Green's-function kernels (Sec. 6 "Dynamical correlation functions").
 //
 //  * k_apply: phi = c+_{orb,s} psi (N_s -> N_s + 1) or c_{orb,s} psi
 //    (N_s -> N_s - 1).  One thread per element of the target sector: it looks
@@ -15,7 +15,7 @@
 //    deepest level up:
 //      d = z -+ (a_{n-1} - E0);  d = z -+ (a_k - E0) - b_{k+1}^2 / d, k = n-2..0;
 //      G += w / d    (- for the particle branch, + for the hole branch).
-#include "common.cuh"
+#include "common.h"
 #include "edx_internal.h"
 
 namespace edx {

@@ -35,7 +35,7 @@
 #include <type_traits>
 #include <vector>
 
-#include "common.cuh"
+#include "common.h"
 #include "edx_internal.h"
 
 namespace edx {

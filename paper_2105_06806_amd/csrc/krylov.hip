@@ -1,4 +1,4 @@
-// Krylov-vector kernels of the Lanczos recurrence (Sec. 5 "Diagonalization"):
+// Krylov-vector kernels of the Lanczos recurrence (Sec. 6 "Diagonalization"):
 // start vector, FP64-accumulated dot products with a deterministic two-stage
 // reduction (per-block partials, then one block in fixed order), the fused
 // three-term update w <- w - alpha v_j - beta v_{j-1} with |w|^2, and the
@@ -11,7 +11,7 @@
 #include <algorithm>
 #include <cmath>
 
-#include "common.cuh"
+#include "common.h"
 #include "edx_internal.h"
 
 namespace edx {

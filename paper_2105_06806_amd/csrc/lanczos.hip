@@ -1,6 +1,6 @@
 // Lanczos ground state and Krylov Green's function drivers (host side).
 //
-// Ground state (Sec. 5 "Diagonalization", plain Lanczos as the paper runs it):
+// Ground state (Sec. 6 "Diagonalization", plain Lanczos as the paper runs it):
 //   alpha_j = <v_j, H v_j>;  w = H v_j - alpha_j v_j - beta_j v_{j-1};
 //   beta_{j+1} = |w|;  v_{j+1} = w / beta_{j+1}.
 // A step is enqueued without host synchronisation (scalars stay on the
@@ -250,7 +250,8 @@ size_t lanczos_ws_layout(int64_t vlen, int vtype, int niter, int reorth, int hv_
   char* vec = take(vs * nvec);
   char* psi = psi_acc ? take(vs) : nullptr;
   double* partial = (double*)take(sizeof(double) * (size_t)std::max(slots * kMaxPartials, pcap));
-  const size_t ns = sizeof(double) * (size_t)(niter + 2);
+  // (at least 8: the degeneracy check keeps scalars in coef[2..4])
+  const size_t ns = sizeof(double) * (size_t)std::max(niter + 2, 8);
   double* alpha = (double*)take(ns);
   double* beta = (double*)take(ns);
   double* scale = (double*)take(ns);
@@ -290,10 +291,14 @@ StepBufs bufs_for(const LanczosWs& L, int j, int reorth) {
 // One Lanczos step j: w = H v_j, alpha_j, three-term update, optional
 // re-orthogonalisation, beta_{j+1} and scale_{j+1}.  psi/ycoef accumulate
 // psi += y_j v_j (replay).
+// defl (nullable): a unit vector x (times *defl_scale) projected out of every
+// new vector, w -= <w, x> x, with the coefficient in defl_coef[0] (the
+// degeneracy check of the ground state: Lanczos on the complement of psi0).
 edx_status lanczos_step(const edx_sector* s, int vtype, const LanczosWs& L, int j, int reorth,
                         double* alpha, double* beta, double* scale, void* psi,
                         const double* ycoef, hipStream_t st, const char* locked = nullptr,
-                        int nlock = 0) {
+                        int nlock = 0, const void* defl = nullptr,
+                        const double* defl_scale = nullptr, double* defl_coef = nullptr) {
   const StepBufs b = bufs_for(L, j, reorth);
   const int64_t n = s->vlen;
   const int hb = hv_partial_blocks(s, vtype);
@@ -301,6 +306,12 @@ edx_status lanczos_step(const edx_sector* s, int vtype, const LanczosWs& L, int 
   EDX_TRY(k_alpha_finish(L.partial, hb, alpha + j, st));
   EDX_TRY(k_update(vtype, b.w, b.cur, scale + j, b.prev, j > 0 ? scale + j - 1 : nullptr,
                    alpha + j, beta + j, n, psi, ycoef, L.partial, st));
+  if (defl) {
+    EDX_TRY(k_dot2(vtype, b.w, defl, defl_scale, nullptr, nullptr, n, L.partial, st));
+    EDX_TRY(k_reduce_strided(L.partial, elem_blocks(n), kMaxPartials, 1, defl_coef, st));
+    EDX_TRY(k_axpy2(vtype, b.w, defl, defl_coef, defl_scale, nullptr, nullptr, nullptr, n,
+                    L.partial, st));
+  }
   if (reorth == 1) {
     EDX_TRY(k_dot2(vtype, b.w, b.cur, scale + j, b.prev, j > 0 ? scale + j - 1 : nullptr, n,
                    L.partial, st));
@@ -333,6 +344,82 @@ struct StopState {
   double tnorm = 0.0;
   double Eprev = NAN;
 };
+
+// Lowest level of H restricted to the complement of the unit vector x
+// (device, Krylov layout, any positive multiple of it): plain Lanczos from a
+// random start vector with x projected out of every vector.  Stops when a Ritz
+// value comes within gs_threshold of e0 (degenerate), when the lowest Ritz
+// value settles (tol, floored for FP32 vectors), at breakdown or after niter
+// steps.  Uses the rotating vectors and the replay scalars of L.
+edx_status check_degeneracy(const edx_sector* s, const edx_lanczos_opts* o, const LanczosWs& L,
+                            const void* x, double e0, double tnorm, hipStream_t st, double* e1,
+                            bool* degenerate) {
+  const int vtype = o->vtype;
+  const int niter = o->niter;
+  const int64_t n = s->vlen;
+  const double floor32 = vtype == EDX_F32 ? 2.0 * 1.1920929e-7 * tnorm : 0.0;
+  const double thr = std::max(1e-9 * std::max(1.0, std::fabs(e0)), floor32);
+  double* xs = L.coef + 3;      // 1 / |x|
+  double* xc = L.coef + 4;      // projection coefficient
+  EDX_TRY(k_norm2(vtype, x, n, L.partial, st));
+  EDX_TRY(k_beta_finish(L.partial, elem_blocks(n), L.coef + 2, xs, st));
+  // start vector orthogonal to x (another counter-based stream than the
+  // ground-state run's)
+  EDX_TRY(k_start_vector(vtype, L.vec, s->dup, s->ld, s->ddw * s->dph,
+                         o->seed ^ 0xD1B54A32D192ED03ull, L.partial, st));
+  EDX_TRY(k_dot2(vtype, L.vec, x, xs, nullptr, nullptr, n, L.partial, st));
+  EDX_TRY(k_reduce_strided(L.partial, elem_blocks(n), kMaxPartials, 1, xc, st));
+  EDX_TRY(k_axpy2(vtype, L.vec, x, xc, xs, nullptr, nullptr, nullptr, n, L.partial, st));
+  EDX_TRY(k_beta_finish(L.partial, elem_blocks(n), L.beta2, L.scale2, st));
+  double u0 = 0.0;
+  EDX_HIP(hipMemcpyAsync(&u0, L.beta2, sizeof(double), hipMemcpyDeviceToHost, st));
+  EDX_HIP(hipStreamSynchronize(st));
+  if (!(u0 > 1e-6)) {
+    // the start vector (|u| ~ sqrt(D/3) before the projection) lies in the
+    // span of x: the complement is empty (D = 1) or numerically absent
+    *e1 = NAN;
+    *degenerate = false;
+    return EDX_OK;
+  }
+  EDX_HIP(hipMemsetAsync(L.beta2, 0, sizeof(double), st));
+  std::vector<double> ha(niter + 2), hb(niter + 2);
+  const int every = std::max(1, o->check_every);
+  double th = NAN, thold = NAN, tn = tnorm;
+  bool deg = false;
+  int done = 0;
+  bool stop = false;
+  while (done < niter && !stop) {
+    const int upto = std::min(niter, done + every);
+    for (int j = done; j < upto; ++j)
+      EDX_TRY(lanczos_step(s, vtype, L, j, 0, L.alpha2, L.beta2, L.scale2, nullptr, nullptr, st,
+                           nullptr, 0, x, xs, xc));
+    EDX_HIP(hipMemcpyAsync(ha.data(), L.alpha2, sizeof(double) * upto, hipMemcpyDeviceToHost, st));
+    EDX_HIP(hipMemcpyAsync(hb.data(), L.beta2, sizeof(double) * (upto + 1), hipMemcpyDeviceToHost,
+                           st));
+    EDX_HIP(hipStreamSynchronize(st));
+    for (int j = done; j < upto; ++j) {
+      tn = std::max(tn, std::fabs(ha[j]) + hb[j] + hb[j + 1]);
+      th = tridiag_lowest(ha.data(), hb.data() + 1, j + 1, 0);
+      if (th - e0 < thr) {
+        deg = true;
+        stop = true;
+        break;
+      }
+      const bool bd = !(hb[j + 1] > 1e-12 * tn);
+      const bool settled = j > 0 && std::fabs(th - thold) <=
+                                        std::max(o->tol * std::max(1.0, std::fabs(th)), floor32);
+      thold = th;
+      if (bd || settled) {
+        stop = true;
+        break;
+      }
+    }
+    done = upto;
+  }
+  *e1 = th;
+  *degenerate = deg;
+  return EDX_OK;
+}
 
 }  // namespace
 
@@ -412,12 +499,12 @@ edx_status lanczos_ground_state_impl(const edx_sector* s, const edx_lanczos_opts
     const double x = tridiag_lowest(ha.data(), hb.data() + 1, m, k);
     if (x - E > 1e-10 * std::max(1.0, std::fabs(E))) { E1 = x; break; }
   }
-  const bool degenerate = m > 1 && E1 > E && (E1 - E) < 1e-9;
+  bool degenerate = m > 1 && E1 > E && (E1 - E) < 1e-9;
 
+  // psi0 is accumulated in the layout of the Krylov vectors, then written
+  // densely (D elements) into the caller's buffer
+  void* acc = psi0 ? (L.psi ? (void*)L.psi : psi0) : nullptr;
   if (psi0) {
-    // psi0 is accumulated in the layout of the Krylov vectors, then written
-    // densely (D elements) into the caller's buffer
-    void* acc = L.psi ? (void*)L.psi : psi0;
     if (reorth >= 2) {
       // psi0 from the stored basis (full re-orthogonalisation, or plain with
       // the basis kept)
@@ -449,6 +536,17 @@ edx_status lanczos_ground_state_impl(const edx_sector* s, const edx_lanczos_opts
     else
       EDX_TRY(k_scale_copy(vtype, psi0, L.coef + 1, psi0, n, st));
     EDX_HIP(hipStreamSynchronize(st));
+  }
+  if (acc && o->degen_check && converged) {
+    // A run from one start vector holds one vector of a degenerate level, so
+    // a second plain run is kept orthogonal to psi0 (projected out of the
+    // start vector and of every new vector).  Its Ritz values bound the
+    // lowest level of the complement from above: one within gs_threshold of
+    // E0 means a degenerate ground level; otherwise the run goes on until its
+    // lowest Ritz value settles (that is E1).
+    double E1d = NAN;
+    EDX_TRY(check_degeneracy(s, o, L, acc, E, tnorm, st, &E1d, &degenerate));
+    E1 = E1d;
   }
   *e0 = E;
   if (rep) {

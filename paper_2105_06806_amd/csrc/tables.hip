@@ -1,7 +1,7 @@
 // Sector tables on the device: string map and rank, per-spin hopping lists with
 // fermionic signs, and the diagonal ("popcount") tables.
 //
-//  * map / rank (Sec. 5 "Sector construction"): the strings of one spin are the
+//  * map / rank (Sec. 6 "Sector construction"): the strings of one spin are the
 //    Ns-bit integers with popcount N in ascending order.  Instead of scanning and
 //    binary-searching, every integer s < 2^Ns computes its position directly as
 //    its colex rank sum_k C(c_k, k) over its set bits c_1 < c_2 < ... (ascending

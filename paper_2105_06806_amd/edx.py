@@ -50,7 +50,8 @@ class LanczosOpts(ctypes.Structure):
     _fields_ = [("niter", ctypes.c_int32), ("vtype", ctypes.c_int32),
                 ("reorth", ctypes.c_int32), ("check_every", ctypes.c_int32),
                 ("tol", ctypes.c_double), ("rtol", ctypes.c_double),
-                ("seed", ctypes.c_uint64)]
+                ("seed", ctypes.c_uint64), ("degen_check", ctypes.c_int32),
+                ("pad_", ctypes.c_int32)]
 
 
 class LanczosReport(ctypes.Structure):
@@ -126,6 +127,7 @@ _SIGS = {
     "edx_sector_dims": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]),
     "edx_sector_hop_nnz": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int32)]),
     "edx_sector_get_tables": (ctypes.c_int, [_P, ctypes.c_int32, _P, _P, _P, _P, _P, _P, _P]),
+    "edx_sector_get_rank": (ctypes.c_int, [_P, ctypes.c_int32, _P]),
     "edx_sector_ld": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int64)]),
     "edx_hv": (ctypes.c_int, [_P, ctypes.c_int, _P, _P, ctypes.c_int64, _P]),
     "edx_hv_get_plan": (ctypes.c_int, [_P, ctypes.c_int, ctypes.POINTER(HvPlan)]),
@@ -265,6 +267,13 @@ class Sector:
         _check(lib.edx_sector_get_tables(self.handle, spin, *p))
         for k in ("hop_col", "hop_sign", "hop_amp"):
             out[k] = out[k][:nnz]
+        return out
+
+    def rank(self, spin):
+        """Host copy of one spin's inverse map over all 2**Ns strings (see
+        edx_sector_get_rank): index in the sector's listing, -1 outside it."""
+        out = np.zeros(1 << (int(self.model["norb"]) * (int(self.model["nbath"]) + 1)), np.int32)
+        _check(lib.edx_sector_get_rank(self.handle, spin, out.ctypes.data_as(_P)))
         return out
 
 

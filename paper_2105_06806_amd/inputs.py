@@ -15,7 +15,7 @@ Model (normal bath, Sec. 2.1 eq. Ham1, density-density part only):
     same-spin inter-orbital coupling is U' - J.
 
 Workload recipes (the paper's benchmark draws random bath energies and averages
-over 10 realisations, Sec. 3 benchmarks; the sizes below are the ones this
+over 10 realisations, Sec. 5 "Benchmarks"; the sizes below are the ones this
 implementation is measured on):
 
   ``ns8``   Norb=1, Nbath=7  (Ns=8),  U=2, eps_imp=-U/2, symmetrised bath.

@@ -519,10 +519,13 @@ def test_server_alone_equals_in_mix(edx, vtype):
     overlap = any(out[i]["t_start"] < out[i - 1]["t_done"] for i in range(1, len(out)))
     assert overlap, "requests did not overlap"
     for (m, a, b), r in zip(reqs, out):
-        assert r["status"] == 0, r
+        # two-orbital half-filled requests have a spin-swap degenerate ground
+        # level, flagged by the degeneracy check in both paths
+        assert r["status"] in (0, edx.EDX_E_DEGENERATE), r
         S = edx.build_sector(m, a, b)
-        e0, psi, rep, _ = edx.lanczos_ground_state(S, vtype=vtype, niter=300, tol=1e-12, seed=5,
-                                                   check_every=4)
+        e0, psi, rep, st = edx.lanczos_ground_state(S, vtype=vtype, niter=300, tol=1e-12, seed=5,
+                                                    check_every=4, allow=(edx.EDX_E_DEGENERATE,))
+        assert r["status"] == st
         G, gr = edx.green_cf(S, psi, e0, 0, 0, ngf=60, beta=50.0, lmats=128)
         assert r["e0"] == e0
         assert np.array_equal(r["g"], G)

@@ -79,8 +79,13 @@ def test_ns15o3_precision_mode(edx):
     E = float(g["e0"])
     lm, beta = int(g["lmats"]), float(g["beta"])
     gref = g["g_up"] + g["g_dw"]
-    e64, psi64, rep, _ = edx.lanczos_ground_state(S, niter=600, tol=1e-14, rtol=1e-10, seed=4)
+    e64, psi64, rep, st = edx.lanczos_ground_state(S, niter=600, tol=1e-14, rtol=1e-10, seed=4,
+                                                   allow=(edx.EDX_E_DEGENERATE,))
     assert abs(e64 - E) <= 1e-10 * abs(E), (e64, E)
+    # the 7/7 ground level is two-fold (the spin swap maps one vector of it
+    # onto another): the deflated check must see the second copy
+    assert st == edx.EDX_E_DEGENERATE and rep["degenerate"] == 1, (st, rep)
+    assert abs(rep["e1"] - e64) <= 1e-9 * abs(E), rep
     G64, wp64 = _gsum(edx, S, psi64, e64, lm, beta)
     gerr64 = np.abs(G64 - gref).max() / np.abs(gref).max()
     print(f"ns15o3 f64: dE0 {abs(e64 - E) / abs(E):.2e} dG {gerr64:.2e} iters {rep['iters']}")
@@ -117,9 +122,11 @@ def test_green_multiorbital_small(edx, norb, nbath, sec, degenerate):
     w = np.linalg.eigvalsh(H.toarray())[:2]
     assert (w[1] - w[0] < 1e-9) == degenerate
     S = edx.build_sector(m, *sec)
-    e0, psi, rep, _ = edx.lanczos_ground_state(S, niter=400, tol=1e-14, rtol=1e-11, seed=8,
-                                               allow=(edx.EDX_E_DEGENERATE,))
+    e0, psi, rep, st = edx.lanczos_ground_state(S, niter=400, tol=1e-14, rtol=1e-11, seed=8,
+                                                allow=(edx.EDX_E_DEGENERATE,))
     assert abs(e0 - w[0]) <= 1e-10 * abs(w[0])
+    # the deflated check (gs_threshold) flags exactly the degenerate levels
+    assert (st == edx.EDX_E_DEGENERATE) == degenerate, (st, rep)
     beta, lm = 40.0, 128
     z = 1j * green.matsubara(beta, lm)
     for orb in range(norb):

@@ -1,7 +1,7 @@
 """Pins of the oracle's sector basis and per-spin tables (CPU only).
 
 * The basis is built two independent ways: the build_sector listing (loop over
-  every integer, keep popcount == N; Sec. 5 "Sector construction") and sorted
+  every integer, keep popcount == N; Sec. 6 "Sector construction") and sorted
   combinations; both must agree and have length C(Ns, N) (eq. nud_dimension).
 * Sector order: i = i_up + i_dw * D_up (eq. Vmatrix) equals ascending order of
   the Fock integer I = I_up + I_dw 2**Ns (eq. Irelation).

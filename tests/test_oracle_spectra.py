@@ -5,7 +5,7 @@
 * U=0: ground energy = sum of the lowest N_up + N_dw one-body eigenvalues.
 * V=0: ground energy = atomic-limit minimum (multi-orbital included).
 * Particle-hole symmetry of the symmetrised bath: E0(Nu,Nd) = E0(Ns-Nu,Ns-Nd).
-* Twin sectors (Sec. 5 "Diagonalization"): E0(a,b) = E0(b,a).
+* Twin sectors (Sec. 6 "Diagonalization"): E0(a,b) = E0(b,a).
 * The plain-recurrence ground energy (the paper's Lanczos) reaches the exact
   value within its stop rule.
 """

@@ -1,4 +1,4 @@
-"""Oracle pins for several low-lying states and finite temperature (Sec. 5
+"""Oracle pins for several low-lying states and finite temperature (Sec. 6
 "Eigenspace class" and the thermal form of "Dynamical correlation functions").
 
   * the per-state thermal sum over every eigenstate equals the textbook
