@@ -257,6 +257,23 @@ edx_status edx_lanczos_ground_state(const edx_sector* s,
                                     size_t ws_bytes, double* e0, void* psi0,
                                     edx_lanczos_report* rep, void* stream);
 
+/* The same ground state for callers that cannot allocate device memory
+ * (code under stream capture, tight serving loops, harnesses that forbid
+ * hipMalloc): identical arguments, checks and results to
+ * edx_lanczos_ground_state, but the workspace is a fixed 256 MiB array per
+ * GPU inside the library (held from the first call on that GPU until the
+ * process ends) instead of a caller buffer, and the call itself allocates
+ * nothing.  The sector's device must be the current device.  A sector whose
+ * workspace (edx_workspace_bytes, what = EDX_WS_LANCZOS, or
+ * EDX_WS_LANCZOS_BASIS for reorth 2 and 3) exceeds 256 MiB -> EDX_E_NOMEM.
+ * Every call on one GPU uses the same array: calls that overlap on one GPU
+ * (from several host threads or streams) race and must be serialised by the
+ * caller. */
+edx_status edx_lanczos_ground_state_static(const edx_sector* s,
+                                           const edx_lanczos_opts* opts, double* e0,
+                                           void* psi0, edx_lanczos_report* rep,
+                                           void* stream);
+
 /* ---- the per-GPU pieces of the column-distributed product (Sec. 3.2:
  * columns of V split over processes, two transposes per product), callable on
  * one GPU so that a sharded product can be composed and its per-GPU work

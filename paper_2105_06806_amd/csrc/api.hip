@@ -324,6 +324,18 @@ edx_status edx_lanczos_ground_state(const edx_sector* s, const edx_lanczos_opts*
                                    static_cast<hipStream_t>(stream));
 }
 
+edx_status edx_lanczos_ground_state_static(const edx_sector* s, const edx_lanczos_opts* opts,
+                                           double* e0, void* psi0, edx_lanczos_report* rep,
+                                           void* stream) {
+  EDX_TRY(check_sector(s));
+  if (!opts || !e0) return invalid("opts and e0 must be non-NULL");
+  if (!valid_vtype(opts->vtype)) return invalid("vtype must be EDX_F64 or EDX_F32");
+  if (opts->niter < 1 || opts->niter > 4096) return invalid("niter must be in [1, 4096]");
+  if (opts->reorth < 0 || opts->reorth > 3) return invalid("reorth must be 0, 1, 2 or 3");
+  if (!(opts->tol >= 0.0) || !(opts->rtol >= 0.0)) return invalid("tol/rtol must be >= 0");
+  return lanczos_ground_state_static(s, opts, e0, psi0, rep, static_cast<hipStream_t>(stream));
+}
+
 size_t edx_lowest_workspace_bytes(const edx_sector* s, int32_t vtype, int32_t niter, int32_t k) {
   if (!s || !valid_vtype(vtype) || niter < 1 || k < 1 || k > EDX_MAX_STATES) return 0;
   return lowest_workspace_bytes(s, vtype, niter, k);

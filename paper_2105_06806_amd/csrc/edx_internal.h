@@ -277,6 +277,11 @@ size_t lanczos_workspace_bytes(const edx_sector* s, int vtype, int niter, int re
 edx_status lanczos_ground_state_impl(const edx_sector* s, const edx_lanczos_opts* o, void* ws,
                                      size_t ws_bytes, double* e0, void* psi0,
                                      edx_lanczos_report* rep, hipStream_t st);
+// ---- noalloc.hip: the same ground state with the workspace in a fixed
+// per-device scratch array (no device allocation)
+edx_status lanczos_ground_state_static(const edx_sector* s, const edx_lanczos_opts* o,
+                                       double* e0, void* psi0, edx_lanczos_report* rep,
+                                       hipStream_t st);
 size_t lowest_workspace_bytes(const edx_sector* s, int vtype, int niter, int k);
 edx_status lowest_states_impl(const edx_sector* s, int k, const edx_lanczos_opts* o, int verify,
                               void* ws, size_t ws_bytes, double* e, void* psi,

@@ -136,6 +136,7 @@ _SIGS = {
     "edx_lanczos_default_opts": (None, [ctypes.POINTER(LanczosOpts)]),
     "edx_workspace_bytes": (ctypes.c_size_t, [_P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]),
     "edx_lanczos_ground_state": (ctypes.c_int, [_P, ctypes.POINTER(LanczosOpts), _P, ctypes.c_size_t, ctypes.POINTER(ctypes.c_double), _P, ctypes.POINTER(LanczosReport), _P]),
+    "edx_lanczos_ground_state_static": (ctypes.c_int, [_P, ctypes.POINTER(LanczosOpts), ctypes.POINTER(ctypes.c_double), _P, ctypes.POINTER(LanczosReport), _P]),
     "edx_lowest_workspace_bytes": (ctypes.c_size_t, [_P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]),
     "edx_lanczos_lowest": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.POINTER(LanczosOpts), ctypes.c_int32, _P, ctypes.c_size_t, _P, _P, ctypes.POINTER(LowestReport), _P]),
     "edx_espace_default_opts": (None, [ctypes.POINTER(EspaceOpts)]),
@@ -442,6 +443,25 @@ def lanczos_ground_state(sector, want_psi=True, ws=None, stream=None, allow=(EDX
     st = lib.edx_lanczos_ground_state(sector.handle, ctypes.byref(o), _P(ws.data_ptr()), ws.numel(),
                                       ctypes.byref(e0), _P(psi.data_ptr()) if psi is not None else None,
                                       ctypes.byref(rep), _stream_ptr(stream))
+    _check(st, ok=tuple(allow) + (EDX_OK,))
+    r = {f: getattr(rep, f) for f, _ in LanczosReport._fields_}
+    return e0.value, psi, r, st
+
+
+def lanczos_ground_state_static(sector, psi=None, stream=None, allow=(EDX_OK,), **kw):
+    """edx_lanczos_ground_state_static: the ground state with the library's
+    fixed per-device workspace (no device allocation inside the call).  psi:
+    a caller-owned device tensor of sector.dim elements of the vector type, or
+    None.  Returns (e0, psi, report dict, status)."""
+    o = lanczos_opts(**kw)
+    if psi is not None:
+        if psi.dtype != _dtype_of(o.vtype) or psi.numel() != sector.dim or not psi.is_cuda:
+            raise ValueError("psi must be a device tensor of sector.dim elements of the vector type")
+    e0 = ctypes.c_double()
+    rep = LanczosReport()
+    st = lib.edx_lanczos_ground_state_static(sector.handle, ctypes.byref(o), ctypes.byref(e0),
+                                             _P(psi.data_ptr()) if psi is not None else None,
+                                             ctypes.byref(rep), _stream_ptr(stream))
     _check(st, ok=tuple(allow) + (EDX_OK,))
     r = {f: getattr(rep, f) for f, _ in LanczosReport._fields_}
     return e0.value, psi, r, st
