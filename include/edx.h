@@ -210,6 +210,12 @@ typedef struct {
                            2 * 2^-23 |T|) makes the ground level degenerate.
                            Runs only when psi0 is requested.               */
   int32_t pad_;
+  const void* start;    /* nullable: a dense device vector (D elements of
+                           vtype, any nonzero norm) used as the start vector
+                           instead of the SplitMix64 one -- e.g. an FP32
+                           ground vector, cast to FP64, to refine it in FP64
+                           with a few steps.  Ground state only; must not
+                           alias psi0.  Zero or non-finite: EDX_E_INVALID.  */
 } edx_lanczos_opts;
 
 typedef struct {

@@ -299,6 +299,7 @@ void edx_lanczos_default_opts(edx_lanczos_opts* o) {
   o->seed = 1234567;
   o->degen_check = 1;
   o->pad_ = 0;
+  o->start = nullptr;
 }
 
 size_t edx_workspace_bytes(const edx_sector* s, int32_t what, int32_t vtype, int32_t n) {

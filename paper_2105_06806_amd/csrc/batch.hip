@@ -538,6 +538,7 @@ edx_status batch_run(const edx_sector* const* secs, int n, const edx_lanczos_opt
   if (nwide > 0) {
     edx_lanczos_opts q = *o;
     q.reorth = 0;
+    q.start = nullptr;   // every job starts from its own SplitMix64 vector
     // helper threads start on device 0: they are given the caller's device
     int dev = 0;
     EDX_HIP(hipGetDevice(&dev));
@@ -682,6 +683,7 @@ edx_status batch_autotune(const edx_sector* const* secs, int n, const edx_lanczo
                           void* ws, size_t ws_bytes, int* ccols, int* rcols, int* lane_wgs,
                           int64_t* wide_min, hipStream_t st) {
   edx_lanczos_opts q = *o;
+  q.start = nullptr;
   q.niter = 6;
   q.tol = 0.0;
   q.check_every = 1000;

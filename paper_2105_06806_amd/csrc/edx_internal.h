@@ -192,9 +192,11 @@ edx_status k_transpose(int vtype, const void* src, int64_t rows, int64_t cols, i
 // ---- krylov.hip
 int elem_blocks(int64_t n);
 // random start vector in [-1, 1) of the element with logical index r + c*dup
-// (the same values for every ld); zero in the padding rows
+// (the same values for every ld); zero in the padding rows.  With src, the
+// dense vector src (dup * ddw elements) is copied into that layout instead.
 edx_status k_start_vector(int vtype, void* u, int64_t dup, int64_t ld, int64_t ddw,
-                          uint64_t seed, double* partial, hipStream_t st);
+                          uint64_t seed, double* partial, hipStream_t st,
+                          const void* src = nullptr);
 // y[r + c*dup] = scale * x[r + c*ld] (drops the padding rows)
 edx_status k_unpad_scale(int vtype, const void* x, int64_t ld, int64_t dup, int64_t ddw,
                          const double* scale, void* y, hipStream_t st);

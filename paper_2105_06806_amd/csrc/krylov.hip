@@ -30,10 +30,12 @@ __device__ __forceinline__ uint64_t splitmix64(uint64_t seed, uint64_t k) {
 
 // element (r, c) of a vector with column stride ld draws counter r + c*dup, so
 // the start vector is the same for every ld; padding rows are zero
+// src (nullable): a dense caller vector copied into the padded layout instead
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_start(T* __restrict__ u, int64_t dup, int64_t ld,
                                                     int64_t n, uint64_t seed,
-                                                    double* __restrict__ partial) {
+                                                    double* __restrict__ partial,
+                                                    const T* __restrict__ src) {
   __shared__ double red[kThreads / 64];
   double acc = 0.0;
   for (int64_t i = blockIdx.x * (int64_t)kThreads + threadIdx.x; i < n;
@@ -41,9 +43,13 @@ __global__ __launch_bounds__(kThreads) void k_start(T* __restrict__ u, int64_t d
     const int64_t c = i / ld, r = i - c * ld;
     T t = T(0);
     if (r < dup) {
-      const uint64_t z = splitmix64(seed, (uint64_t)(r + c * dup));
-      const double x = (double)(z >> 11) * 0x1.0p-53 * 2.0 - 1.0;
-      t = (T)x;
+      if (src) {
+        t = src[r + c * dup];
+      } else {
+        const uint64_t z = splitmix64(seed, (uint64_t)(r + c * dup));
+        const double x = (double)(z >> 11) * 0x1.0p-53 * 2.0 - 1.0;
+        t = (T)x;
+      }
     }
     u[i] = t;
     acc += (double)t * (double)t;
@@ -278,15 +284,15 @@ int multi_blocks(int64_t n) { return elem_blocks(n); }
 #define PT(x) reinterpret_cast<T*>(x)
 
 edx_status k_start_vector(int vtype, void* u, int64_t dup, int64_t ld, int64_t ddw,
-                          uint64_t seed, double* partial, hipStream_t st) {
+                          uint64_t seed, double* partial, hipStream_t st, const void* src) {
   const int64_t n = ld * ddw;
   const int g = elem_blocks(n);
   if (vtype == EDX_F64)
     hipLaunchKernelGGL(k_start<double>, dim3(g), dim3(kThreads), 0, st, (double*)u, dup, ld, n,
-                       seed, partial);
+                       seed, partial, (const double*)src);
   else
     hipLaunchKernelGGL(k_start<float>, dim3(g), dim3(kThreads), 0, st, (float*)u, dup, ld, n,
-                       seed, partial);
+                       seed, partial, (const float*)src);
   EDX_HIP(hipGetLastError());
   return EDX_OK;
 }

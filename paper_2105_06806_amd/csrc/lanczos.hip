@@ -443,9 +443,19 @@ edx_status lanczos_ground_state_impl(const edx_sector* s, const edx_lanczos_opts
     return EDX_E_NOMEM;
   }
   const int64_t n = s->vlen;
-  // start vector u_0 and scale_0 = 1/|u_0|
-  EDX_TRY(k_start_vector(vtype, L.vec, s->dup, s->ld, s->ddw * s->dph, o->seed, L.partial, st));
+  // start vector u_0 (random, or the caller's) and scale_0 = 1/|u_0|
+  EDX_TRY(k_start_vector(vtype, L.vec, s->dup, s->ld, s->ddw * s->dph, o->seed, L.partial, st,
+                         o->start));
   EDX_TRY(k_beta_finish(L.partial, elem_blocks(n), L.beta, L.scale, st));
+  if (o->start) {
+    double u0 = 0.0;
+    EDX_HIP(hipMemcpyAsync(&u0, L.beta, sizeof(double), hipMemcpyDeviceToHost, st));
+    EDX_HIP(hipStreamSynchronize(st));
+    if (!(u0 > 0.0) || !std::isfinite(u0)) {
+      set_error("lanczos: the start vector is zero or not finite");
+      return EDX_E_INVALID;
+    }
+  }
   EDX_HIP(hipMemsetAsync(L.beta, 0, sizeof(double), st));   // beta_0 couples nothing
 
   std::vector<double> ha(niter + 2), hb(niter + 2);
@@ -521,7 +531,8 @@ edx_status lanczos_ground_state_impl(const edx_sector* s, const edx_lanczos_opts
       // replay: identical start vector and recurrence, psi += y_j v_j
       EDX_HIP(hipMemcpyAsync(L.y, y.data(), sizeof(double) * m, hipMemcpyHostToDevice, st));
       EDX_HIP(hipMemsetAsync(acc, 0, (size_t)n * vbytes(vtype), st));
-      EDX_TRY(k_start_vector(vtype, L.vec, s->dup, s->ld, s->ddw * s->dph, o->seed, L.partial, st));
+      EDX_TRY(k_start_vector(vtype, L.vec, s->dup, s->ld, s->ddw * s->dph, o->seed, L.partial, st,
+                             o->start));
       EDX_TRY(k_beta_finish(L.partial, elem_blocks(n), L.beta2, L.scale2, st));
       EDX_HIP(hipMemsetAsync(L.beta2, 0, sizeof(double), st));
       for (int j = 0; j < m; ++j)

@@ -244,6 +244,7 @@ void worker_main(edx_server* S, int slot) {
         edx_lanczos_opts lo = o.lanczos;
         lo.vtype = o.vtype;
         lo.reorth = 0;
+        lo.start = nullptr;
         edx_lanczos_report rep{};
         double e0 = 0;
         st2 = lanczos_ground_state_impl(sec, &lo, ws, lw, &e0, psi, &rep, st);

@@ -51,7 +51,7 @@ class LanczosOpts(ctypes.Structure):
                 ("reorth", ctypes.c_int32), ("check_every", ctypes.c_int32),
                 ("tol", ctypes.c_double), ("rtol", ctypes.c_double),
                 ("seed", ctypes.c_uint64), ("degen_check", ctypes.c_int32),
-                ("pad_", ctypes.c_int32)]
+                ("pad_", ctypes.c_int32), ("start", ctypes.c_void_p)]
 
 
 class LanczosReport(ctypes.Structure):
@@ -418,8 +418,17 @@ def lanczos_opts(**kw):
     for k, v in kw.items():
         if k == "vtype":
             v = _vt(v)
+        if k == "start":          # a device tensor (kept alive by the caller) or None
+            v = None if v is None else v.data_ptr()
         setattr(o, k, v)
     return o
+
+
+def _check_start(sector, o, start):
+    if start is not None and (start.dtype != _dtype_of(o.vtype) or start.numel() != sector.dim
+                              or not start.is_cuda or not start.is_contiguous()):
+        raise ValueError("start must be a contiguous device tensor of sector.dim elements of the "
+                         "vector type")
 
 
 def workspace_bytes(sector, what, vtype, n):
@@ -433,6 +442,7 @@ def alloc_workspace(nbytes, device="cuda"):
 def lanczos_ground_state(sector, want_psi=True, ws=None, stream=None, allow=(EDX_OK,), **kw):
     """Returns (e0, psi0 tensor or None, report dict, status)."""
     o = lanczos_opts(**kw)
+    _check_start(sector, o, kw.get("start"))
     what = WS_LANCZOS_FULL if o.reorth >= 2 else WS_LANCZOS
     need = workspace_bytes(sector, what, o.vtype, o.niter)
     if ws is None:
@@ -454,6 +464,7 @@ def lanczos_ground_state_static(sector, psi=None, stream=None, allow=(EDX_OK,), 
     a caller-owned device tensor of sector.dim elements of the vector type, or
     None.  Returns (e0, psi, report dict, status)."""
     o = lanczos_opts(**kw)
+    _check_start(sector, o, kw.get("start"))
     if psi is not None:
         if psi.dtype != _dtype_of(o.vtype) or psi.numel() != sector.dim or not psi.is_cuda:
             raise ValueError("psi must be a device tensor of sector.dim elements of the vector type")
