@@ -70,6 +70,9 @@ def parse():
                     help="largest Ns of the serving requests (default 16)")
     ap.add_argument("--serve-rates", default=None,
                     help="comma-separated multiples of the plain capacity for the serving sweep")
+    ap.add_argument("--serve-cap", type=float, default=None,
+                    help="plain capacity (requests/s) measured by an earlier run of the same mix: "
+                         "the sweep's rates are multiples of it (a sweep split over several runs)")
     ap.add_argument("--only", default=None,
                     help="comma-separated sections (hv_ns16o2, hv_kanamori, orbital, lowest_thermal, "
                          "eph, shard, ns12, ns15o3, batch, serve): run just these, no headline "
@@ -128,17 +131,19 @@ def traffic_from_profile(plan, dt):
 
 
 def copy_bandwidth(torch, nbytes=1 << 30, reps=10):
-    """Device-to-device copy GB/s (read + write) of a 1 GiB buffer: the
-    streaming rate this GPU reaches with a plain copy."""
+    """Streaming GB/s (read + write) of a plain elementwise pass y = -x over a
+    1 GiB FP32 buffer: the rate this GPU reaches with a copy-like kernel.  The
+    same kernel (torch's neg, 1 GiB read and 1 GiB written per launch) is the
+    calibration of the counter summaries under profiles/."""
     x = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda").uniform_()
     y = torch.empty_like(x)
     for _ in range(3):
-        y.copy_(x)
+        torch.neg(x, out=y)
     a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     a.record()
     for _ in range(reps):
-        y.copy_(x)
+        torch.neg(x, out=y)
     b.record()
     torch.cuda.synchronize()
     ms = a.elapsed_time(b) / reps
@@ -569,7 +574,7 @@ def bench_batch(edx, torch):
                                          "max_rel_dev_vs_plain": float(max(dev_all))}}
 
 
-def bench_serve(edx, torch, full, nreq=None, ns_hi=None, rates=None):
+def bench_serve(edx, torch, full, nreq=None, ns_hi=None, rates=None, cap_given=None):
     """Config 5: a Poisson stream of ground state + G requests (Norb in {1,2},
     Ns 10..16, U in [1,6]; FP32 vectors) served with continuous batching, at
     offered rates that are multiples of the measured one-at-a-time capacity,
@@ -594,7 +599,8 @@ def bench_serve(edx, torch, full, nreq=None, ns_hi=None, rates=None):
         edx.green_cf(S, psi, e0, 0, 0, **gkw)
         lat_plain.append(time.perf_counter() - ts)
         del S, psi
-    cap = len(lat_plain) / (time.perf_counter() - t0)     # plain requests/s
+    cap_here = len(lat_plain) / (time.perf_counter() - t0)     # plain requests/s
+    cap = cap_given or cap_here
     ns_mix = [inputs.ns_of(m) for (m, _, _) in reqs]
     out = {"workload": f"Poisson stream of ground state + G requests, Norb in {{1,2}}, Ns 10..{ns_hi} "
                        f"(largest 12870^2 = 165,636,900), U in [1,6], FP32 vectors, G depth "
@@ -602,7 +608,8 @@ def bench_serve(edx, torch, full, nreq=None, ns_hi=None, rates=None):
            "requests_per_rate": nreq,
            "ns16_share": round(sum(1 for x in ns_mix if x == 16) / len(ns_mix), 3),
            "plain_requests": nplain,
-           "plain_solves_per_s": round(cap, 2), "plain_p50_s": round(float(np.median(lat_plain)), 4),
+           "plain_solves_per_s": round(cap_here, 2), "rate_unit_per_s": round(cap, 3),
+           "plain_p50_s": round(float(np.median(lat_plain)), 4),
            "plain_p99_s": round(float(np.percentile(lat_plain, 99)), 4),
            "rates": []}
     srv = edx.Server(hbm_budget=96 << 30, max_slots=8, vtype="f32", **gkw, **kw)
@@ -657,7 +664,8 @@ def main():
                 "batch": lambda: bench_batch(edx, torch),
                 "serve": lambda: bench_serve(
                     edx, torch, a.full, a.serve_n, a.serve_ns_hi,
-                    tuple(float(x) for x in a.serve_rates.split(",")) if a.serve_rates else None)}
+                    tuple(float(x) for x in a.serve_rates.split(",")) if a.serve_rates else None,
+                    a.serve_cap)}
     if a.only:
         out = {}
         for name in a.only.split(","):

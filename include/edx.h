@@ -171,7 +171,10 @@ edx_status edx_hv(const edx_sector* s, edx_vtype vtype, const void* v, void* w,
  * col_order (mode 2): which columns a workgroup takes -- 0 consecutive groups
  * in workgroup order, 1 the groups running at once on one XCD are
  * consecutive, 2 as 1 over the columns sorted by impurity occupation (so
- * that concurrently processed columns share more spin-down neighbours). */
+ * that concurrently processed columns share more spin-down neighbours), 3 and
+ * 4 as 1 and 2 inside windows of about one group per CU (3) or two (4) that
+ * all XCDs walk together (their neighbour columns then also meet in the
+ * MALL). */
 typedef struct {
   int32_t mode, col_cols, col_threads, row_rows, row_cols, col_order;
 } edx_hv_plan;

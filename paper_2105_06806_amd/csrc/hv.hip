@@ -420,6 +420,8 @@ inline size_t nd_tab_lds(int P, int nt, size_t tsz) {
   return al16((size_t)(P * P + 1) * 4) + al16((size_t)nt * 8) + al16((size_t)nt * tsz);
 }
 
+constexpr int64_t kWinGroups = 32;   // column groups per XCD in a window (its CUs)
+
 template <typename T, int WUP, int WDW, int NC, bool ND, bool PH, bool BUF>
 __global__ __launch_bounds__(1024) void k_hv_fused(HvArgs<T> a, const T* __restrict__ v,
                                                    T* __restrict__ w,
@@ -453,17 +455,33 @@ __global__ __launch_bounds__(1024) void k_hv_fused(HvArgs<T> a, const T* __restr
     }
   }
   // Which columns: group cb = workgroup index (order 0), or XCD-contiguous
-  // numbering (order >= 1): workgroups go round-robin over the 8 XCDs, so
+  // numbering (orders 1 and 2): workgroups go round-robin over the 8 XCDs, so
   // workgroup b takes group x*q + min(x, r) + b/8 (x = b % 8) and the groups
   // running at once on one XCD are consecutive; their spin-down neighbours
-  // overlap and are served by that XCD's L2.  Order 2 walks the columns
+  // overlap and are served by that XCD's L2.  Orders 3 and 4: the same inside
+  // windows that all XCDs walk together.  Orders 2 and 4 walk the columns
   // sorted by impurity occupation, where consecutive columns share more
   // neighbours.
   int64_t cb = blockIdx.x;
-  if (order >= 1) {
+  if (order == 1 || order == 2) {
     const int64_t nblk = gridDim.x, q8 = nblk / 8, r8 = nblk % 8;
     const int64_t x8 = blockIdx.x % 8;
     cb = x8 * q8 + std::min<int64_t>(x8, r8) + blockIdx.x / 8;
+  } else if (order >= 3) {
+    // windows of 8 * wg consecutive groups (wg = 32, one per CU, over the
+    // columns in listing order; 64 over the sorted columns -- the measured
+    // best): inside a window XCD x takes the groups x*wg ... x*wg + wg - 1,
+    // so the groups resident on one XCD are consecutive (their neighbours
+    // meet in its L2) and all XCDs work in the same window (its neighbour
+    // columns meet in the MALL); the last, partial window keeps the
+    // workgroup order
+    const int64_t wg = order == 3 ? kWinGroups : 2 * kWinGroups;
+    const int64_t win = 8 * wg;
+    const int64_t b = blockIdx.x, w0 = b - b % win;
+    if (w0 + win <= (int64_t)gridDim.x) {
+      const int64_t r = b - w0;
+      cb = w0 + (r % 8) * wg + r / 8;
+    }
   }
   const int64_t j0 = cb * NC;
   const int nc = (int)std::min<int64_t>(NC, a.ddw - j0);
@@ -471,7 +489,7 @@ __global__ __launch_bounds__(1024) void k_hv_fused(HvArgs<T> a, const T* __restr
 #pragma unroll
   for (int c = 0; c < NC; ++c) {
     const int64_t jj = std::min<int64_t>(j0 + c, a.ddw - 1);
-    jc[c] = order == 2 ? (int64_t)__builtin_amdgcn_readfirstlane(corder[jj]) : jj;
+    jc[c] = (order == 2 || order == 4) ? (int64_t)__builtin_amdgcn_readfirstlane(corder[jj]) : jj;
   }
   const T sc = vscale ? (T)(*vscale) : T(1);
   // first staging pass in flight while the tables and the block-uniform
@@ -871,10 +889,11 @@ HvPlan hv_default_plan(const edx_sector* s, int vtype) {
   p.col_threads = colb >= 48 * 1024 && c == 3 ? 1024 : 512;
   p.col_blocks = (int)((s->ddw + c - 1) / c);
   p.mode = 2;
-  // FP32: XCD-contiguous groups over pattern-sorted columns (L2 reuse of the
-  // spin-down neighbours); FP64 vectors are twice the size and did better
-  // with consecutive workgroups on different XCDs sharing the MALL
-  p.col_order = vtype == EDX_F32 ? 2 : 0;
+  // XCD-contiguous groups inside windows all XCDs walk together (the L2 and
+  // the MALL both see the shared spin-down neighbours): FP32 over the
+  // pattern-sorted columns, FP64 (vectors twice the size) in listing order --
+  // the faster of each on the Ns = 16 sector
+  p.col_order = vtype == EDX_F32 ? 4 : 3;
   p.row_rows = (s->dup % 2 == 0) ? 128 : 64;
   p.row_cols = 8;
   return p;
@@ -894,8 +913,8 @@ edx_status hv_validate(const edx_sector* s, int vtype, HvPlan* p) {
     set_error("hv plan: mode must be 0, 1 or 2");
     return EDX_E_INVALID;
   }
-  if (p->col_order < 0 || p->col_order > 2) {
-    set_error("hv plan: col_order must be 0, 1 or 2");
+  if (p->col_order < 0 || p->col_order > 4) {
+    set_error("hv plan: col_order must be in [0, 4]");
     return EDX_E_INVALID;
   }
   if (p->col_cols < 1 || p->col_cols > kColMax ||
@@ -1119,7 +1138,9 @@ edx_status launch_t(const edx_sector* s, const T* v, T* w, int64_t ld, const dou
       return EDX_E_INVALID;
   }
   const bool fused = p.mode == 2;
-  FusedOrder<T> fo{s->corder ? p.col_order : std::min(p.col_order, 1), s->corder, nd};
+  // without the sorted column list, 2 falls back to 1 and 4 to 3
+  FusedOrder<T> fo{s->corder ? p.col_order : (p.col_order == 4 ? 3 : std::min(p.col_order, 1)),
+                   s->corder, nd};
   fo.ph = use_ph;
   fo.pa = pa;
   switch (a.sup) {
@@ -1516,7 +1537,7 @@ edx_status hv_autotune(edx_sector* s, int vtype, const void* v, void* w, int64_t
       p.mode = 2;
       p.col_cols = cc;
       p.col_threads = th;
-      for (int co : {0, 1, 2}) {
+      for (int co : {0, 1, 2, 3, 4}) {
         HvPlan r = p;
         r.col_order = co;
         add(r);

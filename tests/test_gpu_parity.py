@@ -107,6 +107,8 @@ PLANS = [
     dict(mode=2, col_cols=2, col_threads=512, row_rows=64, row_cols=32, col_order=1),
     dict(mode=2, col_cols=3, col_threads=1024, row_rows=64, row_cols=32, col_order=2),
     dict(mode=2, col_cols=4, col_threads=256, row_rows=64, row_cols=32, col_order=2),
+    dict(mode=2, col_cols=2, col_threads=1024, row_rows=64, row_cols=32, col_order=3),
+    dict(mode=2, col_cols=1, col_threads=512, row_rows=64, row_cols=32, col_order=4),
     dict(mode=1, col_cols=1, col_threads=512, row_rows=64, row_cols=16),
     dict(mode=1, col_cols=4, col_threads=256, row_rows=16, row_cols=7),
     dict(mode=1, col_cols=2, col_threads=1024, row_rows=32, row_cols=64),
@@ -316,7 +318,7 @@ def test_hv_headline_sector_sampled(edx, dtype):
     pos = rows % S.dup + (rows // S.dup) * S.ld
     tol = (1e-13 if dtype == "f64" else 2e-6) * _hscale(m)
     fused = [dict(mode=2, col_cols=3 if dtype == "f32" else 1, col_threads=1024, col_order=o)
-             for o in (0, 1, 2)]
+             for o in (0, 1, 2, 3, 4)]
     for plan in fused + [dict(mode=1, col_cols=1, col_threads=512, row_rows=128, row_cols=8)]:
         assert _set_plan(edx, S, vt, plan) == 0, edx.last_error()
         w = torch.full_like(v, float("nan"))
