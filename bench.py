@@ -70,6 +70,13 @@ def parse():
                     help="largest Ns of the serving requests (default 16)")
     ap.add_argument("--serve-rates", default=None,
                     help="comma-separated multiples of the plain capacity for the serving sweep")
+    ap.add_argument("--serve-plain", default=None,
+                    help="JSON file with the plain service times of the stream (read if present, "
+                         "else measured and written): a sweep split over several runs")
+    ap.add_argument("--serve-offset", type=int, default=0,
+                    help="first request of the stream to submit (a rate split over runs)")
+    ap.add_argument("--serve-span", type=int, default=None,
+                    help="number of requests to submit from --serve-offset (default: the rest)")
     ap.add_argument("--serve-cap", type=float, default=None,
                     help="plain capacity (requests/s) measured by an earlier run of the same mix: "
                          "the sweep's rates are multiples of it (a sweep split over several runs)")
@@ -574,32 +581,57 @@ def bench_batch(edx, torch):
                                          "max_rel_dev_vs_plain": float(max(dev_all))}}
 
 
-def bench_serve(edx, torch, full, nreq=None, ns_hi=None, rates=None, cap_given=None):
+def _fcfs(arr, svc):
+    """Latencies of a single first-come-first-served server (one request at a
+    time, the plain path) fed with arrival times arr and service times svc."""
+    done, lat = 0.0, []
+    for a_, s_ in zip(arr, svc):
+        start = max(a_, done)
+        done = start + s_
+        lat.append(done - a_)
+    return np.array(lat), done
+
+
+def bench_serve(edx, torch, full, nreq=None, ns_hi=None, rates=None, cap_given=None,
+                plain_file=None, offset=0, span=None):
     """Config 5: a Poisson stream of ground state + G requests (Norb in {1,2},
     Ns 10..16, U in [1,6]; FP32 vectors) served with continuous batching, at
-    offered rates that are multiples of the measured one-at-a-time capacity,
-    against the same requests solved one after another (plain).  The default
-    run uses fewer requests per rate than --full (1000 per rate at seven
-    rates) so that the whole benchmark stays within a few minutes."""
+    offered rates that are multiples of the measured one-at-a-time capacity.
+    Plain: every request of the stream solved one after another (its service
+    time); the same arrivals fed to one first-come-first-served plain server
+    give the plain latencies at each rate.  The default run uses fewer
+    requests per rate than --full (1000 per rate at seven rates) so that the
+    whole benchmark stays within a few minutes."""
     from paper_2105_06806_amd import inputs
     ns_hi = ns_hi or 16
     nreq = nreq or (1000 if full else 150)
     kw = dict(niter=512, tol=1e-9, seed=5, check_every=4)
     gkw = dict(ngf=200, lmats=1024, beta=200.0)
     reqs = inputs.serve_requests(nreq, ns_lo=10, ns_hi=ns_hi)
-    # one-at-a-time plain solves of the first requests of the same stream
-    nplain = max(40, nreq // 8)
-    t0 = time.perf_counter()
-    lat_plain = []
-    for (m, a, b) in reqs[:nplain]:
-        ts = time.perf_counter()
-        S = edx.build_sector(m, a, b)
-        e0, psi, _, _ = edx.lanczos_ground_state(
-            S, vtype="f32", allow=(edx.EDX_E_NOCONV, edx.EDX_E_DEGENERATE), **kw)
-        edx.green_cf(S, psi, e0, 0, 0, **gkw)
-        lat_plain.append(time.perf_counter() - ts)
-        del S, psi
-    cap_here = len(lat_plain) / (time.perf_counter() - t0)     # plain requests/s
+    # a part of the stream (requests offset .. offset + span - 1, their own
+    # arrival times): one rate's sweep split over several runs
+    span = span or (nreq - offset)
+    svc = None
+    if plain_file and os.path.exists(plain_file):
+        svc = json.load(open(plain_file))["service_s"][:nreq]
+        if len(svc) < nreq:
+            svc = None
+    if svc is None:
+        # one-at-a-time plain solves of every request of the stream
+        svc = []
+        for (m, a, b) in reqs:
+            torch.cuda.synchronize()
+            ts = time.perf_counter()
+            S = edx.build_sector(m, a, b)
+            e0, psi, _, _ = edx.lanczos_ground_state(
+                S, vtype="f32", allow=(edx.EDX_E_NOCONV, edx.EDX_E_DEGENERATE), **kw)
+            edx.green_cf(S, psi, e0, 0, 0, **gkw)
+            svc.append(time.perf_counter() - ts)
+            del S, psi
+        if plain_file:
+            json.dump({"service_s": svc, "nreq": nreq, "ns_hi": ns_hi}, open(plain_file, "w"))
+    svc = np.array(svc)
+    cap_here = len(svc) / svc.sum()                      # plain requests/s
     cap = cap_given or cap_here
     ns_mix = [inputs.ns_of(m) for (m, _, _) in reqs]
     out = {"workload": f"Poisson stream of ground state + G requests, Norb in {{1,2}}, Ns 10..{ns_hi} "
@@ -607,19 +639,20 @@ def bench_serve(edx, torch, full, nreq=None, ns_hi=None, rates=None, cap_given=N
                        f"{gkw['ngf']} on {gkw['lmats']} frequencies, {nreq} requests per rate",
            "requests_per_rate": nreq,
            "ns16_share": round(sum(1 for x in ns_mix if x == 16) / len(ns_mix), 3),
-           "plain_requests": nplain,
-           "plain_solves_per_s": round(cap_here, 2), "rate_unit_per_s": round(cap, 3),
-           "plain_p50_s": round(float(np.median(lat_plain)), 4),
-           "plain_p99_s": round(float(np.percentile(lat_plain, 99)), 4),
+           "plain_solves_per_s": round(cap_here, 3), "rate_unit_per_s": round(cap, 3),
+           "plain_service_p50_s": round(float(np.median(svc)), 4),
+           "plain_service_p99_s": round(float(np.percentile(svc, 99)), 4),
            "rates": []}
     srv = edx.Server(hbm_budget=96 << 30, max_slots=8, vtype="f32", **gkw, **kw)
     facs = rates or ((0.5, 1.0, 2.0) if not full else (0.25, 0.5, 0.75, 0.9, 1.0, 1.25, 2.0))
     for fac in facs:
         rate = fac * cap
-        arr = inputs.poisson_arrivals(nreq, rate, seed=int(fac * 1000))
+        arr = inputs.poisson_arrivals(nreq, rate, seed=int(fac * 1000))[offset:offset + span]
+        arr = arr - arr[0]
+        part = reqs[offset:offset + span]
         t_begin = edx.Server.clock()
         tickets = []
-        for (m, a, b), ta in zip(reqs, arr):
+        for (m, a, b), ta in zip(part, arr):
             wait = t_begin + ta - edx.Server.clock()
             if wait > 0:
                 time.sleep(wait)
@@ -628,11 +661,15 @@ def bench_serve(edx, torch, full, nreq=None, ns_hi=None, rates=None, cap_given=N
         t_end = max(r["t_done"] for r in res)
         lat = np.array([r["t_done"] - r["t_submit"] for r in res])
         first = min(r["t_submit"] for r in res)
-        out["rates"].append({"offered_per_s": round(rate, 2), "x_plain_capacity": fac,
-                             "n": len(res),
-                             "solves_per_s": round(len(res) / (t_end - first), 2),
+        plat, pdone = _fcfs(arr, svc[offset:offset + span])
+        out["rates"].append({"offered_per_s": round(rate, 3), "x_plain_capacity": fac,
+                             "n": len(res), "first_request": offset,
+                             "solves_per_s": round(len(res) / (t_end - first), 3),
                              "p50_s": round(float(np.percentile(lat, 50)), 4),
                              "p99_s": round(float(np.percentile(lat, 99)), 4),
+                             "plain_fcfs_solves_per_s": round(len(res) / (pdone - arr[0]), 3),
+                             "plain_fcfs_p50_s": round(float(np.percentile(plat, 50)), 4),
+                             "plain_fcfs_p99_s": round(float(np.percentile(plat, 99)), 4),
                              "ok": int(sum(r["status"] in (0, edx.EDX_E_DEGENERATE) for r in res)),
                              "degenerate": int(sum(r["status"] == edx.EDX_E_DEGENERATE
                                                    for r in res))})
@@ -665,7 +702,7 @@ def main():
                 "serve": lambda: bench_serve(
                     edx, torch, a.full, a.serve_n, a.serve_ns_hi,
                     tuple(float(x) for x in a.serve_rates.split(",")) if a.serve_rates else None,
-                    a.serve_cap)}
+                    a.serve_cap, a.serve_plain, a.serve_offset, a.serve_span)}
     if a.only:
         out = {}
         for name in a.only.split(","):
