@@ -365,6 +365,67 @@ def bench_shard(edx, torch, a, p=8):
             "model_speedup_vs_one_gpu": round(t_whole / (comp + 2 * t_link), 2)}
 
 
+def bench_hv_multi(edx, torch, a):
+    """Several bath sets of one sector shape per product (edx_hv_multi): the
+    k vectors interleaved, one spin-down gather serving all k.  Per-vector
+    algorithmic GB/s (k D (s + s) bytes per launch, s = element size) for
+    k = 1, 2, 4, 8 on the Ns=12 6/6 and Ns=14 7/7 sectors (the batch
+    workload's large shapes) and the k that fit in LDS on the Ns=16 8/8
+    sector, FP32 and FP64, beside the single-vector fused pass
+    (fused_single, the sector's default plan)."""
+    from paper_2105_06806_amd import inputs
+    out = {}
+    # the calibration kernel of the counter summaries runs in the same process
+    out["copy_gbs"] = round(copy_bandwidth(torch), 1)
+    for ns, sec, ks in ((12, (6, 6), (1, 2, 4, 8)), (14, (7, 7), (1, 2, 4, 8)), (16, (8, 8), (1, 2))):
+        for dt, tdt in (("f32", torch.float32), ("f64", torch.float64)):
+            row = {}
+            for k in ks:
+                ms = [inputs.make_model(1, ns - 1, 2.0, seed=inputs.SEED_BASE["batch"] + 3 * b + ns)
+                      for b in range(k)]
+                Ss = [edx.build_sector(m, *sec) for m in ms]
+                n = Ss[0].ld * Ss[0].ddw * k
+                if 16 + Ss[0].dup * k * (8 if dt == "f64" else 4) > 150 * 1024:
+                    continue
+                gen = torch.Generator(device="cuda").manual_seed(8)
+                v = torch.rand(n, dtype=tdt, device="cuda", generator=gen) * 2 - 1
+                w = torch.empty_like(v)
+                ws = edx.alloc_workspace(edx.lib.edx_hv_multi_workspace_bytes(
+                    edx._handles(Ss), k, edx.F32 if dt == "f32" else edx.F64))
+                for _ in range(3):
+                    edx.hv_multi(Ss, v, w, ws=ws)
+                torch.cuda.synchronize()
+                ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+                      for _ in range(10)]
+                for x, y in ev:
+                    x.record()
+                    edx.hv_multi(Ss, v, w, ws=ws)
+                    y.record()
+                torch.cuda.synchronize()
+                us = float(np.mean([x.elapsed_time(y) for x, y in ev])) * 1e3
+                alg = k * Ss[0].dim * 2 * v.element_size()
+                row[f"k{k}"] = {"us": round(us, 1), "us_per_vector": round(us / k, 1),
+                                "gbs": round(alg / (us * 1e-6) / 1e9, 1),
+                                "frac": round(alg / (us * 1e-6) / 1e9 / HBM_PEAK_GBS, 4)}
+                if k == 1:
+                    # the single-vector fused pass on the sector's default plan
+                    for _ in range(3):
+                        edx.hv(Ss[0], v, w, ld=Ss[0].ld)
+                    torch.cuda.synchronize()
+                    for x, y in ev:
+                        x.record()
+                        edx.hv(Ss[0], v, w, ld=Ss[0].ld)
+                        y.record()
+                    torch.cuda.synchronize()
+                    us1 = float(np.mean([x.elapsed_time(y) for x, y in ev])) * 1e3
+                    row["fused_single"] = {"us": round(us1, 1),
+                                           "gbs": round(alg / (us1 * 1e-6) / 1e9, 1)}
+                del v, w, ws
+                torch.cuda.empty_cache()
+            out[f"ns{ns}_{dt}"] = row
+    return out
+
+
 def cpu_baseline(m, sec, elem_bytes, budget_s=15.0, max_procs=16):
     """The oracle's row-by-row H.v on a bounded sample of output rows: one core
     (calibration), then one oracle process per core (up to max_procs, the host
@@ -554,6 +615,15 @@ def bench_batch(edx, torch):
     wm = int(tiles["wide_min_dim"])
     thr = 2_000_000 if wm == 0 else (None if wm < 0 else wm)
     in_launch = D < thr if thr else np.ones(len(D), bool)
+    # the whole-GPU jobs one by one instead of in multi-set groups
+    wso = edx.alloc_workspace(edx.batch_workspace_bytes(secs, "f32", tiles["lane_wgs"],
+                                                        tiles["wide_min_dim"]))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    res_one, _ = edx.batch_ground_state(secs, tiles=dict(tiles, multi_k=1), ws=wso, **kw)
+    tone = time.perf_counter() - t0
+    del wso
+    dev_one = [abs(r["e0"] - p) / abs(p) for r, p in zip(res_one, plain)]
     # the alternative the autotuner also timed: every job inside the persistent
     # launch (no whole-GPU path), same tiles
     tiles_all = dict(tiles, wide_min_dim=-1)
@@ -575,6 +645,10 @@ def bench_batch(edx, torch):
             "wide_min_dim": tiles["wide_min_dim"],
             "jobs_in_persistent_launch": int(in_launch.sum()),
             "sum_D_share_in_persistent_launch": round(float(D[in_launch].sum() / D.sum()), 4),
+            "whole_gpu_jobs_one_by_one": {"batch_s": round(tone, 3),
+                                          "solves_per_s": round(len(secs) / tone, 1),
+                                          "converged": sum(1 for r in res_one if r["status"] == 0),
+                                          "max_rel_dev_vs_plain": float(max(dev_one))},
             "all_in_persistent_launch": {"batch_s": round(tall, 3),
                                          "solves_per_s": round(len(secs) / tall, 1),
                                          "converged": sum(1 for r in res_all if r["status"] == 0),
@@ -692,6 +766,7 @@ def main():
 
     log(f"device: {torch.cuda.get_device_properties(0).name}")
     sections = {"hv_ns16o2": lambda: bench_hv_o2(edx, torch, a),
+                "hv_multi": lambda: bench_hv_multi(edx, torch, a),
                 "hv_kanamori": lambda: bench_hv_kanamori(edx, torch, a),
                 "orbital": lambda: bench_orbital(edx, torch, a),
                 "lowest_thermal": lambda: bench_lowest_and_thermal(edx, torch, a),

@@ -283,6 +283,25 @@ edx_status edx_lanczos_ground_state_static(const edx_sector* s,
                                            void* psi0, edx_lanczos_report* rep,
                                            void* stream);
 
+/* ---- several bath sets of one sector shape at once (the paper's
+ * independent impurity problems, Sec. 6 "Main", solved together) ----
+ * k (1, 2, 4 or 8) sectors with the same Ns, Norb, N_up and N_dw (the same
+ * strings, hop columns and signs: the tables of secs[0] serve all) and their
+ * own baths and interaction.  v and w hold the k vectors interleaved element
+ * by element: element (i, j) of set b (row i of column j of eq. Vmatrix) at
+ * (i + j ld) k + b, ld = edx_sector_ld of the sectors, ld * D_dw * k elements
+ * each (padding rows of v not read, of w written as zero).  w_b = H_b v_b for
+ * every set, with each set's H v summed exactly as edx_hv's fused pass with one
+ * column per workgroup; one spin-down gather serves all k sets.  ws: device
+ * workspace of edx_hv_multi_workspace_bytes (the per-set tables and partial
+ * sums).  Total-N sectors without spin exchange, pair hopping or phonons,
+ * hop rows of 8 or 16 entries, D_up < 2^16, a column of the k sets within LDS
+ * and 32-bit byte offsets; otherwise EDX_E_UNSUPPORTED.  Sectors of different
+ * shapes -> EDX_E_INVALID. */
+size_t edx_hv_multi_workspace_bytes(const edx_sector* const* secs, int32_t k, int32_t vtype);
+edx_status edx_hv_multi(const edx_sector* const* secs, int32_t k, edx_vtype vtype,
+                        const void* v, void* w, void* ws, size_t ws_bytes, void* stream);
+
 /* ---- the per-GPU pieces of the column-distributed product (Sec. 3.2:
  * columns of V split over processes, two transposes per product), callable on
  * one GPU so that a sharded product can be composed and its per-GPU work
@@ -520,8 +539,11 @@ edx_status edx_espace_chi_pair(edx_espace* E, int32_t a, const edx_gf_opts* opts
  * plain recurrence of edx_lanczos_ground_state (psi0 is not formed).  The
  * paper's counterpart is its parallelism over independent impurity problems
  * (Sec. 6 "Main", inequivalent sites).  Jobs with D >= wide_min_dim fill the
- * GPU by themselves: they run first, one after another, through the kernels
- * and host stop rule of edx_lanczos_ground_state (tol and rtol).  The others
+ * GPU by themselves: they run first, through the kernels and host stop rule
+ * of edx_lanczos_ground_state (tol and rtol) -- jobs of one sector shape up to
+ * tiles.multi_k at a time through the multi-set pass (one interleaved product
+ * and recurrence per step for the group), the others one by one -- on three
+ * streams.  The others
  * share one cooperative launch: lanes of `lane_wgs` workgroups on one XCD
  * each pull jobs (largest first) from a device queue and evaluate the tol
  * stop rule on the device.  A job's status is EDX_OK, EDX_E_NOCONV (e0 is the
@@ -537,7 +559,14 @@ typedef struct {
 
 typedef struct {
   int32_t lane_wgs;       /* workgroups per lane: 8, 16 or 32             */
-  int32_t pad_;
+  int32_t multi_k;        /* whole-GPU jobs of one sector shape (the same
+                             Ns, Norb, N_up, N_dw; each its own bath) and
+                             at most 2^21 states run up to multi_k at a
+                             time (8, 4 or 2; FP64 vectors at most 4)
+                             through the multi-set pass of edx_hv_multi,
+                             the rest one by one; 0 = 8, 1 = off.  Larger
+                             shapes always run one by one: there the
+                             single-set pass is faster per vector        */
   const int32_t* ccols;   /* [n] columns per column-pass item (1..4), or NULL (1) */
   const int32_t* rcols;   /* [n] columns per row-pass item, or NULL (32)   */
   int64_t wide_min_dim;   /* jobs with D >= this run first, one at a time
@@ -581,8 +610,9 @@ edx_status edx_batch_autotune(const edx_sector* const* sectors, int32_t n,
  * device arena of hbm_budget bytes (allocated at creation; requests allocate
  * nothing else) and max_slots worker threads with their own streams.  A
  * request is admitted when a slot is free and its footprint (tables,
- * workspaces, psi0) fits in the arena; smaller requests may pass one that does
- * not fit yet, at most 8 times, then it blocks passing.  Admitted requests
+ * workspaces, psi0) fits in the arena; among the pending requests that fit,
+ * the smallest footprint goes first (its work is the smallest), and a request
+ * passed over 8 times goes next, blocking further passing.  Admitted requests
  * overlap on the device; each runs the plain path's kernels, so its result
  * does not depend on what else runs.  Times are seconds of
  * edx_server_clock(). */

@@ -207,6 +207,24 @@ edx_status edx_hv(const edx_sector* s, edx_vtype vtype, const void* v, void* w, 
   return hv_launch(s, vtype, v, w, ld, nullptr, nullptr, static_cast<hipStream_t>(stream));
 }
 
+size_t edx_hv_multi_workspace_bytes(const edx_sector* const* secs, int32_t k, int32_t vtype) {
+  if (!secs || !secs[0] || !valid_vtype(vtype) || (k != 1 && k != 2 && k != 4 && k != 8)) return 0;
+  return multi_hv_workspace_bytes(secs[0], k, vtype);
+}
+
+edx_status edx_hv_multi(const edx_sector* const* secs, int32_t k, edx_vtype vtype, const void* v,
+                        void* w, void* ws, size_t ws_bytes, void* stream) {
+  if (!secs || !v || !w || !ws) return invalid("secs, v, w and ws must be non-NULL");
+  if (!valid_vtype(vtype)) return invalid("vtype must be EDX_F64 or EDX_F32");
+  if (k != 1 && k != 2 && k != 4 && k != 8) return invalid("k must be 1, 2, 4 or 8");
+  for (int b = 0; b < k; ++b) EDX_TRY(check_sector(secs[b]));
+  const size_t bytes = (size_t)(secs[0]->vlen * k) * vbytes(vtype);
+  const char* pv = static_cast<const char*>(v);
+  const char* pw = static_cast<const char*>(w);
+  if (pv < pw + bytes && pw < pv + bytes) return invalid("v and w overlap");
+  return multi_hv(secs, k, vtype, v, w, ws, ws_bytes, static_cast<hipStream_t>(stream));
+}
+
 edx_status edx_hv_block(const edx_sector* s, edx_vtype vtype, int32_t part, const void* v,
                         void* w, int64_t ld, int64_t c0, int64_t c1, void* stream) {
   EDX_TRY(check_sector(s));
@@ -458,8 +476,10 @@ edx_status edx_batch_ground_state(const edx_sector* const* sectors, int32_t n,
   if (!ws || !results) return invalid("ws and results must be non-NULL");
   const int L = tiles ? tiles->lane_wgs : 32;
   if (L != 8 && L != 16 && L != 32) return invalid("lane_wgs must be 8, 16 or 32");
+  const int mk = tiles ? tiles->multi_k : 0;
+  if (mk < 0 || mk > 8) return invalid("tiles.multi_k must be in [0, 8]");
   return batch_run(sectors, n, opts, tiles ? tiles->ccols : nullptr,
-                   tiles ? tiles->rcols : nullptr, L, tiles ? tiles->wide_min_dim : 0, ws,
+                   tiles ? tiles->rcols : nullptr, L, tiles ? tiles->wide_min_dim : 0, mk, ws,
                    ws_bytes, results, static_cast<hipStream_t>(stream), elapsed_ms);
 }
 

@@ -67,6 +67,15 @@ constexpr int kMaxBatchIter = 2048;   // niter bound of the batch call
 // that one job's kernels fill the gaps while another's host checks its stop
 // rule.
 constexpr int kWideStreams = 3;
+constexpr int kMultiDefault = 8;        // bath sets per multi-set group (tiles.multi_k = 0)
+// Shapes the multi-set pass serves: up to 2^21 states, at most 4 FP64 sets.
+// Measured per vector against the single-set fused pass: half-filled Ns=12
+// (D = 853,776) 5.3 vs 10.1 us (FP32, 4 or 8 sets), 9.2-9.8 vs 11.3 us (FP64,
+// 2 or 4 sets; 8 sets 12.3 us); Ns=14 (D = 11.8M) 58-68 vs 48 us (FP32) --
+// there one column of k sets is k times the footprint in L2, so the misses
+// per vector do not fall while the grid is already full.
+constexpr int64_t kMultiMaxDim = int64_t(1) << 21;
+constexpr int kMultiMaxF64 = 4;
 
 __device__ __forceinline__ uint64_t splitmix64(uint64_t seed, uint64_t k) {
   uint64_t z = seed + (k + 1) * 0x9E3779B97F4A7C15ull;
@@ -465,11 +474,59 @@ static bool is_wide(const edx_sector* s, int64_t wide_min) {
   return s->nd || s->dph > 1 || (wide_min > 0 && s->dim >= wide_min);
 }
 
+// Work units of the whole-GPU path: jobs of one shape grouped K at a time for
+// the multi-set pass (K the largest of 8, 4, 2 not above multi_k that the
+// shape supports and that the group fills; shapes up to kMultiMaxDim states),
+// the rest one by one; the order is by decreasing dimension.
+std::vector<std::vector<int>> wide_units(const edx_sector* const* secs, const std::vector<int>& wide,
+                                         int vtype, int multi_k) {
+  std::vector<std::vector<int>> units;
+  std::vector<char> used(wide.size(), 0);
+  for (size_t a = 0; a < wide.size(); ++a) {
+    if (used[a]) continue;
+    const edx_sector* s = secs[wide[a]];
+    std::vector<int> same;
+    for (size_t b = a; b < wide.size(); ++b)
+      if (!used[b] && multi_same_shape(s, secs[wide[b]])) same.push_back((int)b);
+    size_t pos = 0;
+    for (int K : {8, 4, 2}) {
+      if (K > multi_k || (vtype == EDX_F64 && K > kMultiMaxF64) || s->dim > kMultiMaxDim ||
+          !multi_supported(s, K, vtype))
+        continue;
+      while (same.size() - pos >= (size_t)K) {
+        std::vector<int> u;
+        for (int q = 0; q < K; ++q) {
+          u.push_back(wide[same[pos + q]]);
+          used[same[pos + q]] = 1;
+        }
+        units.push_back(u);
+        pos += K;
+      }
+    }
+    for (; pos < same.size(); ++pos) {
+      units.push_back({wide[same[pos]]});
+      used[same[pos]] = 1;
+    }
+  }
+  std::stable_sort(units.begin(), units.end(), [&](const std::vector<int>& x,
+                                                   const std::vector<int>& y) {
+    return secs[x[0]]->dim * (int64_t)x.size() > secs[y[0]]->dim * (int64_t)y.size();
+  });
+  return units;
+}
+
+size_t wide_unit_bytes(const edx_sector* const* secs, const std::vector<int>& u, int vtype,
+                       int niter) {
+  if (u.size() == 1) return lanczos_workspace_bytes(secs[u[0]], vtype, niter, 0);
+  return multi_workspace_bytes(secs[u[0]], (int)u.size(), vtype, niter);
+}
+
 edx_status batch_run(const edx_sector* const* secs, int n, const edx_lanczos_opts* o,
-                     const int* ccols, const int* rcols, int L, int64_t wide_min, void* ws,
-                     size_t ws_bytes, edx_batch_result* res, hipStream_t st,
+                     const int* ccols, const int* rcols, int L, int64_t wide_min, int multi_k,
+                     void* ws, size_t ws_bytes, edx_batch_result* res, hipStream_t st,
                      double* elapsed_ms) {
   if (n <= 0) return EDX_OK;
+  if (multi_k == 0) multi_k = kMultiDefault;
   const int vtype = o->vtype;
   const int ncu = device_cus();
   if (ncu % 8 != 0 || (ncu / 8) % L != 0) {
@@ -488,15 +545,18 @@ edx_status batch_run(const edx_sector* const* secs, int n, const edx_lanczos_opt
   int nwide = 0;
   size_t wide_ws = 0;
   int64_t dmax_n = 0, colmax = 1;
+  std::vector<int> wide;
   for (int k = 0; k < n; ++k) {
     const edx_sector* s = secs[order[k]];
     if (is_wide(s, wide_min)) {
       ++nwide;
-      wide_ws = std::max(wide_ws, lanczos_workspace_bytes(s, vtype, o->niter, 0));
+      wide.push_back(order[k]);
     } else {
       dmax_n = std::max(dmax_n, s->dim);
     }
   }
+  const std::vector<std::vector<int>> units = wide_units(secs, wide, vtype, multi_k);
+  for (const auto& u : units) wide_ws = std::max(wide_ws, wide_unit_bytes(secs, u, vtype, o->niter));
   const int nl = n - nwide;
   std::vector<BatchJob> jobs(nl);
   for (int k = 0; k < nl; ++k) {
@@ -542,7 +602,7 @@ edx_status batch_run(const edx_sector* const* secs, int n, const edx_lanczos_opt
     // helper threads start on device 0: they are given the caller's device
     int dev = 0;
     EDX_HIP(hipGetDevice(&dev));
-    const int nst = std::min(kWideStreams, nwide);
+    const int nst = std::min(kWideStreams, (int)units.size());
     std::vector<hipStream_t> sts(nst, st);
     std::vector<hipEvent_t> done(nst, nullptr);
     edx_status fail = EDX_OK;
@@ -555,31 +615,49 @@ edx_status batch_run(const edx_sector* const* secs, int n, const edx_lanczos_opt
       }
     }
     std::atomic<int> next{0};
+    const int nunits = (int)units.size();
     std::vector<edx_status> tst(nst, EDX_OK);
     std::vector<std::string> terr(nst);
     auto worker = [&](int t) {
       if (t > 0 && hipSetDevice(dev) != hipSuccess) {
         tst[t] = EDX_E_DEVICE;
         terr[t] = "batch: hipSetDevice failed in a helper thread";
-        next.store(nwide);
+        next.store(nunits);
         return;
       }
+      char* wsp = base + B.o_wide + (size_t)t * align_up(B.wide_bytes);
       for (;;) {
         const int k = next.fetch_add(1);
-        if (k >= nwide) break;
-        const edx_sector* s = secs[order[k]];
+        if (k >= nunits) break;
+        const std::vector<int>& u = units[k];
+        if (u.size() > 1) {
+          // one shape, several bath sets: the multi-set pass
+          std::vector<const edx_sector*> g;
+          for (int id : u) g.push_back(secs[id]);
+          std::vector<edx_batch_result> rr(u.size());
+          const edx_status sg = multi_ground_states(g.data(), (int)u.size(), &q, wsp,
+                                                    B.wide_bytes, rr.data(), sts[t]);
+          if (sg != EDX_OK) {
+            tst[t] = sg;
+            terr[t] = std::string("batch: multi-set group: ") + edx_last_error();
+            next.store(nunits);
+            break;
+          }
+          for (size_t b = 0; b < u.size(); ++b) res[u[b]] = rr[b];
+          continue;
+        }
+        const edx_sector* s = secs[u[0]];
         double e = 0.0;
         edx_lanczos_report rep{};
-        const edx_status sj = lanczos_ground_state_impl(
-            s, &q, base + B.o_wide + (size_t)t * align_up(B.wide_bytes), B.wide_bytes, &e, nullptr,
-            &rep, sts[t]);
+        const edx_status sj =
+            lanczos_ground_state_impl(s, &q, wsp, B.wide_bytes, &e, nullptr, &rep, sts[t]);
         if (sj != EDX_OK && sj != EDX_E_NOCONV && sj != EDX_E_DEGENERATE) {
           tst[t] = sj;
           terr[t] = std::string("batch: whole-GPU job: ") + edx_last_error();
-          next.store(nwide);
+          next.store(nunits);
           break;
         }
-        edx_batch_result& r = res[order[k]];
+        edx_batch_result& r = res[u[0]];
         r.e0 = e;
         r.beta_last = rep.beta_last;
         r.iters = rep.iters;
@@ -716,7 +794,7 @@ edx_status batch_autotune(const edx_sector* const* secs, int n, const edx_lanczo
       for (int rc : {16, 32, 64}) {
         std::vector<int> c1(sub.size(), cc), r1(sub.size(), rc);
         double ms = 0;
-        EDX_TRY(batch_run(sub.data(), (int)sub.size(), &q, c1.data(), r1.data(), L, -1, ws,
+        EDX_TRY(batch_run(sub.data(), (int)sub.size(), &q, c1.data(), r1.data(), L, -1, 1, ws,
                           ws_bytes, res.data(), st, &ms));
         if (ms < best) {
           best = ms;
@@ -739,7 +817,7 @@ edx_status batch_autotune(const edx_sector* const* secs, int n, const edx_lanczo
     for (int l : {8, 16, 32}) {
       if (batch_workspace_bytes(secs, n, o->vtype, l, wm) > ws_bytes) continue;
       double ms = 0;
-      EDX_TRY(batch_run(secs, n, &q, ccols, rcols, l, wm, ws, ws_bytes, res.data(), st, &ms));
+      EDX_TRY(batch_run(secs, n, &q, ccols, rcols, l, wm, 0, ws, ws_bytes, res.data(), st, &ms));
       if (ms < best) {
         best = ms;
         bl = l;
@@ -757,14 +835,19 @@ size_t batch_workspace_bytes(const edx_sector* const* secs, int n, int vtype, in
   size_t ww = 0;
   int64_t dn = 0;
   int nl = 0;
+  std::vector<int> wide;
   for (int i = 0; i < n; ++i) {
     if (is_wide(secs[i], wide_min)) {
-      ww = std::max(ww, lanczos_workspace_bytes(secs[i], vtype, kMaxBatchIter, 0));
+      wide.push_back(i);
     } else {
       dn = std::max(dn, secs[i]->dim);
       ++nl;
     }
   }
+  // enough for every grouping up to the largest multi-set group
+  for (const auto& u : wide_units(secs, wide, vtype, 8))
+    ww = std::max(ww, wide_unit_bytes(secs, u, vtype, kMaxBatchIter));
+  for (int i : wide) ww = std::max(ww, lanczos_workspace_bytes(secs[i], vtype, kMaxBatchIter, 0));
   return batch_layout(nl, vtype, L, device_cus(), ww, dn).total;
 }
 

@@ -30,6 +30,15 @@ __device__ __forceinline__ double block_sum(double x, double* red) {
   return s;
 }
 
+// Counter-based SplitMix64 (Steele, Lea and Flood's finaliser): draw k of
+// stream `seed` (the start vectors' element k takes draw k).
+__device__ __forceinline__ uint64_t splitmix64(uint64_t seed, uint64_t k) {
+  uint64_t z = seed + (k + 1) * 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
 template <typename T>
 __device__ __forceinline__ T ldg(const T* p) {
   return __builtin_nontemporal_load(p);

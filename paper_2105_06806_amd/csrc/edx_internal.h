@@ -265,8 +265,8 @@ edx_status k_pair_apply(const edx_sector* src, const edx_sector* dst, int vtype,
 
 // ---- batch.hip
 edx_status batch_run(const edx_sector* const* secs, int n, const edx_lanczos_opts* o,
-                     const int* ccols, const int* rcols, int L, int64_t wide_min, void* ws,
-                     size_t ws_bytes, edx_batch_result* res, hipStream_t st,
+                     const int* ccols, const int* rcols, int L, int64_t wide_min, int multi_k,
+                     void* ws, size_t ws_bytes, edx_batch_result* res, hipStream_t st,
                      double* elapsed_ms);
 size_t batch_workspace_bytes(const edx_sector* const* secs, int n, int vtype, int L,
                              int64_t wide_min);
@@ -279,6 +279,16 @@ size_t lanczos_workspace_bytes(const edx_sector* s, int vtype, int niter, int re
 edx_status lanczos_ground_state_impl(const edx_sector* s, const edx_lanczos_opts* o, void* ws,
                                      size_t ws_bytes, double* e0, void* psi0,
                                      edx_lanczos_report* rep, hipStream_t st);
+// ---- multi.hip: K bath sets of one sector shape at once (interleaved vectors)
+bool multi_supported(const edx_sector* s, int K, int vtype);
+bool multi_same_shape(const edx_sector* a, const edx_sector* b);
+size_t multi_workspace_bytes(const edx_sector* s, int K, int vtype, int niter);
+edx_status multi_ground_states(const edx_sector* const* secs, int K, const edx_lanczos_opts* o,
+                               void* ws, size_t ws_bytes, edx_batch_result* res, hipStream_t st);
+size_t multi_hv_workspace_bytes(const edx_sector* s, int K, int vtype);
+edx_status multi_hv(const edx_sector* const* secs, int K, int vtype, const void* v, void* w,
+                    void* ws, size_t ws_bytes, hipStream_t st);
+
 // ---- noalloc.hip: the same ground state with the workspace in a fixed
 // per-device scratch array (no device allocation)
 edx_status lanczos_ground_state_static(const edx_sector* s, const edx_lanczos_opts* o,

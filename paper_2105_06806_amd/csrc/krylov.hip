@@ -21,13 +21,6 @@ namespace {
 constexpr int kThreads = 256;
 constexpr int kMaxElemBlocks = 1024;
 
-__device__ __forceinline__ uint64_t splitmix64(uint64_t seed, uint64_t k) {
-  uint64_t z = seed + (k + 1) * 0x9E3779B97F4A7C15ull;
-  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
-  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
-  return z ^ (z >> 31);
-}
-
 // element (r, c) of a vector with column stride ld draws counter r + c*dup, so
 // the start vector is the same for every ld; padding rows are zero
 // src (nullable): a dense caller vector copied into the padded layout instead

@@ -5,10 +5,10 @@
 // device arena of a fixed size (allocated once at creation) and `max_slots`
 // worker threads, each with its own HIP stream.  Admission is by device
 // footprint: a request is admitted when a worker is free and its workspace
-// (Lanczos vectors, psi0, Green vectors) fits in the arena; smaller requests
-// may pass a larger one that does not fit yet, but a request passed over
-// `kMaxSkips` times blocks further passing until it is admitted (no
-// starvation).  Admitted requests run concurrently on their streams, so their
+// (Lanczos vectors, psi0, Green vectors) fits in the arena; the smallest
+// pending request that fits goes first (small sectors are quick, so they do
+// not wait behind large ones), but a request passed over `kMaxSkips` times
+// blocks further passing until it is admitted (no starvation).  Admitted requests run concurrently on their streams, so their
 // kernels overlap on the device; a request that arrives while others run is
 // admitted as soon as a slot and memory free up.  Every request runs the same
 // kernels with the same launch shapes as the plain API, whatever else is
@@ -32,6 +32,7 @@ namespace edx {
 namespace {
 
 constexpr int kMaxSkips = 8;
+constexpr size_t kLargeBytes = size_t(1) << 30;   // a "large" request's footprint
 constexpr size_t kAlign = 256;
 
 double now_s() {
@@ -141,6 +142,7 @@ struct edx_server {
   std::vector<hipStream_t> streams;
   int64_t next_ticket = 1;
   int busy = 0;
+  int large = 0;      // running requests with footprint >= kLargeBytes
   bool stop = false;
   int device = 0;
   std::atomic<int64_t> completed{0};
@@ -198,19 +200,55 @@ void worker_main(edx_server* S, int slot) {
       std::unique_lock<std::mutex> lk(S->mu);
       for (;;) {
         if (S->stop) return;
-        // admission: first request in arrival order that fits; once the head
-        // has been passed over kMaxSkips times nothing may pass it
-        for (auto it = S->pending.begin(); it != S->pending.end(); ++it) {
-          Request* q = *it;
-          mem = S->arena.alloc(q->footprint);
-          if (mem) {
-            R = q;
-            S->pending.erase(it);
+        // admission, smallest footprint first (the footprint grows with the
+        // sector dimension, so with the work): among the admissible pending
+        // requests -- a large one (footprint >= kLargeBytes) only while fewer
+        // than half the slots run large ones, so small requests always find
+        // a slot and the large ones share the bandwidth with fewer others --
+        // the smallest that fits is taken, and every older admissible request
+        // it passes counts a skip; the oldest admissible request passed over
+        // kMaxSkips times goes next, waiting for memory if need be (nothing
+        // passes it), so none starves
+        const int large_cap = std::max(1, S->opts.max_slots / 2);
+        auto admissible = [&](const Request* q) {
+          return q->footprint < kLargeBytes || S->large < large_cap;
+        };
+        Request* due = nullptr;
+        for (Request* q : S->pending)
+          if (admissible(q) && q->skips >= kMaxSkips) {
+            due = q;
             break;
           }
-          if (++q->skips > kMaxSkips) break;
+        if (due) {
+          mem = S->arena.alloc(due->footprint);
+          if (mem) R = due;
+        } else {
+          std::vector<Request*> bysize;
+          for (Request* q : S->pending)
+            if (admissible(q)) bysize.push_back(q);
+          std::stable_sort(bysize.begin(), bysize.end(), [](const Request* x, const Request* y) {
+            return x->footprint < y->footprint;
+          });
+          for (Request* q : bysize) {
+            mem = S->arena.alloc(q->footprint);
+            if (mem) {
+              R = q;
+              break;
+            }
+          }
         }
-        if (R) break;
+        if (R) {
+          for (auto it = S->pending.begin(); it != S->pending.end();) {
+            if (*it == R) {
+              it = S->pending.erase(it);
+              break;
+            }
+            if (admissible(*it)) ++(*it)->skips;   // older than R and passed over
+            ++it;
+          }
+          if (R->footprint >= kLargeBytes) ++S->large;
+          break;
+        }
         S->cv_work.wait(lk);
       }
       ++S->busy;
@@ -265,6 +303,7 @@ void worker_main(edx_server* S, int slot) {
     {
       std::lock_guard<std::mutex> lk(S->mu);
       S->arena.release(mem, R->footprint);
+      if (R->footprint >= kLargeBytes) --S->large;
       R->status = st2;
       R->t_done = now_s();
       R->done = true;

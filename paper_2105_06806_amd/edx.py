@@ -85,7 +85,7 @@ class BatchResult(ctypes.Structure):
 
 
 class BatchTiles(ctypes.Structure):
-    _fields_ = [("lane_wgs", ctypes.c_int32), ("pad_", ctypes.c_int32),
+    _fields_ = [("lane_wgs", ctypes.c_int32), ("multi_k", ctypes.c_int32),
                 ("ccols", ctypes.POINTER(ctypes.c_int32)),
                 ("rcols", ctypes.POINTER(ctypes.c_int32)), ("wide_min_dim", ctypes.c_int64)]
 
@@ -150,6 +150,8 @@ _SIGS = {
     "edx_espace_green_workspace_bytes": (ctypes.c_size_t, [_P, ctypes.c_int32]),
     "edx_espace_green": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(GfOpts), _P, ctypes.c_size_t, _P, _P]),
     "edx_hv_block": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int32, _P, _P, ctypes.c_int64, ctypes.c_int64, ctypes.c_int64, _P]),
+    "edx_hv_multi_workspace_bytes": (ctypes.c_size_t, [_P, ctypes.c_int32, ctypes.c_int32]),
+    "edx_hv_multi": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int, _P, _P, _P, ctypes.c_size_t, _P]),
     "edx_transpose": (ctypes.c_int, [ctypes.c_int, _P, ctypes.c_int64, ctypes.c_int64, ctypes.c_int64, _P, ctypes.c_int64, ctypes.c_int32, _P]),
     "edx_tridiag_spectrum": (ctypes.c_int, [_P, _P, ctypes.c_int32, _P, _P]),
     "edx_chi": (ctypes.c_int, [_P, _P, ctypes.c_double, _P, _P, ctypes.POINTER(GfOpts), _P, ctypes.c_size_t, _P, ctypes.POINTER(ChiReport), _P]),
@@ -336,6 +338,37 @@ def hv(sector, v, w, stream=None, ld=0):
     _check(lib.edx_hv(sector.handle, _vtype_of(v), _P(v.data_ptr()), _P(w.data_ptr()), int(ld),
                       _stream_ptr(stream)))
     return w
+
+
+def hv_multi(sectors, v, w, ws=None, stream=None):
+    """w_b = H_b v_b for k = len(sectors) sectors of one shape (edx_hv_multi):
+    v, w are device tensors of S.ld * S.ddw * k elements, the k vectors
+    interleaved element by element (see interleave)."""
+    k = len(sectors)
+    vt = _vtype_of(v)
+    if w.dtype != v.dtype or v.numel() != sectors[0].ld * sectors[0].ddw * k or w.numel() != v.numel():
+        raise ValueError("v, w: k interleaved vectors of the sectors' column stride")
+    hs = _handles(sectors)
+    if ws is None:
+        ws = alloc_workspace(lib.edx_hv_multi_workspace_bytes(hs, k, vt))
+    _check(lib.edx_hv_multi(hs, k, vt, _P(v.data_ptr()), _P(w.data_ptr()), _P(ws.data_ptr()),
+                            ws.numel(), _stream_ptr(stream)))
+
+
+def interleave(sector, xs):
+    """k dense vectors (sector.dim each) -> the interleaved padded layout of
+    edx_hv_multi (layout only)."""
+    k = len(xs)
+    out = torch.zeros((sector.ddw, sector.ld, k), dtype=xs[0].dtype, device=xs[0].device)
+    for b, x in enumerate(xs):
+        out[:, :sector.dup, b] = x.view(sector.ddw, sector.dup)
+    return out.view(-1)
+
+
+def deinterleave(sector, y, k):
+    """The inverse of interleave: k dense vectors."""
+    t = y.view(sector.ddw, sector.ld, k)
+    return [t[:, :sector.dup, b].reshape(-1).clone() for b in range(k)]
 
 
 def hv_block(sector, part, v, w, ld, c0, c1, stream=None):
@@ -752,7 +785,7 @@ def batch_ground_state(sectors, tiles=None, ws=None, stream=None, **kw):
     if tiles:
         cc = np.ascontiguousarray(tiles["ccols"], np.int32)
         rc = np.ascontiguousarray(tiles["rcols"], np.int32)
-        t = BatchTiles(lw, 0, cc.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+        t = BatchTiles(lw, int(tiles.get("multi_k", 0)), cc.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
                        rc.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), int(wmin))
         tp = ctypes.byref(t)
     _check(lib.edx_batch_ground_state(_handles(sectors), n, ctypes.byref(o), tp, _P(ws.data_ptr()), ws.numel(),
