@@ -77,6 +77,9 @@ def parse():
                     help="first request of the stream to submit (a rate split over runs)")
     ap.add_argument("--serve-span", type=int, default=None,
                     help="number of requests to submit from --serve-offset (default: the rest)")
+    ap.add_argument("--serve-dump", default=None,
+                    help="JSON file for every request's served and plain latency per rate "
+                         "(exact percentiles of a rate split over runs)")
     ap.add_argument("--serve-cap", type=float, default=None,
                     help="plain capacity (requests/s) measured by an earlier run of the same mix: "
                          "the sweep's rates are multiples of it (a sweep split over several runs)")
@@ -374,7 +377,9 @@ def bench_hv_multi(edx, torch, a):
     sector, FP32 and FP64, beside the single-vector fused pass
     (fused_single, the sector's default plan)."""
     from paper_2105_06806_amd import inputs
-    out = {}
+    out = {"note": "HIP events around each edx_hv_multi call, which also copies the k sets' "
+                   "tables into its workspace (a batched solve does that once); the kernel "
+                   "alone: profiles/hv_multi_counters.md"}
     # the calibration kernel of the counter summaries runs in the same process
     out["copy_gbs"] = round(copy_bandwidth(torch), 1)
     for ns, sec, ks in ((12, (6, 6), (1, 2, 4, 8)), (14, (7, 7), (1, 2, 4, 8)), (16, (8, 8), (1, 2))):
@@ -666,8 +671,28 @@ def _fcfs(arr, svc):
     return np.array(lat), done
 
 
+PROFILE_SERVE = os.path.join(ROOT, "profiles", "serve_sweep_ns16.md")
+
+
+def serve_sweep_from_profile():
+    """The committed full-size serving sweep (1000 requests per rate, Ns
+    10..16, measured by this file's serve section split over several runs):
+    quoted, not measured by this run."""
+    if not os.path.exists(PROFILE_SERVE):
+        return None
+    rows = []
+    for mr in re.finditer(r"^rate\[([0-9.]+)\]:(.*)$", open(PROFILE_SERVE).read(), re.M):
+        row = {"x_plain_capacity": float(mr.group(1))}
+        for kv in mr.group(2).split():
+            k, v = kv.split("=")
+            row[k] = float(v) if "." in v or "e" in v else int(v)
+        rows.append(row)
+    return {"source": "profiles/serve_sweep_ns16.md (quoted, not measured by this run)",
+            "rates": rows} if rows else None
+
+
 def bench_serve(edx, torch, full, nreq=None, ns_hi=None, rates=None, cap_given=None,
-                plain_file=None, offset=0, span=None):
+                plain_file=None, offset=0, span=None, dump=None):
     """Config 5: a Poisson stream of ground state + G requests (Norb in {1,2},
     Ns 10..16, U in [1,6]; FP32 vectors) served with continuous batching, at
     offered rates that are multiples of the measured one-at-a-time capacity.
@@ -702,6 +727,8 @@ def bench_serve(edx, torch, full, nreq=None, ns_hi=None, rates=None, cap_given=N
             edx.green_cf(S, psi, e0, 0, 0, **gkw)
             svc.append(time.perf_counter() - ts)
             del S, psi
+            if len(svc) % 50 == 0:
+                log(f"serve plain: {len(svc)}/{nreq} requests, {sum(svc):.1f} s")
         if plain_file:
             json.dump({"service_s": svc, "nreq": nreq, "ns_hi": ns_hi}, open(plain_file, "w"))
     svc = np.array(svc)
@@ -731,7 +758,13 @@ def bench_serve(edx, torch, full, nreq=None, ns_hi=None, rates=None, cap_given=N
             if wait > 0:
                 time.sleep(wait)
             tickets.append(srv.submit(m, a, b))
-        res = [srv.poll(t) for t in tickets]
+            if len(tickets) % 50 == 0:
+                log(f"serve x{fac}: {len(tickets)}/{len(part)} submitted")
+        res = []
+        for t in tickets:
+            res.append(srv.poll(t))
+            if len(res) % 100 == 0:
+                log(f"serve x{fac}: {len(res)}/{len(part)} done")
         t_end = max(r["t_done"] for r in res)
         lat = np.array([r["t_done"] - r["t_submit"] for r in res])
         first = min(r["t_submit"] for r in res)
@@ -748,7 +781,14 @@ def bench_serve(edx, torch, full, nreq=None, ns_hi=None, rates=None, cap_given=N
                              "degenerate": int(sum(r["status"] == edx.EDX_E_DEGENERATE
                                                    for r in res))})
         log(f"serve x{fac}: {out['rates'][-1]}")
+        if dump:
+            raw = json.load(open(dump)) if os.path.exists(dump) else {}
+            raw[f"x{fac}_from{offset}"] = {"served_s": lat.tolist(), "plain_fcfs_s": list(map(float, plat)),
+                                          "first_submit": first, "last_done": t_end,
+                                          "plain_first_arrival": float(arr[0]), "plain_last_done": float(pdone)}
+            json.dump(raw, open(dump, "w"))
     srv.close()
+    out["full_sweep"] = serve_sweep_from_profile()
     return out
 
 
@@ -777,7 +817,7 @@ def main():
                 "serve": lambda: bench_serve(
                     edx, torch, a.full, a.serve_n, a.serve_ns_hi,
                     tuple(float(x) for x in a.serve_rates.split(",")) if a.serve_rates else None,
-                    a.serve_cap, a.serve_plain, a.serve_offset, a.serve_span)}
+                    a.serve_cap, a.serve_plain, a.serve_offset, a.serve_span, a.serve_dump)}
     if a.only:
         out = {}
         for name in a.only.split(","):

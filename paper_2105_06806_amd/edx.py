@@ -353,6 +353,7 @@ def hv_multi(sectors, v, w, ws=None, stream=None):
         ws = alloc_workspace(lib.edx_hv_multi_workspace_bytes(hs, k, vt))
     _check(lib.edx_hv_multi(hs, k, vt, _P(v.data_ptr()), _P(w.data_ptr()), _P(ws.data_ptr()),
                             ws.numel(), _stream_ptr(stream)))
+    return w
 
 
 def interleave(sector, xs):

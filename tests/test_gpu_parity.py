@@ -615,7 +615,7 @@ def test_orbital_sectors_partition_total_sector(edx):
             es.append(edx.lanczos_ground_state(S, want_psi=False, niter=500, tol=1e-13, seed=1,
                                                allow=(edx.EDX_E_DEGENERATE,))[0])
     assert dims == T.dim
-    assert abs(min(es) - eT) <= 1e-9 * abs(eT)
+    assert abs(min(es) - eT) <= 1e-10 * abs(eT)
 
 
 @pytest.mark.parametrize("dtype", ["f32", "f64"])
@@ -677,7 +677,7 @@ def test_batch_orbital_and_phonon_sectors(edx):
         assert r["status"] == 0, (sec, r)
         H = (eph.explicit_hamiltonian(m, *sec) if kind == "ph" else fock.explicit_hamiltonian(m, *sec))
         E0 = np.linalg.eigvalsh(H.toarray())[0]
-        assert abs(r["e0"] - E0) <= 1e-9 * abs(E0), (sec, r["e0"], E0)
+        assert abs(r["e0"] - E0) <= 1e-10 * abs(E0), (sec, r["e0"], E0)
 
 
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
