@@ -65,7 +65,7 @@ def parse():
     ap.add_argument("--full", action="store_true", help="full-size serving sweep")
     ap.add_argument("--tune-reps", type=int, default=3)
     ap.add_argument("--serve-n", type=int, default=None,
-                    help="requests per rate of the serving sweep (default 150, 1000 with --full)")
+                    help="requests per rate of the serving sweep (default 120, 1000 with --full)")
     ap.add_argument("--serve-ns-hi", type=int, default=None,
                     help="largest Ns of the serving requests (default 16)")
     ap.add_argument("--serve-rates", default=None,
@@ -703,7 +703,7 @@ def bench_serve(edx, torch, full, nreq=None, ns_hi=None, rates=None, cap_given=N
     whole benchmark stays within a few minutes."""
     from paper_2105_06806_amd import inputs
     ns_hi = ns_hi or 16
-    nreq = nreq or (1000 if full else 150)
+    nreq = nreq or (1000 if full else 120)
     kw = dict(niter=512, tol=1e-9, seed=5, check_every=4)
     gkw = dict(ngf=200, lmats=1024, beta=200.0)
     reqs = inputs.serve_requests(nreq, ns_lo=10, ns_hi=ns_hi)
@@ -745,7 +745,7 @@ def bench_serve(edx, torch, full, nreq=None, ns_hi=None, rates=None, cap_given=N
            "plain_service_p99_s": round(float(np.percentile(svc, 99)), 4),
            "rates": []}
     srv = edx.Server(hbm_budget=96 << 30, max_slots=8, vtype="f32", **gkw, **kw)
-    facs = rates or ((0.5, 1.0, 2.0) if not full else (0.25, 0.5, 0.75, 0.9, 1.0, 1.25, 2.0))
+    facs = rates or ((1.0, 2.0) if not full else (0.25, 0.5, 0.75, 0.9, 1.0, 1.25, 2.0))
     for fac in facs:
         rate = fac * cap
         arr = inputs.poisson_arrivals(nreq, rate, seed=int(fac * 1000))[offset:offset + span]

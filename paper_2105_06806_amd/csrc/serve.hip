@@ -7,12 +7,14 @@
 // footprint: a request is admitted when a worker is free and its workspace
 // (Lanczos vectors, psi0, Green vectors) fits in the arena; the smallest
 // pending request that fits goes first (small sectors are quick, so they do
-// not wait behind large ones), but a request passed over `kMaxSkips` times
-// blocks further passing until it is admitted (no starvation).  Admitted requests run concurrently on their streams, so their
-// kernels overlap on the device; a request that arrives while others run is
-// admitted as soon as a slot and memory free up.  Every request runs the same
-// kernels with the same launch shapes as the plain API, whatever else is
-// running, so its result is bitwise the same alone and in the mix.
+// not wait behind large ones), at most half the slots run requests of
+// `kLargeBytes` or more, and a request passed over `kMaxSkips` times blocks
+// further passing until it is admitted (no starvation).  Admitted requests
+// run concurrently on their streams, so their kernels overlap on the device;
+// a request that arrives while others run is admitted as soon as a slot and
+// memory free up.  Every request runs the same kernels with the same launch
+// shapes as the plain API, whatever else is running, so its result is
+// bitwise the same alone and in the mix.
 #include <algorithm>
 #include <atomic>
 #include <chrono>

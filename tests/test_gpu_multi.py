@@ -77,22 +77,48 @@ def test_hv_multi_against_oracle_and_single(edx, name, norb, nbath, sec, k, dtyp
         assert bool(torch.equal(w1, ys[b])), (b, float((w1 - ys[b]).abs().max()))
 
 
-def test_hv_multi_ns14_against_kron(edx):
-    """Config-4-size sector (Ns=14 7/7, D=11,778,624), four bath sets, FP32."""
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_hv_multi_ns14_against_kron(edx, dtype):
+    """Config-4-size sector (Ns=14 7/7, D=11,778,624), four bath sets: the
+    first and last set against the oracle's Kronecker form."""
     import torch
+    tdt = torch.float64 if dtype == "f64" else torch.float32
     ms = _models(1, 13, 4, seed0=4100)
     Ss = [edx.build_sector(m, 7, 7) for m in ms]
     gen = torch.Generator(device="cuda").manual_seed(3)
-    xs = [torch.rand(Ss[0].dim, dtype=torch.float32, device="cuda", generator=gen) * 2 - 1
+    xs = [torch.rand(Ss[0].dim, dtype=tdt, device="cuda", generator=gen) * 2 - 1
           for _ in range(4)]
     v = edx.interleave(Ss[0], xs)
     w = torch.empty_like(v)
     edx.hv_multi(Ss, v, w)
     ys = edx.deinterleave(Ss[0], w, 4)
+    tol = 1e-13 if dtype == "f64" else 2e-6
     for b in (0, 3):
         ref = kron.KronH(ms[b], 7, 7).matvec(xs[b].double().cpu().numpy())
         err = np.abs(ys[b].double().cpu().numpy() - ref).max()
-        assert err <= 2e-6 * _hscale(ms[b]), (b, err)
+        assert err <= tol * _hscale(ms[b]), (b, err)
+
+
+@pytest.mark.parametrize("dtype,k", [("f32", 8), ("f64", 8), ("f64", 4)])
+def test_hv_multi_ns12_equals_single(edx, dtype, k):
+    """The shape the batch groups (Ns=12 6/6, D=853,776), up to eight sets:
+    every set bit for bit equal to the one-column fused pass on its own."""
+    import torch
+    tdt = torch.float64 if dtype == "f64" else torch.float32
+    ms = _models(1, 11, k, seed0=1200 + k)
+    Ss = [edx.build_sector(m, 6, 6) for m in ms]
+    gen = torch.Generator(device="cuda").manual_seed(4)
+    xs = [torch.rand(Ss[0].dim, dtype=tdt, device="cuda", generator=gen) * 2 - 1 for _ in range(k)]
+    w = edx.hv_multi(Ss, edx.interleave(Ss[0], xs), torch.empty(Ss[0].ld * Ss[0].ddw * k, dtype=tdt,
+                                                                  device="cuda"))
+    ys = edx.deinterleave(Ss[0], w, k)
+    for b in range(k):
+        assert edx.set_plan(Ss[b], dtype, raise_on_error=False, mode=2, col_cols=1,
+                            col_threads=256, row_rows=64, row_cols=16, col_order=0) == 0
+        w1 = torch.empty_like(xs[b])
+        edx.hv(Ss[b], xs[b], w1)
+        torch.cuda.synchronize()
+        assert bool(torch.equal(w1, ys[b])), (b, float((w1 - ys[b]).abs().max()))
 
 
 def test_hv_multi_refusals(edx):
