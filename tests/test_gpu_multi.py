@@ -175,3 +175,25 @@ def test_batch_groups_same_shape_jobs(edx, dtype):
             assert r1["e0"] == plain          # grouping off: the plain path itself
         else:
             assert abs(r["e0"] - plain) <= 1e-4 * abs(plain), (sec, r["e0"], plain)
+
+
+def test_batch_groups_edge_shapes(edx):
+    """Edge sectors through the grouped path (wide_min_dim 1 sends every job
+    to it): no electron of one spin, a completely filled spin, D = 1, and a
+    small ragged sector; four bath sets of each shape, FP64 energies against
+    the dense oracle spectrum (a D = 1 sector breaks down at the first step)."""
+    ns = 6
+    ms = _models(1, ns - 1, 4, seed0=2600)
+    secs = [(0, 3), (3, 0), (0, 0), (ns, ns), (ns, 2), (2, 3)]
+    jobs, refs = [], []
+    for sec in secs:
+        for m in ms:
+            jobs.append(edx.build_sector(m, *sec))
+            refs.append(spectra.dense_lowest(fock.explicit_hamiltonian(m, *sec))[0][0])
+    kw = dict(vtype="f64", niter=200, tol=1e-13, seed=4, check_every=2)
+    tiles = {"lane_wgs": 8, "ccols": np.ones(len(jobs), np.int32),
+             "rcols": np.full(len(jobs), 32, np.int32), "wide_min_dim": 1, "multi_k": 4}
+    res, _ = edx.batch_ground_state(jobs, tiles=tiles, **kw)
+    for S, r, E0 in zip(jobs, res, refs):
+        assert r["status"] == 0, (S.dim, r)
+        assert abs(r["e0"] - E0) <= 1e-10 * max(1.0, abs(E0)), (S.dim, r["e0"], E0)
