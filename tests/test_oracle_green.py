@@ -99,3 +99,21 @@ def test_spin_down_string_sign():
             assert phi[j] == (-1) ** nup * psi[i]
             k += 1
         assert k > 0
+
+
+def test_krylov_depth_200_converged():
+    """The Green's function is evaluated at Krylov depth 200 (the paper's
+    N_gf default); on a half-filled Ns=10 sector (D = 63,504) on the config-2
+    grid (beta = 200, 4096 Matsubara frequencies) depth 400 changes it by less
+    than the FP64 parity tolerance (1e-8 of max|G|), while a shallow depth
+    is visibly off, so the comparison resolves the truncation."""
+    m = inputs.make_model(1, 9, 2.0, seed=61)
+    sec = (5, 5)
+    H = fock.explicit_hamiltonian(m, *sec)
+    E0, psi = spectra.arpack_lowest(H)
+    psi = psi / np.linalg.norm(psi)
+    z = 1j * green.matsubara(200.0, 4096)
+    G = {n: green.krylov_gf(m, *sec, psi, E0, 0, 0, n, z, _mv(m))[0] for n in (12, 200, 400)}
+    scale = np.abs(G[400]).max()
+    assert np.abs(G[200] - G[400]).max() <= 1e-8 * scale
+    assert np.abs(G[12] - G[400]).max() > 1e-6 * scale
