@@ -96,6 +96,67 @@ __global__ __launch_bounds__(kThreads) void k_update_kernel(
   if (threadIdx.x == 0) partial[blockIdx.x] = s;
 }
 
+// The same update on 16-byte vectors (4 FP32 or 2 FP64 elements a lane):
+// with at most kMaxElemBlocks blocks a CU holds 16 waves, and 4-byte FP32
+// lanes left too few bytes in flight to stream at the copy rate (Ns=15 7/7,
+// D = 41.4M: 170 us for 663 MB, against 228 us for the 1.33 GB of FP64).
+// Requires every vector 16-byte aligned; elements past the last full vector
+// are done by scalar lanes.  Each lane sums its elements' squares in element
+// order, so the result is deterministic for a given n and grid.
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_update_vec_kernel(
+    T* __restrict__ w, const T* __restrict__ vc, const double* __restrict__ scur,
+    const T* __restrict__ vp, const double* __restrict__ sprev,
+    const double* __restrict__ alpha, const double* __restrict__ beta, int64_t n,
+    T* __restrict__ psi, const double* __restrict__ ycoef, double* __restrict__ partial) {
+  constexpr int V = 16 / (int)sizeof(T);
+  typedef T VT __attribute__((ext_vector_type(V)));
+  __shared__ double red[kThreads / 64];
+  const double ac = (*alpha) * (*scur);
+  const double bp = vp ? (*beta) * (*sprev) : 0.0;
+  const double yc = psi ? (*ycoef) * (*scur) : 0.0;
+  VT* __restrict__ wv = reinterpret_cast<VT*>(w);
+  const VT* __restrict__ cv = reinterpret_cast<const VT*>(vc);
+  const VT* __restrict__ pv = reinterpret_cast<const VT*>(vp);
+  VT* __restrict__ sv = reinterpret_cast<VT*>(psi);
+  const int64_t nv = n / V;
+  const int64_t stride = (int64_t)gridDim.x * kThreads;
+  double acc = 0.0;
+  for (int64_t q = blockIdx.x * (int64_t)kThreads + threadIdx.x; q < nv; q += stride) {
+    const VT x = cv[q];
+    const VT a = wv[q];
+    VT b = {};
+    if (vp) b = pv[q];
+    VT out;
+#pragma unroll
+    for (int k = 0; k < V; ++k) {
+      double r = (double)a[k] - ac * (double)x[k];
+      if (vp) r -= bp * (double)b[k];
+      const T t = (T)r;
+      out[k] = t;
+      acc += (double)t * (double)t;
+    }
+    wv[q] = out;
+    if (psi) {
+      VT y = sv[q];
+#pragma unroll
+      for (int k = 0; k < V; ++k) y[k] = (T)((double)y[k] + yc * (double)x[k]);
+      sv[q] = y;
+    }
+  }
+  for (int64_t i = nv * V + blockIdx.x * (int64_t)kThreads + threadIdx.x; i < n; i += stride) {
+    const double x = (double)vc[i];
+    double r = (double)w[i] - ac * x;
+    if (vp) r -= bp * (double)vp[i];
+    const T t = (T)r;
+    w[i] = t;
+    acc += (double)t * (double)t;
+    if (psi) psi[i] = (T)((double)psi[i] + yc * x);
+  }
+  const double s = block_sum(acc, red);
+  if (threadIdx.x == 0) partial[blockIdx.x] = s;
+}
+
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_norm2_kernel(const T* __restrict__ x, int64_t n,
                                                            double* __restrict__ partial) {
@@ -167,7 +228,10 @@ __global__ __launch_bounds__(kThreads) void k_axpy2_kernel(
   if (threadIdx.x == 0) partial[blockIdx.x] = s;
 }
 
-// Full re-orthogonalisation: partial[k][b] = <basis_k, w> for k < m
+// Full re-orthogonalisation: partial[k][b] = <basis_k, w> for k < m.  Row y
+// of the grid takes basis vectors 8y .. 8y + 7 (one pass over w each), so
+// small sectors with long bases still spread over the chip; block (x, y)
+// sums the same elements in the same order for every y.
 constexpr int kMultiChunk = 8;   // basis vectors per pass over w
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_multi_dot_kernel(const T* __restrict__ basis,
@@ -177,7 +241,8 @@ __global__ __launch_bounds__(kThreads) void k_multi_dot_kernel(const T* __restri
                                                                double* __restrict__ partial,
                                                                int stride) {
   __shared__ double red[kThreads / 64];
-  for (int k0 = 0; k0 < m; k0 += kMultiChunk) {
+  {
+    const int k0 = blockIdx.y * kMultiChunk;   // this row of the grid: basis k0 .. k0 + 7
     double acc[kMultiChunk];
 #pragma unroll
     for (int c = 0; c < kMultiChunk; ++c) acc[c] = 0.0;
@@ -209,6 +274,173 @@ __global__ __launch_bounds__(kThreads) void k_multi_axpy_kernel(T* __restrict__ 
        i += (int64_t)gridDim.x * kThreads) {
     double r = (double)w[i];
     for (int k = 0; k < m; ++k) r -= coef[k] * (double)basis[(int64_t)k * ld + i];
+    const T t = (T)r;
+    w[i] = t;
+    acc += (double)t * (double)t;
+  }
+  const double s = block_sum(acc, red);
+  if (partial && threadIdx.x == 0) partial[blockIdx.x] = s;
+}
+
+// 16-byte-lane versions of the four Gram-Schmidt kernels above (the same
+// reason and requirement as k_update_vec_kernel: every vector 16-byte
+// aligned, and so the basis stride; the elements past the last full vector
+// are done by scalar lanes).
+template <typename T>
+using Vec16 = T __attribute__((ext_vector_type(16 / sizeof(T))));
+
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_dot2_vec_kernel(const T* __restrict__ w,
+                                                              const T* __restrict__ a,
+                                                              const double* __restrict__ sa,
+                                                              const T* __restrict__ b,
+                                                              const double* __restrict__ sb,
+                                                              int64_t n, double* __restrict__ partial,
+                                                              int stride) {
+  constexpr int V = 16 / (int)sizeof(T);
+  __shared__ double red[kThreads / 64];
+  const Vec16<T>* __restrict__ wv = reinterpret_cast<const Vec16<T>*>(w);
+  const Vec16<T>* __restrict__ av = reinterpret_cast<const Vec16<T>*>(a);
+  const Vec16<T>* __restrict__ bv = reinterpret_cast<const Vec16<T>*>(b);
+  const int64_t nv = n / V, step = (int64_t)gridDim.x * kThreads;
+  double da = 0.0, db = 0.0;
+  for (int64_t q = blockIdx.x * (int64_t)kThreads + threadIdx.x; q < nv; q += step) {
+    const Vec16<T> x = wv[q], y = av[q];
+    Vec16<T> z = {};
+    if (b) z = bv[q];
+#pragma unroll
+    for (int k = 0; k < V; ++k) {
+      da += (double)x[k] * (double)y[k];
+      if (b) db += (double)x[k] * (double)z[k];
+    }
+  }
+  for (int64_t i = nv * V + blockIdx.x * (int64_t)kThreads + threadIdx.x; i < n; i += step) {
+    const double x = (double)w[i];
+    da += x * (double)a[i];
+    if (b) db += x * (double)b[i];
+  }
+  const double s1 = block_sum(da, red);
+  const double s2 = block_sum(db, red);
+  if (threadIdx.x == 0) {
+    partial[blockIdx.x] = s1 * (*sa);
+    partial[stride + blockIdx.x] = b ? s2 * (*sb) : 0.0;
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_axpy2_vec_kernel(
+    T* __restrict__ w, const T* __restrict__ a, const double* __restrict__ ca,
+    const double* __restrict__ sa, const T* __restrict__ b, const double* __restrict__ cb,
+    const double* __restrict__ sb, int64_t n, double* __restrict__ partial) {
+  constexpr int V = 16 / (int)sizeof(T);
+  __shared__ double red[kThreads / 64];
+  const double fa = (*ca) * (*sa);
+  const double fb = b ? (*cb) * (*sb) : 0.0;
+  Vec16<T>* __restrict__ wv = reinterpret_cast<Vec16<T>*>(w);
+  const Vec16<T>* __restrict__ av = reinterpret_cast<const Vec16<T>*>(a);
+  const Vec16<T>* __restrict__ bv = reinterpret_cast<const Vec16<T>*>(b);
+  const int64_t nv = n / V, step = (int64_t)gridDim.x * kThreads;
+  double acc = 0.0;
+  for (int64_t q = blockIdx.x * (int64_t)kThreads + threadIdx.x; q < nv; q += step) {
+    const Vec16<T> x = wv[q], y = av[q];
+    Vec16<T> z = {};
+    if (b) z = bv[q];
+    Vec16<T> out;
+#pragma unroll
+    for (int k = 0; k < V; ++k) {
+      double r = (double)x[k] - fa * (double)y[k];
+      if (b) r -= fb * (double)z[k];
+      out[k] = (T)r;
+      acc += (double)out[k] * (double)out[k];
+    }
+    wv[q] = out;
+  }
+  for (int64_t i = nv * V + blockIdx.x * (int64_t)kThreads + threadIdx.x; i < n; i += step) {
+    double r = (double)w[i] - fa * (double)a[i];
+    if (b) r -= fb * (double)b[i];
+    const T t = (T)r;
+    w[i] = t;
+    acc += (double)t * (double)t;
+  }
+  const double s = block_sum(acc, red);
+  if (threadIdx.x == 0) partial[blockIdx.x] = s;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_multi_dot_vec_kernel(const T* __restrict__ basis,
+                                                                   int64_t ld, int m,
+                                                                   const T* __restrict__ w,
+                                                                   int64_t n,
+                                                                   double* __restrict__ partial,
+                                                                   int stride) {
+  constexpr int V = 16 / (int)sizeof(T);
+  __shared__ double red[kThreads / 64];
+  const Vec16<T>* __restrict__ wv = reinterpret_cast<const Vec16<T>*>(w);
+  const Vec16<T>* __restrict__ bv = reinterpret_cast<const Vec16<T>*>(basis);
+  const int64_t nv = n / V, ldv = ld / V, step = (int64_t)gridDim.x * kThreads;
+  {
+    const int k0 = blockIdx.y * kMultiChunk;   // this row of the grid: basis k0 .. k0 + 7
+    double acc[kMultiChunk];
+#pragma unroll
+    for (int c = 0; c < kMultiChunk; ++c) acc[c] = 0.0;
+    for (int64_t q = blockIdx.x * (int64_t)kThreads + threadIdx.x; q < nv; q += step) {
+      const Vec16<T> x = wv[q];
+#pragma unroll
+      for (int c = 0; c < kMultiChunk; ++c)
+        if (k0 + c < m) {
+          const Vec16<T> y = bv[(int64_t)(k0 + c) * ldv + q];
+#pragma unroll
+          for (int k = 0; k < V; ++k) acc[c] += (double)x[k] * (double)y[k];
+        }
+    }
+    for (int64_t i = nv * V + blockIdx.x * (int64_t)kThreads + threadIdx.x; i < n; i += step) {
+      const double x = (double)w[i];
+#pragma unroll
+      for (int c = 0; c < kMultiChunk; ++c)
+        if (k0 + c < m) acc[c] += x * (double)basis[(int64_t)(k0 + c) * ld + i];
+    }
+    for (int c = 0; c < kMultiChunk && k0 + c < m; ++c) {
+      const double s = block_sum(acc[c], red);
+      if (threadIdx.x == 0) partial[(int64_t)(k0 + c) * stride + blockIdx.x] = s;
+    }
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_multi_axpy_vec_kernel(T* __restrict__ w,
+                                                                    const T* __restrict__ basis,
+                                                                    int64_t ld, int m,
+                                                                    const double* __restrict__ coef,
+                                                                    int64_t n,
+                                                                    double* __restrict__ partial) {
+  constexpr int V = 16 / (int)sizeof(T);
+  __shared__ double red[kThreads / 64];
+  Vec16<T>* __restrict__ wv = reinterpret_cast<Vec16<T>*>(w);
+  const Vec16<T>* __restrict__ bv = reinterpret_cast<const Vec16<T>*>(basis);
+  const int64_t nv = n / V, ldv = ld / V, step = (int64_t)gridDim.x * kThreads;
+  double acc = 0.0;
+  for (int64_t q = blockIdx.x * (int64_t)kThreads + threadIdx.x; q < nv; q += step) {
+    const Vec16<T> x = wv[q];
+    double r[V];
+#pragma unroll
+    for (int k = 0; k < V; ++k) r[k] = (double)x[k];
+    for (int j = 0; j < m; ++j) {
+      const Vec16<T> y = bv[(int64_t)j * ldv + q];
+      const double c = coef[j];
+#pragma unroll
+      for (int k = 0; k < V; ++k) r[k] -= c * (double)y[k];
+    }
+    Vec16<T> out;
+#pragma unroll
+    for (int k = 0; k < V; ++k) {
+      out[k] = (T)r[k];
+      acc += (double)out[k] * (double)out[k];
+    }
+    wv[q] = out;
+  }
+  for (int64_t i = nv * V + blockIdx.x * (int64_t)kThreads + threadIdx.x; i < n; i += step) {
+    double r = (double)w[i];
+    for (int j = 0; j < m; ++j) r -= coef[j] * (double)basis[(int64_t)j * ld + i];
     const T t = (T)r;
     w[i] = t;
     acc += (double)t * (double)t;
@@ -264,6 +496,12 @@ int elem_blocks(int64_t n) {
 }
 
 int multi_blocks(int64_t n) { return elem_blocks(n); }
+
+// every non-null pointer 16-byte aligned (the vector-lane kernels)
+template <typename... P>
+bool aligned16(const P*... p) {
+  return ((reinterpret_cast<uintptr_t>(p) | ... | uintptr_t(0)) & 15) == 0;
+}
 
 #define EDX_DISPATCH(vtype, KERN, GRID, ...)                                           \
   do {                                                                                 \
@@ -353,14 +591,18 @@ edx_status k_update(int vtype, void* w, const void* vcur, const double* scur, co
                     const double* sprev, const double* alpha, const double* beta, int64_t n,
                     void* psi, const double* ycoef, double* partial, hipStream_t st) {
   const int g = elem_blocks(n);
-  if (vtype == EDX_F64)
-    hipLaunchKernelGGL(k_update_kernel<double>, dim3(g), dim3(kThreads), 0, st, (double*)w,
-                       (const double*)vcur, scur, (const double*)vprev, sprev, alpha, beta, n,
-                       (double*)psi, ycoef, partial);
-  else
-    hipLaunchKernelGGL(k_update_kernel<float>, dim3(g), dim3(kThreads), 0, st, (float*)w,
-                       (const float*)vcur, scur, (const float*)vprev, sprev, alpha, beta, n,
-                       (float*)psi, ycoef, partial);
+  // 16-byte vector lanes when every vector allows them (workspace vectors are
+  // 256-byte aligned), else the element-wise kernel
+  const bool vec = aligned16(w, vcur, vprev, psi);
+  if (vtype == EDX_F64) {
+    auto kern = vec ? k_update_vec_kernel<double> : k_update_kernel<double>;
+    hipLaunchKernelGGL(kern, dim3(g), dim3(kThreads), 0, st, (double*)w, (const double*)vcur, scur,
+                       (const double*)vprev, sprev, alpha, beta, n, (double*)psi, ycoef, partial);
+  } else {
+    auto kern = vec ? k_update_vec_kernel<float> : k_update_kernel<float>;
+    hipLaunchKernelGGL(kern, dim3(g), dim3(kThreads), 0, st, (float*)w, (const float*)vcur, scur,
+                       (const float*)vprev, sprev, alpha, beta, n, (float*)psi, ycoef, partial);
+  }
   EDX_HIP(hipGetLastError());
   return EDX_OK;
 }
@@ -393,12 +635,16 @@ edx_status k_scale_copy(int vtype, const void* x, const double* scale, void* y, 
 edx_status k_dot2(int vtype, const void* w, const void* a, const double* sa, const void* b,
                   const double* sb, int64_t n, double* partial, hipStream_t st) {
   const int g = elem_blocks(n);
-  if (vtype == EDX_F64)
-    hipLaunchKernelGGL(k_dot2_kernel<double>, dim3(g), dim3(kThreads), 0, st, (const double*)w,
-                       (const double*)a, sa, (const double*)b, sb, n, partial, kMaxPartials);
-  else
-    hipLaunchKernelGGL(k_dot2_kernel<float>, dim3(g), dim3(kThreads), 0, st, (const float*)w,
-                       (const float*)a, sa, (const float*)b, sb, n, partial, kMaxPartials);
+  const bool vec = aligned16(w, a, b);
+  if (vtype == EDX_F64) {
+    auto kern = vec ? k_dot2_vec_kernel<double> : k_dot2_kernel<double>;
+    hipLaunchKernelGGL(kern, dim3(g), dim3(kThreads), 0, st, (const double*)w, (const double*)a,
+                       sa, (const double*)b, sb, n, partial, kMaxPartials);
+  } else {
+    auto kern = vec ? k_dot2_vec_kernel<float> : k_dot2_kernel<float>;
+    hipLaunchKernelGGL(kern, dim3(g), dim3(kThreads), 0, st, (const float*)w, (const float*)a,
+                       sa, (const float*)b, sb, n, partial, kMaxPartials);
+  }
   EDX_HIP(hipGetLastError());
   return EDX_OK;
 }
@@ -407,12 +653,16 @@ edx_status k_axpy2(int vtype, void* w, const void* a, const double* ca, const do
                    const void* b, const double* cb, const double* sb, int64_t n,
                    double* partial, hipStream_t st) {
   const int g = elem_blocks(n);
-  if (vtype == EDX_F64)
-    hipLaunchKernelGGL(k_axpy2_kernel<double>, dim3(g), dim3(kThreads), 0, st, (double*)w,
-                       (const double*)a, ca, sa, (const double*)b, cb, sb, n, partial);
-  else
-    hipLaunchKernelGGL(k_axpy2_kernel<float>, dim3(g), dim3(kThreads), 0, st, (float*)w,
-                       (const float*)a, ca, sa, (const float*)b, cb, sb, n, partial);
+  const bool vec = aligned16(w, a, b);
+  if (vtype == EDX_F64) {
+    auto kern = vec ? k_axpy2_vec_kernel<double> : k_axpy2_kernel<double>;
+    hipLaunchKernelGGL(kern, dim3(g), dim3(kThreads), 0, st, (double*)w, (const double*)a, ca, sa,
+                       (const double*)b, cb, sb, n, partial);
+  } else {
+    auto kern = vec ? k_axpy2_vec_kernel<float> : k_axpy2_kernel<float>;
+    hipLaunchKernelGGL(kern, dim3(g), dim3(kThreads), 0, st, (float*)w, (const float*)a, ca, sa,
+                       (const float*)b, cb, sb, n, partial);
+  }
   EDX_HIP(hipGetLastError());
   return EDX_OK;
 }
@@ -420,12 +670,18 @@ edx_status k_axpy2(int vtype, void* w, const void* a, const double* ca, const do
 edx_status k_multi_dot(int vtype, const void* basis, int64_t ld, int m, const void* w, int64_t n,
                        double* partial, hipStream_t st) {
   const int g = multi_blocks(n);
-  if (vtype == EDX_F64)
-    hipLaunchKernelGGL(k_multi_dot_kernel<double>, dim3(g), dim3(kThreads), 0, st,
-                       (const double*)basis, ld, m, (const double*)w, n, partial, kMaxPartials);
-  else
-    hipLaunchKernelGGL(k_multi_dot_kernel<float>, dim3(g), dim3(kThreads), 0, st,
-                       (const float*)basis, ld, m, (const float*)w, n, partial, kMaxPartials);
+  const bool vec = aligned16(basis, w) && (ld * vbytes(vtype)) % 16 == 0;
+  if (m < 1) return EDX_OK;
+  const dim3 grid((unsigned)g, (unsigned)((m + kMultiChunk - 1) / kMultiChunk));
+  if (vtype == EDX_F64) {
+    auto kern = vec ? k_multi_dot_vec_kernel<double> : k_multi_dot_kernel<double>;
+    hipLaunchKernelGGL(kern, grid, dim3(kThreads), 0, st, (const double*)basis, ld, m,
+                       (const double*)w, n, partial, kMaxPartials);
+  } else {
+    auto kern = vec ? k_multi_dot_vec_kernel<float> : k_multi_dot_kernel<float>;
+    hipLaunchKernelGGL(kern, grid, dim3(kThreads), 0, st, (const float*)basis, ld, m,
+                       (const float*)w, n, partial, kMaxPartials);
+  }
   EDX_HIP(hipGetLastError());
   return EDX_OK;
 }
@@ -450,12 +706,16 @@ edx_status k_basis_rotate(int vtype, void* basis, int64_t ld, int m, int l, cons
 edx_status k_multi_axpy(int vtype, void* w, const void* basis, int64_t ld, int m,
                         const double* coef, int64_t n, double* partial, hipStream_t st) {
   const int g = multi_blocks(n);
-  if (vtype == EDX_F64)
-    hipLaunchKernelGGL(k_multi_axpy_kernel<double>, dim3(g), dim3(kThreads), 0, st, (double*)w,
-                       (const double*)basis, ld, m, coef, n, partial);
-  else
-    hipLaunchKernelGGL(k_multi_axpy_kernel<float>, dim3(g), dim3(kThreads), 0, st, (float*)w,
-                       (const float*)basis, ld, m, coef, n, partial);
+  const bool vec = aligned16(w, basis) && (ld * vbytes(vtype)) % 16 == 0;
+  if (vtype == EDX_F64) {
+    auto kern = vec ? k_multi_axpy_vec_kernel<double> : k_multi_axpy_kernel<double>;
+    hipLaunchKernelGGL(kern, dim3(g), dim3(kThreads), 0, st, (double*)w, (const double*)basis, ld,
+                       m, coef, n, partial);
+  } else {
+    auto kern = vec ? k_multi_axpy_vec_kernel<float> : k_multi_axpy_kernel<float>;
+    hipLaunchKernelGGL(kern, dim3(g), dim3(kThreads), 0, st, (float*)w, (const float*)basis, ld,
+                       m, coef, n, partial);
+  }
   EDX_HIP(hipGetLastError());
   return EDX_OK;
 }

@@ -17,6 +17,11 @@ ns15o3.npz Ns=15, Norb=3, Nbath=4, sector 7/7 (D=41,409,225): E0 and the
            occupation pattern onto another of the same sector), so G of one
            spin depends on which ground vector is found; G_up + G_dw does not
            (the two degenerate vectors lie in decoupled subspaces).
+ns15o3_orb.npz the same sector and ground-state solve, G_up + G_dw for each of
+           the three orbitals (the quantity that does not depend on which
+           vector of the degenerate ground level is found); the six
+           (orbital, spin) Krylov runs share the ground vector and run in
+           forked worker processes.
 Inputs come from the seeded generator (paper_2105_06806_amd.inputs, seeds
 2000 and 3000), which holds no arithmetic of the method.
 """
@@ -81,9 +86,51 @@ def ns15o3():
     print(f"ns15o3: G done ({time.time() - t0:.0f} s)")
 
 
+_ORB = {}
+
+
+def _orb_gf(job):
+    orb, spin = job
+    m, sec, psi, E, z = (_ORB[k] for k in ("m", "sec", "psi", "E", "z"))
+
+    def factory(a, b):
+        return kron.KronH(m, a, b).matvec
+
+    G, wp, wh, _, _ = green.krylov_gf(m, *sec, psi, E, orb, spin, 200, z, factory)
+    return orb, spin, G, wp, wh
+
+
+def ns15o3_orb():
+    import multiprocessing as mp
+    t0 = time.time()
+    m, [sec] = inputs.workload("ns15o3")
+    K = kron.KronH(m, *sec)
+    op = spla.LinearOperator((K.dim, K.dim), matvec=K.matvec, dtype=np.float64)
+    w, V = spla.eigsh(op, k=1, which="SA", tol=1e-13, ncv=24,
+                      v0=rng.start_vector(3, K.dim))
+    E, psi = float(w[0]), np.ascontiguousarray(V[:, 0])
+    del V, op
+    print(f"ns15o3_orb: E0 {E:.15f} ({time.time() - t0:.0f} s)", flush=True)
+    beta, lmats = 200.0, 1024
+    _ORB.update(m=m, sec=sec, psi=psi, E=E, z=1j * green.matsubara(beta, lmats))
+    jobs = [(orb, spin) for orb in range(m["norb"]) for spin in (0, 1)]
+    with mp.get_context("fork").Pool(len(jobs)) as pool:
+        res = pool.map(_orb_gf, jobs)
+    g = np.zeros((m["norb"], lmats), complex)
+    wts = np.zeros((m["norb"], 2, 2))
+    for orb, spin, G, wp, wh in res:
+        g[orb] += G
+        wts[orb, spin] = (wp, wh)
+    np.savez(os.path.join(HERE, "ns15o3_orb.npz"), e0=E, beta=beta, lmats=lmats, g_sum=g,
+             weights=wts)
+    print(f"ns15o3_orb: G done ({time.time() - t0:.0f} s)")
+
+
 if __name__ == "__main__":
     which = sys.argv[1] if len(sys.argv) > 1 else "all"
     if which in ("ns12", "all"):
         ns12()
     if which in ("ns15o3", "all"):
         ns15o3()
+    if which in ("ns15o3_orb", "all"):
+        ns15o3_orb()

@@ -60,12 +60,36 @@ def test_ns12_particle_hole_and_twin(edx):
     assert abs(e[(5, 6)] - e[(6, 5)]) < 1e-10 * abs(e[(5, 6)])
 
 
-def _gsum(edx, S, psi, e0, lm, beta):
-    """G_up + G_dw of orbital 0: independent of which vector of a degenerate
+def _gsum(edx, S, psi, e0, lm, beta, orb=0):
+    """G_up + G_dw of one orbital: independent of which vector of a degenerate
     ground level was found (see tests/golden/make_golden.py)."""
-    Gu, ru = edx.green_cf(S, psi, e0, 0, 0, ngf=200, beta=beta, lmats=lm)
-    Gd, rd = edx.green_cf(S, psi, e0, 0, 1, ngf=200, beta=beta, lmats=lm)
+    Gu, ru = edx.green_cf(S, psi, e0, orb, 0, ngf=200, beta=beta, lmats=lm)
+    Gd, rd = edx.green_cf(S, psi, e0, orb, 1, ngf=200, beta=beta, lmats=lm)
     return Gu + Gd, ru["wp"] + rd["wp"]
+
+
+def test_ns15o3_every_orbital(edx):
+    """Norb=3, D=41.4M, FP64: G_up + G_dw of each orbital against the
+    oracle's (ns15o3_orb.npz, its own ground-state solve), 1e-8 * max|G|,
+    and the particle weights."""
+    path = os.path.join(GOLD, "ns15o3_orb.npz")
+    if not os.path.exists(path):
+        pytest.skip("ns15o3_orb.npz not written")
+    g = np.load(path)
+    m, [sec] = inputs.workload("ns15o3")
+    S = edx.build_sector(m, *sec)
+    E = float(g["e0"])
+    lm, beta = int(g["lmats"]), float(g["beta"])
+    e64, psi, rep, st = edx.lanczos_ground_state(S, niter=600, tol=1e-14, rtol=1e-10, seed=4,
+                                                 allow=(edx.EDX_E_DEGENERATE,))
+    assert abs(e64 - E) <= 1e-10 * abs(E), (e64, E)
+    for orb in range(m["norb"]):
+        G, wp = _gsum(edx, S, psi, e64, lm, beta, orb)
+        ref = g["g_sum"][orb]
+        err = np.abs(G - ref).max() / np.abs(ref).max()
+        print(f"ns15o3 orbital {orb}: dG {err:.2e}")
+        assert err <= 1e-8, (orb, err)
+        assert abs(wp - float(g["weights"][orb, :, 0].sum())) < 1e-9, orb
 
 
 def test_ns15o3_precision_mode(edx):
