@@ -424,6 +424,7 @@ __global__ __launch_bounds__(kThreads) void k_multi_axpy_vec_kernel(T* __restric
     double r[V];
 #pragma unroll
     for (int k = 0; k < V; ++k) r[k] = (double)x[k];
+#pragma unroll 8
     for (int j = 0; j < m; ++j) {
       const Vec16<T> y = bv[(int64_t)j * ldv + q];
       const double c = coef[j];
@@ -495,7 +496,13 @@ int elem_blocks(int64_t n) {
   return (int)std::max<int64_t>(1, std::min<int64_t>(b, kMaxElemBlocks));
 }
 
-int multi_blocks(int64_t n) { return elem_blocks(n); }
+// blocks of the full re-orthogonalisation kernels: one element a thread for
+// small sectors (their bases are long and the grid would otherwise hold a few
+// blocks), the element-kernel cap for large ones
+int multi_blocks(int64_t n) {
+  const int64_t b = (n + kThreads - 1) / kThreads;
+  return (int)std::max<int64_t>(1, std::min<int64_t>(b, kMaxElemBlocks));
+}
 
 // every non-null pointer 16-byte aligned (the vector-lane kernels)
 template <typename... P>

@@ -844,7 +844,10 @@ edx_status lowest_states_impl(const edx_sector* s, int k, const edx_lanczos_opts
                              o->seed + 0x9E3779B97F4A7C15ull * (uint64_t)runs, L.partial, st));
     }
     if (nl > 0) EDX_TRY(project_out(vtype, L.vec, X, L, nl, n, st));
-    EDX_TRY(k_beta_finish(L.partial, elem_blocks(n), L.beta, L.scale, st));
+    // the norm's partial sums come from project_out's last kernel or from the
+    // start / norm kernel: their counts differ
+    EDX_TRY(k_beta_finish(L.partial, nl > 0 ? multi_blocks(n) : elem_blocks(n), L.beta, L.scale,
+                          st));
     if (from_staging) {
       // a staged (unit) Ritz vector that lies in the locked span leaves almost
       // nothing after the projection: start from a random vector instead
@@ -855,7 +858,8 @@ edx_status lowest_states_impl(const edx_sector* s, int k, const edx_lanczos_opts
         EDX_TRY(k_start_vector(vtype, L.vec, s->dup, s->ld, s->ddw * s->dph,
                                o->seed + 0x9E3779B97F4A7C15ull * (uint64_t)runs, L.partial, st));
         if (nl > 0) EDX_TRY(project_out(vtype, L.vec, X, L, nl, n, st));
-        EDX_TRY(k_beta_finish(L.partial, elem_blocks(n), L.beta, L.scale, st));
+        EDX_TRY(k_beta_finish(L.partial, nl > 0 ? multi_blocks(n) : elem_blocks(n), L.beta,
+                              L.scale, st));
       }
     }
     EDX_HIP(hipMemsetAsync(L.beta, 0, sizeof(double), st));
@@ -968,7 +972,8 @@ edx_status lowest_states_impl(const edx_sector* s, int k, const edx_lanczos_opts
       } else {
         EDX_TRY(k_norm2(vtype, dst, n, L.partial, st));
       }
-      EDX_TRY(k_beta_finish(L.partial, elem_blocks(n), L.coef, L.coef + 1, st));
+      EDX_TRY(k_beta_finish(L.partial, !E.empty() ? multi_blocks(n) : elem_blocks(n), L.coef,
+                            L.coef + 1, st));
       double nrm = 0.0;
       EDX_HIP(hipMemcpyAsync(&nrm, L.coef, sizeof(double), hipMemcpyDeviceToHost, st));
       EDX_HIP(hipStreamSynchronize(st));
