@@ -99,7 +99,7 @@ __global__ __launch_bounds__(kThreads) void k_update_kernel(
 // The same update on 16-byte vectors (4 FP32 or 2 FP64 elements a lane):
 // with at most kMaxElemBlocks blocks a CU holds 16 waves, and 4-byte FP32
 // lanes left too few bytes in flight to stream at the copy rate (Ns=15 7/7,
-// D = 41.4M: 170 us for 663 MB, against 228 us for the 1.33 GB of FP64).
+// D = 41.4M: 170 us for 666 MB, against 228 us for the 1.33 GB of FP64).
 // Requires every vector 16-byte aligned; elements past the last full vector
 // are done by scalar lanes.  Each lane sums its elements' squares in element
 // order, so the result is deterministic for a given n and grid.
