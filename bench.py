@@ -162,20 +162,25 @@ def copy_bandwidth(torch, nbytes=1 << 30, reps=10):
 
 
 def bench_hv_o2(edx, torch, a):
-    """FP32 H.v on the Norb=2, Nbath=7 (Ns=16) half-filled sector."""
+    """H.v on the Norb=2, Nbath=7 (Ns=16) half-filled sector, FP32 and FP64
+    (hop rows of 16 slots, 7.47 real hops a string on average)."""
     from paper_2105_06806_amd import inputs
     m, [sec] = inputs.workload("ns16o2")
     S = edx.build_sector(m, *sec)
-    gen = torch.Generator(device="cuda").manual_seed(2)
-    v = edx.pad(S, torch.rand(S.dim, dtype=torch.float32, device="cuda", generator=gen) * 2 - 1)
-    w = torch.empty_like(v)
-    plan, _ = edx.autotune_hv(S, v, w, reps=a.tune_reps, ld=S.ld)
-    ms, _ = time_hv(edx, torch, S, v, w, a.steps, a.warmup, ld=S.ld)
-    gbs = S.dim * 8 / (ms.mean() * 1e-3) / 1e9
-    return {"workload": f"H.v, Norb=2 Nbath=7 (Ns=16) 8/8, D={S.dim}, FP32, hop widths "
-                        f"{S.hop_nnz(0)[1]}/{S.hop_nnz(1)[1]}",
-            "us": round(float(ms.mean()) * 1e3, 1), "gbs": round(gbs, 1),
-            "frac": round(gbs / HBM_PEAK_GBS, 4), "plan": plan}
+    out = {"workload": f"H.v, Norb=2 Nbath=7 (Ns=16) 8/8, D={S.dim}, hop widths "
+                       f"{S.hop_nnz(0)[1]}/{S.hop_nnz(1)[1]}"}
+    for dt, tdt, esz in (("f32", torch.float32, 4), ("f64", torch.float64, 8)):
+        gen = torch.Generator(device="cuda").manual_seed(2)
+        v = edx.pad(S, torch.rand(S.dim, dtype=tdt, device="cuda", generator=gen) * 2 - 1)
+        w = torch.empty_like(v)
+        plan, _ = edx.autotune_hv(S, v, w, reps=a.tune_reps, ld=S.ld)
+        ms, _ = time_hv(edx, torch, S, v, w, a.steps, a.warmup, ld=S.ld)
+        gbs = S.dim * 2 * esz / (ms.mean() * 1e-3) / 1e9
+        out[dt] = {"us": round(float(ms.mean()) * 1e3, 1), "gbs": round(gbs, 1),
+                   "frac": round(gbs / HBM_PEAK_GBS, 4), "plan": plan}
+        del v, w
+        torch.cuda.empty_cache()
+    return out
 
 
 def _cpu_rows_worker(seed, n):

@@ -540,6 +540,7 @@ __global__ __launch_bounds__(1024) void k_hv_fused(HvArgs<T> a, const T* __restr
   gptr<T> gcol[NC][WDW];   // neighbour columns (block-uniform)
   uint32_t goff[NC][WDW];  // BUF: their byte offsets from v
   T gamp[NC][WDW];         // their amplitudes times the vector scale
+  int nreal[NC];           // real (not padding) entries of the column's hop row
   T ed[NC];
   int pd[NC];
   T gd[NC];   // phonon coupling of the spin-down pattern (PH)
@@ -549,9 +550,11 @@ __global__ __launch_bounds__(1024) void k_hv_fused(HvArgs<T> a, const T* __restr
     ed[c] = a.edw[j];
     pd[c] = a.pdw[j];
     gd[c] = PH ? gpat(ph, pd[c]) : T(0);
+    int cnt = 0;
 #pragma unroll
     for (int k = 0; k < WDW; ++k) {
       const uint32_t f = a.hdw[j * WDW + k];
+      cnt += (f >> kAmpShift) != kPadPair ? 1 : 0;
       if constexpr (BUF)
         goff[c][k] = __builtin_amdgcn_readfirstlane(
             (uint32_t)((uint64_t)(f & kColMask) * (uint64_t)ld * sizeof(T)));
@@ -559,6 +562,7 @@ __global__ __launch_bounds__(1024) void k_hv_fused(HvArgs<T> a, const T* __restr
         gcol[c][k] = uniform(v + (int64_t)(f & kColMask) * ld);
       gamp[c][k] = uniform(a.amp[f >> kAmpShift] * sc);
     }
+    nreal[c] = (int)__builtin_amdgcn_readfirstlane((uint32_t)cnt);
   }
   stage_put(vs, sb, nc, dup, (int64_t)threadIdx.x, sc);
   for (int64_t r0 = threadIdx.x + (int64_t)SU * blockDim.x; r0 < dup;
@@ -638,10 +642,24 @@ __global__ __launch_bounds__(1024) void k_hv_fused(HvArgs<T> a, const T* __restr
       for (int c = 0; c < NC; ++c)
 #pragma unroll
         for (int k = 0; k < WDW; ++k) {
-          if constexpr (BUF)
-            g[c][k] = buf_load<T>(vres, voff, goff[c][k]);
-          else
+          if constexpr (BUF) {
+            if constexpr (WDW > 8 && sizeof(T) == 8) {
+              // padded hop rows (Norb >= 2: 16 slots, 6.4-7.5 real hops on
+              // average at Ns = 15-16): the padding entries come after the
+              // real ones and carry amplitude 0, so a block-uniform branch
+              // skips their loads.  FP64: Norb=2 Ns=16 3100 -> 2074 us,
+              // Norb=3 Ns=15 537 -> 459 us; FP32 keeps every load in one
+              // batch (the branches cost it 4-24 %).
+              if (k < nreal[c])
+                g[c][k] = buf_load<T>(vres, voff, goff[c][k]);
+              else
+                g[c][k] = T(0);
+            } else {
+              g[c][k] = buf_load<T>(vres, voff, goff[c][k]);
+            }
+          } else {
             g[c][k] = gcol[c][k][iu32];
+          }
         }
       // phonon neighbours: the same element one slice back / ahead, issued
       // with the gathers so that their latency overlaps
