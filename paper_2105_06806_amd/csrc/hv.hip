@@ -594,8 +594,12 @@ __global__ __launch_bounds__(1024) void k_hv_fused(HvArgs<T> a, const T* __restr
   // ALL: the block owns NC columns (every block but possibly the last); then
   // nothing in the row body is conditional and the compiler keeps all
   // gathers of a row in flight together
-  auto rows = [&](auto all_tag) {
+  // WK: spin-down slots gathered per row -- 8 when no column of the block has
+  // more real hops than that (the padding entries follow the real ones), else
+  // every slot of the padded row
+  auto rows = [&](auto all_tag, auto wk_tag) {
     constexpr bool ALL = decltype(all_tag)::value;
+    constexpr int WK = decltype(wk_tag)::value;
     // (BUF: a 32-bit row index; D_up < 2^24 always)
     using RowT = std::conditional_t<BUF, uint32_t, int64_t>;
     for (RowT iu = threadIdx.x; iu < (RowT)dup; iu += blockDim.x) {
@@ -641,15 +645,16 @@ __global__ __launch_bounds__(1024) void k_hv_fused(HvArgs<T> a, const T* __restr
 #pragma unroll
       for (int c = 0; c < NC; ++c)
 #pragma unroll
-        for (int k = 0; k < WDW; ++k) {
+        for (int k = 0; k < WK; ++k) {
           if constexpr (BUF) {
-            if constexpr (WDW > 8 && sizeof(T) == 8) {
-              // padded hop rows (Norb >= 2: 16 slots, 6.4-7.5 real hops on
-              // average at Ns = 15-16): the padding entries come after the
-              // real ones and carry amplitude 0, so a block-uniform branch
-              // skips their loads.  FP64: Norb=2 Ns=16 3100 -> 2074 us,
-              // Norb=3 Ns=15 537 -> 459 us; FP32 keeps every load in one
-              // batch (the branches cost it 4-24 %).
+            if constexpr (WK > 8 && sizeof(T) == 8) {
+              // the full-width loop over padded hop rows (Norb >= 2: 16
+              // slots, 6.4-7.5 real hops on average at Ns = 15-16): the
+              // padding entries come after the real ones and carry amplitude
+              // 0, so in FP64 a block-uniform branch skips their loads
+              // (Norb=2 Ns=16 3100 -> 2074 us, Norb=3 Ns=15 537 -> 459 us);
+              // FP32 keeps every load of the row in one batch (the branches
+              // cost it 4-24 %).
               if (k < nreal[c])
                 g[c][k] = buf_load<T>(vres, voff, goff[c][k]);
               else
@@ -689,7 +694,7 @@ __global__ __launch_bounds__(1024) void k_hv_fused(HvArgs<T> a, const T* __restr
         const T x = vs[iu32 * (uint32_t)NC + c];
         T s2 = T(0);
 #pragma unroll
-        for (int k = 0; k < WDW; ++k) s2 += gamp[c][k] * g[c][k];
+        for (int k = 0; k < WK; ++k) s2 += gamp[c][k] * g[c][k];
         T res = acc[c] + (eu + ed[c] + Wt[pu + pd[c]]) * x + s2;
         if constexpr (PH) res += (gpat(ph, patu) + gd[c]) * (ph.sp * pv[c] + ph.sp1 * pn[c]) * sc;
         if constexpr (ND) {
@@ -715,10 +720,34 @@ __global__ __launch_bounds__(1024) void k_hv_fused(HvArgs<T> a, const T* __restr
       }
     }
   };
+  // Padded rows of 16 slots (Norb >= 2): 80-93 % of the blocks have no column
+  // with more than 8 real hops (Norb=2 Ns=16, 3 columns: 80 %; Norb=3 Ns=15,
+  // 2 columns: 86 %), and those take a row loop over 8 slots.  Measured: FP32
+  // Norb=2 Ns=16 1169 -> 1038 us, Norb=3 Ns=15 235 -> 217 us; FP64 with 2
+  // columns a block Norb=3 Ns=15 467 -> 412 us.  FP64 with one column a block
+  // keeps the per-load skip alone (the 8-slot loop was 4 % slower there).
+  constexpr bool kNarrow = WDW > 8 && (sizeof(T) == 4 || NC >= 2);
+  bool narrow = false;
+  if constexpr (kNarrow) {
+    int mx = 0;
+#pragma unroll
+    for (int c = 0; c < NC; ++c) mx = std::max(mx, nreal[c]);
+    narrow = mx <= 8;
+  }
+  auto go = [&](auto all_tag) {
+    if constexpr (kNarrow) {
+      if (narrow)
+        rows(all_tag, std::integral_constant<int, 8>{});
+      else
+        rows(all_tag, std::integral_constant<int, WDW>{});
+    } else {
+      rows(all_tag, std::integral_constant<int, WDW>{});
+    }
+  };
   if (nc == NC)
-    rows(std::true_type{});
+    go(std::true_type{});
   else
-    rows(std::false_type{});
+    go(std::false_type{});
   for (int64_t i = dup + threadIdx.x; i < ld; i += blockDim.x)
 #pragma unroll
     for (int c = 0; c < NC; ++c)
