@@ -706,7 +706,7 @@ def serve_sweep_from_profile():
 
 def bench_serve(edx, torch, full, nreq=None, ns_hi=None, rates=None, cap_given=None,
                 plain_file=None, offset=0, span=None, dump=None):
-    """Config 5: a Poisson stream of ground state + G requests (Norb in {1,2},
+    """Serving: a Poisson stream of ground state + G requests (Norb in {1,2},
     Ns 10..16, U in [1,6]; FP32 vectors) served with continuous batching, at
     offered rates that are multiples of the measured one-at-a-time capacity.
     Plain: every request of the stream solved one after another (its service

@@ -79,7 +79,7 @@ def test_hv_multi_against_oracle_and_single(edx, name, norb, nbath, sec, k, dtyp
 
 @pytest.mark.parametrize("dtype", ["f32", "f64"])
 def test_hv_multi_ns14_against_kron(edx, dtype):
-    """Config-4-size sector (Ns=14 7/7, D=11,778,624), four bath sets: the
+    """The batch workload's largest shape (Ns=14 7/7, D=11,778,624), four bath sets: the
     first and last set against the oracle's Kronecker form."""
     import torch
     tdt = torch.float64 if dtype == "f64" else torch.float32

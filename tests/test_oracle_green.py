@@ -103,7 +103,7 @@ def test_spin_down_string_sign():
 
 def test_krylov_depth_200_converged():
     """The Green's function is evaluated at Krylov depth 200 (the paper's
-    N_gf default); on a half-filled Ns=10 sector (D = 63,504) on the config-2
+    N_gf default); on a half-filled Ns=10 sector (D = 63,504) on the Ns=12 workload's
     grid (beta = 200, 4096 Matsubara frequencies) depth 400 changes it by less
     than the FP64 parity tolerance (1e-8 of max|G|), while a shallow depth
     is visibly off, so the comparison resolves the truncation."""
