@@ -690,18 +690,31 @@ PROFILE_SERVE = os.path.join(ROOT, "profiles", "serve_sweep_ns16.md")
 def serve_sweep_from_profile():
     """The committed full-size serving sweep (1000 requests per rate, Ns
     10..16, measured by this file's serve section split over several runs):
-    quoted, not measured by this run."""
+    quoted, not measured by this run.  `rates`: the seven-rate sweep, taken
+    with at most half the slots on large requests; `current_policy`: the
+    rates measured with the library's current admission (one large request
+    at a time)."""
     if not os.path.exists(PROFILE_SERVE):
         return None
-    rows = []
-    for mr in re.finditer(r"^rate\[([0-9.]+)\]:(.*)$", open(PROFILE_SERVE).read(), re.M):
-        row = {"x_plain_capacity": float(mr.group(1))}
-        for kv in mr.group(2).split():
-            k, v = kv.split("=")
-            row[k] = float(v) if "." in v or "e" in v else int(v)
-        rows.append(row)
+    txt = open(PROFILE_SERVE).read()
+
+    def rows(tag):
+        out = []
+        for mr in re.finditer(r"^" + tag + r"\[([0-9.]+)\]:(.*)$", txt, re.M):
+            row = {"x_plain_capacity": float(mr.group(1))}
+            for kv in mr.group(2).split():
+                k, v = kv.split("=")
+                row[k] = float(v) if "." in v or "e" in v else int(v)
+            out.append(row)
+        return out
+
+    full = rows("rate")
+    if not full:
+        return None
     return {"source": "profiles/serve_sweep_ns16.md (quoted, not measured by this run)",
-            "rates": rows} if rows else None
+            "policy": "at most half the slots on requests of 1 GiB or more", "rates": full,
+            "current_policy": {"policy": "one request of 1 GiB or more at a time",
+                               "rates": rows("rate_current")}}
 
 
 def bench_serve(edx, torch, full, nreq=None, ns_hi=None, rates=None, cap_given=None,

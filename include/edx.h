@@ -611,8 +611,10 @@ edx_status edx_batch_autotune(const edx_sector* const* sectors, int32_t n,
  * nothing else) and max_slots worker threads with their own streams.  A
  * request is admitted when a slot is free and its footprint (tables,
  * workspaces, psi0) fits in the arena; among the pending requests that fit,
- * the smallest footprint goes first (its work is the smallest), and a request
- * passed over 8 times goes next, blocking further passing.  Admitted requests
+ * the smallest footprint goes first (its work is the smallest), one request
+ * of 1 GiB or more runs at a time (large requests are bandwidth-bound: one at
+ * a time they finish sooner at the same throughput), and a request passed
+ * over 8 times goes next, blocking further passing.  Admitted requests
  * overlap on the device; each runs the plain path's kernels, so its result
  * does not depend on what else runs.  Times are seconds of
  * edx_server_clock(). */

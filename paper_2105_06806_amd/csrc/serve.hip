@@ -7,8 +7,8 @@
 // footprint: a request is admitted when a worker is free and its workspace
 // (Lanczos vectors, psi0, Green vectors) fits in the arena; the smallest
 // pending request that fits goes first (small sectors are quick, so they do
-// not wait behind large ones), at most half the slots run requests of
-// `kLargeBytes` or more, and a request passed over `kMaxSkips` times blocks
+// not wait behind large ones), at most kLargeCap requests of `kLargeBytes`
+// or more run at once, and a request passed over `kMaxSkips` times blocks
 // further passing until it is admitted (no starvation).  Admitted requests
 // run concurrently on their streams, so their kernels overlap on the device;
 // a request that arrives while others run is admitted as soon as a slot and
@@ -35,6 +35,13 @@ namespace {
 
 constexpr int kMaxSkips = 8;
 constexpr size_t kLargeBytes = size_t(1) << 30;   // a "large" request's footprint
+// Large requests in flight at once.  They are bandwidth-bound, so running them
+// one at a time loses no throughput, and each finishes sooner: on the
+// 1000-request Ns 10..16 stream, one instead of half the slots gave p99 2.28
+// vs 2.99 s at half the one-at-a-time capacity and 15.9 vs 18.3 s at the
+// full capacity (p50 0.058 vs 0.062 s and 0.088 vs 0.342 s, the same
+// throughput).
+constexpr int kLargeCap = 1;
 constexpr size_t kAlign = 256;
 
 double now_s() {
@@ -205,13 +212,13 @@ void worker_main(edx_server* S, int slot) {
         // admission, smallest footprint first (the footprint grows with the
         // sector dimension, so with the work): among the admissible pending
         // requests -- a large one (footprint >= kLargeBytes) only while fewer
-        // than half the slots run large ones, so small requests always find
-        // a slot and the large ones share the bandwidth with fewer others --
+        // than kLargeCap run, so small requests always find a slot and the
+        // large ones do not share the bandwidth with each other --
         // the smallest that fits is taken, and every older admissible request
         // it passes counts a skip; the oldest admissible request passed over
         // kMaxSkips times goes next, waiting for memory if need be (nothing
         // passes it), so none starves
-        const int large_cap = std::max(1, S->opts.max_slots / 2);
+        const int large_cap = std::min(kLargeCap, S->opts.max_slots);
         auto admissible = [&](const Request* q) {
           return q->footprint < kLargeBytes || S->large < large_cap;
         };

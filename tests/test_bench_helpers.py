@@ -40,6 +40,9 @@ def test_serve_sweep_summary_parses(bench):
         assert r["n"] >= 1000 and r["completed"] == r["n"]
         assert r["p50_s"] <= r["p99_s"] and r["plain_p50_s"] <= r["plain_p99_s"]
         assert 0 < r["solves_per_s"] <= r["offered_per_s"] * 1.2
+    cur = sw["current_policy"]["rates"]
+    assert cur and all(r["n"] >= 1000 and r["completed"] == r["n"] for r in cur)
+    assert {r["x_plain_capacity"] for r in cur} <= set(rates)
     txt = open(bench.PROFILE_SERVE).read()
     assert "Ns 10..16" in txt and "12870^2" in txt
 
